@@ -1,0 +1,137 @@
+"""Seeded synthetic workloads for the 2D P1 Helmholtz problems.
+
+Conventions (shared by every consumer):
+  * structured N x N node grid on the unit square [0,1]^2, h = 1/(N-1);
+  * node (i, j) sits at (i*h, j*h) and has id j*N + i;
+  * a source is a Gaussian bump exp(-|x - x0|^2 / (2 w^2)) of amplitude 1,
+    sampled at the nodes (the nodal interpolant f_I);
+  * the speed field c(x) = 1 + 2*sigmoid(g(x)) with g a random-feature
+    Gaussian field of correlation length ell; slowness s = 1/c.
+
+Random draws use numpy's PCG64 with explicit seeds, so every array here is a
+pure function of its arguments.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Problem", "node_coords", "source_centers", "gaussian_sources",
+    "random_field", "speed_field", "make_problem", "CONFIGS",
+    "receiver_nodes", "batch_grid_sizes",
+]
+
+
+def node_coords(N):
+    """(x, y) float64 arrays of length N*N, node id = j*N + i."""
+    h = 1.0 / (N - 1)
+    i = np.arange(N, dtype=np.float64)
+    x = np.tile(i, N) * h
+    y = np.repeat(i, N) * h
+    return x, y
+
+
+def source_centers(seed, count, lo=0.25, hi=0.75):
+    """count source positions drawn uniformly in [lo, hi]^2 (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(lo, hi, size=(count, 2))
+
+
+def gaussian_sources(N, centers, width=0.02):
+    """Nodal samples of Gaussian bumps: array (N*N, len(centers)), float64."""
+    x, y = node_coords(N)
+    centers = np.asarray(centers, dtype=np.float64).reshape(-1, 2)
+    f = np.empty((N * N, centers.shape[0]), dtype=np.float64)
+    for s, (cx, cy) in enumerate(centers):
+        f[:, s] = np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * width * width))
+    return f
+
+
+def random_field(N, seed, ell=0.1, n_features=1024):
+    """Random-feature Gaussian field g(x) = sqrt(2/M) sum_m cos(w_m.x + b_m),
+    w_m ~ N(0, ell^-2 I), b_m ~ U[0, 2pi); unit variance, correlation ell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.normal(0.0, 1.0 / ell, size=(n_features, 2))
+    b = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
+    x, y = node_coords(N)
+    g = np.zeros(N * N)
+    chunk = 4096
+    for s in range(0, N * N, chunk):
+        ph = np.outer(x[s:s + chunk], w[:, 0]) + np.outer(y[s:s + chunk], w[:, 1]) + b
+        g[s:s + chunk] = np.cos(ph).sum(axis=1)
+    return g * np.sqrt(2.0 / n_features)
+
+
+def speed_field(N, seed, ell=0.1):
+    """c(x) = 1 + 2*sigmoid(g(x)) in (1, 3)."""
+    g = random_field(N, seed, ell)
+    return 1.0 + 2.0 / (1.0 + np.exp(-g))
+
+
+def receiver_nodes(N, seed, count=8):
+    """count distinct node ids drawn uniformly without replacement."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(N * N, size=count, replace=False)).astype(np.int64)
+
+
+def batch_grid_sizes(seed, count, lo=65, hi=513):
+    """Uneven grid sizes N_i ~ U{lo..hi}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(lo, hi + 1, size=count).astype(np.int64)
+
+
+@dataclass
+class Problem:
+    """One seeded Helmholtz P1 workload: -lap u - (omega s)^2 u = f on [0,1]^2
+    with the first-order absorbing condition on all four sides."""
+    name: str
+    N: int
+    omega: float
+    slowness: np.ndarray          # (N*N,) float64 nodal slowness s = 1/c
+    f: np.ndarray                 # (N*N, nrhs) float64 nodal source samples
+    leaf_dofs: int = 32           # nested-dissection leaf size (DOFs)
+    beta: int = 16                # HSS leaf size
+    tol: float = 1e-6             # HSS compression tolerance
+    h_sw: int = 4                 # switching height
+    gmres_m: int = 50
+    gmres_tol: float = 1e-8
+    factor_dtype: str = "c128"
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.N * self.N
+
+    @property
+    def nrhs(self):
+        return self.f.shape[1]
+
+
+def _helmholtz(name, N, omega, seed, nsrc, **kw):
+    centers = source_centers(seed, nsrc)
+    return Problem(name=name, N=N, omega=float(omega),
+                   slowness=np.ones(N * N), f=gaussian_sources(N, centers), **kw)
+
+
+#: Named workloads.  The first is the small case the oracle runs in seconds;
+#: the second is the 263k-DOF, 64-source case the benchmark times.
+CONFIGS = {
+    "helmholtz_p1_65": dict(N=65, omega=16.0, seed=0, nsrc=1),
+    "helmholtz_p1_513_x64": dict(N=513, omega=100.0, seed=1, nsrc=64,
+                                 factor_dtype="c64"),
+    # smaller parity cases (several tiles, ragged trees)
+    "helmholtz_p1_17": dict(N=17, omega=4.0, seed=2, nsrc=2),
+    "helmholtz_p1_33": dict(N=33, omega=8.0, seed=3, nsrc=3),
+    "helmholtz_p1_129": dict(N=129, omega=32.0, seed=4, nsrc=4),
+    "helmholtz_p1_257": dict(N=257, omega=50.0, seed=5, nsrc=8),
+}
+
+
+def make_problem(name, **overrides):
+    cfg = dict(CONFIGS[name])
+    cfg.update(overrides)
+    N = cfg.pop("N")
+    omega = cfg.pop("omega")
+    seed = cfg.pop("seed")
+    nsrc = cfg.pop("nsrc")
+    return _helmholtz(name, N, omega, seed, nsrc, **cfg)
