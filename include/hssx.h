@@ -1,0 +1,208 @@
+/*
+ * hssx.h - C ABI of the MI355X (gfx950) implementation of the hierarchical
+ * nested-dissection + HSS preconditioner for 2D Galerkin wave problems
+ * (Bonev & Hesthaven, "A hierarchical preconditioner for wave problems in
+ * quasilinear complexity").
+ *
+ * Problem (Sec. 1, eq. 1.1; Sec. 4.2, eq. 4.2): A x = b with A the P1
+ * Galerkin matrix of -lap u - (omega s(x))^2 u on the unit square with the
+ * absorbing condition d_n u - i omega s u = 0 on its boundary,
+ *     A = K - omega^2 M[s^2] - i omega G[s]         (complex symmetric),
+ * on an N x N node grid (node (i,j) at (i h, j h), id j*N+i, h = 1/(N-1),
+ * each cell split along its SW-NE diagonal).  The solve is preconditioned as
+ * P^-1 A x = P^-1 b (eq. 1.2) with P = LDR (eq. 3.1) built by Algorithm 3.4
+ * and applied by Algorithm 3.1.
+ *
+ * Conventions
+ *   - Every function returns hssx_status; nothing throws across the ABI.
+ *     Negative values are errors (outputs unspecified, handles still valid
+ *     to destroy); HSSX_ENOCONV is a warning (x holds the last iterate).
+ *     hssx_last_error() returns a thread-local message for the last failure.
+ *   - Pointers documented as "device" are HIP device pointers (e.g. the
+ *     data_ptr of a torch CUDA tensor).  Pointers documented as "host" are
+ *     ordinary host memory.  The caller owns every buffer it passes; the
+ *     library owns its handles and every internal buffer (allocated with
+ *     hipMalloc on the handle's device) and frees them in *_destroy.
+ *   - Complex vectors are complex128 (interleaved re, im doubles), column-
+ *     major with leading dimension ld >= n.  Vectors use the natural node
+ *     numbering.
+ *   - stream is a hipStream_t passed as void* (NULL = default stream).  Work
+ *     is stream-ordered; functions that must read results back (factor rank
+ *     decisions, GMRES convergence tests) synchronise that stream and say so.
+ *   - Arguments are validated before any launch; invalid ones give
+ *     HSSX_EINVAL.
+ */
+#ifndef HSSX_H
+#define HSSX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSSX_OK = 0,
+  HSSX_ENOCONV = 1,       /* GMRES hit maxit; x valid, stats filled */
+  HSSX_EINVAL = -1,       /* invalid argument */
+  HSSX_ENOMEM = -2,       /* device allocation failed */
+  HSSX_ESINGULAR = -3,    /* zero pivot in a dense block; message names the node */
+  HSSX_ERANKCAP = -4,     /* compression did not meet tol before its round limit */
+  HSSX_EHIP = -5          /* HIP runtime error */
+} hssx_status;
+
+typedef enum { HSSX_C128 = 0, HSSX_C64 = 1 } hssx_dtype;
+
+typedef struct hssx_op_ *hssx_op;      /* assembled operator A */
+typedef struct hssx_fact_ *hssx_fact;  /* approximate factorization P */
+
+/* Problem description (Sec. 4.2; the paper's Dirichlet data replaced by the
+ * absorbing condition, see DESIGN). */
+typedef struct {
+  int N;          /* nodes per side, N >= 2 */
+  double omega;   /* angular frequency; wavenumber k(x) = omega * s(x) */
+} hssx_problem_desc;
+
+/* Factorization options (Sec. 4 parameter choices; Algorithm 3.4, A.1). */
+typedef struct {
+  int beta;         /* HSS leaf size in DOFs (eq. 2.1); default 16 */
+  int h_sw;         /* switching height: nodes higher than h_sw use HSS
+                       arithmetic, their children compress S; < 0 = never
+                       compress (exact sparse direct factorization) */
+  int k0;           /* initial rank estimate of Algorithm A.1; default 32 */
+  int r;            /* probe / rank step of Algorithm A.1; default 16 */
+  int max_rounds;   /* rank-growth rounds per compression; default 32 */
+  hssx_dtype dtype; /* factor storage / arithmetic: C128 or C64 */
+  uint32_t seed;    /* key of the counter-based sketch generator */
+  double id_rel_tol;/* relative pivot threshold of the interpolative
+                       decomposition; <= 0 selects 1e-2 * tol */
+} hssx_factor_opts;
+
+typedef struct {
+  int m;            /* restart length; default 50 */
+  double tol;       /* relative residual target; default 1e-8 */
+  int maxit;        /* total Arnoldi steps; default 1000 */
+  int flexible;     /* 0: left preconditioning (stop on ||P^-1 r||/||P^-1 b||,
+                       then check ||r||/||b||); 1: flexible right
+                       preconditioning (stop on ||r||/||b||) */
+} hssx_gmres_opts;
+
+typedef struct {
+  int iters;            /* total Arnoldi steps (paper's "iters") */
+  int converged;        /* 1 if true relative residual <= tol */
+  double prec_res;      /* final preconditioned relative residual (left) */
+  double true_res;      /* final ||b - A x|| / ||b|| */
+} hssx_gmres_stats;
+
+typedef struct {
+  int n;                /* unknowns */
+  int nodes;            /* elimination-tree nodes */
+  int depth;            /* tree depth */
+  int n_hss_nodes;      /* nodes using HSS arithmetic */
+  int n_compressed;     /* Schur complements compressed (Algorithm A.1 calls on S) */
+  int k_max;            /* largest rank among compressed blocks (Sec. 4.2) */
+  int max_rounds_used;  /* most rank-growth rounds of any compression */
+  double max_estimate;  /* largest accepted relative error estimate (eq. 2.7) */
+  double factor_bytes;  /* bytes the apply reads (LU blocks, pivots, R) */
+  double factor_flops;  /* nominal flops of the numeric factorization */
+  double ms_symbolic;   /* host symbolic analysis */
+  double ms_numeric;    /* numeric factorization (device, hipEvents) */
+} hssx_factor_stats;
+
+/* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for
+ * the slowness field s (device, float64[N*N], caller-owned, read during the
+ * call).  Sec. 4.2 eq. 4.2 with the closed-form P1 integrals. */
+hssx_status hssx_assemble(int device, const hssx_problem_desc *desc,
+                          const double *s_dev, void *stream, hssx_op *A_out);
+
+/* b = M f with M the plain P1 mass matrix: the load of nodal source samples
+ * f (device, float64, n x nrhs, ld ldf) into b (device, complex128, ld ldb).*/
+hssx_status hssx_load(hssx_op A, int nrhs, const double *f_dev, long ldf,
+                      void *b_dev, long ldb, void *stream);
+
+/* y = A x (trans = 0) or A^T x (trans = 1; equal to A x, A is symmetric).
+ * x, y: device complex128, n x nrhs. */
+hssx_status hssx_matvec(hssx_op A, int trans, int nrhs, const void *x_dev,
+                        long ldx, void *y_dev, long ldy, void *stream);
+
+/* Copy the CSR arrays of A to host buffers (sizes n+1, nnz, 2*nnz doubles);
+ * any pointer may be NULL.  *nnz_out receives nnz.  Synchronises stream. */
+hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col,
+                         double *val, long *nnz_out, void *stream);
+
+/* Approximate factorization P = LDR (Algorithm 3.4): box nested dissection
+ * with leaf boxes of at most leaf_size DOFs (Sec. 4: ND until the leaf boxes
+ * are small), dense elimination below the switching height, Schur
+ * complements compressed to HSS by adaptive randomized sampling (Algorithm
+ * A.1, relative tolerance tol, eq. 2.7), and the HSS-class interior blocks
+ * handled by the 2x2 block inverse of Algorithms 3.2/3.3.  Host-blocking:
+ * synchronises stream after every batch of compressions to read the error
+ * estimates.  opts may be NULL (defaults). */
+hssx_status hssx_factor(hssx_op A, double tol, int leaf_size,
+                        const hssx_factor_opts *opts, void *stream,
+                        hssx_fact *P_out);
+
+/* y = P^-1 x (trans = 0) or P^-T x (trans = 1) by Algorithm 3.1
+ * (bottom-up L sweep, block-diagonal solve, top-down R sweep).  x, y:
+ * device complex128, n x nrhs; y may alias x. */
+hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev,
+                       long ldx, void *y_dev, long ldy, void *stream);
+
+/* Restarted GMRES on A x = b (eq. 1.2) with preconditioner P, all nrhs
+ * right-hand sides advanced together; x0 = 0.  trans = 1 solves A^T x = b
+ * with P^-T (adjoint solves).  stats: host array of nrhs entries (may be
+ * NULL).  Host-blocking: reads residual norms once per Arnoldi step. */
+hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs,
+                             const void *b_dev, long ldb, void *x_dev,
+                             long ldx, const hssx_gmres_opts *opts,
+                             hssx_gmres_stats *stats, void *stream);
+
+/* Adjoint contraction for a real functional J(x(s)), x = A(s)^-1 b:
+ * grad_s[l] += -Re sum_rhs lambda^T (dA/ds_l) x, with lambda = A^-T dJ/dx
+ * as solved by the caller.  lambda, x: device complex128 n x nrhs (ld n);
+ * grad_s: device float64[n], accumulated.  dA/ds_l =
+ * -2 omega^2 s_l M_l - i omega G_l with M_l, G_l the P1 triple-product
+ * matrices of node l. */
+hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev,
+                               const void *x_dev, double *grad_dev,
+                               void *stream);
+
+/* Symbolic analysis only (box nested dissection, elimination tree, cluster
+ * trees; Sec. 3.1 Def. 3.1, Fig. 3, Fig. 4) for an N x N grid with leaf boxes
+ * of at most leaf_size DOFs and HSS leaves of at most beta DOFs.  Host-only:
+ * makes no HIP call, so it runs without a GPU.  The handle supports
+ * hssx_get_perm, hssx_get_tree and hssx_fact_destroy only. */
+hssx_status hssx_analyze(int N, int leaf_size, int beta, hssx_fact *P_out);
+
+/* Elimination permutation (host int32[n]): perm[k] = node id eliminated at
+ * position k (concatenation of I(sigma) over the post-order). */
+hssx_status hssx_get_perm(hssx_fact P, int32_t *perm_host, long n);
+
+/* Elimination tree and cluster trees, flattened to host arrays for
+ * bit-exact comparison.  Call once with NULL arrays to get the sizes in
+ * *sizes_out (int64[4]: nodes, total |I|, total |B|, total clusters), then
+ * with buffers: node_info int32[nodes*10] = (x0,x1,y0,y1,lo,hi,parent,
+ * depth,height,p0); i_ids int32[total |I|] and i_ptr int32[nodes+1];
+ * b_ids int32[total |B|] and b_ptr int32[nodes+1]; clusters int32[total*5] =
+ * (start,size,left,right,level) per cluster, c_ptr int32[nodes+1]. */
+hssx_status hssx_get_tree(hssx_fact P, int64_t *sizes_out,
+                          int32_t *node_info, int32_t *i_ids, int32_t *i_ptr,
+                          int32_t *b_ids, int32_t *b_ptr, int32_t *clusters,
+                          int32_t *c_ptr);
+
+hssx_status hssx_get_factor_stats(hssx_fact P, hssx_factor_stats *s);
+
+/* Read a node's dense Schur complement S(sigma) as passed to its parent
+ * (expanded from HSS when compressed), |B| x |B| column-major complex128 into
+ * host memory.  For tests.  Synchronises. */
+hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld);
+
+void hssx_fact_destroy(hssx_fact P);
+void hssx_op_destroy(hssx_op A);
+const char *hssx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSSX_H */

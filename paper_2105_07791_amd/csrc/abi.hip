@@ -1,0 +1,378 @@
+// extern "C" entry points declared in include/hssx.h.  Every call validates
+// its arguments, runs under the handle's device, converts exceptions into a
+// status code and records the message for hssx_last_error().
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "engine.h"
+
+using namespace hssx;
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F> hssx_status guarded(F &&f) {
+  try {
+    f();
+    return HSSX_OK;
+  } catch (const Error &e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return HSSX_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return HSSX_EINVAL;
+  }
+}
+
+struct DeviceScope {
+  int prev = 0;
+  explicit DeviceScope(int d) {
+    HSSX_HIP(hipGetDevice(&prev));
+    if (prev != d) HSSX_HIP(hipSetDevice(d));
+  }
+  ~DeviceScope() { (void)hipSetDevice(prev); }
+};
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char *hssx_last_error(void) { return g_err.c_str(); }
+
+hssx_status hssx_assemble(int device, const hssx_problem_desc *desc, const double *s_dev,
+                          void *stream, hssx_op *A_out) {
+  return guarded([&] {
+    HSSX_CHECK(desc && A_out && s_dev, HSSX_EINVAL, "null argument");
+    HSSX_CHECK(desc->N >= 2 && desc->N <= 46000, HSSX_EINVAL, "N out of range");
+    HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
+    *A_out = nullptr;
+    DeviceScope ds(device);
+    auto A = std::make_unique<hssx_op_>();
+    A->device = device;
+    A->N = desc->N;
+    A->omega = desc->omega;
+    const int N = desc->N, n = N * N;
+    A->n = n;
+    // fixed 7-point pattern, sorted columns
+    A->h_rowptr.resize(n + 1);
+    A->h_col.reserve((size_t)7 * n);
+    A->h_rowptr[0] = 0;
+    static const int ox[7] = {-1, 0, -1, 0, 1, 0, 1}, oy[7] = {-1, -1, 0, 0, 0, 1, 1};
+    for (int i = 0; i < n; ++i) {
+      int x = i % N, y = i / N;
+      for (int t = 0; t < 7; ++t) {
+        int u = x + ox[t], v = y + oy[t];
+        if (u >= 0 && v >= 0 && u < N && v < N) A->h_col.push_back(v * N + u);
+      }
+      A->h_rowptr[i + 1] = (int)A->h_col.size();
+    }
+    A->nnz = (long)A->h_col.size();
+    upload(A->rowptr, A->h_rowptr);
+    upload(A->col, A->h_col);
+    A->val.alloc(A->nnz * sizeof(c128));
+    A->mval.alloc(A->nnz * sizeof(double));
+    A->s.alloc((size_t)n * sizeof(double));
+    HSSX_HIP(hipMemcpyAsync(A->s.p, s_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
+    launch_assemble(N, desc->omega, A->s.as<double>(), A->rowptr.as<int>(), A->col.as<int>(),
+                    A->val.as<c128>(), A->mval.as<double>(), S(stream));
+    HSSX_HIP(hipStreamSynchronize(S(stream)));
+    *A_out = A.release();
+  });
+}
+
+hssx_status hssx_load(hssx_op A, int nrhs, const double *f_dev, long ldf, void *b_dev, long ldb,
+                      void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(A && f_dev && b_dev && nrhs >= 1 && ldf >= A->n && ldb >= A->n, HSSX_EINVAL,
+               "invalid argument");
+    DeviceScope ds(A->device);
+    launch_load(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->mval.as<double>(), f_dev, ldf,
+                (c128 *)b_dev, ldb, S(stream));
+  });
+}
+
+hssx_status hssx_matvec(hssx_op A, int trans, int nrhs, const void *x_dev, long ldx, void *y_dev,
+                        long ldy, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(A && x_dev && y_dev && nrhs >= 1 && ldx >= A->n && ldy >= A->n, HSSX_EINVAL,
+               "invalid argument");
+    HSSX_CHECK(x_dev != y_dev, HSSX_EINVAL, "matvec output may not alias its input");
+    (void)trans;   // A^T = A
+    DeviceScope ds(A->device);
+    launch_spmv(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->val.as<c128>(),
+                (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, S(stream));
+  });
+}
+
+hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col, double *val, long *nnz_out,
+                         void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(A, HSSX_EINVAL, "null operator");
+    DeviceScope ds(A->device);
+    HSSX_HIP(hipStreamSynchronize(S(stream)));
+    if (nnz_out) *nnz_out = A->nnz;
+    if (rowptr) std::memcpy(rowptr, A->h_rowptr.data(), (A->n + 1) * sizeof(int));
+    if (col) std::memcpy(col, A->h_col.data(), A->nnz * sizeof(int));
+    if (val) HSSX_HIP(hipMemcpy(val, A->val.p, A->nnz * sizeof(c128), hipMemcpyDeviceToHost));
+  });
+}
+
+hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_opts *opts,
+                        void *stream, hssx_fact *P_out) {
+  return guarded([&] {
+    HSSX_CHECK(A && P_out, HSSX_EINVAL, "null argument");
+    HSSX_CHECK(tol > 0 && tol < 1, HSSX_EINVAL, "tol must lie in (0, 1)");
+    HSSX_CHECK(leaf_size >= 1, HSSX_EINVAL, "leaf_size must be >= 1");
+    *P_out = nullptr;
+    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0};
+    if (opts) o = *opts;
+    HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
+               HSSX_EINVAL, "invalid factor options");
+    HSSX_CHECK(o.dtype == HSSX_C128 || o.dtype == HSSX_C64, HSSX_EINVAL, "dtype");
+    DeviceScope ds(A->device);
+    hipStream_t st = S(stream);
+    auto P = std::make_unique<hssx_fact_>();
+    P->A = A;
+    P->dtype = o.dtype;
+    P->tol = tol;
+    P->leaf = leaf_size;
+    P->opts = o;
+    auto t0 = std::chrono::steady_clock::now();
+    P->sym = build_symbolic(A->N, leaf_size, o.beta);
+    const Symbolic &sym = P->sym;
+    const int nn = (int)sym.nodes.size();
+    P->arith.assign(nn, 0);
+    P->comp.assign(nn, 0);
+    for (int k = 0; k < nn; ++k) P->arith[k] = o.h_sw >= 0 && sym.nodes[k].height > o.h_sw;
+    for (int k = 0; k < nn; ++k) P->comp[k] = sym.nodes[k].parent >= 0 && P->arith[sym.nodes[k].parent];
+    P->node_rank.assign(nn, 0);
+
+    // descriptors and front-entry sources
+    std::vector<FrontDesc> dsc(nn);
+    std::vector<int> bpos, sg, sc, sp;
+    std::vector<int> owner(A->n, -1), opos(A->n, -1);
+    long foff = 0;
+    double fbytes = 0, flops = 0;
+    const size_t esz = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
+    for (int k = 0; k < nn; ++k) {
+      const NDNode &nd = sym.nodes[k];
+      FrontDesc &d = dsc[k];
+      d.ni = (int)nd.I.size();
+      d.nb = (int)nd.B.size();
+      d.f = d.ni + d.nb;
+      d.foff = foff;
+      foff += (long)d.f * (d.f + d.ni);
+      d.ioff = nd.offset;
+      d.bpos_off = (int)bpos.size();
+      for (int v : nd.B) bpos.push_back(sym.iperm[v]);
+      d.src_off = (int)sg.size();
+      d.lo = nd.lo;
+      d.hi = nd.hi;
+      if (!nd.leafnode()) {
+        const NDNode &lo = sym.nodes[nd.lo], &hi = sym.nodes[nd.hi];
+        for (size_t b = 0; b < lo.B.size(); ++b) { owner[lo.B[b]] = 0; opos[lo.B[b]] = (int)b; }
+        for (size_t b = 0; b < hi.B.size(); ++b) { owner[hi.B[b]] = 1; opos[hi.B[b]] = (int)b; }
+      }
+      auto push = [&](int v) {
+        sg.push_back(v);
+        if (nd.leafnode()) { sc.push_back(-1); sp.push_back(0); }
+        else {
+          HSSX_CHECK(owner[v] >= 0, HSSX_EINVAL, "front entry outside the children's boundaries");
+          sc.push_back(owner[v]);
+          sp.push_back(opos[v]);
+        }
+      };
+      for (int v : nd.I) push(v);
+      for (int v : nd.B) push(v);
+      if (!nd.leafnode()) {
+        for (int v : sym.nodes[nd.lo].B) owner[v] = -1;
+        for (int v : sym.nodes[nd.hi].B) owner[v] = -1;
+      }
+      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * esz;
+      // Gauss-Jordan on f rows x (f + ni) columns, complex multiply-add = 8 flops
+      for (int p = 0; p < d.ni; ++p) flops += 8.0 * (d.f - 1) * (d.f + d.ni - p - 1);
+    }
+    P->h_desc = dsc;
+    upload(P->desc, dsc);
+    upload(P->bpos, bpos);
+    upload(P->src_gid, sg);
+    upload(P->src_child, sc);
+    upload(P->src_pos, sp);
+    upload(P->perm, sym.perm);
+    P->depth_nodes.assign(sym.max_depth + 1, {});
+    for (int k = 0; k < nn; ++k) P->depth_nodes[sym.nodes[k].depth].push_back(k);
+    P->depth_dev.resize(sym.max_depth + 1);
+    P->depth_max_ni.assign(sym.max_depth + 1, 0);
+    P->depth_max_nb.assign(sym.max_depth + 1, 0);
+    P->depth_max_f.assign(sym.max_depth + 1, 0);
+    for (int d = 0; d <= sym.max_depth; ++d) {
+      upload(P->depth_dev[d], P->depth_nodes[d]);
+      for (int k : P->depth_nodes[d]) {
+        P->depth_max_ni[d] = std::max(P->depth_max_ni[d], dsc[k].ni);
+        P->depth_max_nb[d] = std::max(P->depth_max_nb[d], dsc[k].nb);
+        P->depth_max_f[d] = std::max(P->depth_max_f[d], dsc[k].f);
+      }
+    }
+    P->front.alloc(std::max(1L, foff) * esz);
+    auto t1 = std::chrono::steady_clock::now();
+    P->stats.ms_symbolic = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    P->stats.n = A->n;
+    P->stats.nodes = nn;
+    P->stats.depth = sym.max_depth;
+    int nh = 0;
+    for (int k = 0; k < nn; ++k) nh += P->arith[k];
+    P->stats.n_hss_nodes = nh;
+    P->stats.factor_bytes = fbytes;
+    P->stats.factor_flops = flops;
+    factor_numeric(*P, st);
+    *P_out = P.release();
+  });
+}
+
+hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev, long ldx, void *y_dev,
+                       long ldy, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(P && x_dev && y_dev && nrhs >= 1 && ldx >= P->A->n && ldy >= P->A->n, HSSX_EINVAL,
+               "invalid argument");
+    DeviceScope ds(P->A->device);
+    hssx::apply(*P, trans ? 1 : 0, nrhs, (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, S(stream));
+  });
+}
+
+hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const void *b_dev,
+                             long ldb, void *x_dev, long ldx, const hssx_gmres_opts *opts,
+                             hssx_gmres_stats *stats, void *stream) {
+  hssx_status st = guarded([&] {
+    HSSX_CHECK(A && b_dev && x_dev && nrhs >= 1 && ldb >= A->n && ldx >= A->n, HSSX_EINVAL,
+               "invalid argument");
+    HSSX_CHECK(!P || P->A == A, HSSX_EINVAL, "preconditioner built for another operator");
+    hssx_gmres_opts o{50, 1e-8, 1000, 0};
+    if (opts) o = *opts;
+    HSSX_CHECK(o.m >= 1 && o.m <= 500 && o.tol > 0 && o.maxit >= 1, HSSX_EINVAL, "gmres options");
+    DeviceScope ds(A->device);
+    gmres(*A, P, trans ? 1 : 0, nrhs, (const c128 *)b_dev, ldb, (c128 *)x_dev, ldx, o, stats,
+          S(stream));
+  });
+  if (st == HSSX_OK && stats) {
+    for (int r = 0; r < nrhs; ++r)
+      if (!stats[r].converged) { g_err = "GMRES did not reach the tolerance"; return HSSX_ENOCONV; }
+  }
+  return st;
+}
+
+hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, const void *x_dev,
+                               double *grad_dev, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
+    DeviceScope ds(A->device);
+    launch_dads(A->N, A->omega, A->s.as<double>(), nrhs, (const c128 *)lambda_dev,
+                (const c128 *)x_dev, grad_dev, S(stream));
+  });
+}
+
+hssx_status hssx_analyze(int N, int leaf_size, int beta, hssx_fact *P_out) {
+  return guarded([&] {
+    HSSX_CHECK(P_out && N >= 2 && N <= 46000 && leaf_size >= 1 && beta >= 1, HSSX_EINVAL,
+               "invalid argument");
+    *P_out = nullptr;
+    auto P = std::make_unique<hssx_fact_>();
+    P->leaf = leaf_size;
+    P->opts.beta = beta;
+    P->sym = build_symbolic(N, leaf_size, beta);
+    *P_out = P.release();
+  });
+}
+
+hssx_status hssx_get_perm(hssx_fact P, int32_t *perm_host, long n) {
+  return guarded([&] {
+    HSSX_CHECK(P && perm_host && n == (long)P->sym.perm.size(), HSSX_EINVAL, "invalid argument");
+    std::memcpy(perm_host, P->sym.perm.data(), n * sizeof(int));
+  });
+}
+
+hssx_status hssx_get_tree(hssx_fact P, int64_t *sizes, int32_t *node_info, int32_t *i_ids,
+                          int32_t *i_ptr, int32_t *b_ids, int32_t *b_ptr, int32_t *clusters,
+                          int32_t *c_ptr) {
+  return guarded([&] {
+    HSSX_CHECK(P && sizes, HSSX_EINVAL, "invalid argument");
+    const auto &nodes = P->sym.nodes;
+    long ti = 0, tb = 0, tc = 0;
+    for (const auto &nd : nodes) { ti += nd.I.size(); tb += nd.B.size(); tc += nd.ct.count(); }
+    sizes[0] = (int64_t)nodes.size();
+    sizes[1] = ti;
+    sizes[2] = tb;
+    sizes[3] = tc;
+    if (!node_info) return;
+    HSSX_CHECK(i_ids && i_ptr && b_ids && b_ptr && clusters && c_ptr, HSSX_EINVAL, "null array");
+    long pi = 0, pb = 0, pc = 0;
+    for (size_t k = 0; k < nodes.size(); ++k) {
+      const auto &nd = nodes[k];
+      int32_t *ni = node_info + 10 * k;
+      ni[0] = nd.x0; ni[1] = nd.x1; ni[2] = nd.y0; ni[3] = nd.y1; ni[4] = nd.lo; ni[5] = nd.hi;
+      ni[6] = nd.parent; ni[7] = nd.depth; ni[8] = nd.height; ni[9] = nd.p0;
+      i_ptr[k] = (int32_t)pi;
+      for (int v : nd.I) i_ids[pi++] = v;
+      b_ptr[k] = (int32_t)pb;
+      for (int v : nd.B) b_ids[pb++] = v;
+      c_ptr[k] = (int32_t)pc;
+      for (int c = 0; c < nd.ct.count(); ++c, ++pc) {
+        int32_t *cc = clusters + 5 * pc;
+        cc[0] = nd.ct.start[c]; cc[1] = nd.ct.size[c]; cc[2] = nd.ct.left[c];
+        cc[3] = nd.ct.right[c]; cc[4] = nd.ct.level[c];
+      }
+    }
+    i_ptr[nodes.size()] = (int32_t)pi;
+    b_ptr[nodes.size()] = (int32_t)pb;
+    c_ptr[nodes.size()] = (int32_t)pc;
+  });
+}
+
+hssx_status hssx_get_factor_stats(hssx_fact P, hssx_factor_stats *s) {
+  return guarded([&] {
+    HSSX_CHECK(P && s, HSSX_EINVAL, "invalid argument");
+    *s = P->stats;
+  });
+}
+
+hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
+  return guarded([&] {
+    HSSX_CHECK(P && S_host && node >= 0 && node < (int)P->h_desc.size(), HSSX_EINVAL,
+               "invalid argument");
+    const FrontDesc &d = P->h_desc[node];
+    HSSX_CHECK(ld >= d.nb, HSSX_EINVAL, "ld < |B|");
+    DeviceScope ds(P->A->device);
+    HSSX_HIP(hipDeviceSynchronize());
+    const size_t esz = P->dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
+    std::vector<char> buf((size_t)d.f * (d.f + d.ni) * esz);
+    HSSX_HIP(hipMemcpy(buf.data(), (char *)P->front.p + d.foff * esz, buf.size(),
+                       hipMemcpyDeviceToHost));
+    for (int j = 0; j < d.nb; ++j)
+      for (int i = 0; i < d.nb; ++i) {
+        long e = (d.ni + i) + (long)(d.ni + j) * d.f;
+        double re, im;
+        if (P->dtype == HSSX_C128) {
+          c128 v;
+          std::memcpy(&v, buf.data() + e * esz, esz);
+          re = v.re; im = v.im;
+        } else {
+          c64 v;
+          std::memcpy(&v, buf.data() + e * esz, esz);
+          re = v.re; im = v.im;
+        }
+        S_host[2 * (i + (long)j * ld)] = re;
+        S_host[2 * (i + (long)j * ld) + 1] = im;
+      }
+  });
+}
+
+void hssx_fact_destroy(hssx_fact P) { delete P; }
+void hssx_op_destroy(hssx_op A) { delete A; }
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Internal shared definitions of the hssx library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hssx.h"
+
+namespace hssx {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  hssx_status code;
+  Error(hssx_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HSSX_HIP(expr)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::hssx::Error(HSSX_EHIP, std::string(#expr) + ": " +              \
+                                         hipGetErrorString(e_));              \
+  } while (0)
+
+#define HSSX_CHECK(cond, code, msg)                                           \
+  do {                                                                        \
+    if (!(cond)) throw ::hssx::Error(code, msg);                              \
+  } while (0)
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cplx {
+  T re, im;
+};
+using c64 = cplx<float>;
+using c128 = cplx<double>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T r, T i) {
+  cplx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) {
+  return mk(a.re + b.re, a.im + b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) {
+  return mk(a.re - b.re, a.im - b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a) {
+  return mk(-a.re, -a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> b) {
+  return mk(s * b.re, s * b.im);
+}
+// a += b * c
+template <typename T>
+__host__ __device__ __forceinline__ void cfma(cplx<T> &a, cplx<T> b, cplx<T> c) {
+  a.re += b.re * c.re - b.im * c.im;
+  a.im += b.re * c.im + b.im * c.re;
+}
+// a -= b * c
+template <typename T>
+__host__ __device__ __forceinline__ void cfms(cplx<T> &a, cplx<T> b, cplx<T> c) {
+  a.re -= b.re * c.re - b.im * c.im;
+  a.im -= b.re * c.im + b.im * c.re;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> conj(cplx<T> a) {
+  return mk(a.re, -a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T abs2(cplx<T> a) {
+  return a.re * a.re + a.im * a.im;
+}
+// |re| + |im|: the pivot magnitude used by partial pivoting (LAPACK cabs1)
+template <typename T>
+__host__ __device__ __forceinline__ T cabs1(cplx<T> a) {
+  return fabs(a.re) + fabs(a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cinv(cplx<T> a) {
+  // Smith-free scaled reciprocal: 1/(a) = conj(a)/|a|^2 with scaling by the
+  // larger component to avoid overflow/underflow.
+  T s = fmax(fabs(a.re), fabs(a.im));
+  T ar = a.re / s, ai = a.im / s;
+  T d = s * (ar * ar + ai * ai);
+  return mk(ar / d, -ai / d);
+}
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) {
+  return mk((To)a.re, (To)a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> czero() {
+  return mk((T)0, (T)0);
+}
+
+// ---------------------------------------------------------------- memory
+// Device buffer owned by the library (RAII, not copyable).
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(HSSX_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// Blocking upload of set-up data (symbolic schedules); never in a timed loop.
+template <typename T>
+inline void upload(DevBuf &d, const std::vector<T> &h) {
+  d.alloc(h.size() * sizeof(T));
+  if (!h.empty())
+    HSSX_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace hssx

@@ -1,0 +1,496 @@
+// Numeric factorization P = LDR (Algorithm 3.4) and its application
+// (Algorithm 3.1).
+//
+// Nodes are processed one tree depth at a time, deepest first; all nodes of
+// a depth are independent (their boxes are disjoint).  Per depth:
+//   1. assemble the augmented fronts (eq. 3.2 at leaves, eq. 3.4 above);
+//   2. nodes with HSS arithmetic (height > h_sw): form the inner Schur
+//      complement S~ = S_ii^nu - A~^(nu,mu) (S_ii^mu)^-1 A~^(mu,nu) of the
+//      interior block, compress it with Algorithm A.1 on nu's interior
+//      cluster tree, and replace S~ by its HSS approximation inside A_ii:
+//      the factor then applies exactly the 2x2 block inverse of
+//      Algorithm 3.2 whose Schur block is the HSS matrix (Algorithm 3.3);
+//   3. Gauss-Jordan elimination of every front (A_ii^-1, R, L, S);
+//   4. nodes whose parent uses HSS arithmetic compress S with Algorithm A.1
+//      (dense S below the switch, "form S directly in HSS form" above it)
+//      and pass the HSS approximation on to the parent's front.
+// The compressions of a depth are batched: all instances sample, compress
+// level by level, and estimate together; only those whose estimate
+// (eq. 2.7) misses the tolerance grow k <- k + r and go round again.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "engine.h"
+
+namespace hssx {
+
+namespace {
+
+template <typename T> struct CompressTask {
+  int node = 0, kind = 0;
+  int m = 0;
+  ClusterTree ct;
+  cplx<T> *S = nullptr;
+  int ldS = 0;
+  cplx<T> *target = nullptr;
+  int ldT = 0;
+  // state / results
+  int k = 0, s = 0, rounds = 0, cap = 0;
+  double est = 0;
+  int maxrank = 0;
+  bool done = false;
+  long ooff = 0, yoff = 0;
+};
+
+struct Layout {
+  std::vector<HssCluster> cl;
+  long pool = 0, ipool = 0, scratch = 0, xh = 0;
+};
+
+// cluster capacities and pool offsets of one instance for rank cap k and s columns
+Layout layout_instance(const ClusterTree &ct, int k, int s) {
+  Layout L;
+  int nc = ct.count();
+  L.cl.resize(nc);
+  std::vector<int> kcap(nc, 0), rcap(nc, 0);
+  for (int c = nc - 1; c >= 0; --c) {
+    if (ct.leaf(c)) rcap[c] = ct.size[c];
+    else rcap[c] = kcap[ct.left[c]] + kcap[ct.right[c]];
+    int kc = std::min(k, std::min(rcap[c], s));
+    kcap[c] = c == 0 ? 0 : kc;
+  }
+  for (int c = 0; c < nc; ++c) {
+    HssCluster &h = L.cl[c];
+    h.start = ct.start[c];
+    h.size = ct.size[c];
+    h.left = ct.left[c];
+    h.right = ct.right[c];
+    h.level = ct.level[c];
+    h.rows_cap = rcap[c];
+    h.k_cap = kcap[c];
+    long r = rcap[c], kk = kcap[c];
+    h.U = L.pool; L.pool += std::max(1L, r * kk);
+    h.Om = L.pool; L.pool += std::max(1L, kk * s);
+    h.Sr = L.pool; L.pool += std::max(1L, kk * s);
+    if (ct.leaf(c)) { h.D = L.pool; L.pool += (long)h.size * h.size; } else h.D = 0;
+    if (!ct.leaf(c)) {
+      long kl = kcap[ct.left[c]], kr = kcap[ct.right[c]];
+      h.B12 = L.pool; L.pool += std::max(1L, kl * kr);
+      h.B21 = L.pool; L.pool += std::max(1L, kl * kr);
+    } else {
+      h.B12 = h.B21 = 0;
+    }
+    h.sk = (int)L.ipool; L.ipool += std::max(1L, kk);
+    h.W = L.scratch; L.scratch += 3 * r * s + std::max(1L, kk) * std::max(1L, r);
+    h.XH = L.xh; L.xh += 2 * std::max(1L, kk) * 64;
+  }
+  return L;
+}
+
+template <typename T>
+void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts &o, double tol,
+                    double id_tol, hipStream_t st) {
+  if (tasks.empty()) return;
+  const int k0 = o.k0, r = o.r;
+  long osz = 0, ysz = 0;
+  for (auto &t : tasks) {
+    t.k = std::max(1, std::min(k0, t.m));
+    t.s = t.k + r;
+    t.cap = std::min(k0 + r * (o.max_rounds + 1), t.m + 2 * r);
+    t.cap = std::max(t.cap, t.s + r);
+    t.ooff = osz;
+    t.yoff = ysz;
+    osz += (long)t.m * t.cap;
+    ysz += (long)t.m * t.cap;
+    t.rounds = 0;
+    t.done = false;
+    HSSX_CHECK(t.cap <= 1024, HSSX_EINVAL, "sample block wider than the compression kernel holds");
+    HSSX_CHECK(t.m <= 1 << 24, HSSX_EINVAL, "compression size");
+  }
+  DevBuf Om, Y, errs;
+  Om.alloc(osz * sizeof(double));
+  Y.alloc(ysz * sizeof(cplx<T>));
+  errs.alloc(2 * tasks.size() * sizeof(double));
+  double *d_err = errs.as<double>();
+
+  auto gen_and_sample = [&](const std::vector<int> &ids, bool probe) {
+    std::vector<GaussJob> gj;
+    std::vector<SampleJob<T>> sj;
+    int mm = 0, mc = 0;
+    for (int i : ids) {
+      auto &t = tasks[i];
+      int c0 = probe ? t.s : 0, nc = probe ? r : t.s;
+      GaussJob g{Om.as<double>() + t.ooff, t.m, t.m, c0, nc, 0, (uint32_t)(4 * t.node + t.kind)};
+      gj.push_back(g);
+      SampleJob<T> s{t.S, Om.as<double>() + t.ooff + (long)c0 * t.m, Y.as<cplx<T>>() + t.yoff + (long)c0 * t.m,
+                     t.ldS, t.m, t.m, t.m, nc};
+      sj.push_back(s);
+      mm = std::max(mm, t.m);
+      mc = std::max(mc, nc);
+    }
+    DevBuf dg, ds;
+    upload(dg, gj);
+    upload(ds, sj);
+    launch_gaussian((int)gj.size(), dg.as<GaussJob>(), o.seed, mm, mc, st);
+    launch_sample<T>((int)sj.size(), ds.as<SampleJob<T>>(), mm, mc, st);
+    HSSX_HIP(hipStreamSynchronize(st));
+  };
+
+  std::vector<int> all(tasks.size());
+  for (size_t i = 0; i < tasks.size(); ++i) all[i] = (int)i;
+  gen_and_sample(all, false);
+
+  std::vector<int> active = all;
+  while (!active.empty()) {
+    // ---- layout of the active instances
+    std::vector<HssInstance> inst;
+    std::vector<HssCluster> cls;
+    std::vector<Layout> lay;
+    long pool = 0, ipool = 0, scratch = 0, xh_per_job_max = 0;
+    int maxlev = 0;
+    for (int i : active) {
+      auto &t = tasks[i];
+      Layout L = layout_instance(t.ct, t.k, t.s);
+      for (const auto &c : L.cl)
+        HSSX_CHECK(c.rows_cap <= 1024, HSSX_EINVAL,
+                   "local sample block taller than the compression kernel holds");
+      HssInstance h{};
+      h.m = t.m;
+      h.ncl = t.ct.count();
+      h.cl_off = (int)cls.size();
+      h.s = t.s;
+      h.k = t.k;
+      h.pool = pool;
+      h.ipool = ipool;
+      h.soff = 0;
+      h.ldS = t.ldS;
+      h.yoff = t.yoff;
+      h.ooff = t.ooff;
+      h.ldY = t.m;
+      h.woff = scratch;
+      pool += L.pool;
+      ipool += L.ipool;
+      scratch += L.scratch;
+      xh_per_job_max = std::max(xh_per_job_max, L.xh);
+      cls.insert(cls.end(), L.cl.begin(), L.cl.end());
+      inst.push_back(h);
+      maxlev = std::max(maxlev, t.ct.depth());
+      lay.push_back(std::move(L));
+    }
+    // each instance's operator S lives in device memory of its own; the
+    // kernel adds soff to a common base, so pass base = nullptr-offset form
+    // through per-instance soff relative to the first task's S.
+    const cplx<T> *base = tasks[active[0]].S;
+    for (size_t a = 0; a < active.size(); ++a) inst[a].soff = tasks[active[a]].S - base;
+
+    DevBuf d_inst, d_cls, d_pool, d_ipool, d_rank, d_scr;
+    upload(d_inst, inst);
+    upload(d_cls, cls);
+    d_pool.alloc(std::max(1L, pool) * sizeof(cplx<T>));
+    d_ipool.alloc(std::max(1L, ipool) * sizeof(int));
+    d_rank.alloc(std::max<size_t>(1, cls.size()) * sizeof(int));
+    d_scr.alloc(std::max(1L, scratch) * sizeof(cplx<T>));
+    HSSX_HIP(hipMemsetAsync(d_rank.p, 0, cls.size() * sizeof(int), st));
+
+    // ---- bottom-up compression, one launch per cluster-tree level
+    for (int lev = maxlev; lev >= 0; --lev) {
+      std::vector<HssItem> items;
+      for (size_t a = 0; a < active.size(); ++a) {
+        const auto &ct = tasks[active[a]].ct;
+        for (int c = 0; c < ct.count(); ++c)
+          if (ct.level[c] == lev) items.push_back(HssItem{(int)a, c});
+      }
+      if (items.empty()) continue;
+      DevBuf d_items;
+      upload(d_items, items);
+      launch_compress_level<T>((int)items.size(), d_items.as<HssItem>(), d_inst.as<HssInstance>(),
+                               d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_ipool.as<int>(),
+                               d_rank.as<int>(), base, Y.as<cplx<T>>(), Om.as<double>(),
+                               d_scr.as<cplx<T>>(), id_tol, st);
+      HSSX_HIP(hipStreamSynchronize(st));
+    }
+
+    // ---- error estimate with r fresh probes (eq. 2.7)
+    gen_and_sample(active, true);
+    std::vector<MatvecJob<T>> mj;
+    for (size_t a = 0; a < active.size(); ++a) {
+      auto &t = tasks[active[a]];
+      MatvecJob<T> j{};
+      j.inst = (int)a;
+      j.X = Om.as<double>() + t.ooff + (long)t.s * t.m;
+      j.ldX = t.m;
+      j.nc = r;
+      j.c0 = 0;
+      j.out = nullptr;
+      j.ldO = 0;
+      j.Yref = Y.as<cplx<T>>() + t.yoff + (long)t.s * t.m;
+      j.ldR = t.m;
+      j.err2 = d_err + 2 * active[a];
+      j.ref2 = d_err + 2 * active[a] + 1;
+      j.woff = (long)a * xh_per_job_max;
+      mj.push_back(j);
+    }
+    DevBuf d_mj, d_xh;
+    upload(d_mj, mj);
+    d_xh.alloc(std::max(1L, (long)mj.size() * xh_per_job_max) * sizeof(cplx<T>));
+    HSSX_CHECK(r <= 64, HSSX_EINVAL, "probe block wider than 64 columns");
+    launch_hss_matvec<T>((int)mj.size(), d_mj.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
+                         d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
+                         d_xh.as<cplx<T>>(), st);
+    std::vector<double> h_err(2 * tasks.size());
+    std::vector<int> h_rank(cls.size());
+    HSSX_HIP(hipMemcpyAsync(h_err.data(), d_err, h_err.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+    HSSX_HIP(hipMemcpyAsync(h_rank.data(), d_rank.p, h_rank.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, st));
+    HSSX_HIP(hipStreamSynchronize(st));
+
+    // ---- decisions; expand the accepted instances into their targets
+    std::vector<int> next;
+    std::vector<MatvecJob<T>> ej;
+    for (size_t a = 0; a < active.size(); ++a) {
+      auto &t = tasks[active[a]];
+      t.rounds += 1;
+      double e2 = h_err[2 * active[a]], r2 = h_err[2 * active[a] + 1];
+      t.est = r2 > 0 ? std::sqrt(e2 / r2) : 0.0;
+      int mr = 0;
+      for (int c = 0; c < t.ct.count(); ++c) mr = std::max(mr, h_rank[inst[a].cl_off + c]);
+      t.maxrank = mr;
+      // growing needs room for the next round's probes: columns [s + r, s + 2r)
+      bool accept = t.est <= tol || t.k >= t.m || t.rounds >= o.max_rounds ||
+                    t.s + 2 * r > t.cap;
+      if (!accept) {
+        t.k += r;
+        t.s += r;
+        next.push_back(active[a]);
+        continue;
+      }
+      t.done = true;
+      for (int c0 = 0; c0 < t.m; c0 += 64) {
+        MatvecJob<T> j{};
+        j.inst = (int)a;
+        j.X = nullptr;
+        j.c0 = c0;
+        j.nc = std::min(64, t.m - c0);
+        j.out = t.target + (long)c0 * t.ldT;
+        j.ldO = t.ldT;
+        j.Yref = nullptr;
+        j.woff = (long)ej.size() * xh_per_job_max;
+        ej.push_back(j);
+      }
+    }
+    if (!ej.empty()) {
+      DevBuf d_ej, d_xh2;
+      upload(d_ej, ej);
+      d_xh2.alloc(std::max(1L, (long)ej.size() * xh_per_job_max) * sizeof(cplx<T>));
+      launch_hss_matvec<T>((int)ej.size(), d_ej.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
+                           d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
+                           d_xh2.as<cplx<T>>(), st);
+      HSSX_HIP(hipStreamSynchronize(st));
+    }
+    active.swap(next);
+  }
+}
+
+template <typename T>
+void factor_impl(hssx_fact_ &P, hipStream_t st) {
+  hssx_op_ &A = *P.A;
+  const Symbolic &sym = P.sym;
+  const int root = sym.root();
+  cplx<T> *F = P.front.as<cplx<T>>();
+  const FrontDesc *desc = P.desc.as<FrontDesc>();
+  const double id_tol = P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : 1e-2 * P.tol;
+  DevBuf err;
+  err.alloc(sizeof(int));
+  int minus1 = -1;
+  HSSX_HIP(hipMemcpy(err.p, &minus1, sizeof(int), hipMemcpyHostToDevice));
+  int kmax = 0, rounds_max = 0, ncomp = 0;
+  double est_max = 0;
+
+  for (int d = sym.max_depth; d >= 0; --d) {
+    const auto &nodes = P.depth_nodes[d];
+    if (nodes.empty()) continue;
+    const int cnt = (int)nodes.size();
+    launch_front_assemble<T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
+                             P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
+                             A.col.as<int>(), A.val.as<c128>(), F, st, P.depth_max_f[d]);
+
+    // ---- HSS-arithmetic interiors: compress S~ and substitute it (Alg. 3.3)
+    std::vector<int> hn;
+    for (int k : nodes)
+      if (P.arith[k] && k != root && P.h_desc[k].ni > 0) hn.push_back(k);
+    if (!hn.empty()) {
+      long gsz = 0, hsz = 0;
+      std::vector<long> goff, hoff;
+      for (int k : hn) {
+        int ni = P.h_desc[k].ni, p = sym.nodes[sym.nodes[k].lo].p0;
+        goff.push_back(gsz);
+        hoff.push_back(hsz);
+        gsz += (long)ni * ni;
+        hsz += (long)(ni - p) * (ni - p);
+      }
+      DevBuf G, H;
+      G.alloc(std::max(1L, gsz) * sizeof(cplx<T>));
+      H.alloc(std::max(1L, hsz) * sizeof(cplx<T>));
+      std::vector<AxpbyJob<T>> cp;
+      std::vector<ElimJob<T>> ej;
+      std::vector<CompressTask<T>> tasks;
+      int mm = 0;
+      for (size_t a = 0; a < hn.size(); ++a) {
+        int k = hn[a];
+        const FrontDesc &fd = P.h_desc[k];
+        int ni = fd.ni, p = sym.nodes[sym.nodes[k].lo].p0;
+        cplx<T> *g = G.as<cplx<T>>() + goff[a];
+        cp.push_back(AxpbyJob<T>{g, F + fd.foff, nullptr, ni, fd.f, 0, ni, ni, (T)1, (T)0});
+        mm = std::max(mm, ni);
+        ej.push_back(ElimJob<T>{g, ni, ni, ni, p, 0, k});
+        if (ni - p > 0) {
+          CompressTask<T> t;
+          t.node = k;
+          t.kind = 1;
+          t.m = ni - p;
+          t.ct = interior_subtree(sym.nodes[sym.nodes[k].hi]);
+          t.S = g + p + (long)p * ni;
+          t.ldS = ni;
+          t.target = H.as<cplx<T>>() + hoff[a];
+          t.ldT = ni - p;
+          tasks.push_back(std::move(t));
+        }
+      }
+      // G := 0 then G += A_ii
+      HSSX_HIP(hipMemsetAsync(G.p, 0, G.bytes, st));
+      DevBuf dcp, dej;
+      upload(dcp, cp);
+      upload(dej, ej);
+      launch_axpby<T>((int)cp.size(), dcp.as<AxpbyJob<T>>(), mm, mm, st);
+      launch_eliminate<T>((int)ej.size(), dej.as<ElimJob<T>>(), err.as<int>(), st);
+      HSSX_HIP(hipStreamSynchronize(st));
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
+      std::vector<AxpbyJob<T>> fix;
+      int fm = 0;
+      size_t ti = 0;
+      for (size_t a = 0; a < hn.size(); ++a) {
+        int k = hn[a];
+        const FrontDesc &fd = P.h_desc[k];
+        int ni = fd.ni, p = sym.nodes[sym.nodes[k].lo].p0;
+        if (ni - p <= 0) continue;
+        auto &t = tasks[ti++];
+        kmax = std::max(kmax, t.maxrank);
+        rounds_max = std::max(rounds_max, t.rounds);
+        est_max = std::max(est_max, t.est);
+        P.node_rank[k] = std::max(P.node_rank[k], t.maxrank);
+        // F(p:ni, p:ni) += S~_HSS - S~
+        fix.push_back(AxpbyJob<T>{F + fd.foff + p + (long)p * fd.f, t.target,
+                                  G.as<cplx<T>>() + goff[a] + p + (long)p * ni, fd.f, ni - p,
+                                  ni, ni - p, ni - p, (T)1, (T)-1});
+        fm = std::max(fm, ni - p);
+      }
+      DevBuf dfix;
+      upload(dfix, fix);
+      launch_axpby<T>((int)fix.size(), dfix.as<AxpbyJob<T>>(), fm, fm, st);
+      HSSX_HIP(hipStreamSynchronize(st));
+    }
+
+    // ---- eliminate all fronts of this depth
+    std::vector<ElimJob<T>> jobs;
+    for (int k : nodes) {
+      const FrontDesc &fd = P.h_desc[k];
+      jobs.push_back(ElimJob<T>{F + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
+    }
+    DevBuf dj;
+    upload(dj, jobs);
+    launch_eliminate<T>((int)jobs.size(), dj.as<ElimJob<T>>(), err.as<int>(), st);
+
+    // ---- compress the Schur complements the parents will use in HSS form
+    std::vector<CompressTask<T>> tasks;
+    for (int k : nodes) {
+      const FrontDesc &fd = P.h_desc[k];
+      if (!P.comp[k] || fd.nb == 0) continue;
+      CompressTask<T> t;
+      t.node = k;
+      t.kind = 0;
+      t.m = fd.nb;
+      t.ct = sym.nodes[k].ct;
+      t.S = F + fd.foff + fd.ni + (long)fd.ni * fd.f;
+      t.ldS = fd.f;
+      t.target = t.S;
+      t.ldT = fd.f;
+      tasks.push_back(std::move(t));
+    }
+    HSSX_HIP(hipStreamSynchronize(st));
+    if (!tasks.empty()) {
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
+      for (auto &t : tasks) {
+        kmax = std::max(kmax, t.maxrank);
+        rounds_max = std::max(rounds_max, t.rounds);
+        est_max = std::max(est_max, t.est);
+        P.node_rank[t.node] = std::max(P.node_rank[t.node], t.maxrank);
+        ++ncomp;
+      }
+    }
+  }
+  int bad = -1;
+  HSSX_HIP(hipStreamSynchronize(st));
+  HSSX_HIP(hipMemcpy(&bad, err.p, sizeof(int), hipMemcpyDeviceToHost));
+  HSSX_CHECK(bad < 0, HSSX_ESINGULAR, "zero pivot in the dense block of tree node " + std::to_string(bad));
+  P.stats.k_max = kmax;
+  P.stats.max_rounds_used = rounds_max;
+  P.stats.max_estimate = est_max;
+  P.stats.n_compressed = ncomp;
+}
+
+}  // namespace
+
+void factor_numeric(hssx_fact_ &P, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HSSX_HIP(hipEventCreate(&e0));
+  HSSX_HIP(hipEventCreate(&e1));
+  HSSX_HIP(hipEventRecord(e0, st));
+  if (P.dtype == HSSX_C128) factor_impl<double>(P, st);
+  else factor_impl<float>(P, st);
+  HSSX_HIP(hipEventRecord(e1, st));
+  HSSX_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  HSSX_HIP(hipEventElapsedTime(&ms, e0, e1));
+  P.stats.ms_numeric = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
+           hipStream_t st) {
+  const int n = P.A->n;
+  if (P.work_cols < (size_t)nrhs) {
+    HSSX_HIP(hipStreamSynchronize(st));
+    P.work.alloc((size_t)n * nrhs * sizeof(c128));
+    P.work_cols = nrhs;
+  }
+  c128 *w = P.work.as<c128>();
+  launch_permute(n, nrhs, P.perm.as<int>(), x, ldx, w, n, 0, st);
+  const FrontDesc *desc = P.desc.as<FrontDesc>();
+  const int D = P.sym.max_depth;
+  for (int d = D; d >= 0; --d) {
+    int cnt = (int)P.depth_nodes[d].size();
+    if (!cnt) continue;
+    if (P.dtype == HSSX_C128)
+      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
+                              P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
+    else
+      launch_apply_up<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
+                             P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
+  }
+  for (int d = 0; d <= D; ++d) {
+    int cnt = (int)P.depth_nodes[d].size();
+    if (!cnt) continue;
+    if (P.dtype == HSSX_C128)
+      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
+                                P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
+    else
+      launch_apply_down<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
+                               P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
+  }
+  launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);
+}
+
+}  // namespace hssx

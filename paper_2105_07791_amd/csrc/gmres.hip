@@ -1,0 +1,187 @@
+// Restarted GMRES for A x = b with the approximate factorization as
+// preconditioner (eq. 1.2; Sec. 4: restarted GMRES stopped on the relative
+// residual).  All right-hand sides advance together, each with its own
+// Krylov basis; converged ones are frozen (their step count stops).
+//
+// Left preconditioning (paper): Arnoldi on P^-1 A, stop when
+// ||P^-1 (b - A x)|| / ||P^-1 b|| <= target; then the true residual
+// ||b - A x|| / ||b|| is checked and, while it is above tol, up to three
+// more cycles run with the target scaled by the observed ratio.
+// Flexible right preconditioning: z_j = P^-1 v_j, Arnoldi on A z_j, and the
+// GMRES residual is the true residual.
+// Orthogonalisation: classical Gram-Schmidt applied twice (CGS2).
+#include <algorithm>
+#include <cmath>
+
+#include "engine.h"
+
+namespace hssx {
+
+void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb, c128 *x,
+           long ldx, const hssx_gmres_opts &o, hssx_gmres_stats *stats, hipStream_t st) {
+  const int n = A.n, m = o.m;
+  const bool left = !o.flexible;
+  const long blk = (long)n * nrhs;
+  auto precond = [&](const c128 *in, c128 *out) {
+    if (P) apply(*P, trans, nrhs, in, n, out, n, st);
+    else HSSX_HIP(hipMemcpyAsync(out, in, blk * sizeof(c128), hipMemcpyDeviceToDevice, st));
+  };
+  auto matvec = [&](const c128 *in, c128 *out) {
+    launch_spmv(n, nrhs, A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), in, n, out, n, st);
+  };
+  DevBuf V, Z, w, t1, H, cs, sn, g, y, hcol, h2, hn, res, cnt, act, part, partd, nrm, xc, bc;
+  V.alloc((size_t)(m + 1) * blk * sizeof(c128));
+  if (!left) Z.alloc((size_t)m * blk * sizeof(c128));
+  w.alloc(blk * sizeof(c128));
+  t1.alloc(blk * sizeof(c128));
+  xc.alloc(blk * sizeof(c128));
+  bc.alloc(blk * sizeof(c128));
+  H.alloc((size_t)(m + 1) * m * nrhs * sizeof(c128));
+  cs.alloc((size_t)m * nrhs * sizeof(double));
+  sn.alloc((size_t)m * nrhs * sizeof(c128));
+  g.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
+  y.alloc((size_t)m * nrhs * sizeof(c128));
+  hcol.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
+  h2.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
+  hn.alloc(nrhs * sizeof(double));
+  res.alloc(nrhs * sizeof(double));
+  nrm.alloc(nrhs * sizeof(double));
+  cnt.alloc(nrhs * sizeof(int));
+  act.alloc(nrhs * sizeof(int));
+  const int nblk = std::max(1, std::min(64, ceil_div(n, 256 * 8)));
+  part.alloc((size_t)nblk * (m + 1) * nrhs * sizeof(c128));
+  partd.alloc((size_t)nblk * nrhs * sizeof(double));
+
+  // contiguous copies of b and x
+  HSSX_HIP(hipMemcpy2DAsync(bc.p, n * sizeof(c128), b, ldb * sizeof(c128), n * sizeof(c128), nrhs,
+                            hipMemcpyDeviceToDevice, st));
+  launch_fill(blk, czero<double>(), xc.as<c128>(), st);
+
+  auto norms_host = [&](const c128 *v, std::vector<double> &out) {
+    launch_norms(n, nrhs, v, nrm.as<double>(), partd.as<double>(), nblk, st);
+    out.resize(nrhs);
+    HSSX_HIP(hipMemcpyAsync(out.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HSSX_HIP(hipStreamSynchronize(st));
+  };
+
+  std::vector<double> bnorm, pbnorm;
+  norms_host(bc.as<c128>(), bnorm);
+  if (left) {
+    precond(bc.as<c128>(), t1.as<c128>());
+    norms_host(t1.as<c128>(), pbnorm);
+  } else {
+    pbnorm = bnorm;
+  }
+  std::vector<double> target(nrhs, o.tol), prec_rel(nrhs, 0.0), true_rel(nrhs, 0.0);
+  std::vector<int> extra(nrhs, 0), done(nrhs, 0), iters(nrhs, 0), conv(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r)
+    if (bnorm[r] == 0.0) { done[r] = 1; conv[r] = 1; }
+  int total = 0;
+  const long stride = blk;
+  c128 *Vp = V.as<c128>();
+  c128 *Zp = left ? nullptr : Z.as<c128>();
+
+  while (true) {
+    // residuals of the current iterate
+    matvec(xc.as<c128>(), t1.as<c128>());
+    launch_sub(n, nrhs, bc.as<c128>(), n, t1.as<c128>(), n, w.as<c128>(), n, st);
+    std::vector<double> tr, pr;
+    norms_host(w.as<c128>(), tr);
+    if (left) {
+      precond(w.as<c128>(), Vp);
+      norms_host(Vp, pr);
+    } else {
+      HSSX_HIP(hipMemcpyAsync(Vp, w.p, blk * sizeof(c128), hipMemcpyDeviceToDevice, st));
+      pr = tr;
+    }
+    std::vector<int> active(nrhs, 0);
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r]) continue;
+      true_rel[r] = tr[r] / bnorm[r];
+      prec_rel[r] = pr[r] / pbnorm[r];
+      if (prec_rel[r] <= target[r]) {
+        if (true_rel[r] <= o.tol || extra[r] >= 3) {
+          done[r] = 1;
+          conv[r] = true_rel[r] <= o.tol;
+          continue;
+        }
+        target[r] *= o.tol / true_rel[r];
+        ++extra[r];
+      }
+      if (iters[r] >= o.maxit) { done[r] = 1; continue; }
+      active[r] = 1;
+      any = true;
+    }
+    if (!any) break;
+    // v0 = r0 / beta (zero for inactive right-hand sides)
+    std::vector<double> beta(nrhs);
+    for (int r = 0; r < nrhs; ++r) beta[r] = active[r] ? pr[r] : 0.0;
+    HSSX_HIP(hipMemcpyAsync(hn.p, beta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_scale(n, nrhs, Vp, hn.as<double>(), Vp, st);
+    std::vector<c128> g0((size_t)(m + 1) * nrhs, czero<double>());
+    for (int r = 0; r < nrhs; ++r) g0[r] = mk(beta[r], 0.0);
+    HSSX_HIP(hipMemcpyAsync(g.p, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, st));
+    HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<int> count(nrhs, 0);
+    for (int j = 0; j < m; ++j) {
+      c128 *vj = Vp + j * stride;
+      if (left) {
+        matvec(vj, t1.as<c128>());
+        precond(t1.as<c128>(), w.as<c128>());
+      } else {
+        precond(vj, Zp + j * stride);
+        matvec(Zp + j * stride, w.as<c128>());
+      }
+      launch_mdot(n, nrhs, j + 1, Vp, stride, w.as<c128>(), hcol.as<c128>(), part.as<c128>(), nblk, st);
+      launch_mupdate(n, nrhs, j + 1, Vp, stride, hcol.as<c128>(), w.as<c128>(), st);
+      launch_mdot(n, nrhs, j + 1, Vp, stride, w.as<c128>(), h2.as<c128>(), part.as<c128>(), nblk, st);
+      launch_mupdate(n, nrhs, j + 1, Vp, stride, h2.as<c128>(), w.as<c128>(), st);
+      {
+        std::vector<AxpbyJob<double>> aj{AxpbyJob<double>{hcol.as<c128>(), h2.as<c128>(), nullptr,
+                                                          (j + 1) * nrhs, (j + 1) * nrhs, 0,
+                                                          (j + 1) * nrhs, 1, 1.0, 0.0}};
+        DevBuf da;
+        upload(da, aj);
+        launch_axpby<double>(1, da.as<AxpbyJob<double>>(), (j + 1) * nrhs, 1, st);
+        HSSX_HIP(hipStreamSynchronize(st));
+      }
+      launch_norms(n, nrhs, w.as<c128>(), hn.as<double>(), partd.as<double>(), nblk, st);
+      launch_scale(n, nrhs, w.as<c128>(), hn.as<double>(), Vp + (j + 1) * stride, st);
+      launch_givens(nrhs, j, m, H.as<c128>(), hcol.as<c128>(), hn.as<double>(), cs.as<double>(),
+                    sn.as<c128>(), g.as<c128>(), res.as<double>(), act.as<int>(), st);
+      std::vector<double> rs(nrhs);
+      HSSX_HIP(hipMemcpyAsync(rs.data(), res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      HSSX_HIP(hipStreamSynchronize(st));
+      ++total;
+      bool still = false;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!active[r]) continue;
+        ++iters[r];
+        count[r] = j + 1;
+        if (rs[r] / pbnorm[r] <= target[r] || iters[r] >= o.maxit) active[r] = 0;
+        else still = true;
+      }
+      HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      if (!still) break;
+    }
+    HSSX_HIP(hipMemcpyAsync(cnt.p, count.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_hsolve(nrhs, m, H.as<c128>(), g.as<c128>(), cnt.as<int>(), y.as<c128>(), st);
+    launch_xupdate(n, nrhs, cnt.as<int>(), m, left ? Vp : Zp, stride, y.as<c128>(), xc.as<c128>(), n,
+                   st);
+    HSSX_HIP(hipStreamSynchronize(st));
+  }
+  HSSX_HIP(hipMemcpy2DAsync(x, ldx * sizeof(c128), xc.p, n * sizeof(c128), n * sizeof(c128), nrhs,
+                            hipMemcpyDeviceToDevice, st));
+  HSSX_HIP(hipStreamSynchronize(st));
+  if (stats)
+    for (int r = 0; r < nrhs; ++r) {
+      stats[r].iters = iters[r];
+      stats[r].converged = conv[r];
+      stats[r].prec_res = prec_rel[r];
+      stats[r].true_res = true_rel[r];
+    }
+  (void)total;
+}
+
+}  // namespace hssx

@@ -1,0 +1,193 @@
+// Host-side launchers of the device kernels, and the descriptor structs the
+// batched kernels read.  Every launcher enqueues on the given stream and
+// checks the launch.
+#pragma once
+
+#include "common.h"
+
+namespace hssx {
+
+// ------------------------------------------------------------ FEM / SpMV
+void launch_assemble(int N, double omega, const double *s, const int *rowptr, const int *col,
+                     c128 *val, double *mval, hipStream_t st);
+void launch_load(int n, int nrhs, const int *rowptr, const int *col, const double *mval,
+                 const double *f, long ldf, c128 *b, long ldb, hipStream_t st);
+void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
+                 const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st);
+void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
+                 const c128 *x, double *grad, hipStream_t st);
+
+// ------------------------------------------------------------ dense fronts
+// One elimination-tree node's augmented dense front
+//   F = [[A_ii, A_ib, I], [A_bi, A_bb, 0]]      (f x (f + ni), f = ni + nb)
+// column-major with leading dimension f, and where its inputs live.  After
+// Gauss-Jordan elimination of the first ni columns it holds
+//   F(0:ni, ni:f)  = R = -A_ii^-1 A_ib       (eq. 3.3b, negated in place)
+//   F(0:ni, f:)    = A_ii^-1                  (block-diagonal factor D^-1)
+//   F(ni:f, ni:f)  = S = A_bb - A_bi A_ii^-1 A_ib   (eq. 3.5)
+//   F(ni:f, f:)    = L = -A_bi A_ii^-1        (eq. 3.3a)
+struct FrontDesc {
+  long foff;        // element offset of F in the front pool
+  int f, ni, nb;    // front size, |I|, |B|
+  int ioff;         // first position of I in the elimination order
+  int bpos_off;     // offset of the nb positions of B in the B-position pool
+  int src_off;      // offset of the f front-entry sources in the source pools
+  int lo, hi;       // children (-1 for leaves)
+};
+
+// Assemble the augmented fronts of `count` nodes (ids in nodes[]): entries
+// from the children's Schur blocks (same child) or from A (natural CSR,
+// c128), and the identity block.
+template <typename T>
+void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
+                           const int *src_gid, const int *src_child, const int *src_pos,
+                           const int *rowptr, const int *col, const c128 *val,
+                           cplx<T> *pool, hipStream_t st, int max_f);
+
+// Elimination job: Gauss-Jordan elimination of the first ne columns of the
+// m x ncols matrix at ptr (leading dimension ld), partial pivoting among the
+// first ne rows (pivot magnitude |re|+|im|, first row on ties), pivot rows
+// normalised; every other row, including rows >= ne, is reduced.  Columns
+// >= ne of rows >= ne end as the Schur complement.  With negate_r the block
+// (0:ne, ne:m) is negated afterwards.
+template <typename T> struct ElimJob {
+  cplx<T> *ptr;
+  int ld, m, ncols, ne, negate_r;
+  int node;         // reported on a zero pivot
+};
+template <typename T>
+void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st);
+
+// dst(i,j) += a * src1(i,j) + b * src2(i,j) for an m x n block (all column-major)
+template <typename T> struct AxpbyJob {
+  cplx<T> *dst;
+  const cplx<T> *s1;
+  const cplx<T> *s2;
+  int ld_dst, ld1, ld2, m, n;
+  T a, b;
+};
+template <typename T>
+void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipStream_t st);
+
+// ------------------------------------------------------------ sketches (Alg. A.1)
+// Gaussian block Omega(i, j), i < m, j in [c0, c0 + nc) of instance key
+// (seed, key1), stored real in out (leading dimension ld) at column j - cbase.
+struct GaussJob {
+  double *out;
+  int ld, m, c0, nc, cbase;
+  uint32_t key1;
+};
+void launch_gaussian(int count, const GaussJob *jobs, uint32_t seed, int max_m, int max_nc,
+                     hipStream_t st);
+
+// Y(:, 0:nc) = S(m x m complex T) * Om(m x nc real double)
+template <typename T> struct SampleJob {
+  const cplx<T> *S;
+  const double *Om;
+  cplx<T> *Y;
+  int ldS, ldO, ldY, m, nc;
+};
+template <typename T>
+void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, hipStream_t st);
+
+// One cluster of one compression instance at the current tree level.
+// Layout of an instance's HSS generators: per cluster offsets (elements of
+// cplx<T>) into the instance generator pool, capacities fixed by the host.
+struct HssCluster {
+  int start, size;      // index range in the instance's ordering
+  int left, right;      // children (cluster ids within the instance) or -1
+  int level;            // depth in the cluster tree (root 0, level order)
+  int rows_cap, k_cap;  // capacity of U (rows_cap x k_cap)
+  long U, Om, Sr, D, B12, B21;  // offsets in the instance generator pool
+  int sk;               // offset of skeleton ids in the instance int pool
+  long W;               // compression scratch offset (relative to the instance)
+  long XH;              // matvec scratch offset (relative to the job)
+};
+struct HssInstance {
+  int m;                // matrix size
+  int ncl;              // clusters (level order, root = 0)
+  int cl_off;           // first cluster in the global cluster array
+  int s;                // sample columns (k + r)
+  int k;                // rank cap of this round
+  long pool;            // offset of this instance in the generator pool
+  long ipool;           // offset in the int pool
+  long soff;            // offset of the dense operator S (front pool)
+  int ldS;
+  long yoff;            // offset of the samples Y = S Omega (sample pool)
+  long ooff;            // offset of Omega (real pool)
+  int ldY;
+  long woff;            // scratch offset (two rows_cap x s blocks per cluster)
+};
+struct HssItem {
+  int inst, cl;         // instance, cluster id within it
+};
+template <typename T>
+void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
+                           const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
+                           const cplx<T> *front, const cplx<T> *Y, const double *Om,
+                           cplx<T> *scratch, double id_tol, hipStream_t st);
+// Per instance (one workgroup each): out = H X for the compressed H, with X
+// given (ldX) or the identity when X is null; if Yref is given, accumulate
+// err2 = ||Yref - H X||_F^2 and ref2 = ||Yref||_F^2 instead of writing out.
+template <typename T> struct MatvecJob {
+  int inst;
+  const double *X;      // real input (m x nc), or null for identity columns c0..
+  int ldX, nc, c0;
+  cplx<T> *out;         // m x nc output (ldO) or null
+  int ldO;
+  const cplx<T> *Yref;  // reference samples (ldR) or null
+  int ldR;
+  double *err2, *ref2;
+  long woff;            // scratch offset for the sweep vectors
+};
+template <typename T>
+void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *inst,
+                       const HssCluster *cl, const cplx<T> *pool, const int *rank,
+                       cplx<T> *scratch, hipStream_t st);
+
+// ------------------------------------------------------------ apply (Alg. 3.1)
+// y = x(perm) (inverse = 0) or y(perm) = x (inverse = 1), n x nrhs
+void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c128 *y,
+                    long ldy, int inverse, hipStream_t st);
+// Up-sweep of one tree depth: t = x(I); x(I) = A_ii^-1 t; x(B) += L t
+// (trans: A_ii^-T t and R^T t).  x is in elimination order (ld n).
+template <typename T>
+void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+                     const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
+                     hipStream_t st);
+// Down-sweep of one tree depth: x(I) += R x(B) (trans: L^T x(B)).
+template <typename T>
+void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+                       const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
+                       hipStream_t st);
+
+// ------------------------------------------------------------ Krylov
+// h[i*nrhs + r] = sum_k conj(V_i[k, r]) w[k, r], i < cnt; V_i at V + i*stride
+void launch_mdot(int n, int nrhs, int cnt, const c128 *V, long stride, const c128 *w,
+                 c128 *h, c128 *partial, int nblk, hipStream_t st);
+// w[k, r] -= sum_{i<cnt} V_i[k, r] h[i*nrhs + r]
+void launch_mupdate(int n, int nrhs, int cnt, const c128 *V, long stride, const c128 *h,
+                    c128 *w, hipStream_t st);
+// norms[r] = ||w[:, r]||_2
+void launch_norms(int n, int nrhs, const c128 *w, double *norms, double *partial, int nblk,
+                  hipStream_t st);
+// out[k, r] = in[k, r] * scale[r]^-1 (scale real; zero when scale == 0)
+void launch_scale(int n, int nrhs, const c128 *in, const double *scale, c128 *out,
+                  hipStream_t st);
+// y[k, r] = a[k, r] - b[k, r]
+void launch_sub(int n, int nrhs, const c128 *a, long lda, const c128 *b, long ldb, c128 *y,
+                long ldy, hipStream_t st);
+// x[k, r] += sum_{i<cnt[r]} Z_i[k, r] y[i*nrhs + r]
+void launch_xupdate(int n, int nrhs, const int *cnt, int maxcnt, const c128 *Z, long stride,
+                    const c128 *y, c128 *x, long ldx, hipStream_t st);
+// Arnoldi column j bookkeeping for every right-hand side: store h, apply the
+// previous Givens rotations, build the new one, update g; res[r] = |g_{j+1}|.
+void launch_givens(int nrhs, int j, int m, c128 *H, const c128 *hcol, const double *hnext,
+                   double *cs, c128 *sn, c128 *g, double *res, const int *active,
+                   hipStream_t st);
+// back substitution H(0:cnt,0:cnt) y = g per right-hand side
+void launch_hsolve(int nrhs, int m, const c128 *H, const c128 *g, const int *cnt, c128 *y,
+                   hipStream_t st);
+void launch_fill(long n, c128 v, c128 *x, hipStream_t st);
+
+}  // namespace hssx

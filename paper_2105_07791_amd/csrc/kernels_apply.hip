@@ -1,0 +1,170 @@
+// Application of P^-1 = R^-1 D^-1 L^-1 (Algorithm 3.1) on vectors held in
+// elimination order.
+//
+// The bottom-up sweep b(B) += L b(I) and the block-diagonal solve
+// b(I) <- A_ii^-1 b(I) are fused per node: once a node's L-step has run no
+// later L-step reads or writes its I block, so the solve can follow
+// immediately.  With the Gauss-Jordan front, rows [0, f) of the appended
+// column block F(:, f:f+ni) are exactly [A_ii^-1 ; L], so the fused up-step
+// is one small product with t = b(I) staged in LDS.  Nodes of one tree depth
+// have disjoint I and B sets (boxes of one depth are disjoint and
+// B(sigma) lies inside sigma's box), so a depth is one launch.  The top-down
+// sweep b(I) += R b(B) reads ancestors' blocks only.
+//
+// The transposed apply (P^-T) uses R^T in the up-sweep, A_ii^-T for the
+// solve and L^T in the down-sweep.
+#include "common.h"
+#include "kernels.h"
+
+namespace hssx {
+
+namespace {
+
+constexpr int kT = 256;
+
+__global__ void permute_kernel(int n, int nrhs, const int *__restrict__ perm,
+                               const c128 *__restrict__ x, long ldx, c128 *__restrict__ y,
+                               long ldy, int inverse) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)n * nrhs) return;
+  int k = (int)(t % n), r = (int)(t / n);
+  if (inverse) y[perm[k] + r * ldy] = x[k + r * ldx];
+  else y[k + r * ldy] = x[perm[k] + r * ldx];
+}
+
+// grid: (node in batch, rhs chunk); dynamic LDS holds t (ni x rc)
+template <typename T>
+__global__ __launch_bounds__(kT) void apply_up_kernel(const int *__restrict__ nodes,
+                                                      const FrontDesc *__restrict__ desc,
+                                                      const cplx<T> *__restrict__ pool,
+                                                      const int *__restrict__ bpos,
+                                                      c128 *__restrict__ x, int n, int nrhs,
+                                                      int trans, int rc) {
+  extern __shared__ c128 tsh[];
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  const int ni = d.ni, nb = d.nb, f = d.f;
+  if (ni == 0) return;
+  const int r0 = blockIdx.y * rc;
+  const int nr = min(rc, nrhs - r0);
+  if (nr <= 0) return;
+  const cplx<T> *F = pool + d.foff;
+  const int *bp = bpos + d.bpos_off;
+  for (int e = threadIdx.x; e < ni * nr; e += kT) {
+    int i = e % ni, r = e / ni;
+    tsh[e] = x[d.ioff + i + (long)(r0 + r) * n];
+  }
+  __syncthreads();
+  // outputs: rows [0, ni) -> x(I) (replaced), rows [ni, f) -> x(B) (accumulated)
+  for (int e = threadIdx.x; e < f * nr; e += kT) {
+    int i = e % f, r = e / f;
+    c128 acc = czero<double>();
+    const c128 *t = tsh + (long)r * ni;
+    if (!trans) {
+      // [A_ii^-1 ; L](i, :) = F(i, f + l)
+      for (int l = 0; l < ni; ++l) cfma(acc, ccast<double>(F[i + (long)(f + l) * f]), t[l]);
+    } else if (i < ni) {
+      // A_ii^-T(i, l) = F(l, f + i)
+      for (int l = 0; l < ni; ++l) cfma(acc, ccast<double>(F[l + (long)(f + i) * f]), t[l]);
+    } else {
+      // R^T(b, l) = F(l, ni + b)
+      int b = i - ni;
+      for (int l = 0; l < ni; ++l) cfma(acc, ccast<double>(F[l + (long)(ni + b) * f]), t[l]);
+    }
+    if (i < ni) {
+      x[d.ioff + i + (long)(r0 + r) * n] = acc;
+    } else {
+      long pos = bp[i - ni] + (long)(r0 + r) * n;
+      x[pos] = x[pos] + acc;
+    }
+  }
+  (void)nb;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void apply_down_kernel(const int *__restrict__ nodes,
+                                                        const FrontDesc *__restrict__ desc,
+                                                        const cplx<T> *__restrict__ pool,
+                                                        const int *__restrict__ bpos,
+                                                        c128 *__restrict__ x, int n, int nrhs,
+                                                        int trans, int rc) {
+  extern __shared__ c128 tsh[];
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  const int ni = d.ni, nb = d.nb, f = d.f;
+  if (ni == 0 || nb == 0) return;
+  const int r0 = blockIdx.y * rc;
+  const int nr = min(rc, nrhs - r0);
+  if (nr <= 0) return;
+  const cplx<T> *F = pool + d.foff;
+  const int *bp = bpos + d.bpos_off;
+  for (int e = threadIdx.x; e < nb * nr; e += kT) {
+    int b = e % nb, r = e / nb;
+    tsh[e] = x[bp[b] + (long)(r0 + r) * n];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ni * nr; e += kT) {
+    int i = e % ni, r = e / ni;
+    c128 acc = x[d.ioff + i + (long)(r0 + r) * n];
+    const c128 *t = tsh + (long)r * nb;
+    if (!trans) {
+      for (int b = 0; b < nb; ++b) cfma(acc, ccast<double>(F[i + (long)(ni + b) * f]), t[b]);
+    } else {
+      // L^T(i, b) = L(b, i) = F(ni + b, f + i)
+      for (int b = 0; b < nb; ++b) cfma(acc, ccast<double>(F[ni + b + (long)(f + i) * f]), t[b]);
+    }
+    x[d.ioff + i + (long)(r0 + r) * n] = acc;
+  }
+}
+
+int rhs_chunk(int nrhs, int rows) {
+  // stage at most 4096 complex doubles (64 KiB) of the input block in LDS
+  int rc = rows > 0 ? 4096 / rows : nrhs;
+  if (rc < 1) rc = 1;
+  return rc < nrhs ? rc : nrhs;
+}
+
+}  // namespace
+
+void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c128 *y, long ldy,
+                    int inverse, hipStream_t st) {
+  long tot = (long)n * nrhs;
+  hipLaunchKernelGGL(permute_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, st, n, nrhs, perm,
+                     x, ldx, y, ldy, inverse);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+                     const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
+                     hipStream_t st) {
+  if (count <= 0 || max_ni <= 0) return;
+  HSSX_CHECK(max_ni <= 4096, HSSX_EINVAL, "interior block larger than the apply kernel stages");
+  int rc = rhs_chunk(nrhs, max_ni);
+  size_t lds = (size_t)rc * max_ni * sizeof(c128);
+  hipLaunchKernelGGL(apply_up_kernel<T>, dim3(count, ceil_div(nrhs, rc)), dim3(kT), lds, st,
+                     nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+                       const int *bpos, c128 *x, int n, int nrhs, int trans, int max_nb,
+                       hipStream_t st) {
+  if (count <= 0 || max_nb <= 0) return;
+  HSSX_CHECK(max_nb <= 4096, HSSX_EINVAL, "boundary block larger than the apply kernel stages");
+  int rc = rhs_chunk(nrhs, max_nb);
+  size_t lds = (size_t)rc * max_nb * sizeof(c128);
+  hipLaunchKernelGGL(apply_down_kernel<T>, dim3(count, ceil_div(nrhs, rc)), dim3(kT), lds, st,
+                     nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  HSSX_HIP(hipGetLastError());
+}
+
+#define HSSX_INST(T)                                                                          \
+  template void launch_apply_up<T>(int, const int *, const FrontDesc *, const cplx<T> *,      \
+                                   const int *, c128 *, int, int, int, int, hipStream_t);     \
+  template void launch_apply_down<T>(int, const int *, const FrontDesc *, const cplx<T> *,    \
+                                     const int *, c128 *, int, int, int, int, hipStream_t);
+HSSX_INST(double)
+HSSX_INST(float)
+#undef HSSX_INST
+
+}  // namespace hssx

@@ -1,0 +1,185 @@
+// Dense fronts of the nested-dissection elimination (eqs. 3.2-3.5).
+//
+// front_assemble: F(p, q) = S_child(p, q) when both front entries belong to
+// the same child's boundary (the child's Schur complement, held in the
+// trailing block of the child's front), else A(p, q) from the CSR (eq. 3.4);
+// the appended ni columns start as [I; 0].
+//
+// eliminate: Gauss-Jordan elimination of the first ne columns with partial
+// pivoting among the first ne rows.  On the augmented front this yields in
+// one pass A_ii^-1, A_ii^-1 A_ib (negated into R, eq. 3.3b), L = -A_bi A_ii^-1
+// (eq. 3.3a) and the Schur complement S (eq. 3.5).  One workgroup per job;
+// each thread owns whole rows during an elimination step, so the multiplier
+// column can be cleared without an extra barrier.
+#include "common.h"
+#include "kernels.h"
+
+namespace hssx {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void front_assemble_kernel(
+    const int *__restrict__ nodes, const FrontDesc *__restrict__ desc,
+    const int *__restrict__ src_gid, const int *__restrict__ src_child,
+    const int *__restrict__ src_pos, const int *__restrict__ rowptr,
+    const int *__restrict__ col, const c128 *__restrict__ val, cplx<T> *__restrict__ pool) {
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  const long f = d.f;
+  const long total = f * (f + d.ni);
+  const long per = (long)kThreads * 16;
+  long e0 = (long)blockIdx.y * per;
+  if (e0 >= total) return;
+  long e1 = e0 + per < total ? e0 + per : total;
+  const int *gid = src_gid + d.src_off;
+  const int *chd = src_child + d.src_off;
+  const int *pos = src_pos + d.src_off;
+  cplx<T> *F = pool + d.foff;
+  for (long e = e0 + threadIdx.x; e < e1; e += kThreads) {
+    int p = (int)(e % f), q = (int)(e / f);
+    cplx<T> v;
+    if (q >= f) {
+      v = mk((T)(p == q - f ? 1 : 0), (T)0);
+    } else {
+      int cp = chd[p], cq = chd[q];
+      if (cp >= 0 && cp == cq) {
+        const FrontDesc c = desc[cp == 0 ? d.lo : d.hi];
+        v = pool[c.foff + (long)(c.ni + pos[p]) + (long)(c.ni + pos[q]) * c.f];
+      } else {
+        int gi = gid[p], gj = gid[q];
+        c128 a = czero<double>();
+        for (int t = rowptr[gi]; t < rowptr[gi + 1]; ++t)
+          if (col[t] == gj) { a = val[t]; break; }
+        v = ccast<T>(a);
+      }
+    }
+    F[e] = v;
+  }
+}
+
+template <typename T>
+__device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
+  // wave reduction then across waves; ties keep the smaller index
+  for (int off = 32; off > 0; off >>= 1) {
+    T ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) { sv[w] = v; si[w] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kThreads / 64; ++k)
+      if (sv[k] > sv[0] || (sv[k] == sv[0] && si[k] < si[0])) { sv[0] = sv[k]; si[0] = si[k]; }
+  }
+  __syncthreads();
+  v = sv[0];
+  idx = si[0];
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void eliminate_kernel(const ElimJob<T> *__restrict__ jobs,
+                                                            int *__restrict__ err_node) {
+  __shared__ T sv[kThreads / 64];
+  __shared__ int si[kThreads / 64];
+  const ElimJob<T> jb = jobs[blockIdx.x];
+  cplx<T> *F = jb.ptr;
+  const long ld = jb.ld;
+  const int m = jb.m, nc = jb.ncols, ne = jb.ne;
+  const int tid = threadIdx.x;
+  for (int p = 0; p < ne; ++p) {
+    T best = (T)-1;
+    int bi = 0x7fffffff;
+    for (int i = p + tid; i < ne; i += kThreads) {
+      T a = cabs1(F[i + p * ld]);
+      if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+    }
+    block_argmax(best, bi, sv, si);
+    const bool zero = !(best > (T)0);
+    if (zero && tid == 0) atomicCAS(err_node, -1, jb.node);
+    const int piv = zero ? p : bi;
+    if (piv != p) {
+      for (int j = p + tid; j < nc; j += kThreads) {
+        cplx<T> a = F[p + j * ld];
+        F[p + j * ld] = F[piv + j * ld];
+        F[piv + j * ld] = a;
+      }
+    }
+    __syncthreads();
+    const cplx<T> inv = zero ? czero<T>() : cinv(F[p + p * ld]);
+    for (int j = p + 1 + tid; j < nc; j += kThreads) F[p + j * ld] = F[p + j * ld] * inv;
+    __syncthreads();
+    for (int i = tid; i < m; i += kThreads) {
+      if (i == p) continue;
+      const cplx<T> l = F[i + p * ld];
+      for (int j = p + 1; j < nc; ++j) cfms(F[i + j * ld], l, F[p + j * ld]);
+      F[i + p * ld] = czero<T>();
+    }
+    if (tid == 0) F[p + p * ld] = mk((T)1, (T)0);
+    __syncthreads();
+  }
+  if (!jb.negate_r) return;
+  const int nb = m - ne;
+  for (long t = tid; t < (long)ne * nb; t += kThreads) {
+    int l = (int)(t % ne), c = (int)(t / ne);
+    long e = l + (long)(ne + c) * ld;
+    F[e] = -F[e];
+  }
+}
+
+template <typename T>
+__global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
+  const AxpbyJob<T> jb = jobs[blockIdx.z];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i >= jb.m || j >= jb.n) return;
+  cplx<T> v = jb.dst[i + (long)j * jb.ld_dst];
+  if (jb.s1) v = v + jb.a * jb.s1[i + (long)j * jb.ld1];
+  if (jb.s2) v = v + jb.b * jb.s2[i + (long)j * jb.ld2];
+  jb.dst[i + (long)j * jb.ld_dst] = v;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
+                           const int *src_gid, const int *src_child, const int *src_pos,
+                           const int *rowptr, const int *col, const c128 *val,
+                           cplx<T> *pool, hipStream_t st, int max_f) {
+  if (count <= 0) return;
+  long per = (long)kThreads * 16;
+  int ny = ceil_div((long)max_f * (2L * max_f), per);
+  hipLaunchKernelGGL(front_assemble_kernel<T>, dim3(count, ny), dim3(kThreads), 0, st, nodes,
+                     desc, src_gid, src_child, src_pos, rowptr, col, val, pool);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(eliminate_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel<T>, dim3(ceil_div(max_m, 256), max_n, count), dim3(256), 0,
+                     st, jobs);
+  HSSX_HIP(hipGetLastError());
+}
+
+#define HSSX_INST(T)                                                                        \
+  template void launch_front_assemble<T>(int, const int *, const FrontDesc *, const int *,  \
+                                         const int *, const int *, const int *, const int *, \
+                                         const c128 *, cplx<T> *, hipStream_t, int);         \
+  template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
+  template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);
+HSSX_INST(double)
+HSSX_INST(float)
+#undef HSSX_INST
+
+}  // namespace hssx

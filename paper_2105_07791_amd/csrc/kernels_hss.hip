@@ -1,0 +1,462 @@
+// Adaptive randomized HSS compression (Sec. 2.3, Appendix A, Algorithm A.1)
+// for complex symmetric operators (V = U, transposes, no conjugates).
+//
+// gaussian: Omega(i, j) = Box-Muller(Philox4x32-10(ctr = (i, j, 0, 0),
+//           key = (seed, instance))), u = (word + 0.5) 2^-32, using the first
+//           two output words: g = sqrt(-2 ln u1) cos(2 pi u2).
+// sample:   Y = S Omega (complex operator times real sketch).
+// compress_level: one workgroup per cluster of the current tree level.  A
+//           leaf removes its diagonal block, S_loc = Y(I, :) - D Omega(I, :),
+//           D = S(I, I); an internal cluster stacks the children's reduced
+//           samples minus the sibling coupling, S_loc = [Sr_l - B12 Om_r;
+//           Sr_r - B21 Om_l], B12 = S(sk_l, sk_r), B21 = S(sk_r, sk_l).  The
+//           interpolative decomposition S_loc ~ U S_loc(J, :) comes from a
+//           pivoted Gram-Schmidt QR of S_loc^T (pivot = largest remaining row
+//           norm, first on ties; each projection applied twice), rank =
+//           min(k, rows, s) reduced to the pivots above id_tol * first pivot;
+//           T = R11^-1 R12, U(J, :) = I, U(rest, :) = T^T.  The cluster keeps
+//           Om_c = U^T Om_loc, Sr_c = S_loc(J, :), skeleton I_loc(J).  The
+//           root only reads its B blocks.
+// hss_matvec: telescoping product (eqs. 2.5-2.6) by one workgroup per job,
+//           used both for the error estimate of eq. 2.7 and to expand the
+//           compressed matrix column block by column block.
+#include "common.h"
+#include "kernels.h"
+
+namespace hssx {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kMaxRows = 1024;   // rows of one local sample block (LDS index arrays)
+constexpr int kMaxS = 1024;      // sample columns held in LDS for the projector
+
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+__global__ void gaussian_kernel(const GaussJob *__restrict__ jobs, uint32_t seed) {
+  const GaussJob jb = jobs[blockIdx.z];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int jj = blockIdx.y;
+  if (i >= jb.m || jj >= jb.nc) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)(jb.c0 + jj), 0u, 0u};
+  philox(c, seed, jb.key1);
+  double u1 = ((double)c[0] + 0.5) * 0x1p-32;
+  double u2 = ((double)c[1] + 0.5) * 0x1p-32;
+  double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  jb.out[i + (long)(jb.c0 + jj - jb.cbase) * jb.ld] = g;
+}
+
+template <typename T>
+__global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
+  const SampleJob<T> jb = jobs[blockIdx.z];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i >= jb.m || j >= jb.nc) return;
+  cplx<T> acc = czero<T>();
+  const double *o = jb.Om + (long)j * jb.ldO;
+  for (int k = 0; k < jb.m; ++k) {
+    cplx<T> s = jb.S[i + (long)k * jb.ldS];
+    T w = (T)o[k];
+    acc.re += s.re * w;
+    acc.im += s.im * w;
+  }
+  jb.Y[i + (long)j * jb.ldY] = acc;
+}
+
+template <typename T>
+__device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
+  for (int off = 32; off > 0; off >>= 1) {
+    T ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) { sv[w] = v; si[w] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k < kT / 64; ++k)
+      if (sv[k] > sv[0] || (sv[k] == sv[0] && si[k] < si[0])) { sv[0] = sv[k]; si[0] = si[k]; }
+  __syncthreads();
+  v = sv[0];
+  idx = si[0];
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void compress_level_kernel(
+    const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
+    const HssCluster *__restrict__ cls, cplx<T> *__restrict__ pool, int *__restrict__ ipool,
+    int *__restrict__ rank, const cplx<T> *__restrict__ front, const cplx<T> *__restrict__ Yall,
+    const double *__restrict__ Omall, cplx<T> *__restrict__ scratch, double id_tol) {
+  __shared__ int I_loc[kMaxRows];
+  __shared__ int perm[kMaxRows];
+  __shared__ cplx<T> q[kMaxS];
+  __shared__ T sv[kT / 64];
+  __shared__ int si[kT / 64];
+  __shared__ int s_rank;
+  const HssItem it = items[blockIdx.x];
+  const HssInstance I = insts[it.inst];
+  const int cg = I.cl_off + it.cl;
+  const HssCluster C = cls[cg];
+  const int tid = threadIdx.x;
+  const int s = I.s;
+  cplx<T> *P = pool + I.pool;
+  int *IP = ipool + I.ipool;
+  const cplx<T> *S = front + I.soff;
+  const long ldS = I.ldS;
+  const cplx<T> *Y = Yall + I.yoff;
+  const double *Om = Omall + I.ooff;
+  const long ldY = I.ldY, ldO = I.m;
+  cplx<T> *Sloc = scratch + I.woff + C.W;
+  const int rcap = C.rows_cap;
+  cplx<T> *Wm = Sloc + (long)rcap * s;
+  cplx<T> *Oloc = Wm + (long)rcap * s;
+  cplx<T> *Rm = Oloc + (long)rcap * s;           // k_cap x rows_cap (by original row)
+
+  int rows;
+  const bool leaf = C.left < 0;
+  if (leaf) {
+    rows = C.size;
+    for (int i = tid; i < rows; i += kT) I_loc[i] = C.start + i;
+    __syncthreads();
+    cplx<T> *D = P + C.D;
+    for (int e = tid; e < rows * rows; e += kT) {
+      int i = e % rows, l = e / rows;
+      D[e] = S[(C.start + i) + (long)(C.start + l) * ldS];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * s; e += kT) {
+      int i = e % rows, j = e / rows;
+      cplx<T> v = Y[(C.start + i) + (long)j * ldY];
+      for (int l = 0; l < rows; ++l) {
+        T w = (T)Om[(C.start + l) + (long)j * ldO];
+        cplx<T> d = D[i + (long)l * rows];
+        v.re -= d.re * w;
+        v.im -= d.im * w;
+      }
+      Sloc[i + (long)j * rcap] = v;
+      Oloc[i + (long)j * rcap] = mk((T)Om[(C.start + i) + (long)j * ldO], (T)0);
+    }
+  } else {
+    const HssCluster L = cls[I.cl_off + C.left], R = cls[I.cl_off + C.right];
+    const int kl = rank[I.cl_off + C.left], kr = rank[I.cl_off + C.right];
+    rows = kl + kr;
+    const int *skl = IP + L.sk, *skr = IP + R.sk;
+    for (int i = tid; i < rows; i += kT) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
+    cplx<T> *B12 = P + C.B12, *B21 = P + C.B21;
+    for (int e = tid; e < kl * kr; e += kT) {
+      int a = e % kl, b = e / kl;
+      B12[a + (long)b * kl] = S[skl[a] + (long)skr[b] * ldS];
+    }
+    for (int e = tid; e < kr * kl; e += kT) {
+      int a = e % kr, b = e / kr;
+      B21[a + (long)b * kr] = S[skr[a] + (long)skl[b] * ldS];
+    }
+    __syncthreads();
+    if (it.cl != 0) {
+      const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
+      for (int e = tid; e < rows * s; e += kT) {
+        int i = e % rows, j = e / rows;
+        cplx<T> v, o;
+        if (i < kl) {
+          v = Srl[i + (long)j * kl];
+          for (int b = 0; b < kr; ++b) cfms(v, B12[i + (long)b * kl], Omr[b + (long)j * kr]);
+          o = Oml[i + (long)j * kl];
+        } else {
+          int a = i - kl;
+          v = Srr[a + (long)j * kr];
+          for (int b = 0; b < kl; ++b) cfms(v, B21[a + (long)b * kr], Oml[b + (long)j * kl]);
+          o = Omr[a + (long)j * kr];
+        }
+        Sloc[i + (long)j * rcap] = v;
+        Oloc[i + (long)j * rcap] = o;
+      }
+    }
+  }
+  __syncthreads();
+  if (it.cl == 0) {                 // root: generators B (or D) only
+    if (tid == 0) rank[cg] = 0;
+    return;
+  }
+
+  // ---- interpolative decomposition of S_loc (rows x s)
+  for (int e = tid; e < rows * s; e += kT) {
+    int i = e % rows, j = e / rows;
+    Wm[i + (long)j * rcap] = Sloc[i + (long)j * rcap];
+  }
+  for (int i = tid; i < rows; i += kT) perm[i] = i;
+  __syncthreads();
+  int kmax = I.k < rows ? I.k : rows;
+  kmax = kmax < s ? kmax : s;
+  kmax = kmax < C.k_cap ? kmax : C.k_cap;
+  T first = (T)0;
+  int t = 0;
+  for (; t < kmax; ++t) {
+    T best = (T)-1;
+    int bi = 0x7fffffff;
+    for (int pp = t + tid; pp < rows; pp += kT) {
+      int row = perm[pp];
+      T nrm = 0;
+      for (int j = 0; j < s; ++j) nrm += abs2(Wm[row + (long)j * rcap]);
+      if (nrm > best || (nrm == best && pp < bi)) { best = nrm; bi = pp; }
+    }
+    block_argmax(best, bi, sv, si);
+    T pn = sqrt(best);
+    if (t == 0) first = pn;
+    if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
+    if (tid == 0 && bi != t) {
+      int a = perm[t];
+      perm[t] = perm[bi];
+      perm[bi] = a;
+    }
+    __syncthreads();
+    const int prow = perm[t];
+    T inv = (T)1 / pn;
+    for (int j = tid; j < s; j += kT) q[j] = inv * Wm[prow + (long)j * rcap];
+    if (tid == 0) Rm[t + (long)prow * C.k_cap] = mk(pn, (T)0);
+    __syncthreads();
+    for (int pp = t + 1 + tid; pp < rows; pp += kT) {
+      int row = perm[pp];
+      cplx<T> rr = czero<T>();
+      for (int pass = 0; pass < 2; ++pass) {
+        cplx<T> d = czero<T>();
+        for (int j = 0; j < s; ++j) cfma(d, conj(q[j]), Wm[row + (long)j * rcap]);
+        for (int j = 0; j < s; ++j) cfms(Wm[row + (long)j * rcap], d, q[j]);
+        rr = rr + d;
+      }
+      Rm[t + (long)row * C.k_cap] = rr;
+    }
+    __syncthreads();
+  }
+  const int rk = t;
+  if (tid == 0) s_rank = rk;
+  __syncthreads();
+
+  // U (rows x rk): identity rows at the skeleton, T^T = (R11^-1 R12)^T elsewhere
+  cplx<T> *U = P + C.U;
+  for (int e = tid; e < rows * rk; e += kT) U[e] = czero<T>();
+  __syncthreads();
+  for (int a = tid; a < rk; a += kT) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
+  for (int c2 = tid; c2 < rows - rk; c2 += kT) {
+    int row = perm[rk + c2];
+    // back substitution, solution written straight into U(row, :)
+    for (int a = rk - 1; a >= 0; --a) {
+      cplx<T> v = Rm[a + (long)row * C.k_cap];
+      for (int b = a + 1; b < rk; ++b)
+        cfms(v, Rm[a + (long)perm[b] * C.k_cap], U[row + (long)b * rows]);
+      U[row + (long)a * rows] = v * cinv(Rm[a + (long)perm[a] * C.k_cap]);
+    }
+  }
+  __syncthreads();
+  int *sk = IP + C.sk;
+  for (int a = tid; a < rk; a += kT) sk[a] = I_loc[perm[a]];
+  cplx<T> *Omc = P + C.Om, *Src = P + C.Sr;
+  for (int e = tid; e < rk * s; e += kT) {
+    int a = e % rk, j = e / rk;
+    cplx<T> o = czero<T>();
+    for (int i = 0; i < rows; ++i) cfma(o, U[i + (long)a * rows], Oloc[i + (long)j * rcap]);
+    Omc[a + (long)j * rk] = o;
+    Src[a + (long)j * rk] = Sloc[perm[a] + (long)j * rcap];
+  }
+  if (tid == 0) rank[cg] = rk;
+}
+
+// Telescoping product out = H X by one workgroup.
+template <typename T>
+__global__ __launch_bounds__(kT) void hss_matvec_kernel(
+    const MatvecJob<T> *__restrict__ jobs, const HssInstance *__restrict__ insts,
+    const HssCluster *__restrict__ cls, const cplx<T> *__restrict__ pool,
+    const int *__restrict__ rank, cplx<T> *__restrict__ scratch) {
+  __shared__ double red[2][kT];
+  const MatvecJob<T> jb = jobs[blockIdx.x];
+  const HssInstance I = insts[jb.inst];
+  const HssCluster *C = cls + I.cl_off;
+  const int *rk = rank + I.cl_off;
+  const cplx<T> *P = pool + I.pool;
+  const int nc = jb.nc, tid = threadIdx.x;
+  cplx<T> *W = scratch + jb.woff;
+  auto X = [&](int i, int j) -> T {
+    if (!jb.X) return (i == jb.c0 + j) ? (T)1 : (T)0;
+    return (T)jb.X[i + (long)j * jb.ldX];
+  };
+  int maxlev = 0;
+  for (int c = 0; c < I.ncl; ++c) maxlev = C[c].level > maxlev ? C[c].level : maxlev;
+  // up-sweep: xh_c = U_c^T (X rows | stacked children)
+  for (int lev = maxlev; lev >= 1; --lev) {
+    for (int c = 0; c < I.ncl; ++c) {
+      const HssCluster cc = C[c];
+      if (cc.level != lev) continue;
+      const int k = rk[c];
+      const cplx<T> *U = P + cc.U;
+      cplx<T> *xh = W + cc.XH;
+      if (cc.left < 0) {
+        for (int e = tid; e < k * nc; e += kT) {
+          int a = e % k, j = e / k;
+          cplx<T> v = czero<T>();
+          for (int i = 0; i < cc.size; ++i) {
+            cplx<T> u = U[i + (long)a * cc.size];
+            T x = X(cc.start + i, j);
+            v.re += u.re * x;
+            v.im += u.im * x;
+          }
+          xh[a + (long)j * k] = v;
+        }
+      } else {
+        const int kl = rk[cc.left], kr = rk[cc.right], rows = kl + kr;
+        const cplx<T> *xl = W + C[cc.left].XH, *xr = W + C[cc.right].XH;
+        for (int e = tid; e < k * nc; e += kT) {
+          int a = e % k, j = e / k;
+          cplx<T> v = czero<T>();
+          for (int i = 0; i < kl; ++i) cfma(v, U[i + (long)a * rows], xl[i + (long)j * kl]);
+          for (int i = 0; i < kr; ++i) cfma(v, U[kl + i + (long)a * rows], xr[i + (long)j * kr]);
+          xh[a + (long)j * k] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // couplings: yh_l = B12 xh_r, yh_r = B21 xh_l (yh stored after xh: XH + k_cap*64)
+  for (int c = 0; c < I.ncl; ++c) {
+    const HssCluster cc = C[c];
+    if (cc.left < 0) continue;
+    const int kl = rk[cc.left], kr = rk[cc.right];
+    const HssCluster L = C[cc.left], R = C[cc.right];
+    const cplx<T> *B12 = P + cc.B12, *B21 = P + cc.B21;
+    cplx<T> *yl = W + L.XH + (long)L.k_cap * 64, *yr = W + R.XH + (long)R.k_cap * 64;
+    const cplx<T> *xl = W + L.XH, *xr = W + R.XH;
+    for (int e = tid; e < (kl + kr) * nc; e += kT) {
+      int a = e % (kl + kr), j = e / (kl + kr);
+      cplx<T> v = czero<T>();
+      if (a < kl) {
+        for (int b = 0; b < kr; ++b) cfma(v, B12[a + (long)b * kl], xr[b + (long)j * kr]);
+        yl[a + (long)j * kl] = v;
+      } else {
+        a -= kl;
+        for (int b = 0; b < kl; ++b) cfma(v, B21[a + (long)b * kr], xl[b + (long)j * kl]);
+        yr[a + (long)j * kr] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // down-sweep through internal non-root clusters
+  for (int lev = 1; lev <= maxlev; ++lev) {
+    for (int c = 0; c < I.ncl; ++c) {
+      const HssCluster cc = C[c];
+      if (cc.level != lev || cc.left < 0) continue;
+      const int k = rk[c], kl = rk[cc.left], kr = rk[cc.right], rows = kl + kr;
+      const cplx<T> *U = P + cc.U;
+      const cplx<T> *yh = W + cc.XH + (long)cc.k_cap * 64;
+      cplx<T> *yl = W + C[cc.left].XH + (long)C[cc.left].k_cap * 64;
+      cplx<T> *yr = W + C[cc.right].XH + (long)C[cc.right].k_cap * 64;
+      for (int e = tid; e < rows * nc; e += kT) {
+        int i = e % rows, j = e / rows;
+        cplx<T> v = czero<T>();
+        for (int a = 0; a < k; ++a) cfma(v, U[i + (long)a * rows], yh[a + (long)j * k]);
+        if (i < kl) yl[i + (long)j * kl] = yl[i + (long)j * kl] + v;
+        else yr[(i - kl) + (long)j * kr] = yr[(i - kl) + (long)j * kr] + v;
+      }
+    }
+    __syncthreads();
+  }
+  // leaves
+  double e2 = 0.0, r2 = 0.0;
+  for (int c = 0; c < I.ncl; ++c) {
+    const HssCluster cc = C[c];
+    if (cc.left >= 0) continue;
+    const int k = c == 0 ? 0 : rk[c];
+    const cplx<T> *U = P + cc.U, *D = P + cc.D;
+    const cplx<T> *yh = W + cc.XH + (long)cc.k_cap * 64;
+    for (int e = tid; e < cc.size * nc; e += kT) {
+      int i = e % cc.size, j = e / cc.size;
+      cplx<T> v = czero<T>();
+      for (int l = 0; l < cc.size; ++l) {
+        cplx<T> d = D[i + (long)l * cc.size];
+        T x = X(cc.start + l, j);
+        v.re += d.re * x;
+        v.im += d.im * x;
+      }
+      for (int a = 0; a < k; ++a) cfma(v, U[i + (long)a * cc.size], yh[a + (long)j * k]);
+      int gi = cc.start + i;
+      if (jb.Yref) {
+        cplx<T> yr = jb.Yref[gi + (long)j * jb.ldR];
+        e2 += (double)abs2(yr - v);
+        r2 += (double)abs2(yr);
+      } else {
+        jb.out[gi + (long)j * jb.ldO] = v;
+      }
+    }
+  }
+  if (jb.Yref) {
+    red[0][tid] = e2;
+    red[1][tid] = r2;
+    __syncthreads();
+    for (int w = kT / 2; w > 0; w >>= 1) {
+      if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+      __syncthreads();
+    }
+    if (tid == 0) { *jb.err2 = red[0][0]; *jb.ref2 = red[1][0]; }
+  }
+}
+
+}  // namespace
+
+void launch_gaussian(int count, const GaussJob *jobs, uint32_t seed, int max_m, int max_nc,
+                     hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
+  hipLaunchKernelGGL(gaussian_kernel, dim3(ceil_div(max_m, 256), max_nc, count), dim3(256), 0,
+                     st, jobs, seed);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
+  hipLaunchKernelGGL(sample_kernel<T>, dim3(ceil_div(max_m, 256), max_nc, count), dim3(256), 0,
+                     st, jobs);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
+                           const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
+                           const cplx<T> *front, const cplx<T> *Y, const double *Om,
+                           cplx<T> *scratch, double id_tol, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(compress_level_kernel<T>, dim3(count), dim3(kT), 0, st, items, inst, cl,
+                     pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *inst,
+                       const HssCluster *cl, const cplx<T> *pool, const int *rank,
+                       cplx<T> *scratch, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(hss_matvec_kernel<T>, dim3(count), dim3(kT), 0, st, jobs, inst, cl, pool,
+                     rank, scratch);
+  HSSX_HIP(hipGetLastError());
+}
+
+#define HSSX_INST(T)                                                                          \
+  template void launch_sample<T>(int, const SampleJob<T> *, int, int, hipStream_t);          \
+  template void launch_compress_level<T>(int, const HssItem *, const HssInstance *,           \
+                                         const HssCluster *, cplx<T> *, int *, int *,         \
+                                         const cplx<T> *, const cplx<T> *, const double *,    \
+                                         cplx<T> *, double, hipStream_t);                     \
+  template void launch_hss_matvec<T>(int, const MatvecJob<T> *, const HssInstance *,          \
+                                     const HssCluster *, const cplx<T> *, const int *,        \
+                                     cplx<T> *, hipStream_t);
+HSSX_INST(double)
+HSSX_INST(float)
+#undef HSSX_INST
+
+}  // namespace hssx

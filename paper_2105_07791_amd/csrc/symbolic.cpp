@@ -1,0 +1,231 @@
+// Box nested dissection and cluster trees (host, integer-only).
+//
+// Rules: a box [x0,x1) x [y0,y1) of grid nodes is a leaf when nx*ny <=
+// leaf_dofs; otherwise it is cut across its longer side (x on ties) at
+// x0 + nx/2 (y0 + ny/2) into (low, high).  Nodes are numbered in post-order
+// (Sec. 3.1, Fig. 1).  Bd(sigma) holds the box's grid nodes with a stencil
+// neighbour outside the box; the P1 stencil couples (i,j) to (i+-1,j),
+// (i,j+-1), (i+1,j+1) and (i-1,j-1) (shared triangles of the SW-NE split).
+// Leaf I = box \ Bd in id order; non-leaf I = [P0(lo) ; P0(hi)] (eq. 3.4
+// layout); B = Bd(sigma) ordered by its cluster tree whose root separates
+// P0 = Bd \ Bd(parent) from P1 = Bd n Bd(parent) (Fig. 4); each part is
+// bisected geometrically (axis of larger extent, x on ties; order by axis
+// coordinate then the other coordinate; split at count/2) down to <= beta.
+#include "symbolic.h"
+
+#include <algorithm>
+#include <functional>
+#include <memory>
+
+namespace hssx {
+
+namespace {
+
+struct CNode {
+  std::vector<int> ids;  // leaf payload
+  std::unique_ptr<CNode> l, r;
+};
+
+std::unique_ptr<CNode> bisect(std::vector<int> ids, int N, int beta) {
+  auto node = std::make_unique<CNode>();
+  if ((int)ids.size() <= beta) {
+    node->ids = std::move(ids);
+    return node;
+  }
+  int xmin = N, xmax = -1, ymin = N, ymax = -1;
+  for (int v : ids) {
+    int x = v % N, y = v / N;
+    xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+    ymin = std::min(ymin, y); ymax = std::max(ymax, y);
+  }
+  bool by_x = (xmax - xmin) >= (ymax - ymin);
+  std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+    int ax = a % N, ay = a / N, bx = b % N, by = b / N;
+    if (by_x) {
+      if (ax != bx) return ax < bx;
+      if (ay != by) return ay < by;
+    } else {
+      if (ay != by) return ay < by;
+      if (ax != bx) return ax < bx;
+    }
+    return a < b;
+  });
+  size_t h = ids.size() / 2;
+  node->l = bisect(std::vector<int>(ids.begin(), ids.begin() + h), N, beta);
+  node->r = bisect(std::vector<int>(ids.begin() + h, ids.end()), N, beta);
+  return node;
+}
+
+// Level-order cluster tree + leaf order of the given parts.
+void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
+                       int N, int beta, ClusterTree &ct, std::vector<int> &order) {
+  ct = ClusterTree();
+  order.clear();
+  std::unique_ptr<CNode> root;
+  if (!P0.empty() && !P1.empty()) {
+    root = std::make_unique<CNode>();
+    root->l = bisect(P0, N, beta);
+    root->r = bisect(P1, N, beta);
+  } else if (!P0.empty()) {
+    root = bisect(P0, N, beta);
+  } else if (!P1.empty()) {
+    root = bisect(P1, N, beta);
+  } else {
+    return;
+  }
+  // in-order ranges
+  std::vector<std::pair<const CNode *, std::pair<int, int>>> rng;
+  std::function<void(const CNode *)> walk = [&](const CNode *t) {
+    int st = (int)order.size();
+    if (!t->l) {
+      order.insert(order.end(), t->ids.begin(), t->ids.end());
+    } else {
+      walk(t->l.get());
+      walk(t->r.get());
+    }
+    rng.push_back({t, {st, (int)order.size()}});
+  };
+  walk(root.get());
+  auto range_of = [&](const CNode *t) {
+    for (auto &p : rng)
+      if (p.first == t) return p.second;
+    return std::make_pair(0, 0);
+  };
+  // breadth-first numbering
+  std::vector<std::pair<const CNode *, int>> q{{root.get(), 0}};
+  for (size_t k = 0; k < q.size(); ++k) {
+    const CNode *t = q[k].first;
+    if (t->l) {
+      q.push_back({t->l.get(), q[k].second + 1});
+      q.push_back({t->r.get(), q[k].second + 1});
+    }
+  }
+  int nc = (int)q.size();
+  ct.start.resize(nc); ct.size.resize(nc); ct.left.assign(nc, -1);
+  ct.right.assign(nc, -1); ct.level.resize(nc);
+  for (int k = 0, child = 1; k < nc; ++k) {
+    auto r = range_of(q[k].first);
+    ct.start[k] = r.first;
+    ct.size[k] = r.second - r.first;
+    ct.level[k] = q[k].second;
+    if (q[k].first->l) {
+      // children of the k-th node were appended in order; locate them
+      for (int j = child; j < nc; ++j)
+        if (q[j].first == q[k].first->l.get()) { ct.left[k] = j; ct.right[k] = j + 1; child = j + 2; break; }
+    }
+  }
+}
+
+}  // namespace
+
+Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
+  Symbolic s;
+  s.N = N;
+  s.leaf_dofs = leaf_dofs;
+  s.beta = beta;
+  auto &nodes = s.nodes;
+
+  std::function<int(int, int, int, int, int)> rec = [&](int x0, int x1, int y0, int y1, int depth) {
+    NDNode b;
+    b.x0 = x0; b.x1 = x1; b.y0 = y0; b.y1 = y1; b.depth = depth;
+    int nx = x1 - x0, ny = y1 - y0;
+    if ((long)nx * ny > leaf_dofs) {
+      int lo, hi;
+      if (nx >= ny) {
+        int xm = x0 + nx / 2;
+        lo = rec(x0, xm, y0, y1, depth + 1);
+        hi = rec(xm, x1, y0, y1, depth + 1);
+      } else {
+        int ym = y0 + ny / 2;
+        lo = rec(x0, x1, y0, ym, depth + 1);
+        hi = rec(x0, x1, ym, y1, depth + 1);
+      }
+      b.lo = lo; b.hi = hi;
+      b.height = 1 + std::max(nodes[lo].height, nodes[hi].height);
+    }
+    nodes.push_back(std::move(b));
+    int k = (int)nodes.size() - 1;
+    if (nodes[k].lo >= 0) { nodes[nodes[k].lo].parent = k; nodes[nodes[k].hi].parent = k; }
+    s.max_depth = std::max(s.max_depth, depth);
+    return k;
+  };
+  rec(0, N, 0, N, 0);
+
+  static const int dx[6] = {1, -1, 0, 0, 1, -1};
+  static const int dy[6] = {0, 0, 1, -1, 1, -1};
+  for (auto &b : nodes) {
+    for (int y = b.y0; y < b.y1; ++y)
+      for (int x = b.x0; x < b.x1; ++x) {
+        bool out = false;
+        for (int d = 0; d < 6 && !out; ++d) {
+          int u = x + dx[d], v = y + dy[d];
+          if (u < 0 || v < 0 || u >= N || v >= N) continue;
+          if (u < b.x0 || u >= b.x1 || v < b.y0 || v >= b.y1) out = true;
+        }
+        if (out) b.bd.push_back(y * N + x);     // row-major scan = sorted ids
+      }
+  }
+
+  for (auto &b : nodes) {
+    if (b.parent < 0) continue;
+    const auto &pbd = nodes[b.parent].bd;
+    std::vector<int> P0, P1;
+    for (int v : b.bd)
+      (std::binary_search(pbd.begin(), pbd.end(), v) ? P1 : P0).push_back(v);
+    make_cluster_tree(P0, P1, N, beta, b.ct, b.B);
+    b.p0 = (int)P0.size();
+  }
+
+  for (auto &b : nodes) {
+    if (b.leafnode()) {
+      for (int y = b.y0; y < b.y1; ++y)
+        for (int x = b.x0; x < b.x1; ++x) {
+          int v = y * N + x;
+          if (!std::binary_search(b.bd.begin(), b.bd.end(), v)) b.I.push_back(v);
+        }
+    } else {
+      const auto &mu = nodes[b.lo], &nu = nodes[b.hi];
+      b.I.assign(mu.B.begin(), mu.B.begin() + mu.p0);
+      b.I.insert(b.I.end(), nu.B.begin(), nu.B.begin() + nu.p0);
+    }
+  }
+
+  s.perm.reserve((size_t)N * N);
+  for (auto &b : nodes) {
+    b.offset = (int)s.perm.size();
+    s.perm.insert(s.perm.end(), b.I.begin(), b.I.end());
+  }
+  s.iperm.assign((size_t)N * N, -1);
+  for (size_t k = 0; k < s.perm.size(); ++k) s.iperm[s.perm[k]] = (int)k;
+  return s;
+}
+
+ClusterTree interior_subtree(const NDNode &nd) {
+  const ClusterTree &ct = nd.ct;
+  if (ct.count() == 0 || nd.p0 == (int)nd.B.size()) return ct;
+  ClusterTree out;
+  std::vector<std::pair<int, int>> q{{ct.left[0], 0}};
+  for (size_t k = 0; k < q.size(); ++k) {
+    int c = q[k].first;
+    if (ct.left[c] >= 0) {
+      q.push_back({ct.left[c], q[k].second + 1});
+      q.push_back({ct.right[c], q[k].second + 1});
+    }
+  }
+  int nc = (int)q.size();
+  out.start.resize(nc); out.size.resize(nc); out.left.assign(nc, -1);
+  out.right.assign(nc, -1); out.level.resize(nc);
+  std::vector<int> num(ct.count(), -1);
+  for (int k = 0; k < nc; ++k) num[q[k].first] = k;
+  int base = ct.start[ct.left[0]];
+  for (int k = 0; k < nc; ++k) {
+    int c = q[k].first;
+    out.start[k] = ct.start[c] - base;
+    out.size[k] = ct.size[c];
+    out.level[k] = q[k].second;
+    if (ct.left[c] >= 0) { out.left[k] = num[ct.left[c]]; out.right[k] = num[ct.right[c]]; }
+  }
+  return out;
+}
+
+}  // namespace hssx

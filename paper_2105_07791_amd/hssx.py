@@ -1,0 +1,156 @@
+"""Python binding of the hssx C ABI: argument marshalling only.
+
+Device buffers are torch CUDA tensors (complex128 vectors, float64 fields),
+streams are torch streams; every computation runs in libhssx.so.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+from .symbolic import read_perm, read_tree
+
+__all__ = ["Operator", "Factor", "assemble", "factor", "gmres_solve"]
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _col_major(x, dtype):
+    """(n,) or (n, nrhs) tensor -> column-major (ptr, ld, nrhs, keepalive)."""
+    if x.dim() == 1:
+        x = x.reshape(-1, 1)
+    t = x.t().contiguous() if not x.t().is_contiguous() else x.t()
+    assert t.dtype == dtype and t.is_cuda
+    return t, x.shape[0], x.shape[1]
+
+
+class Operator:
+    """A(s) = K - omega^2 M[s^2] - i omega G[s] on the N x N P1 grid."""
+
+    def __init__(self, N, omega, slowness, device=0, stream=None):
+        s = torch.as_tensor(slowness, dtype=torch.float64, device=f"cuda:{device}").contiguous()
+        assert s.numel() == N * N
+        self.N, self.omega, self.n, self.device = N, float(omega), N * N, device
+        self.slowness = s
+        h = C.c_void_p()
+        desc = _lib.ProblemDesc(N, float(omega))
+        check(lib().hssx_assemble(device, C.byref(desc), C.c_void_p(s.data_ptr()),
+                                  _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._LIB is not None:
+            lib().hssx_op_destroy(self.handle)
+            self.handle = None
+
+    def load(self, f, stream=None):
+        """b = M f for nodal source samples f (n,) or (n, nrhs) float64."""
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.slowness.device)
+        ft, n, nrhs = _col_major(f, torch.float64)
+        b = torch.empty((nrhs, n), dtype=torch.complex128, device=f.device)
+        check(lib().hssx_load(self.handle, nrhs, C.c_void_p(ft.data_ptr()), n,
+                              C.c_void_p(b.data_ptr()), n, _stream(stream)))
+        return b.t() if f.dim() == 2 else b[0]
+
+    def matvec(self, x, stream=None):
+        xt, n, nrhs = _col_major(x, torch.complex128)
+        y = torch.empty((nrhs, n), dtype=torch.complex128, device=x.device)
+        check(lib().hssx_matvec(self.handle, 0, nrhs, C.c_void_p(xt.data_ptr()), n,
+                                C.c_void_p(y.data_ptr()), n, _stream(stream)))
+        return y.t() if x.dim() == 2 else y[0]
+
+    def csr(self):
+        """(rowptr, col, val) as numpy arrays (host copies)."""
+        nnz = C.c_long()
+        check(lib().hssx_get_csr(self.handle, None, None, None, C.byref(nnz), None))
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(2 * nnz.value, dtype=np.float64)
+        check(lib().hssx_get_csr(self.handle, rp.ctypes.data_as(_lib._ip),
+                                 col.ctypes.data_as(_lib._ip), val.ctypes.data_as(_lib._dp),
+                                 None, _stream()))
+        return rp, col, val.view(np.complex128)
+
+    def dAds_contract(self, lam, x, grad=None, stream=None):
+        """grad += -Re sum_rhs lam^T (dA/ds) x."""
+        lt, n, nrhs = _col_major(lam, torch.complex128)
+        xt, _, _ = _col_major(x, torch.complex128)
+        if grad is None:
+            grad = torch.zeros(n, dtype=torch.float64, device=lt.device)
+        check(lib().hssx_dAds_contract(self.handle, nrhs, C.c_void_p(lt.data_ptr()),
+                                       C.c_void_p(xt.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                       _stream(stream)))
+        return grad
+
+
+class Factor:
+    """Approximate factorization P = LDR of an Operator (Algorithm 3.4)."""
+
+    def __init__(self, A, tol=1e-6, leaf_size=32, beta=16, h_sw=4, k0=32, r=16,
+                 max_rounds=32, dtype="c128", seed=0, id_rel_tol=0.0, stream=None):
+        self.A = A
+        opts = _lib.FactorOpts(beta, h_sw, k0, r, max_rounds,
+                               _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64,
+                               seed, id_rel_tol)
+        h = C.c_void_p()
+        check(lib().hssx_factor(A.handle, float(tol), int(leaf_size), C.byref(opts),
+                                _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._LIB is not None:
+            lib().hssx_fact_destroy(self.handle)
+            self.handle = None
+
+    def apply(self, x, trans=False, stream=None):
+        xt, n, nrhs = _col_major(x, torch.complex128)
+        y = torch.empty((nrhs, n), dtype=torch.complex128, device=x.device)
+        check(lib().hssx_apply(self.handle, int(trans), nrhs, C.c_void_p(xt.data_ptr()), n,
+                               C.c_void_p(y.data_ptr()), n, _stream(stream)))
+        return y.t() if x.dim() == 2 else y[0]
+
+    def stats(self):
+        s = _lib.FactorStats()
+        check(lib().hssx_get_factor_stats(self.handle, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def perm(self):
+        return read_perm(self.handle, self.A.n)
+
+    def tree(self):
+        """Flattened elimination and cluster trees (see hssx_get_tree)."""
+        return read_tree(self.handle)
+
+    def schur(self, node, nb):
+        S = np.empty((nb, nb), dtype=np.complex128, order="F")
+        check(lib().hssx_get_schur(self.handle, int(node),
+                                   S.ctypes.data_as(_lib._dp), nb))
+        return S
+
+
+def gmres_solve(A, P, b, m=50, tol=1e-8, maxit=1000, flexible=False, trans=False, stream=None):
+    """Preconditioned restarted GMRES; returns (x, list of per-rhs stats)."""
+    bt, n, nrhs = _col_major(b, torch.complex128)
+    x = torch.empty((nrhs, n), dtype=torch.complex128, device=b.device)
+    opts = _lib.GmresOpts(m, tol, maxit, int(flexible))
+    stats = (_lib.GmresStats * nrhs)()
+    code = lib().hssx_gmres_solve(A.handle, P.handle if P is not None else None, int(trans), nrhs,
+                                  C.c_void_p(bt.data_ptr()), n, C.c_void_p(x.data_ptr()), n,
+                                  C.byref(opts), stats, _stream(stream))
+    check(code)
+    st = [dict(iters=s.iters, converged=bool(s.converged), prec_res=s.prec_res,
+               true_res=s.true_res) for s in stats]
+    return (x.t() if b.dim() == 2 else x[0]), st
+
+
+def assemble(N, omega, slowness, device=0):
+    return Operator(N, omega, slowness, device)
+
+
+def factor(A, tol=1e-6, leaf_size=32, **kw):
+    return Factor(A, tol, leaf_size, **kw)

@@ -1,0 +1,61 @@
+"""C-ABI library checks that need no GPU: every symbol declared in
+include/hssx.h is exported, and the library's host symbolic analysis equals
+the oracle's bit for bit (integer index work, Sec. 3.1-3.3)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import nd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2105_07791_amd", "libhssx.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhssx.so not built")
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hssx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hssx_[a-zA-Z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 15
+    L = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("N,leaf,beta", [(9, 8, 4), (17, 32, 16), (40, 20, 8), (65, 32, 16),
+                                         (100, 32, 16), (129, 24, 12), (513, 32, 16)])
+def test_symbolic_bit_exact(N, leaf, beta):
+    from paper_2105_07791_amd.symbolic import Analysis
+    an = Analysis(N, leaf, beta)
+    t = nd.build_nd(N, leaf, beta)
+    assert np.array_equal(an.perm(), t.perm)
+    tr = an.tree()
+    assert tr["info"].shape[0] == len(t.boxes)
+    for k, b in enumerate(t.boxes):
+        info = tr["info"][k]
+        assert list(info) == [b.x0, b.x1, b.y0, b.y1, b.lo, b.hi, b.parent, b.depth,
+                              b.height, b.p0], k
+        assert np.array_equal(tr["I"][tr["I_ptr"][k]:tr["I_ptr"][k + 1]], b.I), k
+        assert np.array_equal(tr["B"][tr["B_ptr"][k]:tr["B_ptr"][k + 1]], b.B), k
+        cl = tr["clusters"][tr["c_ptr"][k]:tr["c_ptr"][k + 1]]
+        ct = b.ctree
+        ref = np.stack([ct.start, ct.size, ct.left, ct.right, ct.level], axis=1) \
+            if ct.nclusters else np.zeros((0, 5))
+        assert np.array_equal(cl, ref), k
+
+
+def test_invalid_arguments_rejected():
+    from paper_2105_07791_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.hssx_analyze(1, 32, 16, ctypes.byref(h)) == -1
+    assert b"invalid" in L.hssx_last_error()
+    assert L.hssx_analyze(9, 0, 16, ctypes.byref(h)) == -1
