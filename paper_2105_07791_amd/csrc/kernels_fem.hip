@@ -3,10 +3,11 @@
 //
 // A = K - omega^2 M[s^2] - i omega G[s] in CSR with the fixed 7-point
 // pattern (columns sorted: -N-1, -N, -1, 0, +1, +N, +N+1).  Each thread
-// builds one row by visiting the four cells around its node in global cell
-// order (triangle SW-SE-NE before SW-NE-NW) and then the boundary edges in
-// global edge order, so entry (i,j) and (j,i) add the same terms in the same
-// order: A is bitwise symmetric and the assembly uses no atomics.
+// builds one row; entry (i,j) is evaluated for the ordered pair
+// (lo, hi) = (min, max) by visiting the four cells around lo in global cell
+// order (triangle SW-SE-NE before SW-NE-NW) and then the boundary edge they
+// share, so (i,j) and (j,i) run the identical computation: A is bitwise
+// symmetric and the assembly uses no atomics.
 //
 // Closed forms (barycentric monomials): int_T l_l l_a l_b = 2|T| * {1/20 if
 // l=a=b, 1/60 if two equal, 1/120 if distinct}; int_e l_l l_a l_b = |e| *
@@ -112,17 +113,19 @@ __global__ void assemble_kernel(int N, double omega, const double *__restrict__ 
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * N) return;
   double h = 1.0 / (N - 1);
-  int xi = i % N, yi = i / N;
   for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-    int j = col[p];
+    // entry (i, j) and (j, i) run the identical computation on the ordered
+    // pair (lo, hi), so the matrix is symmetric bit for bit
+    const int lo = min(i, col[p]), hi = max(i, col[p]);
+    const int xl = lo % N, yl = lo / N;
     double k = 0.0, m = 0.0, m1 = 0.0;
-    // cells around node i in global cell order
-    for (int cy = yi - 1; cy <= yi; ++cy)
-      for (int cx = xi - 1; cx <= xi; ++cx) {
+    // cells around node lo in global cell order
+    for (int cy = yl - 1; cy <= yl; ++cy)
+      for (int cx = xl - 1; cx <= xl; ++cx) {
         if (cx < 0 || cy < 0 || cx >= N - 1 || cy >= N - 1) continue;
         for (int t = 0; t < 2; ++t) {
           Tri T = cell_tri(N, cx, cy, t);
-          int a = local_index(T, i), b = local_index(T, j);
+          int a = local_index(T, lo), b = local_index(T, hi);
           if (a < 0 || b < 0) continue;
           double kk, mm, mm1;
           tri_terms(N, h, T, a, b, s, kk, mm, mm1);
@@ -131,7 +134,7 @@ __global__ void assemble_kernel(int N, double omega, const double *__restrict__ 
           m1 += mm1;
         }
       }
-    double g = edge_terms(N, h, i, j, s);
+    double g = edge_terms(N, h, lo, hi, s);
     val[p] = mk(k - omega * omega * m, -omega * g);
     mval[p] = m1;
   }
