@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the preconditioned solve on one MI355X.
+
+Workload (default): 2D Helmholtz, P1 on a 513 x 513 node grid (263,169 DOFs),
+omega = 100, unit wave speed, absorbing boundary, 64 seeded Gaussian sources
+(width 0.02) solved together.  One step = numeric factorization P = LDR
+(complex64 factors, HSS tolerance 1e-6, ND leaves <= 32 DOFs, HSS leaves 16,
+switching height 4) + flexible GMRES(50) in FP64 to a true relative residual
+of 1e-8 for all 64 right-hand sides.  The operator and the right-hand sides
+are resident in HBM before the timed region.
+
+Printed: one JSON line with the metric (seconds per factor+solve, lower is
+better), GMRES iterations, the FP64 plain form (complex128 factors, left
+GMRES, right-hand sides solved one at a time) for comparison, the roofline
+of the dominant kernel from HIP events, and the oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "factor+solve s to 1e-8 residual, GMRES iters; FP64 plain vs mixed/batched"
+WORKLOAD = "helmholtz_p1_513_x64"
+PEAKS = {  # MI355X published peaks
+    "hbm": (8000.0, "GB/s"),
+    "alu_f32": (157.3, "TFLOP/s"),
+    "alu_f64": (78.6, "TFLOP/s"),
+}
+KERNELS = ["front_eliminate", "front_assemble", "compress_level", "hss_matvec", "sample",
+           "apply_up", "apply_down", "spmv"]
+BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "spmv"}
+
+
+def cpu_baseline_child(workload):
+    """Oracle (exact nested-dissection factor + solve of all right-hand sides)
+    on the same workload; prints a JSON line."""
+    import numpy as np
+    from oracle import exact, fem, nd
+    from synth import make_problem
+    pr = make_problem(workload)
+    A = fem.assemble_helmholtz(pr.N, pr.omega, pr.slowness)
+    t = nd.build_nd(pr.N, pr.leaf_dofs, pr.beta)
+    b = (fem.mass_matrix(pr.N) @ pr.f).astype(np.complex128)
+    t0 = time.perf_counter()
+    f = exact.factor_exact(A, t, keep_S=False)
+    x = f.apply(b)
+    t1 = time.perf_counter()
+    res = float(np.max(np.linalg.norm(A @ x - b, axis=0) / np.linalg.norm(b, axis=0)))
+    print(json.dumps({"seconds": t1 - t0, "true_res": res}))
+
+
+def run_cpu_baseline(workload):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                        "--workload", workload], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["seconds"], "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"full {workload}: exact nested-dissection factorization (no compression) "
+                      f"+ solve of all right-hand sides, float64, one thread "
+                      f"(true residual {d['true_res']:.1e})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true")
+    args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.workload)
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import ctypes
+    import torch
+    from paper_2105_07791_amd import _lib, hssx
+    from synth import make_problem
+
+    pr = make_problem(args.workload)
+    dev = torch.device("cuda:0")
+    A = hssx.Operator(pr.N, pr.omega, pr.slowness)
+    b = A.load(torch.tensor(pr.f, device=dev))
+    torch.cuda.synchronize()
+    L = _lib.lib()
+
+    def step(dtype, flexible, tol_hss=pr.tol):
+        P = hssx.Factor(A, tol=tol_hss, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
+                        dtype=dtype, seed=1)
+        x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol, flexible=flexible)
+        return P, x, st
+
+    print(f"[bench] {args.workload}: n={pr.n} nrhs={pr.nrhs} warmup={args.warmup} "
+          f"steps={args.steps}", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        step("c64", True)
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    _lib.check(L.hssx_prof_enable(1))
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        P, x, st = step("c64", True)
+        torch.cuda.synchronize()
+        results.append((P.stats(), st, time.perf_counter() - ts))
+        print(f"[bench] step {k} {results[-1][2]:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+
+    kern = {}
+    for name in KERNELS:
+        ms, n, work = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
+        _lib.check(L.hssx_prof_query(name.encode(), ctypes.byref(ms), ctypes.byref(n),
+                                     ctypes.byref(work)))
+        kern[name] = (ms.value, n.value, work.value)
+    _lib.check(L.hssx_prof_enable(0))
+
+    # verification of the last step against the true residual
+    r = A.matvec(x) - b
+    true_res = (torch.linalg.vector_norm(r, dim=0) / torch.linalg.vector_norm(b, dim=0)).max().item()
+    fstats, gst, _ = results[-1]
+    iters = [s["iters"] for s in gst]
+
+    # dominant kernel (largest event time per step) and its roofline
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, nl, work = kern[dom]
+    avg_s = ms / 1e3 / max(nl, 1)
+    per_launch = work / max(nl, 1)
+    if dom in BYTE_KERNELS:
+        bound, (peak, unit) = "hbm", PEAKS["hbm"]
+        achieved = per_launch / avg_s / 1e9
+    else:
+        bound, (peak, unit) = "alu", PEAKS["alu_f32"]
+        achieved = per_launch / avg_s / 1e12
+    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
+            "avg_launch_us": avg_s * 1e6}
+    kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in kern.items()}
+
+    plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        Pp = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
+                         dtype="c128", seed=1)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        pit = []
+        xs = []
+        for rr in range(pr.nrhs):
+            xr, sr = hssx.gmres_solve(A, Pp, b[:, rr].contiguous(), m=pr.gmres_m,
+                                      tol=pr.gmres_tol, flexible=False)
+            pit.append(sr[0]["iters"])
+            xs.append(xr)
+        torch.cuda.synchronize()
+        tp2 = time.perf_counter()
+        xp = torch.stack(xs, dim=1)
+        rp = (torch.linalg.vector_norm(A.matvec(xp) - b, dim=0)
+              / torch.linalg.vector_norm(b, dim=0)).max().item()
+        dx = (torch.linalg.vector_norm(x - xp, dim=0)
+              / torch.linalg.vector_norm(xp, dim=0)).max().item()
+        plain = {"seconds": tp2 - tp0, "factor_s": tp1 - tp0, "solve_s": tp2 - tp1,
+                 "iters_max": max(pit), "true_res_max": rp, "factor_dtype": "c128",
+                 "gmres": "left GMRES(50), one rhs at a time",
+                 "mixed_vs_plain_rel_diff_max": dx}
+        print(f"[bench] plain fp64 form {tp2 - tp0:.3f}s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] oracle on the host ...", file=sys.stderr, flush=True)
+        cpu = run_cpu_baseline(args.workload)
+
+    out = {
+        "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 factor / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": pr.N, "n": pr.n, "omega": pr.omega,
+                   "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": pr.tol,
+                   "nd_leaf_dofs": pr.leaf_dofs, "hss_leaf": pr.beta, "h_sw": pr.h_sw,
+                   "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
+        "gmres_iters_max": max(iters), "gmres_iters_mean": sum(iters) / len(iters),
+        "true_res_max": true_res, "factor_ms": fstats["ms_numeric"],
+        "k_max": fstats["k_max"], "factor_bytes": fstats["factor_bytes"],
+        "kernel_ms_per_step": kernel_ms,
+        "plain_fp64": plain,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -198,6 +198,20 @@ hssx_status hssx_get_factor_stats(hssx_fact P, hssx_factor_stats *s);
  * host memory.  For tests.  Synchronises. */
 hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld);
 
+/* Measurement support.  hssx_prof_enable(1) clears the records and starts
+ * bracketing the main kernels with HIP events on their launch stream;
+ * hssx_prof_query returns, for one kernel name, the summed event time (ms),
+ * the number of launches and the summed algorithmic work of those launches:
+ *   "front_eliminate"  flops (8 per complex multiply-add of Gauss-Jordan)
+ *   "front_assemble"   bytes written
+ *   "apply_up", "apply_down"  bytes of factor blocks and vectors moved
+ *   "spmv"             bytes of CSR arrays and vectors moved
+ *   "compress_level", "hss_matvec", "sample"  flops (nominal)
+ * Unknown names report zero launches. */
+hssx_status hssx_prof_enable(int on);
+hssx_status hssx_prof_query(const char *kernel, double *ms, long *launches,
+                            double *work);
+
 void hssx_fact_destroy(hssx_fact P);
 void hssx_op_destroy(hssx_op A);
 const char *hssx_last_error(void);

@@ -63,6 +63,8 @@ SIGNATURES = {
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),
     "hssx_get_schur": (_i, [_vp, _i, _dp, _l]),
+    "hssx_prof_enable": (_i, [_i]),
+    "hssx_prof_query": (_i, [C.c_char_p, _dp, C.POINTER(_l), _dp]),
     "hssx_fact_destroy": (None, [_vp]),
     "hssx_op_destroy": (None, [_vp]),
     "hssx_last_error": (C.c_char_p, []),

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "engine.h"
+#include "prof.h"
 
 using namespace hssx;
 
@@ -212,12 +213,25 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->depth_max_ni.assign(sym.max_depth + 1, 0);
     P->depth_max_nb.assign(sym.max_depth + 1, 0);
     P->depth_max_f.assign(sym.max_depth + 1, 0);
+    const int D1 = sym.max_depth + 1;
+    P->up_fbytes.assign(D1, 0); P->up_velems.assign(D1, 0);
+    P->down_fbytes.assign(D1, 0); P->down_velems.assign(D1, 0); P->asm_bytes.assign(D1, 0);
     for (int d = 0; d <= sym.max_depth; ++d) {
       upload(P->depth_dev[d], P->depth_nodes[d]);
       for (int k : P->depth_nodes[d]) {
-        P->depth_max_ni[d] = std::max(P->depth_max_ni[d], dsc[k].ni);
-        P->depth_max_nb[d] = std::max(P->depth_max_nb[d], dsc[k].nb);
-        P->depth_max_f[d] = std::max(P->depth_max_f[d], dsc[k].f);
+        const FrontDesc &q = dsc[k];
+        P->depth_max_ni[d] = std::max(P->depth_max_ni[d], q.ni);
+        P->depth_max_nb[d] = std::max(P->depth_max_nb[d], q.nb);
+        P->depth_max_f[d] = std::max(P->depth_max_f[d], q.f);
+        if (q.ni) {
+          P->up_fbytes[d] += (double)q.f * q.ni * esz;          // [A_ii^-1; L]
+          P->up_velems[d] += 2.0 * q.ni + 2.0 * q.nb;           // t in, x(I) out, x(B) rw
+          if (q.nb) {
+            P->down_fbytes[d] += (double)q.ni * q.nb * esz;     // R
+            P->down_velems[d] += q.nb + 2.0 * q.ni;             // x(B) in, x(I) rw
+          }
+        }
+        P->asm_bytes[d] += (double)q.f * (q.f + q.ni) * esz;
       }
     }
     P->front.alloc(std::max(1L, foff) * esz);
@@ -369,6 +383,17 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
         S_host[2 * (i + (long)j * ld)] = re;
         S_host[2 * (i + (long)j * ld) + 1] = im;
       }
+  });
+}
+
+hssx_status hssx_prof_enable(int on) {
+  return guarded([&] { prof_enable(on != 0); });
+}
+
+hssx_status hssx_prof_query(const char *kernel, double *ms, long *launches, double *work) {
+  return guarded([&] {
+    HSSX_CHECK(kernel, HSSX_EINVAL, "null kernel name");
+    prof_query(kernel, ms, launches, work);
   });
 }
 

@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "prof.h"
 #include "symbolic.h"
 
 struct hssx_op_ {
@@ -31,6 +32,8 @@ struct hssx_fact_ {
   std::vector<std::vector<int>> depth_nodes;
   std::vector<hssx::DevBuf> depth_dev;
   std::vector<int> depth_max_ni, depth_max_nb, depth_max_f;
+  // per depth: factor bytes and vector elements (per rhs) the apply moves
+  std::vector<double> up_fbytes, up_velems, down_fbytes, down_velems, asm_bytes;
   hssx_factor_stats stats{};
   std::vector<int> node_rank;   // largest compressed rank per node (stats)
   hssx::DevBuf work;            // apply workspace (elimination-order vectors)

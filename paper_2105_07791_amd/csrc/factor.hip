@@ -133,7 +133,11 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     upload(dg, gj);
     upload(ds, sj);
     launch_gaussian((int)gj.size(), dg.as<GaussJob>(), o.seed, mm, mc, st);
+    double sflops = 0;
+    for (const auto &q : sj) sflops += 4.0 * q.m * (double)q.m * q.nc;
+    hipEvent_t ps = prof_begin(st);
     launch_sample<T>((int)sj.size(), ds.as<SampleJob<T>>(), mm, mc, st);
+    prof_end("sample", st, ps, sflops);
     HSSX_HIP(hipStreamSynchronize(st));
   };
 
@@ -204,10 +208,12 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       if (items.empty()) continue;
       DevBuf d_items;
       upload(d_items, items);
+      hipEvent_t pc = prof_begin(st);
       launch_compress_level<T>((int)items.size(), d_items.as<HssItem>(), d_inst.as<HssInstance>(),
                                d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_ipool.as<int>(),
                                d_rank.as<int>(), base, Y.as<cplx<T>>(), Om.as<double>(),
                                d_scr.as<cplx<T>>(), id_tol, st);
+      prof_end("compress_level", st, pc, 0.0);
       HSSX_HIP(hipStreamSynchronize(st));
     }
 
@@ -235,9 +241,11 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     upload(d_mj, mj);
     d_xh.alloc(std::max(1L, (long)mj.size() * xh_per_job_max) * sizeof(cplx<T>));
     HSSX_CHECK(r <= 64, HSSX_EINVAL, "probe block wider than 64 columns");
+    hipEvent_t pm = prof_begin(st);
     launch_hss_matvec<T>((int)mj.size(), d_mj.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
                          d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
                          d_xh.as<cplx<T>>(), st);
+    prof_end("hss_matvec", st, pm, 0.0);
     std::vector<double> h_err(2 * tasks.size());
     std::vector<int> h_rank(cls.size());
     HSSX_HIP(hipMemcpyAsync(h_err.data(), d_err, h_err.size() * sizeof(double),
@@ -284,13 +292,23 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       DevBuf d_ej, d_xh2;
       upload(d_ej, ej);
       d_xh2.alloc(std::max(1L, (long)ej.size() * xh_per_job_max) * sizeof(cplx<T>));
+      hipEvent_t pm2 = prof_begin(st);
       launch_hss_matvec<T>((int)ej.size(), d_ej.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
                            d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
                            d_xh2.as<cplx<T>>(), st);
+      prof_end("hss_matvec", st, pm2, 0.0);
       HSSX_HIP(hipStreamSynchronize(st));
     }
     active.swap(next);
   }
+}
+
+// Gauss-Jordan flops: 8 per complex multiply-add over the reduced rows
+template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
+  double f = 0;
+  for (const auto &j : jobs)
+    for (int p = 0; p < j.ne; ++p) f += 8.0 * (j.m - 1) * (double)(j.ncols - p - 1);
+  return f;
 }
 
 template <typename T>
@@ -312,9 +330,11 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     const auto &nodes = P.depth_nodes[d];
     if (nodes.empty()) continue;
     const int cnt = (int)nodes.size();
+    hipEvent_t pa = prof_begin(st);
     launch_front_assemble<T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
                              P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
                              A.col.as<int>(), A.val.as<c128>(), F, st, P.depth_max_f[d]);
+    prof_end("front_assemble", st, pa, P.asm_bytes[d]);
 
     // ---- HSS-arithmetic interiors: compress S~ and substitute it (Alg. 3.3)
     std::vector<int> hn;
@@ -364,7 +384,9 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       upload(dcp, cp);
       upload(dej, ej);
       launch_axpby<T>((int)cp.size(), dcp.as<AxpbyJob<T>>(), mm, mm, st);
+      hipEvent_t pe = prof_begin(st);
       launch_eliminate<T>((int)ej.size(), dej.as<ElimJob<T>>(), err.as<int>(), st);
+      prof_end("front_eliminate", st, pe, elim_flops(ej));
       HSSX_HIP(hipStreamSynchronize(st));
       compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
       std::vector<AxpbyJob<T>> fix;
@@ -400,7 +422,9 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     }
     DevBuf dj;
     upload(dj, jobs);
+    hipEvent_t pe = prof_begin(st);
     launch_eliminate<T>((int)jobs.size(), dj.as<ElimJob<T>>(), err.as<int>(), st);
+    prof_end("front_eliminate", st, pe, elim_flops(jobs));
 
     // ---- compress the Schur complements the parents will use in HSS form
     std::vector<CompressTask<T>> tasks;
@@ -473,22 +497,26 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
   for (int d = D; d >= 0; --d) {
     int cnt = (int)P.depth_nodes[d].size();
     if (!cnt) continue;
+    hipEvent_t pu = prof_begin(st);
     if (P.dtype == HSSX_C128)
       launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
                               P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
     else
       launch_apply_up<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
                              P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
+    prof_end("apply_up", st, pu, P.up_fbytes[d] + P.up_velems[d] * nrhs * sizeof(c128));
   }
   for (int d = 0; d <= D; ++d) {
     int cnt = (int)P.depth_nodes[d].size();
     if (!cnt) continue;
+    hipEvent_t pd = prof_begin(st);
     if (P.dtype == HSSX_C128)
       launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
                                 P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
     else
       launch_apply_down<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
                                P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
+    prof_end("apply_down", st, pd, P.down_fbytes[d] + P.down_velems[d] * nrhs * sizeof(c128));
   }
   launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);
 }

@@ -27,7 +27,10 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
     else HSSX_HIP(hipMemcpyAsync(out, in, blk * sizeof(c128), hipMemcpyDeviceToDevice, st));
   };
   auto matvec = [&](const c128 *in, c128 *out) {
+    hipEvent_t pe = prof_begin(st);
     launch_spmv(n, nrhs, A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), in, n, out, n, st);
+    // CSR values + column indices once, row pointers, x read and y written per rhs
+    prof_end("spmv", st, pe, A.nnz * 20.0 + (n + 1) * 4.0 + 2.0 * blk * sizeof(c128));
   };
   DevBuf V, Z, w, t1, H, cs, sn, g, y, hcol, h2, hn, res, cnt, act, part, partd, nrm, xc, bc;
   V.alloc((size_t)(m + 1) * blk * sizeof(c128));
