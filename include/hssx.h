@@ -76,7 +76,8 @@ typedef struct {
   hssx_dtype dtype; /* factor storage / arithmetic: C128 or C64 */
   uint32_t seed;    /* key of the counter-based sketch generator */
   double id_rel_tol;/* relative pivot threshold of the interpolative
-                       decomposition; <= 0 selects 1e-2 * tol */
+                       decomposition; <= 0 selects max(1e-2 * tol,
+                       4 * unit roundoff of the factor dtype) */
 } hssx_factor_opts;
 
 typedef struct {

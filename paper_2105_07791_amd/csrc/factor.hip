@@ -275,12 +275,14 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
         continue;
       }
       t.done = true;
-      for (int c0 = 0; c0 < t.m; c0 += 64) {
+      // expansion H I in 16-column blocks: more workgroups for the few large
+      // instances near the root
+      for (int c0 = 0; c0 < t.m; c0 += 16) {
         MatvecJob<T> j{};
         j.inst = (int)a;
         j.X = nullptr;
         j.c0 = c0;
-        j.nc = std::min(64, t.m - c0);
+        j.nc = std::min(16, t.m - c0);
         j.out = t.target + (long)c0 * t.ldT;
         j.ldO = t.ldT;
         j.Yref = nullptr;
@@ -311,6 +313,84 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
   return f;
 }
 
+// Gauss-Jordan elimination of a batch of jobs: fronts with few pivots run in
+// one workgroup each; larger ones go panel by panel (32 columns) through the
+// blocked sequence, all fronts of the batch advancing together.
+template <typename T>
+void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, hipStream_t st) {
+  constexpr int NB = 32, kSmall = 64;
+  std::vector<ElimJob<T>> small, big;
+  for (const auto &j : jobs) (j.ne < kSmall ? small : big).push_back(j);
+  if (!small.empty()) {
+    DevBuf d;
+    upload(d, small);
+    launch_eliminate<T>((int)small.size(), d.as<ElimJob<T>>(), err, st);
+    HSSX_HIP(hipStreamSynchronize(st));
+  }
+  if (big.empty()) return;
+  // scratch per job: pivots, G, Y, W
+  long ysz = 0, wsz = 0;
+  std::vector<long> yo, wo;
+  int steps = 0;
+  for (const auto &j : big) {
+    yo.push_back(ysz);
+    wo.push_back(wsz);
+    ysz += (long)NB * j.ncols;
+    wsz += (long)j.ne * NB;
+    steps = std::max(steps, ceil_div(j.ne, NB));
+  }
+  DevBuf piv, G, Y, W;
+  piv.alloc(big.size() * NB * sizeof(int));
+  G.alloc(big.size() * NB * NB * sizeof(cplx<T>));
+  Y.alloc(ysz * sizeof(cplx<T>));
+  W.alloc(wsz * sizeof(cplx<T>));
+  for (int k = 0; k < steps; ++k) {
+    std::vector<PanelJob<T>> pj;
+    int mm = 0, mc = 0;
+    for (size_t a = 0; a < big.size(); ++a) {
+      const auto &j = big[a];
+      int p0 = k * NB;
+      if (p0 >= j.ne) continue;
+      PanelJob<T> q;
+      q.F = j.ptr;
+      q.ld = j.ld;
+      q.m = j.m;
+      q.ncols = j.ncols;
+      q.ne = j.ne;
+      q.p0 = p0;
+      q.nb = std::min(NB, j.ne - p0);
+      q.piv = piv.as<int>() + a * NB;
+      q.G = G.as<cplx<T>>() + a * NB * NB;
+      q.Y = Y.as<cplx<T>>() + yo[a];
+      q.W = W.as<cplx<T>>() + wo[a];
+      q.node = j.node;
+      pj.push_back(q);
+      mm = std::max(mm, j.m);
+      mc = std::max(mc, j.ncols - p0);
+    }
+    DevBuf d;
+    upload(d, pj);
+    launch_panel_step<T>((int)pj.size(), d.as<PanelJob<T>>(), mm, mc, err, st);
+    HSSX_HIP(hipStreamSynchronize(st));
+  }
+  // R = -(A_ii^-1 A_ib): negate the block F(0:ne, ne:m)
+  std::vector<AxpbyJob<T>> neg;
+  int nm = 0, nn = 0;
+  for (const auto &j : big) {
+    if (!j.negate_r || j.m == j.ne) continue;
+    cplx<T> *R = j.ptr + (long)j.ne * j.ld;
+    neg.push_back(AxpbyJob<T>{R, R, nullptr, j.ld, j.ld, 0, j.ne, j.m - j.ne, (T)-2, (T)0});
+    nm = std::max(nm, j.ne);
+    nn = std::max(nn, j.m - j.ne);
+  }
+  if (!neg.empty()) {
+    DevBuf d;
+    upload(d, neg);
+    launch_axpby<T>((int)neg.size(), d.as<AxpbyJob<T>>(), nm, nn, st);
+    HSSX_HIP(hipStreamSynchronize(st));
+  }
+}
+
 template <typename T>
 void factor_impl(hssx_fact_ &P, hipStream_t st) {
   hssx_op_ &A = *P.A;
@@ -318,7 +398,11 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
   const int root = sym.root();
   cplx<T> *F = P.front.as<cplx<T>>();
   const FrontDesc *desc = P.desc.as<FrontDesc>();
-  const double id_tol = P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : 1e-2 * P.tol;
+  // default pivot threshold of the interpolative decomposition: 1e-2 tol,
+  // but not below the working precision's noise level
+  const double eps = sizeof(T) == sizeof(float) ? 1.1920929e-7 : 2.220446049250313e-16;
+  const double id_tol =
+      P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : std::max(1e-2 * P.tol, 4.0 * eps);
   DevBuf err;
   err.alloc(sizeof(int));
   int minus1 = -1;
@@ -380,12 +464,11 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       }
       // G := 0 then G += A_ii
       HSSX_HIP(hipMemsetAsync(G.p, 0, G.bytes, st));
-      DevBuf dcp, dej;
+      DevBuf dcp;
       upload(dcp, cp);
-      upload(dej, ej);
       launch_axpby<T>((int)cp.size(), dcp.as<AxpbyJob<T>>(), mm, mm, st);
       hipEvent_t pe = prof_begin(st);
-      launch_eliminate<T>((int)ej.size(), dej.as<ElimJob<T>>(), err.as<int>(), st);
+      eliminate_jobs<T>(ej, err.as<int>(), st);
       prof_end("front_eliminate", st, pe, elim_flops(ej));
       HSSX_HIP(hipStreamSynchronize(st));
       compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
@@ -420,10 +503,8 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       const FrontDesc &fd = P.h_desc[k];
       jobs.push_back(ElimJob<T>{F + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
     }
-    DevBuf dj;
-    upload(dj, jobs);
     hipEvent_t pe = prof_begin(st);
-    launch_eliminate<T>((int)jobs.size(), dj.as<ElimJob<T>>(), err.as<int>(), st);
+    eliminate_jobs<T>(jobs, err.as<int>(), st);
     prof_end("front_eliminate", st, pe, elim_flops(jobs));
 
     // ---- compress the Schur complements the parents will use in HSS form
@@ -487,10 +568,11 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
   const int n = P.A->n;
   if (P.work_cols < (size_t)nrhs) {
     HSSX_HIP(hipStreamSynchronize(st));
-    P.work.alloc((size_t)n * nrhs * sizeof(c128));
+    P.work.alloc((size_t)2 * n * nrhs * sizeof(c128));
     P.work_cols = nrhs;
   }
   c128 *w = P.work.as<c128>();
+  c128 *tb = w + (size_t)n * nrhs;
   launch_permute(n, nrhs, P.perm.as<int>(), x, ldx, w, n, 0, st);
   const FrontDesc *desc = P.desc.as<FrontDesc>();
   const int D = P.sym.max_depth;
@@ -500,10 +582,12 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     hipEvent_t pu = prof_begin(st);
     if (P.dtype == HSSX_C128)
       launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
-                              P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
+                              P.bpos.as<int>(), tb, w, n, nrhs, trans, P.depth_max_ni[d],
+                              P.depth_max_f[d], st);
     else
       launch_apply_up<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
-                             P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_ni[d], st);
+                             P.bpos.as<int>(), tb, w, n, nrhs, trans, P.depth_max_ni[d],
+                             P.depth_max_f[d], st);
     prof_end("apply_up", st, pu, P.up_fbytes[d] + P.up_velems[d] * nrhs * sizeof(c128));
   }
   for (int d = 0; d <= D; ++d) {
@@ -512,10 +596,12 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     hipEvent_t pd = prof_begin(st);
     if (P.dtype == HSSX_C128)
       launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
-                                P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
+                                P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d],
+                                P.depth_max_ni[d], st);
     else
       launch_apply_down<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
-                               P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d], st);
+                               P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d],
+                               P.depth_max_ni[d], st);
     prof_end("apply_down", st, pd, P.down_fbytes[d] + P.down_velems[d] * nrhs * sizeof(c128));
   }
   launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);

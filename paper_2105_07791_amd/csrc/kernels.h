@@ -58,6 +58,26 @@ template <typename T> struct ElimJob {
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st);
 
+// Blocked Gauss-Jordan, one column panel P = [p0, p0 + nb) of one job per
+// entry (jobs of one launch may belong to different fronts):
+//   panel:  pivots of P by partial-pivoted LU of rows [p0, ne) (scratch W),
+//           G = (pivot block)^-1
+//   swap:   apply the nb row interchanges to columns [p0, ncols)
+//   gemm_a: Y = G F(P rows, J), J = [p0 + nb, ncols)
+//   gemm_b: F(P rows, J) = Y;  F(other rows, J) -= F(other rows, P) Y
+template <typename T> struct PanelJob {
+  cplx<T> *F;
+  int ld, m, ncols, ne, p0, nb;
+  int *piv;        // nb pivot rows
+  cplx<T> *G;      // nb x nb
+  cplx<T> *Y;      // nb x (ncols - p0 - nb)
+  cplx<T> *W;      // (ne - p0) x nb
+  int node;
+};
+template <typename T>
+void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_cols,
+                       int *err_node, hipStream_t st);
+
 // dst(i,j) += a * src1(i,j) + b * src2(i,j) for an m x n block (all column-major)
 template <typename T> struct AxpbyJob {
   cplx<T> *dst;
@@ -150,16 +170,17 @@ void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *i
 void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c128 *y,
                     long ldy, int inverse, hipStream_t st);
 // Up-sweep of one tree depth: t = x(I); x(I) = A_ii^-1 t; x(B) += L t
-// (trans: A_ii^-T t and R^T t).  x is in elimination order (ld n).
+// (trans: A_ii^-T t and R^T t).  x is in elimination order (ld n); tb is an
+// n x nrhs staging buffer that receives a copy of the I blocks first.
 template <typename T>
 void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
-                     const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
-                     hipStream_t st);
+                     const int *bpos, c128 *tb, c128 *x, int n, int nrhs, int trans, int max_ni,
+                     int max_f, hipStream_t st);
 // Down-sweep of one tree depth: x(I) += R x(B) (trans: L^T x(B)).
 template <typename T>
 void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
-                       const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
-                       hipStream_t st);
+                       const int *bpos, c128 *x, int n, int nrhs, int trans, int max_nb,
+                       int max_ni, hipStream_t st);
 
 // ------------------------------------------------------------ Krylov
 // h[i*nrhs + r] = sum_k conj(V_i[k, r]) w[k, r], i < cnt; V_i at V + i*stride

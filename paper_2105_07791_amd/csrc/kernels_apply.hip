@@ -32,31 +32,48 @@ __global__ void permute_kernel(int n, int nrhs, const int *__restrict__ perm,
   else y[k + r * ldy] = x[perm[k] + r * ldx];
 }
 
-// grid: (node in batch, rhs chunk); dynamic LDS holds t (ni x rc)
+constexpr int kRows = 64;   // output rows per workgroup
+
+// copy the I blocks of one depth's nodes into the staging buffer (same
+// positions), so that the up-sweep can overwrite x(I) while other
+// workgroups of the same node still read t
+__global__ void stage_kernel(const int *__restrict__ nodes, const FrontDesc *__restrict__ desc,
+                             const c128 *__restrict__ x, c128 *__restrict__ tb, int n, int nrhs) {
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  long e = blockIdx.y * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)d.ni * nrhs) return;
+  int i = (int)(e % d.ni), r = (int)(e / d.ni);
+  long pos = d.ioff + i + (long)r * n;
+  tb[pos] = x[pos];
+}
+
+// grid: (node, row tile of [0, f), rhs chunk); LDS holds t = x(I) (ni x rc)
 template <typename T>
 __global__ __launch_bounds__(kT) void apply_up_kernel(const int *__restrict__ nodes,
                                                       const FrontDesc *__restrict__ desc,
                                                       const cplx<T> *__restrict__ pool,
                                                       const int *__restrict__ bpos,
+                                                      const c128 *__restrict__ tb,
                                                       c128 *__restrict__ x, int n, int nrhs,
                                                       int trans, int rc) {
   extern __shared__ c128 tsh[];
   const FrontDesc d = desc[nodes[blockIdx.x]];
-  const int ni = d.ni, nb = d.nb, f = d.f;
-  if (ni == 0) return;
-  const int r0 = blockIdx.y * rc;
+  const int ni = d.ni, f = d.f;
+  const int i0 = blockIdx.y * kRows;
+  if (ni == 0 || i0 >= f) return;
+  const int r0 = blockIdx.z * rc;
   const int nr = min(rc, nrhs - r0);
   if (nr <= 0) return;
   const cplx<T> *F = pool + d.foff;
   const int *bp = bpos + d.bpos_off;
   for (int e = threadIdx.x; e < ni * nr; e += kT) {
     int i = e % ni, r = e / ni;
-    tsh[e] = x[d.ioff + i + (long)(r0 + r) * n];
+    tsh[e] = tb[d.ioff + i + (long)(r0 + r) * n];
   }
   __syncthreads();
-  // outputs: rows [0, ni) -> x(I) (replaced), rows [ni, f) -> x(B) (accumulated)
-  for (int e = threadIdx.x; e < f * nr; e += kT) {
-    int i = e % f, r = e / f;
+  const int i = i0 + threadIdx.x % kRows;
+  if (i >= f) return;
+  for (int r = threadIdx.x / kRows; r < nr; r += kT / kRows) {
     c128 acc = czero<double>();
     const c128 *t = tsh + (long)r * ni;
     if (!trans) {
@@ -67,7 +84,7 @@ __global__ __launch_bounds__(kT) void apply_up_kernel(const int *__restrict__ no
       for (int l = 0; l < ni; ++l) cfma(acc, ccast<double>(F[l + (long)(f + i) * f]), t[l]);
     } else {
       // R^T(b, l) = F(l, ni + b)
-      int b = i - ni;
+      const int b = i - ni;
       for (int l = 0; l < ni; ++l) cfma(acc, ccast<double>(F[l + (long)(ni + b) * f]), t[l]);
     }
     if (i < ni) {
@@ -77,9 +94,9 @@ __global__ __launch_bounds__(kT) void apply_up_kernel(const int *__restrict__ no
       x[pos] = x[pos] + acc;
     }
   }
-  (void)nb;
 }
 
+// grid: (node, row tile of [0, ni), rhs chunk); LDS holds x(B) (nb x rc)
 template <typename T>
 __global__ __launch_bounds__(kT) void apply_down_kernel(const int *__restrict__ nodes,
                                                         const FrontDesc *__restrict__ desc,
@@ -90,8 +107,9 @@ __global__ __launch_bounds__(kT) void apply_down_kernel(const int *__restrict__ 
   extern __shared__ c128 tsh[];
   const FrontDesc d = desc[nodes[blockIdx.x]];
   const int ni = d.ni, nb = d.nb, f = d.f;
-  if (ni == 0 || nb == 0) return;
-  const int r0 = blockIdx.y * rc;
+  const int i0 = blockIdx.y * kRows;
+  if (ni == 0 || nb == 0 || i0 >= ni) return;
+  const int r0 = blockIdx.z * rc;
   const int nr = min(rc, nrhs - r0);
   if (nr <= 0) return;
   const cplx<T> *F = pool + d.foff;
@@ -101,8 +119,9 @@ __global__ __launch_bounds__(kT) void apply_down_kernel(const int *__restrict__ 
     tsh[e] = x[bp[b] + (long)(r0 + r) * n];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ni * nr; e += kT) {
-    int i = e % ni, r = e / ni;
+  const int i = i0 + threadIdx.x % kRows;
+  if (i >= ni) return;
+  for (int r = threadIdx.x / kRows; r < nr; r += kT / kRows) {
     c128 acc = x[d.ioff + i + (long)(r0 + r) * n];
     const c128 *t = tsh + (long)r * nb;
     if (!trans) {
@@ -134,35 +153,38 @@ void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c
 
 template <typename T>
 void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
-                     const int *bpos, c128 *x, int n, int nrhs, int trans, int max_ni,
-                     hipStream_t st) {
+                     const int *bpos, c128 *tb, c128 *x, int n, int nrhs, int trans, int max_ni,
+                     int max_f, hipStream_t st) {
   if (count <= 0 || max_ni <= 0) return;
   HSSX_CHECK(max_ni <= 4096, HSSX_EINVAL, "interior block larger than the apply kernel stages");
+  hipLaunchKernelGGL(stage_kernel, dim3(count, ceil_div((long)max_ni * nrhs, 256)), dim3(256), 0,
+                     st, nodes, desc, x, tb, n, nrhs);
   int rc = rhs_chunk(nrhs, max_ni);
   size_t lds = (size_t)rc * max_ni * sizeof(c128);
-  hipLaunchKernelGGL(apply_up_kernel<T>, dim3(count, ceil_div(nrhs, rc)), dim3(kT), lds, st,
-                     nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  hipLaunchKernelGGL(apply_up_kernel<T>, dim3(count, ceil_div(max_f, kRows), ceil_div(nrhs, rc)),
+                     dim3(kT), lds, st, nodes, desc, pool, bpos, tb, x, n, nrhs, trans, rc);
   HSSX_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
                        const int *bpos, c128 *x, int n, int nrhs, int trans, int max_nb,
-                       hipStream_t st) {
-  if (count <= 0 || max_nb <= 0) return;
+                       int max_ni, hipStream_t st) {
+  if (count <= 0 || max_nb <= 0 || max_ni <= 0) return;
   HSSX_CHECK(max_nb <= 4096, HSSX_EINVAL, "boundary block larger than the apply kernel stages");
   int rc = rhs_chunk(nrhs, max_nb);
   size_t lds = (size_t)rc * max_nb * sizeof(c128);
-  hipLaunchKernelGGL(apply_down_kernel<T>, dim3(count, ceil_div(nrhs, rc)), dim3(kT), lds, st,
-                     nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  hipLaunchKernelGGL(apply_down_kernel<T>, dim3(count, ceil_div(max_ni, kRows), ceil_div(nrhs, rc)),
+                     dim3(kT), lds, st, nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
   HSSX_HIP(hipGetLastError());
 }
 
 #define HSSX_INST(T)                                                                          \
   template void launch_apply_up<T>(int, const int *, const FrontDesc *, const cplx<T> *,      \
-                                   const int *, c128 *, int, int, int, int, hipStream_t);     \
+                                   const int *, c128 *, c128 *, int, int, int, int, int,      \
+                                   hipStream_t);                                              \
   template void launch_apply_down<T>(int, const int *, const FrontDesc *, const cplx<T> *,    \
-                                     const int *, c128 *, int, int, int, int, hipStream_t);
+                                     const int *, c128 *, int, int, int, int, int, hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)
 #undef HSSX_INST

@@ -130,6 +130,142 @@ __global__ __launch_bounds__(kThreads) void eliminate_kernel(const ElimJob<T> *_
   }
 }
 
+
+// ---------------------------------------------------------------- blocked GJ
+constexpr int kNB = 32;   // largest panel width
+constexpr int kTile = 64; // trailing-update tile (rows and columns)
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void panel_kernel(const PanelJob<T> *__restrict__ jobs,
+                                                        int *__restrict__ err_node) {
+  __shared__ T sv[kThreads / 64];
+  __shared__ int si[kThreads / 64];
+  const PanelJob<T> jb = jobs[blockIdx.x];
+  const int rows = jb.ne - jb.p0, nb = jb.nb, tid = threadIdx.x;
+  const long ld = jb.ld;
+  cplx<T> *W = jb.W;
+  for (int e = tid; e < rows * nb; e += kThreads) {
+    int i = e % rows, t = e / rows;
+    W[e] = jb.F[(jb.p0 + i) + (long)(jb.p0 + t) * ld];
+  }
+  __syncthreads();
+  for (int t = 0; t < nb; ++t) {
+    T best = (T)-1;
+    int bi = 0x7fffffff;
+    for (int i = t + tid; i < rows; i += kThreads) {
+      T a = cabs1(W[i + (long)t * rows]);
+      if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+    }
+    block_argmax(best, bi, sv, si);
+    const bool zero = !(best > (T)0);
+    if (zero && tid == 0) atomicCAS(err_node, -1, jb.node);
+    const int pv = zero ? t : bi;
+    if (tid == 0) jb.piv[t] = jb.p0 + pv;
+    if (pv != t)
+      for (int c = tid; c < nb; c += kThreads) {
+        cplx<T> a = W[t + (long)c * rows];
+        W[t + (long)c * rows] = W[pv + (long)c * rows];
+        W[pv + (long)c * rows] = a;
+      }
+    __syncthreads();
+    const cplx<T> inv = zero ? czero<T>() : cinv(W[t + (long)t * rows]);
+    for (int i = t + 1 + tid; i < rows; i += kThreads) {
+      cplx<T> l = W[i + (long)t * rows] * inv;
+      W[i + (long)t * rows] = l;
+      for (int c = t + 1; c < nb; ++c) cfms(W[i + (long)c * rows], l, W[t + (long)c * rows]);
+    }
+    __syncthreads();
+  }
+  // G = (L11 U11)^-1, one column per thread
+  for (int c = tid; c < nb; c += kThreads) {
+    cplx<T> z[kNB];
+    for (int i = 0; i < nb; ++i) {
+      cplx<T> v = mk((T)(i == c ? 1 : 0), (T)0);
+      for (int j = 0; j < i; ++j) cfms(v, W[i + (long)j * rows], z[j]);
+      z[i] = v;
+    }
+    for (int i = nb - 1; i >= 0; --i) {
+      cplx<T> v = z[i];
+      for (int j = i + 1; j < nb; ++j) cfms(v, W[i + (long)j * rows], z[j]);
+      z[i] = v * cinv(W[i + (long)i * rows]);
+    }
+    for (int i = 0; i < nb; ++i) jb.G[i + (long)c * nb] = z[i];
+  }
+}
+
+template <typename T>
+__global__ void swap_kernel(const PanelJob<T> *__restrict__ jobs) {
+  const PanelJob<T> jb = jobs[blockIdx.y];
+  int j = jb.p0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= jb.ncols) return;
+  cplx<T> *col = jb.F + (long)j * jb.ld;
+  for (int t = 0; t < jb.nb; ++t) {
+    int r = jb.piv[t];
+    if (r != jb.p0 + t) {
+      cplx<T> a = col[jb.p0 + t];
+      col[jb.p0 + t] = col[r];
+      col[r] = a;
+    }
+  }
+}
+
+template <typename T>
+__global__ void gemm_a_kernel(const PanelJob<T> *__restrict__ jobs) {
+  const PanelJob<T> jb = jobs[blockIdx.y];
+  const int J = jb.ncols - jb.p0 - jb.nb;
+  long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)J * jb.nb) return;
+  int t = (int)(e % jb.nb), c = (int)(e / jb.nb);
+  const cplx<T> *col = jb.F + (long)(jb.p0 + jb.nb + c) * jb.ld + jb.p0;
+  cplx<T> acc = czero<T>();
+  for (int u = 0; u < jb.nb; ++u) cfma(acc, jb.G[t + (long)u * jb.nb], col[u]);
+  jb.Y[t + (long)c * jb.nb] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_b_kernel(const PanelJob<T> *__restrict__ jobs) {
+  __shared__ cplx<T> As[kTile][kNB + 1];
+  __shared__ cplx<T> Ys[kNB][kTile];
+  const PanelJob<T> jb = jobs[blockIdx.z];
+  const int J = jb.ncols - jb.p0 - jb.nb;
+  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  if (i0 >= jb.m || j0 >= J) return;
+  const int nb = jb.nb, tid = threadIdx.x;
+  const long ld = jb.ld;
+  for (int e = tid; e < kTile * nb; e += 256) {
+    int r = e % kTile, t = e / kTile;
+    int i = i0 + r;
+    As[r][t] = i < jb.m ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<T>();
+  }
+  for (int e = tid; e < kTile * nb; e += 256) {
+    int t = e % nb, c = e / nb;
+    Ys[t][c] = (j0 + c) < J ? jb.Y[t + (long)(j0 + c) * nb] : czero<T>();
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  cplx<T> acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) acc[a][b] = czero<T>();
+  for (int t = 0; t < nb; ++t) {
+    cplx<T> av[4], yv[4];
+    for (int a = 0; a < 4; ++a) av[a] = As[tx + 16 * a][t];
+    for (int b = 0; b < 4; ++b) yv[b] = Ys[t][ty + 16 * b];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], yv[b]);
+  }
+  for (int b = 0; b < 4; ++b) {
+    int c = j0 + ty + 16 * b;
+    if (c >= J) continue;
+    cplx<T> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
+    for (int a = 0; a < 4; ++a) {
+      int i = i0 + tx + 16 * a;
+      if (i >= jb.m) continue;
+      if (i >= jb.p0 && i < jb.p0 + nb) col[i] = Ys[i - jb.p0][ty + 16 * b];
+      else col[i] = col[i] - acc[a][b];
+    }
+  }
+}
+
 template <typename T>
 __global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
   const AxpbyJob<T> jb = jobs[blockIdx.z];
@@ -164,6 +300,20 @@ void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStrea
   HSSX_HIP(hipGetLastError());
 }
 
+
+template <typename T>
+void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_cols,
+                       int *err_node, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(panel_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
+  hipLaunchKernelGGL(swap_kernel<T>, dim3(ceil_div(max_cols, 256), count), dim3(256), 0, st, jobs);
+  hipLaunchKernelGGL(gemm_a_kernel<T>, dim3(ceil_div((long)max_cols * kNB, 256), count), dim3(256),
+                     0, st, jobs);
+  hipLaunchKernelGGL(gemm_b_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
+                     dim3(256), 0, st, jobs);
+  HSSX_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipStream_t st) {
   if (count <= 0 || max_m <= 0 || max_n <= 0) return;
@@ -177,6 +327,7 @@ void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipS
                                          const int *, const int *, const int *, const int *, \
                                          const c128 *, cplx<T> *, hipStream_t, int);         \
   template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
+  template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int *, hipStream_t); \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)

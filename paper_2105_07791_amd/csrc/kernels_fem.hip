@@ -152,16 +152,29 @@ __global__ void load_kernel(int n, int nrhs, const int *__restrict__ rowptr,
   b[i + r * ldb] = mk(acc, 0.0);
 }
 
-__global__ void spmv_kernel(int n, int nrhs, const int *__restrict__ rowptr,
-                            const int *__restrict__ col, const c128 *__restrict__ val,
-                            const c128 *__restrict__ x, long ldx, c128 *__restrict__ y, long ldy) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= (long)n * nrhs) return;
-  int i = (int)(t % n), r = (int)(t / n);
-  c128 acc = czero<double>();
-  const c128 *xr = x + r * ldx;
-  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) cfma(acc, val[p], xr[col[p]]);
-  y[i + r * ldy] = acc;
+// One thread per row: the row's <= 7 entries are read once and reused for
+// every right-hand side; for a fixed rhs a wavefront touches consecutive rows,
+// so x and y accesses stay coalesced.
+__global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *__restrict__ rowptr,
+                                                   const int *__restrict__ col,
+                                                   const c128 *__restrict__ val,
+                                                   const c128 *__restrict__ x, long ldx,
+                                                   c128 *__restrict__ y, long ldy) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = rowptr[i], cnt = rowptr[i + 1] - p0;
+  int cj[7];
+  c128 a[7];
+  for (int q = 0; q < 7; ++q) {
+    cj[q] = q < cnt ? col[p0 + q] : i;
+    a[q] = q < cnt ? val[p0 + q] : czero<double>();
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    const c128 *xr = x + r * ldx;
+    c128 acc = czero<double>();
+    for (int q = 0; q < 7; ++q) cfma(acc, a[q], xr[cj[q]]);
+    y[i + r * ldy] = acc;
+  }
 }
 
 // grad[l] += -Re sum_r sum_{a,b} lam_a (dA/ds_l)_ab x_b, one thread per node l.
@@ -245,8 +258,7 @@ void launch_load(int n, int nrhs, const int *rowptr, const int *col, const doubl
 
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
                  const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st) {
-  long tot = (long)n * nrhs;
-  hipLaunchKernelGGL(spmv_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, st, n, nrhs, rowptr,
+  hipLaunchKernelGGL(spmv_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs, rowptr,
                      col, val, x, ldx, y, ldy);
   HSSX_HIP(hipGetLastError());
 }
