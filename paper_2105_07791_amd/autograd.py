@@ -1,0 +1,45 @@
+"""Differentiable solve x = A(s)^-1 b through the C ABI.
+
+Forward: factor A(s) (Algorithm 3.4) and run preconditioned GMRES.
+Backward (adjoint): for a real loss L with torch's complex gradient
+g = dL/dRe(x) + i dL/dIm(x), dL = Re(g^H dx) and dx = -A^-1 (dA) x, so
+
+    lambda  = A^-T conj(g)                    (GMRES on A^T with P^-T)
+    dL/ds_l = -Re( lambda^T (dA/ds_l) x )     (hssx_dAds_contract)
+    dL/db   = conj(lambda)
+
+All three steps run in libhssx.so; this module only marshals tensors.
+"""
+import torch
+
+from .hssx import Factor, Operator, gmres_solve
+
+__all__ = ["WaveSolve", "solve"]
+
+
+class WaveSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, s, b, N, omega, opts):
+        opts = dict(opts or {})
+        gm = dict(m=opts.pop("gmres_m", 50), tol=opts.pop("gmres_tol", 1e-8),
+                  flexible=opts.pop("flexible", False))
+        A = Operator(N, omega, s.detach())
+        P = Factor(A, **opts)
+        x, st = gmres_solve(A, P, b.detach(), **gm)
+        ctx.A, ctx.P, ctx.gm, ctx.stats = A, P, gm, st
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        A, P, gm = ctx.A, ctx.P, ctx.gm
+        lam, _ = gmres_solve(A, P, gx.conj_physical(), trans=True, **gm)
+        gs = A.dAds_contract(lam, x) if ctx.needs_input_grad[0] else None
+        gb = lam.conj_physical() if ctx.needs_input_grad[1] else None
+        return gs, gb, None, None, None
+
+
+def solve(s, b, N, omega, **opts):
+    """x = A(s)^-1 b, differentiable in the slowness s and the load b."""
+    return WaveSolve.apply(s, b, N, omega, opts)

@@ -27,7 +27,8 @@ namespace hssx {
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 1024;         // threads per workgroup (compression, matvec)
+constexpr int kTPR = 4;          // lanes per row in the pivoted QR
 constexpr int kMaxRows = 1024;   // rows of one local sample block (LDS index arrays)
 constexpr int kMaxS = 1024;      // sample columns held in LDS for the projector
 
@@ -200,14 +201,20 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
   kmax = kmax < C.k_cap ? kmax : C.k_cap;
   T first = (T)0;
   int t = 0;
+  const int sub = tid % kTPR, slot = tid / kTPR, nslot = kT / kTPR;
   for (; t < kmax; ++t) {
+    // residual row norms: kTPR lanes per row, reduced by shuffles
     T best = (T)-1;
     int bi = 0x7fffffff;
-    for (int pp = t + tid; pp < rows; pp += kT) {
-      int row = perm[pp];
+    for (int pp0 = t; pp0 < rows; pp0 += nslot) {
+      const int pp = pp0 + slot;
       T nrm = 0;
-      for (int j = 0; j < s; ++j) nrm += abs2(Wm[row + (long)j * rcap]);
-      if (nrm > best || (nrm == best && pp < bi)) { best = nrm; bi = pp; }
+      if (pp < rows) {
+        const int row = perm[pp];
+        for (int j = sub; j < s; j += kTPR) nrm += abs2(Wm[row + (long)j * rcap]);
+      }
+      for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
+      if (pp < rows && sub == 0 && (nrm > best || (nrm == best && pp < bi))) { best = nrm; bi = pp; }
     }
     block_argmax(best, bi, sv, si);
     T pn = sqrt(best);
@@ -224,16 +231,24 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
     for (int j = tid; j < s; j += kT) q[j] = inv * Wm[prow + (long)j * rcap];
     if (tid == 0) Rm[t + (long)prow * C.k_cap] = mk(pn, (T)0);
     __syncthreads();
-    for (int pp = t + 1 + tid; pp < rows; pp += kT) {
-      int row = perm[pp];
+    for (int pp0 = t + 1; pp0 < rows; pp0 += nslot) {
+      const int pp = pp0 + slot;
+      const bool act = pp < rows;
+      const int row = act ? perm[pp] : 0;
       cplx<T> rr = czero<T>();
       for (int pass = 0; pass < 2; ++pass) {
         cplx<T> d = czero<T>();
-        for (int j = 0; j < s; ++j) cfma(d, conj(q[j]), Wm[row + (long)j * rcap]);
-        for (int j = 0; j < s; ++j) cfms(Wm[row + (long)j * rcap], d, q[j]);
+        if (act)
+          for (int j = sub; j < s; j += kTPR) cfma(d, conj(q[j]), Wm[row + (long)j * rcap]);
+        for (int o = 1; o < kTPR; o <<= 1) {
+          d.re += __shfl_xor(d.re, o);
+          d.im += __shfl_xor(d.im, o);
+        }
+        if (act)
+          for (int j = sub; j < s; j += kTPR) cfms(Wm[row + (long)j * rcap], d, q[j]);
         rr = rr + d;
       }
-      Rm[t + (long)row * C.k_cap] = rr;
+      if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
     }
     __syncthreads();
   }

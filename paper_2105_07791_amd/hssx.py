@@ -24,7 +24,9 @@ def _col_major(x, dtype):
     """(n,) or (n, nrhs) tensor -> column-major (ptr, ld, nrhs, keepalive)."""
     if x.dim() == 1:
         x = x.reshape(-1, 1)
-    t = x.t().contiguous() if not x.t().is_contiguous() else x.t()
+    t = x.t().resolve_conj()
+    if not t.is_contiguous():
+        t = t.contiguous()
     assert t.dtype == dtype and t.is_cuda
     return t, x.shape[0], x.shape[1]
 
