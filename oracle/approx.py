@@ -144,8 +144,12 @@ def _interior_tree(box):
 
 def factor_approx(A, tree, h_sw=4, tol=1e-6, k0=32, r=16, seed=0,
                   id_rel_tol=None):
+    """Algorithm 3.4.  Every Algorithm A.1 call starts from the rank guess
+    max(k0, accepted k of the children's Schur-complement compressions): the
+    rank of a parent's Schur complement grows slowly up the tree."""
     f = ApproxFactor(tree, h_sw)
     root = tree.root
+    kfin = {}
     for k, bx in enumerate(tree.boxes):
         F = _front(A, tree, k, f.child_S)
         ni = bx.I.size
@@ -161,7 +165,7 @@ def factor_approx(A, tree, h_sw=4, tol=1e-6, k0=32, r=16, seed=0,
             ct = _interior_tree(tree.boxes[bx.hi])
             Ht = compress_adaptive(lambda X: St @ X,
                                    lambda I, J: St[np.ix_(I, J)], ct,
-                                   k0=k0, r=r, tol=tol, seed=seed,
+                                   k0=max(k0, kfin.get(bx.hi, 0)), r=r, tol=tol, seed=seed,
                                    instance=4 * k + 1, id_rel_tol=id_rel_tol)
             f.S_tilde[k] = Ht
             f.blk[k] = _Block2x2(B11, B12, B21, Ht.dense())
@@ -176,11 +180,13 @@ def factor_approx(A, tree, h_sw=4, tol=1e-6, k0=32, r=16, seed=0,
             else:
                 S = Abb.copy()
             if f.comp[k]:
+                kc = 0 if bx.is_leaf else max(kfin.get(bx.lo, 0), kfin.get(bx.hi, 0))
                 H = compress_adaptive(lambda X: S @ X,
                                       lambda I, J: S[np.ix_(I, J)], bx.ctree,
-                                      k0=k0, r=r, tol=tol, seed=seed,
+                                      k0=max(k0, kc), r=r, tol=tol, seed=seed,
                                       instance=4 * k, id_rel_tol=id_rel_tol)
                 f.S_hss[k] = H
+                kfin[k] = H.k_final
             else:
                 f.S_dense[k] = S
         if not bx.is_leaf:

@@ -239,7 +239,7 @@ def compress_adaptive(apply, entries, tree, k0=32, r=16, tol=1e-6, seed=0,
     if id_rel_tol is None:
         id_rel_tol = 1e-2 * tol
     m = int(tree.size[0]) if tree.nclusters else 0
-    k = k0
+    k = max(1, min(k0, m))
     Omega = gaussian_block(seed, instance, m, 0, k + r)
     S = apply(Omega)
     col = k + r

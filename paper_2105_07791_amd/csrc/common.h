@@ -5,6 +5,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
+#include <memory>
+#include <algorithm>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -150,5 +153,64 @@ inline void upload(DevBuf &d, const std::vector<T> &h) {
 }
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Stream-ordered upload of small descriptor arrays: host data is copied into
+// pinned chunks and sent with hipMemcpyAsync on the work stream, so uploads
+// block neither the host nor the device.  Chunks are never freed or
+// overwritten while their device copies may still be read; recycle() reuses
+// them and may only be called after the stream has been synchronised and
+// once no pointer returned by put() is used again.
+class Staging {
+ public:
+  explicit Staging(hipStream_t st) : st_(st) {}
+  Staging(const Staging &) = delete;
+  Staging &operator=(const Staging &) = delete;
+  ~Staging() {
+    for (auto &c : chunks_)
+      if (c.host) (void)hipHostFree(c.host);
+  }
+  template <typename T> T *put(const std::vector<T> &v) {
+    size_t bytes = v.size() * sizeof(T);
+    size_t need = ((bytes + 255) / 256) * 256;
+    if (need == 0) need = 256;
+    while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].cap) {
+      ++cur_;
+      off_ = 0;
+    }
+    if (cur_ == chunks_.size()) {
+      Chunk c;
+      c.cap = std::max(need, size_t(8) << 20);
+      HSSX_HIP(hipHostMalloc(&c.host, c.cap, hipHostMallocDefault));
+      c.dev = std::make_unique<DevBuf>();
+      c.dev->alloc(c.cap);
+      chunks_.push_back(std::move(c));
+      off_ = 0;
+    }
+    Chunk &c = chunks_[cur_];
+    char *h = static_cast<char *>(c.host) + off_;
+    char *d = static_cast<char *>(c.dev->p) + off_;
+    if (bytes) {
+      std::memcpy(h, v.data(), bytes);
+      HSSX_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st_));
+    }
+    off_ += need;
+    return reinterpret_cast<T *>(d);
+  }
+  void recycle() {
+    cur_ = 0;
+    off_ = 0;
+  }
+  hipStream_t stream() const { return st_; }
+
+ private:
+  struct Chunk {
+    void *host = nullptr;
+    std::unique_ptr<DevBuf> dev;
+    size_t cap = 0;
+  };
+  hipStream_t st_;
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, off_ = 0;
+};
 
 }  // namespace hssx

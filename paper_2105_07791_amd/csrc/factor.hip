@@ -30,6 +30,7 @@ namespace {
 template <typename T> struct CompressTask {
   int node = 0, kind = 0;
   int m = 0;
+  int k_init = 0;   // initial rank guess (0: the option k0)
   ClusterTree ct;
   cplx<T> *S = nullptr;
   int ldS = 0;
@@ -88,16 +89,31 @@ Layout layout_instance(const ClusterTree &ct, int k, int s) {
   return L;
 }
 
+// nominal flops of one cluster's step of Algorithm A.1 with the rank cap:
+// local samples, pivoted QR of S_loc^T (two projections per pivot), the
+// interpolation matrix and the reduced sketch
+inline double compress_flops(const HssCluster &c, const HssInstance &I) {
+  const double s = I.s, rows = c.rows_cap, k = c.k_cap;
+  double f = 0;
+  if (c.left < 0) f += 4.0 * rows * rows * s;                 // D Omega
+  else f += 8.0 * rows * rows * s / 2;                        // B12 Om_r, B21 Om_l
+  f += k * rows * s * (3.0 + 32.0);                           // norms + 2 x (dot, axpy)
+  f += 4.0 * (rows - k) * k * k + 8.0 * k * rows * s;         // T and U^T Omega
+  return f;
+}
+
 template <typename T>
 void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts &o, double tol,
-                    double id_tol, hipStream_t st) {
+                    double id_tol, Staging &sg) {
   if (tasks.empty()) return;
+  const hipStream_t st = sg.stream();
   const int k0 = o.k0, r = o.r;
   long osz = 0, ysz = 0;
   for (auto &t : tasks) {
-    t.k = std::max(1, std::min(k0, t.m));
+    t.k = std::max(1, std::min(std::max(k0, t.k_init), t.m));
     t.s = t.k + r;
-    t.cap = std::min(k0 + r * (o.max_rounds + 1), t.m + 2 * r);
+    // room for every round up to k >= m (s = k + r samples + r probes)
+    t.cap = std::min(t.k + r * (o.max_rounds + 1), t.m + 3 * r);
     t.cap = std::max(t.cap, t.s + r);
     t.ooff = osz;
     t.yoff = ysz;
@@ -129,16 +145,14 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       mm = std::max(mm, t.m);
       mc = std::max(mc, nc);
     }
-    DevBuf dg, ds;
-    upload(dg, gj);
-    upload(ds, sj);
-    launch_gaussian((int)gj.size(), dg.as<GaussJob>(), o.seed, mm, mc, st);
+    GaussJob *dg = sg.put(gj);
+    SampleJob<T> *ds = sg.put(sj);
+    launch_gaussian((int)gj.size(), dg, o.seed, mm, mc, st);
     double sflops = 0;
     for (const auto &q : sj) sflops += 4.0 * q.m * (double)q.m * q.nc;
     hipEvent_t ps = prof_begin(st);
-    launch_sample<T>((int)sj.size(), ds.as<SampleJob<T>>(), mm, mc, st);
+    launch_sample<T>((int)sj.size(), ds, mm, mc, st);
     prof_end("sample", st, ps, sflops);
-    HSSX_HIP(hipStreamSynchronize(st));
   };
 
   std::vector<int> all(tasks.size());
@@ -188,9 +202,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     const cplx<T> *base = tasks[active[0]].S;
     for (size_t a = 0; a < active.size(); ++a) inst[a].soff = tasks[active[a]].S - base;
 
-    DevBuf d_inst, d_cls, d_pool, d_ipool, d_rank, d_scr;
-    upload(d_inst, inst);
-    upload(d_cls, cls);
+    DevBuf d_pool, d_ipool, d_rank, d_scr;
+    HssInstance *d_inst = sg.put(inst);
+    HssCluster *d_cls = sg.put(cls);
     d_pool.alloc(std::max(1L, pool) * sizeof(cplx<T>));
     d_ipool.alloc(std::max(1L, ipool) * sizeof(int));
     d_rank.alloc(std::max<size_t>(1, cls.size()) * sizeof(int));
@@ -206,15 +220,14 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
           if (ct.level[c] == lev) items.push_back(HssItem{(int)a, c});
       }
       if (items.empty()) continue;
-      DevBuf d_items;
-      upload(d_items, items);
+      HssItem *d_items = sg.put(items);
+      double cflops = 0;
+      for (const auto &it : items) cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
       hipEvent_t pc = prof_begin(st);
-      launch_compress_level<T>((int)items.size(), d_items.as<HssItem>(), d_inst.as<HssInstance>(),
-                               d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_ipool.as<int>(),
-                               d_rank.as<int>(), base, Y.as<cplx<T>>(), Om.as<double>(),
-                               d_scr.as<cplx<T>>(), id_tol, st);
-      prof_end("compress_level", st, pc, 0.0);
-      HSSX_HIP(hipStreamSynchronize(st));
+      launch_compress_level<T>((int)items.size(), d_items, d_inst, d_cls, d_pool.as<cplx<T>>(),
+                               d_ipool.as<int>(), d_rank.as<int>(), base, Y.as<cplx<T>>(),
+                               Om.as<double>(), d_scr.as<cplx<T>>(), id_tol, st);
+      prof_end("compress_level", st, pc, cflops);
     }
 
     // ---- error estimate with r fresh probes (eq. 2.7)
@@ -237,14 +250,13 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       j.woff = (long)a * xh_per_job_max;
       mj.push_back(j);
     }
-    DevBuf d_mj, d_xh;
-    upload(d_mj, mj);
+    DevBuf d_xh;
+    MatvecJob<T> *d_mj = sg.put(mj);
     d_xh.alloc(std::max(1L, (long)mj.size() * xh_per_job_max) * sizeof(cplx<T>));
     HSSX_CHECK(r <= 64, HSSX_EINVAL, "probe block wider than 64 columns");
     hipEvent_t pm = prof_begin(st);
-    launch_hss_matvec<T>((int)mj.size(), d_mj.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
-                         d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
-                         d_xh.as<cplx<T>>(), st);
+    launch_hss_matvec<T>((int)mj.size(), d_mj, d_inst, d_cls, d_pool.as<cplx<T>>(),
+                         d_rank.as<int>(), d_xh.as<cplx<T>>(), st);
     prof_end("hss_matvec", st, pm, 0.0);
     std::vector<double> h_err(2 * tasks.size());
     std::vector<int> h_rank(cls.size());
@@ -291,14 +303,14 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       }
     }
     if (!ej.empty()) {
-      DevBuf d_ej, d_xh2;
-      upload(d_ej, ej);
+      DevBuf d_xh2;
+      MatvecJob<T> *d_ej = sg.put(ej);
       d_xh2.alloc(std::max(1L, (long)ej.size() * xh_per_job_max) * sizeof(cplx<T>));
       hipEvent_t pm2 = prof_begin(st);
-      launch_hss_matvec<T>((int)ej.size(), d_ej.as<MatvecJob<T>>(), d_inst.as<HssInstance>(),
-                           d_cls.as<HssCluster>(), d_pool.as<cplx<T>>(), d_rank.as<int>(),
-                           d_xh2.as<cplx<T>>(), st);
+      launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool.as<cplx<T>>(),
+                           d_rank.as<int>(), d_xh2.as<cplx<T>>(), st);
       prof_end("hss_matvec", st, pm2, 0.0);
+      // the round's pools are freed below; wait for the expansion first
       HSSX_HIP(hipStreamSynchronize(st));
     }
     active.swap(next);
@@ -317,16 +329,12 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
 // one workgroup each; larger ones go panel by panel (32 columns) through the
 // blocked sequence, all fronts of the batch advancing together.
 template <typename T>
-void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, hipStream_t st) {
+void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) {
   constexpr int NB = 32, kSmall = 64;
+  const hipStream_t st = sg.stream();
   std::vector<ElimJob<T>> small, big;
   for (const auto &j : jobs) (j.ne < kSmall ? small : big).push_back(j);
-  if (!small.empty()) {
-    DevBuf d;
-    upload(d, small);
-    launch_eliminate<T>((int)small.size(), d.as<ElimJob<T>>(), err, st);
-    HSSX_HIP(hipStreamSynchronize(st));
-  }
+  if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
   if (big.empty()) return;
   // scratch per job: pivots, G, Y, W
   long ysz = 0, wsz = 0;
@@ -368,10 +376,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, hipStream_t s
       mm = std::max(mm, j.m);
       mc = std::max(mc, j.ncols - p0);
     }
-    DevBuf d;
-    upload(d, pj);
-    launch_panel_step<T>((int)pj.size(), d.as<PanelJob<T>>(), mm, mc, err, st);
-    HSSX_HIP(hipStreamSynchronize(st));
+    launch_panel_step<T>((int)pj.size(), sg.put(pj), mm, mc, err, st);
   }
   // R = -(A_ii^-1 A_ib): negate the block F(0:ne, ne:m)
   std::vector<AxpbyJob<T>> neg;
@@ -383,12 +388,9 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, hipStream_t s
     nm = std::max(nm, j.ne);
     nn = std::max(nn, j.m - j.ne);
   }
-  if (!neg.empty()) {
-    DevBuf d;
-    upload(d, neg);
-    launch_axpby<T>((int)neg.size(), d.as<AxpbyJob<T>>(), nm, nn, st);
-    HSSX_HIP(hipStreamSynchronize(st));
-  }
+  if (!neg.empty()) launch_axpby<T>((int)neg.size(), sg.put(neg), nm, nn, st);
+  // the panel scratch is freed on return
+  HSSX_HIP(hipStreamSynchronize(st));
 }
 
 template <typename T>
@@ -403,12 +405,23 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
   const double eps = sizeof(T) == sizeof(float) ? 1.1920929e-7 : 2.220446049250313e-16;
   const double id_tol =
       P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : std::max(1e-2 * P.tol, 4.0 * eps);
+  Staging sg(st);
   DevBuf err;
   err.alloc(sizeof(int));
-  int minus1 = -1;
-  HSSX_HIP(hipMemcpy(err.p, &minus1, sizeof(int), hipMemcpyHostToDevice));
+  int *d_err = sg.put(std::vector<int>{-1});
+  HSSX_HIP(hipMemcpyAsync(err.p, d_err, sizeof(int), hipMemcpyDeviceToDevice, st));
   int kmax = 0, rounds_max = 0, ncomp = 0;
   double est_max = 0;
+  // accepted rank cap k of each node's Schur-complement compression; a
+  // parent's compressions start from its children's (Algorithm A.1 takes an
+  // initial rank guess)
+  std::vector<int> kfin(sym.nodes.size(), 0);
+  auto record = [&](const CompressTask<T> &t) {
+    kmax = std::max(kmax, t.maxrank);
+    rounds_max = std::max(rounds_max, t.rounds);
+    est_max = std::max(est_max, t.est);
+    P.node_rank[t.node] = std::max(P.node_rank[t.node], t.maxrank);
+  };
 
   for (int d = sym.max_depth; d >= 0; --d) {
     const auto &nodes = P.depth_nodes[d];
@@ -424,6 +437,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     std::vector<int> hn;
     for (int k : nodes)
       if (P.arith[k] && k != root && P.h_desc[k].ni > 0) hn.push_back(k);
+    DevBuf G, H;
     if (!hn.empty()) {
       long gsz = 0, hsz = 0;
       std::vector<long> goff, hoff;
@@ -434,7 +448,6 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         gsz += (long)ni * ni;
         hsz += (long)(ni - p) * (ni - p);
       }
-      DevBuf G, H;
       G.alloc(std::max(1L, gsz) * sizeof(cplx<T>));
       H.alloc(std::max(1L, hsz) * sizeof(cplx<T>));
       std::vector<AxpbyJob<T>> cp;
@@ -454,6 +467,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
           t.node = k;
           t.kind = 1;
           t.m = ni - p;
+          t.k_init = kfin[sym.nodes[k].hi];
           t.ct = interior_subtree(sym.nodes[sym.nodes[k].hi]);
           t.S = g + p + (long)p * ni;
           t.ldS = ni;
@@ -462,16 +476,13 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
           tasks.push_back(std::move(t));
         }
       }
-      // G := 0 then G += A_ii
+      // G := 0 then G += A_ii; eliminate mu's block: G(p:, p:) = S~
       HSSX_HIP(hipMemsetAsync(G.p, 0, G.bytes, st));
-      DevBuf dcp;
-      upload(dcp, cp);
-      launch_axpby<T>((int)cp.size(), dcp.as<AxpbyJob<T>>(), mm, mm, st);
+      launch_axpby<T>((int)cp.size(), sg.put(cp), mm, mm, st);
       hipEvent_t pe = prof_begin(st);
-      eliminate_jobs<T>(ej, err.as<int>(), st);
+      eliminate_jobs<T>(ej, err.as<int>(), sg);
       prof_end("front_eliminate", st, pe, elim_flops(ej));
-      HSSX_HIP(hipStreamSynchronize(st));
-      compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg);
       std::vector<AxpbyJob<T>> fix;
       int fm = 0;
       size_t ti = 0;
@@ -481,20 +492,14 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         int ni = fd.ni, p = sym.nodes[sym.nodes[k].lo].p0;
         if (ni - p <= 0) continue;
         auto &t = tasks[ti++];
-        kmax = std::max(kmax, t.maxrank);
-        rounds_max = std::max(rounds_max, t.rounds);
-        est_max = std::max(est_max, t.est);
-        P.node_rank[k] = std::max(P.node_rank[k], t.maxrank);
+        record(t);
         // F(p:ni, p:ni) += S~_HSS - S~
         fix.push_back(AxpbyJob<T>{F + fd.foff + p + (long)p * fd.f, t.target,
                                   G.as<cplx<T>>() + goff[a] + p + (long)p * ni, fd.f, ni - p,
                                   ni, ni - p, ni - p, (T)1, (T)-1});
         fm = std::max(fm, ni - p);
       }
-      DevBuf dfix;
-      upload(dfix, fix);
-      launch_axpby<T>((int)fix.size(), dfix.as<AxpbyJob<T>>(), fm, fm, st);
-      HSSX_HIP(hipStreamSynchronize(st));
+      launch_axpby<T>((int)fix.size(), sg.put(fix), fm, fm, st);
     }
 
     // ---- eliminate all fronts of this depth
@@ -504,7 +509,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       jobs.push_back(ElimJob<T>{F + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
     }
     hipEvent_t pe = prof_begin(st);
-    eliminate_jobs<T>(jobs, err.as<int>(), st);
+    eliminate_jobs<T>(jobs, err.as<int>(), sg);
     prof_end("front_eliminate", st, pe, elim_flops(jobs));
 
     // ---- compress the Schur complements the parents will use in HSS form
@@ -516,24 +521,27 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       t.node = k;
       t.kind = 0;
       t.m = fd.nb;
-      t.ct = sym.nodes[k].ct;
+      const NDNode &nd = sym.nodes[k];
+      if (!nd.leafnode()) t.k_init = std::max(kfin[nd.lo], kfin[nd.hi]);
+      t.ct = nd.ct;
       t.S = F + fd.foff + fd.ni + (long)fd.ni * fd.f;
       t.ldS = fd.f;
       t.target = t.S;
       t.ldT = fd.f;
       tasks.push_back(std::move(t));
     }
-    HSSX_HIP(hipStreamSynchronize(st));
     if (!tasks.empty()) {
-      compress_batch<T>(tasks, P.opts, P.tol, id_tol, st);
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg);
       for (auto &t : tasks) {
-        kmax = std::max(kmax, t.maxrank);
-        rounds_max = std::max(rounds_max, t.rounds);
-        est_max = std::max(est_max, t.est);
-        P.node_rank[t.node] = std::max(P.node_rank[t.node], t.maxrank);
+        record(t);
+        kfin[t.node] = t.k;
         ++ncomp;
       }
     }
+    // everything launched for this depth is complete before its scratch
+    // (G, H) and the staged descriptors are released
+    HSSX_HIP(hipStreamSynchronize(st));
+    sg.recycle();
   }
   int bad = -1;
   HSSX_HIP(hipStreamSynchronize(st));

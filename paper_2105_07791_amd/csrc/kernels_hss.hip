@@ -313,7 +313,10 @@ __global__ __launch_bounds__(kT) void hss_matvec_kernel(
       const int k = rk[c];
       const cplx<T> *U = P + cc.U;
       cplx<T> *xh = W + cc.XH;
-      if (cc.left < 0) {
+      if (!jb.X && (cc.start + cc.size <= jb.c0 || cc.start >= jb.c0 + nc)) {
+        // identity columns outside this cluster: its up-sweep vector is zero
+        for (int e = tid; e < k * nc; e += kT) xh[e] = czero<T>();
+      } else if (cc.left < 0) {
         for (int e = tid; e < k * nc; e += kT) {
           int a = e % k, j = e / k;
           cplx<T> v = czero<T>();
@@ -393,11 +396,16 @@ __global__ __launch_bounds__(kT) void hss_matvec_kernel(
     for (int e = tid; e < cc.size * nc; e += kT) {
       int i = e % cc.size, j = e / cc.size;
       cplx<T> v = czero<T>();
-      for (int l = 0; l < cc.size; ++l) {
-        cplx<T> d = D[i + (long)l * cc.size];
-        T x = X(cc.start + l, j);
-        v.re += d.re * x;
-        v.im += d.im * x;
+      if (!jb.X) {
+        const int l = jb.c0 + j - cc.start;     // identity column inside the leaf?
+        if (l >= 0 && l < cc.size) v = D[i + (long)l * cc.size];
+      } else {
+        for (int l = 0; l < cc.size; ++l) {
+          cplx<T> d = D[i + (long)l * cc.size];
+          T x = X(cc.start + l, j);
+          v.re += d.re * x;
+          v.im += d.im * x;
+        }
       }
       for (int a = 0; a < k; ++a) cfma(v, U[i + (long)a * cc.size], yh[a + (long)j * k]);
       int gi = cc.start + i;
