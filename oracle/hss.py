@@ -29,7 +29,7 @@ Readings taken where the paper is silent or garbled:
   * the loop also visits the root to read its B block; the root has no ID;
   * the ID is S_loc ~ U S_loc(J, :) with U(J, :) = I, computed by column-
     pivoted Householder QR of S_loc^T (pivot = largest remaining column norm,
-    first index on ties); rank = min(k, rows, cols) and, additionally, the
+    lowest original row index on ties); rank = min(k, rows, cols) and, additionally, the
     pivots whose magnitude falls below id_rel_tol * |first pivot| are dropped;
   * the tolerance is relative: accept when
     ||S~ - A_HSS Omega~||_F <= tol * ||S~||_F, S~ = A Omega~ the probe samples;
@@ -177,7 +177,8 @@ def interp_decomp(S, k, id_rel_tol=0.0):
     rank = 0
     for t in range(kmax):
         norms = np.sum(np.abs(M[t:, t:]) ** 2, axis=0)
-        p = t + int(np.argmax(norms))
+        ties = np.flatnonzero(norms == norms.max())
+        p = t + int(ties[np.argmin(perm[t + ties])])     # lowest original row on ties
         pn = np.sqrt(norms[p - t])
         if first is None:
             first = pn

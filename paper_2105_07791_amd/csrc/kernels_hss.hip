@@ -12,7 +12,9 @@
 //           Sr_r - B21 Om_l], B12 = S(sk_l, sk_r), B21 = S(sk_r, sk_l).  The
 //           interpolative decomposition S_loc ~ U S_loc(J, :) comes from a
 //           pivoted Gram-Schmidt QR of S_loc^T (pivot = largest remaining row
-//           norm, first on ties; each projection applied twice), rank =
+//           norm, lowest row index on ties; each projection applied twice;
+//           for complex64 and blocks up to 256 x 160 the rows stay in
+//           registers, 8 lanes per row), rank =
 //           min(k, rows, s) reduced to the pivots above id_tol * first pivot;
 //           T = R11^-1 R12, U(J, :) = I, U(rest, :) = T^T.  The cluster keeps
 //           Om_c = U^T Om_loc, Sr_c = S_loc(J, :), skeleton I_loc(J).  The
@@ -27,8 +29,12 @@ namespace hssx {
 
 namespace {
 
-constexpr int kT = 1024;         // threads per workgroup (compression, matvec)
-constexpr int kTPR = 4;          // lanes per row in the pivoted QR
+constexpr int kT = 1024;         // threads per workgroup of the HSS matvec
+constexpr int kTC = 512;         // threads per workgroup of the compression
+constexpr int kTPR = 4;          // lanes per row in the global-memory pivoted QR
+// register-resident pivoted QR (complex64): 8 lanes per row, 64 row slots,
+// 4 rows per slot, 20 columns per lane -> rows <= 256, sample columns <= 160
+constexpr int kRT = 8, kRS = kTC / kRT, kRPT = 4, kRSEG = 20;
 constexpr int kMaxRows = 1024;   // rows of one local sample block (LDS index arrays)
 constexpr int kMaxS = 1024;      // sample columns held in LDS for the projector
 
@@ -73,7 +79,7 @@ __global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
   jb.Y[i + (long)j * jb.ldY] = acc;
 }
 
-template <typename T>
+template <int NT, typename T>
 __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   for (int off = 32; off > 0; off >>= 1) {
     T ov = __shfl_xor(v, off);
@@ -84,7 +90,7 @@ __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   if ((threadIdx.x & 63) == 0) { sv[w] = v; si[w] = idx; }
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int k = 1; k < kT / 64; ++k)
+    for (int k = 1; k < NT / 64; ++k)
       if (sv[k] > sv[0] || (sv[k] == sv[0] && si[k] < si[0])) { sv[0] = sv[k]; si[0] = si[k]; }
   __syncthreads();
   v = sv[0];
@@ -93,7 +99,7 @@ __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kT) void compress_level_kernel(
+__global__ __launch_bounds__(kTC) void compress_level_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
     const HssCluster *__restrict__ cls, cplx<T> *__restrict__ pool, int *__restrict__ ipool,
     int *__restrict__ rank, const cplx<T> *__restrict__ front, const cplx<T> *__restrict__ Yall,
@@ -101,8 +107,9 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
   __shared__ int I_loc[kMaxRows];
   __shared__ int perm[kMaxRows];
   __shared__ cplx<T> q[kMaxS];
-  __shared__ T sv[kT / 64];
-  __shared__ int si[kT / 64];
+  __shared__ T sv[kTC / 64];
+  __shared__ int si[kTC / 64];
+  __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
   const HssItem it = items[blockIdx.x];
   const HssInstance I = insts[it.inst];
@@ -127,15 +134,15 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
   const bool leaf = C.left < 0;
   if (leaf) {
     rows = C.size;
-    for (int i = tid; i < rows; i += kT) I_loc[i] = C.start + i;
+    for (int i = tid; i < rows; i += kTC) I_loc[i] = C.start + i;
     __syncthreads();
     cplx<T> *D = P + C.D;
-    for (int e = tid; e < rows * rows; e += kT) {
+    for (int e = tid; e < rows * rows; e += kTC) {
       int i = e % rows, l = e / rows;
       D[e] = S[(C.start + i) + (long)(C.start + l) * ldS];
     }
     __syncthreads();
-    for (int e = tid; e < rows * s; e += kT) {
+    for (int e = tid; e < rows * s; e += kTC) {
       int i = e % rows, j = e / rows;
       cplx<T> v = Y[(C.start + i) + (long)j * ldY];
       for (int l = 0; l < rows; ++l) {
@@ -152,20 +159,20 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
     const int kl = rank[I.cl_off + C.left], kr = rank[I.cl_off + C.right];
     rows = kl + kr;
     const int *skl = IP + L.sk, *skr = IP + R.sk;
-    for (int i = tid; i < rows; i += kT) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
+    for (int i = tid; i < rows; i += kTC) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
     cplx<T> *B12 = P + C.B12, *B21 = P + C.B21;
-    for (int e = tid; e < kl * kr; e += kT) {
+    for (int e = tid; e < kl * kr; e += kTC) {
       int a = e % kl, b = e / kl;
       B12[a + (long)b * kl] = S[skl[a] + (long)skr[b] * ldS];
     }
-    for (int e = tid; e < kr * kl; e += kT) {
+    for (int e = tid; e < kr * kl; e += kTC) {
       int a = e % kr, b = e / kr;
       B21[a + (long)b * kr] = S[skr[a] + (long)skl[b] * ldS];
     }
     __syncthreads();
     if (it.cl != 0) {
       const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
-      for (int e = tid; e < rows * s; e += kT) {
+      for (int e = tid; e < rows * s; e += kTC) {
         int i = e % rows, j = e / rows;
         cplx<T> v, o;
         if (i < kl) {
@@ -190,18 +197,114 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
   }
 
   // ---- interpolative decomposition of S_loc (rows x s)
-  for (int e = tid; e < rows * s; e += kT) {
-    int i = e % rows, j = e / rows;
-    Wm[i + (long)j * rcap] = Sloc[i + (long)j * rcap];
-  }
-  for (int i = tid; i < rows; i += kT) perm[i] = i;
-  __syncthreads();
   int kmax = I.k < rows ? I.k : rows;
   kmax = kmax < s ? kmax : s;
   kmax = kmax < C.k_cap ? kmax : C.k_cap;
   T first = (T)0;
   int t = 0;
-  const int sub = tid % kTPR, slot = tid / kTPR, nslot = kT / kTPR;
+  bool reg_done = false;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (rows <= kRS * kRPT && s <= kRT * kRSEG) {
+      // Register-resident pivoted Gram-Schmidt: each row stays with its 8
+      // lanes for the whole decomposition; pivots are marked, not moved.
+      const int sub = tid % kRT, slot = tid / kRT;
+      cplx<T> w[kRPT][kRSEG];
+#pragma unroll
+      for (int r = 0; r < kRPT; ++r) {
+        const int row = slot + kRS * r;
+#pragma unroll
+        for (int c = 0; c < kRSEG; ++c) {
+          const int j = sub + kRT * c;
+          w[r][c] = (row < rows && j < s) ? Sloc[row + (long)j * rcap] : czero<T>();
+        }
+      }
+      for (int i = tid; i < rows; i += kTC) sel[i] = 0;
+      __syncthreads();
+      for (; t < kmax; ++t) {
+        T best = (T)-1;
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int r = 0; r < kRPT; ++r) {
+          const int row = slot + kRS * r;
+          T nrm = 0;
+#pragma unroll
+          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
+          for (int o = 1; o < kRT; o <<= 1) nrm += __shfl_xor(nrm, o);
+          if (row < rows && !sel[row] && (nrm > best || (nrm == best && row < bi))) {
+            best = nrm;
+            bi = row;
+          }
+        }
+        block_argmax<kTC>(best, bi, sv, si);
+        const T pn = sqrt(best);
+        if (t == 0) first = pn;
+        if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
+        const T inv = (T)1 / pn;
+        if (slot == bi % kRS) {
+          const int ro = bi / kRS;
+#pragma unroll
+          for (int r = 0; r < kRPT; ++r)
+            if (r == ro) {
+#pragma unroll
+              for (int c = 0; c < kRSEG; ++c) {
+                const int j = sub + kRT * c;
+                if (j < s) q[j] = inv * w[r][c];
+              }
+            }
+        }
+        if (tid == 0) {
+          perm[t] = bi;
+          sel[bi] = 1;
+          Rm[t + (long)bi * C.k_cap] = mk(pn, (T)0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRPT; ++r) {
+          const int row = slot + kRS * r;
+          const bool act = row < rows && !sel[row];
+          cplx<T> rr = czero<T>();
+          for (int pass = 0; pass < 2; ++pass) {
+            cplx<T> d = czero<T>();
+#pragma unroll
+            for (int c = 0; c < kRSEG; ++c) {
+              const int j = sub + kRT * c;
+              if (j < s) cfma(d, conj(q[j]), w[r][c]);
+            }
+            for (int o = 1; o < kRT; o <<= 1) {
+              d.re += __shfl_xor(d.re, o);
+              d.im += __shfl_xor(d.im, o);
+            }
+            if (act) {
+#pragma unroll
+              for (int c = 0; c < kRSEG; ++c) {
+                const int j = sub + kRT * c;
+                if (j < s) cfms(w[r][c], d, q[j]);
+              }
+            }
+            rr = rr + d;
+          }
+          if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
+        }
+        __syncthreads();
+      }
+      // the unselected rows follow the pivots in ascending order
+      if (tid == 0) {
+        int pos = t;
+        for (int i = 0; i < rows; ++i)
+          if (!sel[i]) perm[pos++] = i;
+      }
+      __syncthreads();
+      reg_done = true;
+    }
+  }
+  if (!reg_done) {
+  for (int e = tid; e < rows * s; e += kTC) {
+    int i = e % rows, j = e / rows;
+    Wm[i + (long)j * rcap] = Sloc[i + (long)j * rcap];
+  }
+  for (int i = tid; i < rows; i += kTC) perm[i] = i;
+  __syncthreads();
+  const int sub = tid % kTPR, slot = tid / kTPR, nslot = kTC / kTPR;
   for (; t < kmax; ++t) {
     // residual row norms: kTPR lanes per row, reduced by shuffles
     T best = (T)-1;
@@ -216,7 +319,7 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
       for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
       if (pp < rows && sub == 0 && (nrm > best || (nrm == best && pp < bi))) { best = nrm; bi = pp; }
     }
-    block_argmax(best, bi, sv, si);
+    block_argmax<kTC>(best, bi, sv, si);
     T pn = sqrt(best);
     if (t == 0) first = pn;
     if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
@@ -228,7 +331,7 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
     __syncthreads();
     const int prow = perm[t];
     T inv = (T)1 / pn;
-    for (int j = tid; j < s; j += kT) q[j] = inv * Wm[prow + (long)j * rcap];
+    for (int j = tid; j < s; j += kTC) q[j] = inv * Wm[prow + (long)j * rcap];
     if (tid == 0) Rm[t + (long)prow * C.k_cap] = mk(pn, (T)0);
     __syncthreads();
     for (int pp0 = t + 1; pp0 < rows; pp0 += nslot) {
@@ -252,16 +355,17 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
     }
     __syncthreads();
   }
+  }  // global-memory pivoted QR
   const int rk = t;
   if (tid == 0) s_rank = rk;
   __syncthreads();
 
   // U (rows x rk): identity rows at the skeleton, T^T = (R11^-1 R12)^T elsewhere
   cplx<T> *U = P + C.U;
-  for (int e = tid; e < rows * rk; e += kT) U[e] = czero<T>();
+  for (int e = tid; e < rows * rk; e += kTC) U[e] = czero<T>();
   __syncthreads();
-  for (int a = tid; a < rk; a += kT) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
-  for (int c2 = tid; c2 < rows - rk; c2 += kT) {
+  for (int a = tid; a < rk; a += kTC) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
+  for (int c2 = tid; c2 < rows - rk; c2 += kTC) {
     int row = perm[rk + c2];
     // back substitution, solution written straight into U(row, :)
     for (int a = rk - 1; a >= 0; --a) {
@@ -273,9 +377,9 @@ __global__ __launch_bounds__(kT) void compress_level_kernel(
   }
   __syncthreads();
   int *sk = IP + C.sk;
-  for (int a = tid; a < rk; a += kT) sk[a] = I_loc[perm[a]];
+  for (int a = tid; a < rk; a += kTC) sk[a] = I_loc[perm[a]];
   cplx<T> *Omc = P + C.Om, *Src = P + C.Sr;
-  for (int e = tid; e < rk * s; e += kT) {
+  for (int e = tid; e < rk * s; e += kTC) {
     int a = e % rk, j = e / rk;
     cplx<T> o = czero<T>();
     for (int i = 0; i < rows; ++i) cfma(o, U[i + (long)a * rows], Oloc[i + (long)j * rcap]);
@@ -454,7 +558,7 @@ void launch_compress_level(int count, const HssItem *items, const HssInstance *i
                            const cplx<T> *front, const cplx<T> *Y, const double *Om,
                            cplx<T> *scratch, double id_tol, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(compress_level_kernel<T>, dim3(count), dim3(kT), 0, st, items, inst, cl,
+  hipLaunchKernelGGL(compress_level_kernel<T>, dim3(count), dim3(kTC), 0, st, items, inst, cl,
                      pool, ipool, rank, front, Y, Om, scratch, id_tol);
   HSSX_HIP(hipGetLastError());
 }
