@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--tol", type=float, default=None,
+                    help="HSS tolerance of the complex64 factor (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
@@ -113,7 +115,9 @@ def main():
     torch.cuda.synchronize()
     L = _lib.lib()
 
-    def step(dtype, flexible, tol_hss=pr.tol):
+    tol_mixed = args.tol if args.tol is not None else pr.tol
+
+    def step(dtype, flexible, tol_hss=tol_mixed):
         P = hssx.Factor(A, tol=tol_hss, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
                         dtype=dtype, seed=1)
         x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol, flexible=flexible)
@@ -207,7 +211,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "c64 factor / f64 Krylov",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": pr.N, "n": pr.n, "omega": pr.omega,
-                   "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": pr.tol,
+                   "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": tol_mixed,
                    "nd_leaf_dofs": pr.leaf_dofs, "hss_leaf": pr.beta, "h_sw": pr.h_sw,
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
         "gmres_iters_max": max(iters), "gmres_iters_mean": sum(iters) / len(iters),

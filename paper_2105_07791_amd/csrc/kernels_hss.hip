@@ -13,8 +13,8 @@
 //           interpolative decomposition S_loc ~ U S_loc(J, :) comes from a
 //           pivoted Gram-Schmidt QR of S_loc^T (pivot = largest remaining row
 //           norm, lowest row index on ties; each projection applied twice;
-//           for complex64 and blocks up to 256 x 160 the rows stay in
-//           registers, 8 lanes per row), rank =
+//           for complex64 and blocks up to 256 x 192 the rows stay in
+//           registers, 16 lanes per row), rank =
 //           min(k, rows, s) reduced to the pivots above id_tol * first pivot;
 //           T = R11^-1 R12, U(J, :) = I, U(rest, :) = T^T.  The cluster keeps
 //           Om_c = U^T Om_loc, Sr_c = S_loc(J, :), skeleton I_loc(J).  The
@@ -30,11 +30,11 @@ namespace hssx {
 namespace {
 
 constexpr int kT = 1024;         // threads per workgroup of the HSS matvec
-constexpr int kTC = 512;         // threads per workgroup of the compression
+constexpr int kTC = 1024;        // threads per workgroup of the compression
 constexpr int kTPR = 4;          // lanes per row in the global-memory pivoted QR
-// register-resident pivoted QR (complex64): 8 lanes per row, 64 row slots,
-// 4 rows per slot, 20 columns per lane -> rows <= 256, sample columns <= 160
-constexpr int kRT = 8, kRS = kTC / kRT, kRPT = 4, kRSEG = 20;
+// register-resident pivoted QR (complex64): 16 lanes per row, 64 row slots,
+// 4 rows per slot, 12 columns per lane -> rows <= 256, sample columns <= 192
+constexpr int kRT = 16, kRS = kTC / kRT, kRPT = 4, kRSEG = 12;
 constexpr int kMaxRows = 1024;   // rows of one local sample block (LDS index arrays)
 constexpr int kMaxS = 1024;      // sample columns held in LDS for the projector
 
