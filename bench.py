@@ -94,6 +94,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--alt-tol", type=float, default=1e-4,
+                    help="also time the complex64 form at this HSS tolerance (0: skip)")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args.workload)
@@ -172,6 +177,26 @@ def main():
             "avg_launch_us": avg_s * 1e6}
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in kern.items()}
 
+    alt = None
+    if args.alt_tol and args.alt_tol != tol_mixed:
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        Pa, xa, sa = step("c64", True, tol_hss=args.alt_tol)
+        torch.cuda.synchronize()
+        ta1 = time.perf_counter()
+        ra = (torch.linalg.vector_norm(A.matvec(xa) - b, dim=0)
+              / torch.linalg.vector_norm(b, dim=0)).max().item()
+        alt = {"hss_tol": args.alt_tol, "seconds": ta1 - ta0,
+               "gmres_iters_max": max(v["iters"] for v in sa), "true_res_max": ra,
+               "k_max": Pa.stats()["k_max"]}
+        print(f"[bench] c64 form at tol {args.alt_tol}: {ta1 - ta0:.3f}s", file=sys.stderr,
+              flush=True)
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     plain = None
     if not args.no_plain:
         torch.cuda.synchronize()
@@ -221,6 +246,7 @@ def main():
         "max_estimate": fstats["max_estimate"], "hss_nodes": fstats["n_hss_nodes"],
         "kernel_ms_per_step": kernel_ms,
         "plain_fp64": plain,
+        "mixed_alt_tol": alt,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
