@@ -176,6 +176,17 @@ def main():
             "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
             "avg_launch_us": avg_s * 1e6}
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in kern.items()}
+    # HBM traffic per launch from the committed counter measurement, valid only
+    # while the measured kernel's source is unchanged
+    try:
+        import hashlib
+        tj = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        src = open(os.path.join(ROOT, tj["source"]), "rb").read()
+        if tj["kernel"] == dom and hashlib.sha256(src).hexdigest() == tj["source_sha256"]:
+            roof["traffic"] = tj["traffic_bytes_per_launch"]
+            roof["traffic_source"] = "profiles/" + tj["profile"]
+    except (OSError, KeyError, ValueError):
+        pass
 
     alt = None
     if args.alt_tol and args.alt_tol != tol_mixed:
