@@ -135,8 +135,8 @@ def _front(A, tree, k, child_S):
 def _interior_tree(box):
     """Cluster tree of the P0 part of a node's boundary (its S_ii block)."""
     ct = box.ctree
-    if ct.nclusters == 0:
-        return ct
+    if ct.nclusters == 0 or box.p0 == 0:     # no P0 part: empty tree
+        return type(ct)(*(np.zeros(0, np.int64) for _ in range(5)))
     if box.p0 == box.B.size:                 # no P1 part: the whole tree
         return ct
     return subtree(ct, int(ct.left[0]))
@@ -155,7 +155,7 @@ def factor_approx(A, tree, h_sw=4, tol=1e-6, k0=32, r=16, seed=0,
         ni = bx.I.size
         Aii, Aib = F[:ni, :ni], F[:ni, ni:]
         Abi, Abb = F[ni:, :ni], F[ni:, ni:]
-        if f.arith[k] == "hss" and k != root and ni:
+        if f.arith[k] == "hss" and k != root and ni > tree.boxes[bx.lo].p0:
             mu = tree.boxes[bx.lo]
             p = mu.p0
             B11, B12 = Aii[:p, :p], Aii[:p, p:]

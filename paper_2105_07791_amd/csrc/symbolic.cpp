@@ -202,7 +202,8 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
 
 ClusterTree interior_subtree(const NDNode &nd) {
   const ClusterTree &ct = nd.ct;
-  if (ct.count() == 0 || nd.p0 == (int)nd.B.size()) return ct;
+  if (ct.count() == 0 || nd.p0 == 0) return ClusterTree();   // no P0 part
+  if (nd.p0 == (int)nd.B.size()) return ct;                  // no P1 part
   ClusterTree out;
   std::vector<std::pair<int, int>> q{{ct.left[0], 0}};
   for (size_t k = 0; k < q.size(); ++k) {

@@ -45,7 +45,7 @@ struct Symbolic {
 Symbolic build_symbolic(int N, int leaf_dofs, int beta);
 
 // Cluster tree of the P0 block of a node's boundary: the left subtree of the
-// top split, or the whole tree when the node has no P1 part.  Positions are
+// top split, the whole tree when the node has no P1 part, empty without P0.  Positions are
 // relative to the subtree's first position (which is 0).
 ClusterTree interior_subtree(const NDNode &nd);
 
