@@ -161,7 +161,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     std::vector<int> owner(A->n, -1), opos(A->n, -1);
     long foff = 0;
     double fbytes = 0, flops = 0;
-    const size_t esz = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
+    const size_t esz_pool = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
     for (int k = 0; k < nn; ++k) {
       const NDNode &nd = sym.nodes[k];
       FrontDesc &d = dsc[k];
@@ -196,9 +196,22 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
         for (int v : sym.nodes[nd.lo].B) owner[v] = -1;
         for (int v : sym.nodes[nd.hi].B) owner[v] = -1;
       }
-      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * esz;
+      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * esz_pool;
       // Gauss-Jordan on f rows x (f + ni) columns, complex multiply-add = 8 flops
       for (int p = 0; p < d.ni; ++p) flops += 8.0 * (d.f - 1) * (d.f + d.ni - p - 1);
+    }
+    // complex64 factors keep the root front in complex128 in a buffer of its
+    // own (the root is last in post-order, so the pool simply ends before it)
+    const int root = nn - 1;
+    const long root_elems = (long)dsc[root].f * (dsc[root].f + dsc[root].ni);
+    if (o.dtype == HSSX_C64) {
+      foff -= root_elems;
+      const FrontDesc &r = dsc[root];
+      fbytes += ((double)r.ni * r.ni + 2.0 * r.ni * r.nb) * (sizeof(c128) - sizeof(c64));
+      std::vector<FrontDesc> d64 = dsc;
+      d64[root].foff = 0;
+      upload(P->desc64, d64);
+      P->front64.alloc(std::max(1L, root_elems) * sizeof(c128));
     }
     P->h_desc = dsc;
     upload(P->desc, dsc);
@@ -220,6 +233,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       upload(P->depth_dev[d], P->depth_nodes[d]);
       for (int k : P->depth_nodes[d]) {
         const FrontDesc &q = dsc[k];
+        const size_t esz = k == root ? sizeof(c128) : esz_pool;
         P->depth_max_ni[d] = std::max(P->depth_max_ni[d], q.ni);
         P->depth_max_nb[d] = std::max(P->depth_max_nb[d], q.nb);
         P->depth_max_f[d] = std::max(P->depth_max_f[d], q.f);
@@ -234,7 +248,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
         P->asm_bytes[d] += (double)q.f * (q.f + q.ni) * esz;
       }
     }
-    P->front.alloc(std::max(1L, foff) * esz);
+    P->front.alloc(std::max(1L, foff) * esz_pool);
     auto t1 = std::chrono::steady_clock::now();
     P->stats.ms_symbolic = std::chrono::duration<double, std::milli>(t1 - t0).count();
     P->stats.n = A->n;
@@ -361,6 +375,7 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
                "invalid argument");
     const FrontDesc &d = P->h_desc[node];
     HSSX_CHECK(ld >= d.nb, HSSX_EINVAL, "ld < |B|");
+    if (d.nb == 0) return;   // the root: no Schur complement
     DeviceScope ds(P->A->device);
     HSSX_HIP(hipDeviceSynchronize());
     const size_t esz = P->dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);

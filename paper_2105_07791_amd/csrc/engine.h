@@ -28,6 +28,9 @@ struct hssx_fact_ {
   std::vector<int> arith, comp; // per node: HSS arithmetic, compressed S
   std::vector<hssx::FrontDesc> h_desc;
   hssx::DevBuf desc, bpos, src_gid, src_child, src_pos, perm, front;
+  // complex64 factors keep the root (top separator) in complex128: its front
+  // lives in front64 and desc64 is the descriptor table with the root at 0
+  hssx::DevBuf front64, desc64;
   // per depth (index = depth): nodes, and the largest |I|, |B|, front size
   std::vector<std::vector<int>> depth_nodes;
   std::vector<hssx::DevBuf> depth_dev;

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "engine.h"
 
@@ -427,10 +428,31 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     const auto &nodes = P.depth_nodes[d];
     if (nodes.empty()) continue;
     const int cnt = (int)nodes.size();
+    if (std::is_same<T, float>::value && d == 0) {
+      // complex64 factor: the root front (the top separator) is assembled
+      // from the children's complex64 Schur blocks into complex128 storage
+      // and eliminated in FP64
+      const FrontDesc &fd = P.h_desc[root];
+      hipEvent_t pa = prof_begin(st);
+      launch_front_assemble<double, T>(1, P.depth_dev[0].as<int>(), desc, P.src_gid.as<int>(),
+                                       P.src_child.as<int>(), P.src_pos.as<int>(),
+                                       A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), F,
+                                       P.front64.as<c128>(), 0, st, fd.f);
+      prof_end("front_assemble", st, pa, P.asm_bytes[0]);
+      std::vector<ElimJob<double>> rj{
+          ElimJob<double>{P.front64.as<c128>(), fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, root}};
+      hipEvent_t pe = prof_begin(st);
+      eliminate_jobs<double>(rj, err.as<int>(), sg);
+      prof_end("front_eliminate", st, pe, elim_flops(rj));
+      HSSX_HIP(hipStreamSynchronize(st));
+      sg.recycle();
+      continue;
+    }
     hipEvent_t pa = prof_begin(st);
-    launch_front_assemble<T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
-                             P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
-                             A.col.as<int>(), A.val.as<c128>(), F, st, P.depth_max_f[d]);
+    launch_front_assemble<T, T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
+                                P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
+                                A.col.as<int>(), A.val.as<c128>(), F, F, -1, st,
+                                P.depth_max_f[d]);
     prof_end("front_assemble", st, pa, P.asm_bytes[d]);
 
     // ---- HSS-arithmetic interiors: compress S~ and substitute it (Alg. 3.3)
@@ -588,7 +610,11 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     int cnt = (int)P.depth_nodes[d].size();
     if (!cnt) continue;
     hipEvent_t pu = prof_begin(st);
-    if (P.dtype == HSSX_C128)
+    if (P.dtype == HSSX_C64 && d == 0)
+      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), P.desc64.as<FrontDesc>(),
+                              P.front64.as<c128>(), P.bpos.as<int>(), tb, w, n, nrhs, trans,
+                              P.depth_max_ni[d], P.depth_max_f[d], st);
+    else if (P.dtype == HSSX_C128)
       launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
                               P.bpos.as<int>(), tb, w, n, nrhs, trans, P.depth_max_ni[d],
                               P.depth_max_f[d], st);
@@ -602,7 +628,11 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     int cnt = (int)P.depth_nodes[d].size();
     if (!cnt) continue;
     hipEvent_t pd = prof_begin(st);
-    if (P.dtype == HSSX_C128)
+    if (P.dtype == HSSX_C64 && d == 0)
+      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), P.desc64.as<FrontDesc>(),
+                                P.front64.as<c128>(), P.bpos.as<int>(), w, n, nrhs, trans,
+                                P.depth_max_nb[d], P.depth_max_ni[d], st);
+    else if (P.dtype == HSSX_C128)
       launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
                                 P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d],
                                 P.depth_max_ni[d], st);

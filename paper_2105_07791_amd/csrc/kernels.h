@@ -36,13 +36,16 @@ struct FrontDesc {
 };
 
 // Assemble the augmented fronts of `count` nodes (ids in nodes[]): entries
-// from the children's Schur blocks (same child) or from A (natural CSR,
-// c128), and the identity block.
-template <typename T>
+// from the children's Schur blocks (same child, read from cpool) or from A
+// (natural CSR, c128), and the identity block.  A front is written to
+// opool + foff (or opool + ooff when ooff >= 0, for a single node kept in a
+// buffer of its own).
+template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
                            const int *src_gid, const int *src_child, const int *src_pos,
                            const int *rowptr, const int *col, const c128 *val,
-                           cplx<T> *pool, hipStream_t st, int max_f);
+                           const cplx<Tc> *cpool, cplx<T> *opool, long ooff, hipStream_t st,
+                           int max_f);
 
 // Elimination job: Gauss-Jordan elimination of the first ne columns of the
 // m x ncols matrix at ptr (leading dimension ld), partial pivoting among the

@@ -20,12 +20,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <typename T>
+template <typename T, typename Tc>
 __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
     const int *__restrict__ nodes, const FrontDesc *__restrict__ desc,
     const int *__restrict__ src_gid, const int *__restrict__ src_child,
     const int *__restrict__ src_pos, const int *__restrict__ rowptr,
-    const int *__restrict__ col, const c128 *__restrict__ val, cplx<T> *__restrict__ pool) {
+    const int *__restrict__ col, const c128 *__restrict__ val,
+    const cplx<Tc> *__restrict__ cpool, cplx<T> *__restrict__ opool, long ooff) {
   const FrontDesc d = desc[nodes[blockIdx.x]];
   const long f = d.f;
   const long total = f * (f + d.ni);
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
   const int *gid = src_gid + d.src_off;
   const int *chd = src_child + d.src_off;
   const int *pos = src_pos + d.src_off;
-  cplx<T> *F = pool + d.foff;
+  cplx<T> *F = opool + (ooff >= 0 ? ooff : d.foff);
   for (long e = e0 + threadIdx.x; e < e1; e += kThreads) {
     int p = (int)(e % f), q = (int)(e / f);
     cplx<T> v;
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
       int cp = chd[p], cq = chd[q];
       if (cp >= 0 && cp == cq) {
         const FrontDesc c = desc[cp == 0 ? d.lo : d.hi];
-        v = pool[c.foff + (long)(c.ni + pos[p]) + (long)(c.ni + pos[q]) * c.f];
+        v = ccast<T>(cpool[c.foff + (long)(c.ni + pos[p]) + (long)(c.ni + pos[q]) * c.f]);
       } else {
         int gi = gid[p], gj = gid[q];
         c128 a = czero<double>();
@@ -280,16 +281,18 @@ __global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
 
 }  // namespace
 
-template <typename T>
+template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
                            const int *src_gid, const int *src_child, const int *src_pos,
                            const int *rowptr, const int *col, const c128 *val,
-                           cplx<T> *pool, hipStream_t st, int max_f) {
+                           const cplx<Tc> *cpool, cplx<T> *opool, long ooff, hipStream_t st,
+                           int max_f) {
   if (count <= 0) return;
   long per = (long)kThreads * 16;
   int ny = ceil_div((long)max_f * (2L * max_f), per);
-  hipLaunchKernelGGL(front_assemble_kernel<T>, dim3(count, ny), dim3(kThreads), 0, st, nodes,
-                     desc, src_gid, src_child, src_pos, rowptr, col, val, pool);
+  hipLaunchKernelGGL((front_assemble_kernel<T, Tc>), dim3(count, ny), dim3(kThreads), 0, st,
+                     nodes, desc, src_gid, src_child, src_pos, rowptr, col, val, cpool, opool,
+                     ooff);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -322,10 +325,17 @@ void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipS
   HSSX_HIP(hipGetLastError());
 }
 
+#define HSSX_ASM(T, Tc)                                                                      \
+  template void launch_front_assemble<T, Tc>(int, const int *, const FrontDesc *, const int *, \
+                                             const int *, const int *, const int *,           \
+                                             const int *, const c128 *, const cplx<Tc> *,     \
+                                             cplx<T> *, long, hipStream_t, int);
+HSSX_ASM(double, double)
+HSSX_ASM(float, float)
+HSSX_ASM(double, float)
+#undef HSSX_ASM
+
 #define HSSX_INST(T)                                                                        \
-  template void launch_front_assemble<T>(int, const int *, const FrontDesc *, const int *,  \
-                                         const int *, const int *, const int *, const int *, \
-                                         const c128 *, cplx<T> *, hipStream_t, int);         \
   template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int *, hipStream_t); \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);
