@@ -117,6 +117,26 @@ typedef struct {
 hssx_status hssx_assemble(int device, const hssx_problem_desc *desc,
                           const double *s_dev, void *stream, hssx_op *A_out);
 
+/* Batch of independent problems as one block-diagonal operator (the
+ * batching form: fronts of one tree depth, across all problems, are
+ * eliminated and compressed in the same launches, and GMRES advances every
+ * problem's Krylov basis together).  parts: count single-problem operators
+ * (from hssx_assemble) on one device; their CSR, mass matrix and slowness
+ * are copied, so the parts may be destroyed afterwards.  Part p owns rows
+ * [off[p], off[p+1]) with off the running sum of the parts' n.  The batch
+ * works with hssx_load, hssx_matvec, hssx_factor (a forest: one nested
+ * dissection tree per part), hssx_apply, hssx_gmres_solve and
+ * hssx_dAds_contract on vectors of the concatenated length.  EINVAL for an
+ * empty list, a part that is itself a batch, mixed devices, or more than
+ * 2^31 - 1 rows or nonzeros. */
+hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream,
+                          hssx_op *A_out);
+
+/* Size of an operator: *n rows in total, *parts problems (1 unless built by
+ * hssx_op_batch), and part_off (host int32[parts + 1], may be NULL) the row
+ * offsets of the parts.  Host-only. */
+hssx_status hssx_op_info(hssx_op A, int *n, int *parts, int32_t *part_off);
+
 /* b = M f with M the plain P1 mass matrix: the load of nodal source samples
  * f (device, float64, n x nrhs, ld ldf) into b (device, complex128, ld ldb).*/
 hssx_status hssx_load(hssx_op A, int nrhs, const double *f_dev, long ldf,
@@ -137,9 +157,12 @@ hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col,
  * are small), dense elimination below the switching height, Schur
  * complements compressed to HSS by adaptive randomized sampling (Algorithm
  * A.1, relative tolerance tol, eq. 2.7), and the HSS-class interior blocks
- * handled by the 2x2 block inverse of Algorithms 3.2/3.3.  Host-blocking:
- * synchronises stream after every batch of compressions to read the error
- * estimates.  opts may be NULL (defaults). */
+ * handled by the 2x2 block inverse of Algorithms 3.2/3.3.  With dtype
+ * HSSX_C64 every front is stored and eliminated in complex64 except the
+ * roots (top separators), which stay complex128.  A batch operator gets one
+ * tree per problem, all processed depth by depth in the same launches.
+ * Host-blocking: synchronises stream after every batch of compressions to
+ * read the error estimates.  opts may be NULL (defaults). */
 hssx_status hssx_factor(hssx_op A, double tol, int leaf_size,
                         const hssx_factor_opts *opts, void *stream,
                         hssx_fact *P_out);
@@ -152,8 +175,11 @@ hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev,
 
 /* Restarted GMRES on A x = b (eq. 1.2) with preconditioner P, all nrhs
  * right-hand sides advanced together; x0 = 0.  trans = 1 solves A^T x = b
- * with P^-T (adjoint solves).  stats: host array of nrhs entries (may be
- * NULL).  Host-blocking: reads residual norms once per Arnoldi step. */
+ * with P^-T (adjoint solves).  Each (right-hand side, problem) pair is its
+ * own system with its own Krylov basis and stopping test; for a batch of np
+ * problems, system r * np + p is part p of column r.  stats: host array of
+ * nrhs * np entries in that order (may be NULL).  Host-blocking: reads
+ * residual norms once per Arnoldi step. */
 hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs,
                              const void *b_dev, long ldb, void *x_dev,
                              long ldx, const hssx_gmres_opts *opts,
@@ -164,7 +190,7 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs,
  * as solved by the caller.  lambda, x: device complex128 n x nrhs (ld n);
  * grad_s: device float64[n], accumulated.  dA/ds_l =
  * -2 omega^2 s_l M_l - i omega G_l with M_l, G_l the P1 triple-product
- * matrices of node l. */
+ * matrices of node l (of the node's own problem for a batch). */
 hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev,
                                const void *x_dev, double *grad_dev,
                                void *stream);

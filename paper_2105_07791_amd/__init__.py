@@ -7,7 +7,7 @@ from ._lib import HssxError, lib  # noqa: F401
 def __getattr__(name):
     # the torch-facing binding is imported lazily so that the C-ABI loader
     # can be checked without initialising a GPU
-    if name in ("Operator", "Factor", "assemble", "factor", "gmres_solve"):
+    if name in ("Operator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"):
         from . import hssx
         return getattr(hssx, name)
     if name in ("WaveSolve",):

@@ -50,6 +50,8 @@ _dp = C.POINTER(C.c_double)
 
 SIGNATURES = {
     "hssx_assemble": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, C.POINTER(_vp)]),
+    "hssx_op_batch": (_i, [_i, C.POINTER(_vp), _vp, C.POINTER(_vp)]),
+    "hssx_op_info": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), _ip]),
     "hssx_load": (_i, [_vp, _i, _vp, _l, _vp, _l, _vp]),
     "hssx_matvec": (_i, [_vp, _i, _i, _vp, _l, _vp, _l, _vp]),
     "hssx_get_csr": (_i, [_vp, _ip, _ip, _dp, C.POINTER(_l), _vp]),

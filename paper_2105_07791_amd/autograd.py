@@ -9,10 +9,24 @@ g = dL/dRe(x) + i dL/dIm(x), dL = Re(g^H dx) and dx = -A^-1 (dA) x, so
     dL/db   = conj(lambda)
 
 All three steps run in libhssx.so; this module only marshals tensors.
+A batch of uneven problems (N and omega given as lists) is one
+block-diagonal operator: s, b and x are the parts' vectors stacked.
 """
 import torch
 
-from .hssx import Factor, Operator, gmres_solve
+from .hssx import BatchOperator, Factor, Operator, gmres_solve
+
+
+def _operator(s, N, omega):
+    if isinstance(N, (list, tuple)):
+        om = list(omega) if isinstance(omega, (list, tuple)) else [omega] * len(N)
+        parts, o = [], 0
+        for Nq, wq in zip(N, om):
+            parts.append(Operator(int(Nq), float(wq), s[o:o + Nq * Nq]))
+            o += Nq * Nq
+        assert o == s.numel(), "slowness length does not match the grids"
+        return BatchOperator(parts)
+    return Operator(N, omega, s)
 
 __all__ = ["WaveSolve", "solve"]
 
@@ -23,7 +37,7 @@ class WaveSolve(torch.autograd.Function):
         opts = dict(opts or {})
         gm = dict(m=opts.pop("gmres_m", 50), tol=opts.pop("gmres_tol", 1e-8),
                   flexible=opts.pop("flexible", False))
-        A = Operator(N, omega, s.detach())
+        A = _operator(s.detach(), N, omega)
         P = Factor(A, **opts)
         x, st = gmres_solve(A, P, b.detach(), **gm)
         ctx.A, ctx.P, ctx.gm, ctx.stats = A, P, gm, st
@@ -41,5 +55,6 @@ class WaveSolve(torch.autograd.Function):
 
 
 def solve(s, b, N, omega, **opts):
-    """x = A(s)^-1 b, differentiable in the slowness s and the load b."""
+    """x = A(s)^-1 b, differentiable in the slowness s and the load b.  N and
+    omega may be lists (a batch of problems, vectors stacked part by part)."""
     return WaveSolve.apply(s, b, N, omega, opts)

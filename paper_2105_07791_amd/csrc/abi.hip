@@ -83,8 +83,78 @@ hssx_status hssx_assemble(int device, const hssx_problem_desc *desc, const doubl
     HSSX_HIP(hipMemcpyAsync(A->s.p, s_dev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
     launch_assemble(N, desc->omega, A->s.as<double>(), A->rowptr.as<int>(), A->col.as<int>(),
                     A->val.as<c128>(), A->mval.as<double>(), S(stream));
+    A->part_N = {N};
+    A->part_omega = {desc->omega};
+    A->part_off = {0, n};
+    upload(A->part_off_dev, A->part_off);
     HSSX_HIP(hipStreamSynchronize(S(stream)));
     *A_out = A.release();
+  });
+}
+
+hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op *A_out) {
+  return guarded([&] {
+    HSSX_CHECK(parts && A_out && count >= 1, HSSX_EINVAL, "invalid argument");
+    *A_out = nullptr;
+    long n = 0, nnz = 0;
+    for (int q = 0; q < count; ++q) {
+      HSSX_CHECK(parts[q] && parts[q]->part_N.size() == 1, HSSX_EINVAL,
+                 "batch parts must be single-problem operators");
+      HSSX_CHECK(parts[q]->device == parts[0]->device, HSSX_EINVAL, "parts on different devices");
+      n += parts[q]->n;
+      nnz += parts[q]->nnz;
+    }
+    HSSX_CHECK(n < (1L << 31) && nnz < (1L << 31), HSSX_EINVAL, "batch too large for 32-bit indices");
+    DeviceScope ds(parts[0]->device);
+    hipStream_t st = S(stream);
+    auto A = std::make_unique<hssx_op_>();
+    A->device = parts[0]->device;
+    A->n = (int)n;
+    A->nnz = nnz;
+    A->h_rowptr.reserve(n + 1);
+    A->h_col.reserve(nnz);
+    A->h_rowptr.push_back(0);
+    A->part_off.push_back(0);
+    std::vector<int> row_part;
+    row_part.reserve(n);
+    for (int q = 0; q < count; ++q) {
+      const hssx_op_ &B = *parts[q];
+      const int r0 = A->part_off.back(), e0 = (int)A->h_col.size();
+      for (int i = 0; i < B.n; ++i) A->h_rowptr.push_back(e0 + B.h_rowptr[i + 1]);
+      for (int c : B.h_col) A->h_col.push_back(r0 + c);
+      A->part_N.push_back(B.N);
+      A->part_omega.push_back(B.omega);
+      A->part_off.push_back(r0 + B.n);
+      row_part.insert(row_part.end(), B.n, q);
+    }
+    upload(A->rowptr, A->h_rowptr);
+    upload(A->col, A->h_col);
+    upload(A->part_off_dev, A->part_off);
+    upload(A->row_part_dev, row_part);
+    A->val.alloc(nnz * sizeof(c128));
+    A->mval.alloc(nnz * sizeof(double));
+    A->s.alloc(n * sizeof(double));
+    for (int q = 0; q < count; ++q) {
+      const hssx_op_ &B = *parts[q];
+      const long e0 = A->h_rowptr[A->part_off[q]], r0 = A->part_off[q];
+      HSSX_HIP(hipMemcpyAsync(A->val.as<c128>() + e0, B.val.p, B.nnz * sizeof(c128),
+                              hipMemcpyDeviceToDevice, st));
+      HSSX_HIP(hipMemcpyAsync(A->mval.as<double>() + e0, B.mval.p, B.nnz * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+      HSSX_HIP(hipMemcpyAsync(A->s.as<double>() + r0, B.s.p, B.n * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+    }
+    HSSX_HIP(hipStreamSynchronize(st));
+    *A_out = A.release();
+  });
+}
+
+hssx_status hssx_op_info(hssx_op A, int *n, int *parts, int32_t *part_off) {
+  return guarded([&] {
+    HSSX_CHECK(A, HSSX_EINVAL, "null operator");
+    if (n) *n = A->n;
+    if (parts) *parts = (int)A->part_N.size();
+    if (part_off) std::memcpy(part_off, A->part_off.data(), A->part_off.size() * sizeof(int));
   });
 }
 
@@ -146,7 +216,13 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->leaf = leaf_size;
     P->opts = o;
     auto t0 = std::chrono::steady_clock::now();
-    P->sym = build_symbolic(A->N, leaf_size, o.beta);
+    if (A->part_N.size() == 1) {
+      P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta);
+    } else {
+      std::vector<Symbolic> parts;
+      for (int N : A->part_N) parts.push_back(build_symbolic(N, leaf_size, o.beta));
+      P->sym = merge_forest(parts, A->part_off);
+    }
     const Symbolic &sym = P->sym;
     const int nn = (int)sym.nodes.size();
     P->arith.assign(nn, 0);
@@ -159,7 +235,10 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     std::vector<FrontDesc> dsc(nn);
     std::vector<int> bpos, sg, sc, sp;
     std::vector<int> owner(A->n, -1), opos(A->n, -1);
-    long foff = 0;
+    // complex64 factors keep the roots' fronts in complex128, in a buffer of
+    // their own (offsets roff)
+    const bool split_roots = o.dtype == HSSX_C64;
+    long foff = 0, roff = 0;
     double fbytes = 0, flops = 0;
     const size_t esz_pool = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
     for (int k = 0; k < nn; ++k) {
@@ -168,8 +247,10 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       d.ni = (int)nd.I.size();
       d.nb = (int)nd.B.size();
       d.f = d.ni + d.nb;
-      d.foff = foff;
-      foff += (long)d.f * (d.f + d.ni);
+      const bool in64 = split_roots && nd.parent < 0;
+      long &off = in64 ? roff : foff;
+      d.foff = off;
+      off += (long)d.f * (d.f + d.ni);
       d.ioff = nd.offset;
       d.bpos_off = (int)bpos.size();
       for (int v : nd.B) bpos.push_back(sym.iperm[v]);
@@ -196,22 +277,9 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
         for (int v : sym.nodes[nd.lo].B) owner[v] = -1;
         for (int v : sym.nodes[nd.hi].B) owner[v] = -1;
       }
-      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * esz_pool;
+      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * (in64 ? sizeof(c128) : esz_pool);
       // Gauss-Jordan on f rows x (f + ni) columns, complex multiply-add = 8 flops
       for (int p = 0; p < d.ni; ++p) flops += 8.0 * (d.f - 1) * (d.f + d.ni - p - 1);
-    }
-    // complex64 factors keep the root front in complex128 in a buffer of its
-    // own (the root is last in post-order, so the pool simply ends before it)
-    const int root = nn - 1;
-    const long root_elems = (long)dsc[root].f * (dsc[root].f + dsc[root].ni);
-    if (o.dtype == HSSX_C64) {
-      foff -= root_elems;
-      const FrontDesc &r = dsc[root];
-      fbytes += ((double)r.ni * r.ni + 2.0 * r.ni * r.nb) * (sizeof(c128) - sizeof(c64));
-      std::vector<FrontDesc> d64 = dsc;
-      d64[root].foff = 0;
-      upload(P->desc64, d64);
-      P->front64.alloc(std::max(1L, root_elems) * sizeof(c128));
     }
     P->h_desc = dsc;
     upload(P->desc, dsc);
@@ -233,7 +301,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       upload(P->depth_dev[d], P->depth_nodes[d]);
       for (int k : P->depth_nodes[d]) {
         const FrontDesc &q = dsc[k];
-        const size_t esz = k == root ? sizeof(c128) : esz_pool;
+        const size_t esz = split_roots && sym.nodes[k].parent < 0 ? sizeof(c128) : esz_pool;
         P->depth_max_ni[d] = std::max(P->depth_max_ni[d], q.ni);
         P->depth_max_nb[d] = std::max(P->depth_max_nb[d], q.nb);
         P->depth_max_f[d] = std::max(P->depth_max_f[d], q.f);
@@ -249,6 +317,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       }
     }
     P->front.alloc(std::max(1L, foff) * esz_pool);
+    if (split_roots) P->front64.alloc(std::max(1L, roff) * sizeof(c128));
     auto t1 = std::chrono::steady_clock::now();
     P->stats.ms_symbolic = std::chrono::duration<double, std::milli>(t1 - t0).count();
     P->stats.n = A->n;
@@ -289,7 +358,8 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const 
           S(stream));
   });
   if (st == HSSX_OK && stats) {
-    for (int r = 0; r < nrhs; ++r)
+    const int nseg = nrhs * (int)A->part_N.size();
+    for (int r = 0; r < nseg; ++r)
       if (!stats[r].converged) { g_err = "GMRES did not reach the tolerance"; return HSSX_ENOCONV; }
   }
   return st;
@@ -300,8 +370,12 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, cons
   return guarded([&] {
     HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
     DeviceScope ds(A->device);
-    launch_dads(A->N, A->omega, A->s.as<double>(), nrhs, (const c128 *)lambda_dev,
-                (const c128 *)x_dev, grad_dev, S(stream));
+    for (size_t q = 0; q < A->part_N.size(); ++q) {
+      const int o = A->part_off[q];
+      launch_dads(A->part_N[q], A->part_omega[q], A->s.as<double>() + o, nrhs,
+                  (const c128 *)lambda_dev + o, (const c128 *)x_dev + o, A->n, grad_dev + o,
+                  S(stream));
+    }
   });
 }
 

@@ -10,12 +10,22 @@
 
 struct hssx_op_ {
   int device = 0;
-  int N = 0;
+  int N = 0;          // grid side (0 for a batch of problems)
   double omega = 0;
   int n = 0;
   long nnz = 0;
   hssx::DevBuf rowptr, col, val, mval, s;
   std::vector<int> h_rowptr, h_col;
+  // A batch of independent problems is one block-diagonal operator: part p
+  // owns rows [part_off[p], part_off[p+1]) and is the grid of side part_N[p]
+  // at frequency part_omega[p].  A single problem is the batch of one.
+  std::vector<int> part_N, part_off;
+  std::vector<double> part_omega;
+  hssx::DevBuf part_off_dev, row_part_dev;   // row_part_dev only for batches
+  hssx::Segs segs() const {
+    return hssx::Segs{(int)part_N.size(), part_off_dev.as<int>(),
+                      part_N.size() > 1 ? row_part_dev.as<int>() : nullptr};
+  }
 };
 
 struct hssx_fact_ {
@@ -28,9 +38,9 @@ struct hssx_fact_ {
   std::vector<int> arith, comp; // per node: HSS arithmetic, compressed S
   std::vector<hssx::FrontDesc> h_desc;
   hssx::DevBuf desc, bpos, src_gid, src_child, src_pos, perm, front;
-  // complex64 factors keep the root (top separator) in complex128: its front
-  // lives in front64 and desc64 is the descriptor table with the root at 0
-  hssx::DevBuf front64, desc64;
+  // complex64 factors keep the roots (top separators) in complex128: their
+  // fronts live in front64, at the roots' foff
+  hssx::DevBuf front64;
   // per depth (index = depth): nodes, and the largest |I|, |B|, front size
   std::vector<std::vector<int>> depth_nodes;
   std::vector<hssx::DevBuf> depth_dev;

@@ -398,7 +398,6 @@ template <typename T>
 void factor_impl(hssx_fact_ &P, hipStream_t st) {
   hssx_op_ &A = *P.A;
   const Symbolic &sym = P.sym;
-  const int root = sym.root();
   cplx<T> *F = P.front.as<cplx<T>>();
   const FrontDesc *desc = P.desc.as<FrontDesc>();
   // default pivot threshold of the interpolative decomposition: 1e-2 tol,
@@ -429,18 +428,21 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     if (nodes.empty()) continue;
     const int cnt = (int)nodes.size();
     if (std::is_same<T, float>::value && d == 0) {
-      // complex64 factor: the root front (the top separator) is assembled
+      // complex64 factor: the root fronts (top separators) are assembled
       // from the children's complex64 Schur blocks into complex128 storage
       // and eliminated in FP64
-      const FrontDesc &fd = P.h_desc[root];
+      c128 *F64 = P.front64.as<c128>();
       hipEvent_t pa = prof_begin(st);
-      launch_front_assemble<double, T>(1, P.depth_dev[0].as<int>(), desc, P.src_gid.as<int>(),
+      launch_front_assemble<double, T>(cnt, P.depth_dev[0].as<int>(), desc, P.src_gid.as<int>(),
                                        P.src_child.as<int>(), P.src_pos.as<int>(),
                                        A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), F,
-                                       P.front64.as<c128>(), 0, st, fd.f);
+                                       F64, st, P.depth_max_f[0]);
       prof_end("front_assemble", st, pa, P.asm_bytes[0]);
-      std::vector<ElimJob<double>> rj{
-          ElimJob<double>{P.front64.as<c128>(), fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, root}};
+      std::vector<ElimJob<double>> rj;
+      for (int k : nodes) {
+        const FrontDesc &fd = P.h_desc[k];
+        rj.push_back(ElimJob<double>{F64 + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
+      }
       hipEvent_t pe = prof_begin(st);
       eliminate_jobs<double>(rj, err.as<int>(), sg);
       prof_end("front_eliminate", st, pe, elim_flops(rj));
@@ -451,14 +453,13 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     hipEvent_t pa = prof_begin(st);
     launch_front_assemble<T, T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
                                 P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
-                                A.col.as<int>(), A.val.as<c128>(), F, F, -1, st,
-                                P.depth_max_f[d]);
+                                A.col.as<int>(), A.val.as<c128>(), F, F, st, P.depth_max_f[d]);
     prof_end("front_assemble", st, pa, P.asm_bytes[d]);
 
     // ---- HSS-arithmetic interiors: compress S~ and substitute it (Alg. 3.3)
     std::vector<int> hn;
     for (int k : nodes)
-      if (P.arith[k] && k != root && P.h_desc[k].ni > 0) hn.push_back(k);
+      if (P.arith[k] && sym.nodes[k].parent >= 0 && P.h_desc[k].ni > 0) hn.push_back(k);
     DevBuf G, H;
     if (!hn.empty()) {
       long gsz = 0, hsz = 0;
@@ -611,8 +612,7 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     if (!cnt) continue;
     hipEvent_t pu = prof_begin(st);
     if (P.dtype == HSSX_C64 && d == 0)
-      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), P.desc64.as<FrontDesc>(),
-                              P.front64.as<c128>(), P.bpos.as<int>(), tb, w, n, nrhs, trans,
+      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front64.as<c128>(), P.bpos.as<int>(), tb, w, n, nrhs, trans,
                               P.depth_max_ni[d], P.depth_max_f[d], st);
     else if (P.dtype == HSSX_C128)
       launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
@@ -629,8 +629,7 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
     if (!cnt) continue;
     hipEvent_t pd = prof_begin(st);
     if (P.dtype == HSSX_C64 && d == 0)
-      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), P.desc64.as<FrontDesc>(),
-                                P.front64.as<c128>(), P.bpos.as<int>(), w, n, nrhs, trans,
+      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front64.as<c128>(), P.bpos.as<int>(), w, n, nrhs, trans,
                                 P.depth_max_nb[d], P.depth_max_ni[d], st);
     else if (P.dtype == HSSX_C128)
       launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),

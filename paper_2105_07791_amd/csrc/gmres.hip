@@ -1,7 +1,9 @@
 // Restarted GMRES for A x = b with the approximate factorization as
 // preconditioner (eq. 1.2; Sec. 4: restarted GMRES stopped on the relative
-// residual).  All right-hand sides advance together, each with its own
-// Krylov basis; converged ones are frozen (their step count stops).
+// residual).  All systems advance together, each with its own Krylov basis;
+// converged ones are frozen (their step count stops).  A system is one
+// right-hand side of one problem: a batch of np problems with nrhs columns
+// has np * nrhs systems, system r * np + p being part p of column r.
 //
 // Left preconditioning (paper): Arnoldi on P^-1 A, stop when
 // ||P^-1 (b - A x)|| / ||P^-1 b|| <= target; then the true residual
@@ -22,6 +24,10 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
   const int n = A.n, m = o.m;
   const bool left = !o.flexible;
   const long blk = (long)n * nrhs;
+  const Segs sg = A.segs();
+  const int np = sg.np, nseg = np * nrhs;
+  int maxlen = 0;
+  for (int q = 0; q < np; ++q) maxlen = std::max(maxlen, A.part_off[q + 1] - A.part_off[q]);
   auto precond = [&](const c128 *in, c128 *out) {
     if (P) apply(*P, trans, nrhs, in, n, out, n, st);
     else HSSX_HIP(hipMemcpyAsync(out, in, blk * sizeof(c128), hipMemcpyDeviceToDevice, st));
@@ -39,21 +45,31 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
   t1.alloc(blk * sizeof(c128));
   xc.alloc(blk * sizeof(c128));
   bc.alloc(blk * sizeof(c128));
-  H.alloc((size_t)(m + 1) * m * nrhs * sizeof(c128));
-  cs.alloc((size_t)m * nrhs * sizeof(double));
-  sn.alloc((size_t)m * nrhs * sizeof(c128));
-  g.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
-  y.alloc((size_t)m * nrhs * sizeof(c128));
-  hcol.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
-  h2.alloc((size_t)(m + 1) * nrhs * sizeof(c128));
-  hn.alloc(nrhs * sizeof(double));
-  res.alloc(nrhs * sizeof(double));
-  nrm.alloc(nrhs * sizeof(double));
-  cnt.alloc(nrhs * sizeof(int));
-  act.alloc(nrhs * sizeof(int));
-  const int nblk = std::max(1, std::min(64, ceil_div(n, 256 * 8)));
-  part.alloc((size_t)nblk * (m + 1) * nrhs * sizeof(c128));
-  partd.alloc((size_t)nblk * nrhs * sizeof(double));
+  H.alloc((size_t)(m + 1) * m * nseg * sizeof(c128));
+  cs.alloc((size_t)m * nseg * sizeof(double));
+  sn.alloc((size_t)m * nseg * sizeof(c128));
+  g.alloc((size_t)(m + 1) * nseg * sizeof(c128));
+  y.alloc((size_t)m * nseg * sizeof(c128));
+  hcol.alloc((size_t)(m + 1) * nseg * sizeof(c128));
+  h2.alloc((size_t)(m + 1) * nseg * sizeof(c128));
+  hn.alloc(nseg * sizeof(double));
+  res.alloc(nseg * sizeof(double));
+  nrm.alloc(nseg * sizeof(double));
+  cnt.alloc(nseg * sizeof(int));
+  act.alloc(nseg * sizeof(int));
+  const int nblk = std::max(1, std::min(64, ceil_div(maxlen, 256 * 8)));
+  part.alloc((size_t)nblk * (m + 1) * nseg * sizeof(c128));
+  partd.alloc((size_t)nblk * nseg * sizeof(double));
+
+  // hcol += h2 for Arnoldi step j, one descriptor per step, uploaded once
+  DevBuf cgs_job;
+  {
+    std::vector<AxpbyJob<double>> aj;
+    for (int j = 0; j < m; ++j)
+      aj.push_back(AxpbyJob<double>{hcol.as<c128>(), h2.as<c128>(), nullptr, (j + 1) * nseg,
+                                    (j + 1) * nseg, 0, (j + 1) * nseg, 1, 1.0, 0.0});
+    upload(cgs_job, aj);
+  }
 
   // contiguous copies of b and x
   HSSX_HIP(hipMemcpy2DAsync(bc.p, n * sizeof(c128), b, ldb * sizeof(c128), n * sizeof(c128), nrhs,
@@ -61,9 +77,9 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
   launch_fill(blk, czero<double>(), xc.as<c128>(), st);
 
   auto norms_host = [&](const c128 *v, std::vector<double> &out) {
-    launch_norms(n, nrhs, v, nrm.as<double>(), partd.as<double>(), nblk, st);
-    out.resize(nrhs);
-    HSSX_HIP(hipMemcpyAsync(out.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    launch_norms(n, nrhs, sg, v, nrm.as<double>(), partd.as<double>(), nblk, st);
+    out.resize(nseg);
+    HSSX_HIP(hipMemcpyAsync(out.data(), nrm.p, nseg * sizeof(double), hipMemcpyDeviceToHost, st));
     HSSX_HIP(hipStreamSynchronize(st));
   };
 
@@ -75,9 +91,9 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
   } else {
     pbnorm = bnorm;
   }
-  std::vector<double> target(nrhs, o.tol), prec_rel(nrhs, 0.0), true_rel(nrhs, 0.0);
-  std::vector<int> extra(nrhs, 0), done(nrhs, 0), iters(nrhs, 0), conv(nrhs, 0);
-  for (int r = 0; r < nrhs; ++r)
+  std::vector<double> target(nseg, o.tol), prec_rel(nseg, 0.0), true_rel(nseg, 0.0);
+  std::vector<int> extra(nseg, 0), done(nseg, 0), iters(nseg, 0), conv(nseg, 0);
+  for (int r = 0; r < nseg; ++r)
     if (bnorm[r] == 0.0) { done[r] = 1; conv[r] = 1; }
   int total = 0;
   const long stride = blk;
@@ -97,9 +113,9 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
       HSSX_HIP(hipMemcpyAsync(Vp, w.p, blk * sizeof(c128), hipMemcpyDeviceToDevice, st));
       pr = tr;
     }
-    std::vector<int> active(nrhs, 0);
+    std::vector<int> active(nseg, 0);
     bool any = false;
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < nseg; ++r) {
       if (done[r]) continue;
       true_rel[r] = tr[r] / bnorm[r];
       prec_rel[r] = pr[r] / pbnorm[r];
@@ -118,15 +134,15 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
     }
     if (!any) break;
     // v0 = r0 / beta (zero for inactive right-hand sides)
-    std::vector<double> beta(nrhs);
-    for (int r = 0; r < nrhs; ++r) beta[r] = active[r] ? pr[r] : 0.0;
-    HSSX_HIP(hipMemcpyAsync(hn.p, beta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_scale(n, nrhs, Vp, hn.as<double>(), Vp, st);
-    std::vector<c128> g0((size_t)(m + 1) * nrhs, czero<double>());
-    for (int r = 0; r < nrhs; ++r) g0[r] = mk(beta[r], 0.0);
+    std::vector<double> beta(nseg);
+    for (int r = 0; r < nseg; ++r) beta[r] = active[r] ? pr[r] : 0.0;
+    HSSX_HIP(hipMemcpyAsync(hn.p, beta.data(), nseg * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_scale(n, nrhs, sg, Vp, hn.as<double>(), Vp, st);
+    std::vector<c128> g0((size_t)(m + 1) * nseg, czero<double>());
+    for (int r = 0; r < nseg; ++r) g0[r] = mk(beta[r], 0.0);
     HSSX_HIP(hipMemcpyAsync(g.p, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, st));
-    HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-    std::vector<int> count(nrhs, 0);
+    HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nseg * sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<int> count(nseg, 0);
     for (int j = 0; j < m; ++j) {
       c128 *vj = Vp + j * stride;
       if (left) {
@@ -136,49 +152,44 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
         precond(vj, Zp + j * stride);
         matvec(Zp + j * stride, w.as<c128>());
       }
-      launch_mdot(n, nrhs, j + 1, Vp, stride, w.as<c128>(), hcol.as<c128>(), part.as<c128>(), nblk, st);
-      launch_mupdate(n, nrhs, j + 1, Vp, stride, hcol.as<c128>(), w.as<c128>(), st);
-      launch_mdot(n, nrhs, j + 1, Vp, stride, w.as<c128>(), h2.as<c128>(), part.as<c128>(), nblk, st);
-      launch_mupdate(n, nrhs, j + 1, Vp, stride, h2.as<c128>(), w.as<c128>(), st);
-      {
-        std::vector<AxpbyJob<double>> aj{AxpbyJob<double>{hcol.as<c128>(), h2.as<c128>(), nullptr,
-                                                          (j + 1) * nrhs, (j + 1) * nrhs, 0,
-                                                          (j + 1) * nrhs, 1, 1.0, 0.0}};
-        DevBuf da;
-        upload(da, aj);
-        launch_axpby<double>(1, da.as<AxpbyJob<double>>(), (j + 1) * nrhs, 1, st);
-        HSSX_HIP(hipStreamSynchronize(st));
-      }
-      launch_norms(n, nrhs, w.as<c128>(), hn.as<double>(), partd.as<double>(), nblk, st);
-      launch_scale(n, nrhs, w.as<c128>(), hn.as<double>(), Vp + (j + 1) * stride, st);
-      launch_givens(nrhs, j, m, H.as<c128>(), hcol.as<c128>(), hn.as<double>(), cs.as<double>(),
+      launch_mdot(n, nrhs, sg, j + 1, Vp, stride, w.as<c128>(), hcol.as<c128>(), part.as<c128>(),
+                  nblk, st);
+      launch_mupdate(n, nrhs, sg, j + 1, Vp, stride, hcol.as<c128>(), w.as<c128>(), st);
+      launch_mdot(n, nrhs, sg, j + 1, Vp, stride, w.as<c128>(), h2.as<c128>(), part.as<c128>(),
+                  nblk, st);
+      launch_mupdate(n, nrhs, sg, j + 1, Vp, stride, h2.as<c128>(), w.as<c128>(), st);
+      // hcol += h2 (the second Gram-Schmidt pass's coefficients)
+      launch_axpby<double>(1, cgs_job.as<AxpbyJob<double>>() + j, (j + 1) * nseg, 1, st);
+      launch_norms(n, nrhs, sg, w.as<c128>(), hn.as<double>(), partd.as<double>(), nblk, st);
+      launch_scale(n, nrhs, sg, w.as<c128>(), hn.as<double>(), Vp + (j + 1) * stride, st);
+      launch_givens(nseg, j, m, H.as<c128>(), hcol.as<c128>(), hn.as<double>(), cs.as<double>(),
                     sn.as<c128>(), g.as<c128>(), res.as<double>(), act.as<int>(), st);
-      std::vector<double> rs(nrhs);
-      HSSX_HIP(hipMemcpyAsync(rs.data(), res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      std::vector<double> rs(nseg);
+      HSSX_HIP(hipMemcpyAsync(rs.data(), res.p, nseg * sizeof(double), hipMemcpyDeviceToHost, st));
       HSSX_HIP(hipStreamSynchronize(st));
       ++total;
       bool still = false;
-      for (int r = 0; r < nrhs; ++r) {
+      for (int r = 0; r < nseg; ++r) {
         if (!active[r]) continue;
         ++iters[r];
         count[r] = j + 1;
         if (rs[r] / pbnorm[r] <= target[r] || iters[r] >= o.maxit) active[r] = 0;
         else still = true;
       }
-      HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      HSSX_HIP(hipMemcpyAsync(act.p, active.data(), nseg * sizeof(int), hipMemcpyHostToDevice, st));
       if (!still) break;
     }
-    HSSX_HIP(hipMemcpyAsync(cnt.p, count.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-    launch_hsolve(nrhs, m, H.as<c128>(), g.as<c128>(), cnt.as<int>(), y.as<c128>(), st);
-    launch_xupdate(n, nrhs, cnt.as<int>(), m, left ? Vp : Zp, stride, y.as<c128>(), xc.as<c128>(), n,
-                   st);
+    HSSX_HIP(hipMemcpyAsync(cnt.p, count.data(), nseg * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_hsolve(nseg, m, H.as<c128>(), g.as<c128>(), cnt.as<int>(), y.as<c128>(), st);
+    launch_xupdate(n, nrhs, sg, cnt.as<int>(), left ? Vp : Zp, stride, y.as<c128>(), xc.as<c128>(),
+                   n, st);
     HSSX_HIP(hipStreamSynchronize(st));
   }
   HSSX_HIP(hipMemcpy2DAsync(x, ldx * sizeof(c128), xc.p, n * sizeof(c128), n * sizeof(c128), nrhs,
                             hipMemcpyDeviceToDevice, st));
   HSSX_HIP(hipStreamSynchronize(st));
   if (stats)
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < nseg; ++r) {
       stats[r].iters = iters[r];
       stats[r].converged = conv[r];
       stats[r].prec_res = prec_rel[r];

@@ -15,7 +15,7 @@ void launch_load(int n, int nrhs, const int *rowptr, const int *col, const doubl
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
                  const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st);
 void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
-                 const c128 *x, double *grad, hipStream_t st);
+                 const c128 *x, long ld, double *grad, hipStream_t st);
 
 // ------------------------------------------------------------ dense fronts
 // One elimination-tree node's augmented dense front
@@ -37,15 +37,14 @@ struct FrontDesc {
 
 // Assemble the augmented fronts of `count` nodes (ids in nodes[]): entries
 // from the children's Schur blocks (same child, read from cpool) or from A
-// (natural CSR, c128), and the identity block.  A front is written to
-// opool + foff (or opool + ooff when ooff >= 0, for a single node kept in a
-// buffer of its own).
+// (natural CSR, c128), and the identity block.  Each front is written to
+// opool + foff (opool may differ from cpool: the roots of a complex64 factor
+// are kept in complex128).
 template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
                            const int *src_gid, const int *src_child, const int *src_pos,
                            const int *rowptr, const int *col, const c128 *val,
-                           const cplx<Tc> *cpool, cplx<T> *opool, long ooff, hipStream_t st,
-                           int max_f);
+                           const cplx<Tc> *cpool, cplx<T> *opool, hipStream_t st, int max_f);
 
 // Elimination job: Gauss-Jordan elimination of the first ne columns of the
 // m x ncols matrix at ptr (leading dimension ld), partial pivoting among the
@@ -186,31 +185,40 @@ void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const
                        int max_ni, hipStream_t st);
 
 // ------------------------------------------------------------ Krylov
-// h[i*nrhs + r] = sum_k conj(V_i[k, r]) w[k, r], i < cnt; V_i at V + i*stride
-void launch_mdot(int n, int nrhs, int cnt, const c128 *V, long stride, const c128 *w,
-                 c128 *h, c128 *partial, int nblk, hipStream_t st);
-// w[k, r] -= sum_{i<cnt} V_i[k, r] h[i*nrhs + r]
-void launch_mupdate(int n, int nrhs, int cnt, const c128 *V, long stride, const c128 *h,
-                    c128 *w, hipStream_t st);
-// norms[r] = ||w[:, r]||_2
-void launch_norms(int n, int nrhs, const c128 *w, double *norms, double *partial, int nblk,
+// Systems of a vector block (n rows x nrhs columns): the rows split into np
+// parts [off[p], off[p+1]) (device array), rpart[k] is the part of row k
+// (device array, or null when np == 1); system s = r * np + p.  Per-system
+// arrays (h, norms, scale, cnt) are indexed i * nseg + s, nseg = np * nrhs.
+struct Segs {
+  int np;
+  const int *off;
+  const int *rpart;
+};
+// h[i*nseg + s] = sum over system s of conj(V_i) w, i < cnt; V_i at V + i*stride
+void launch_mdot(int n, int nrhs, const Segs &g, int cnt, const c128 *V, long stride,
+                 const c128 *w, c128 *h, c128 *partial, int nblk, hipStream_t st);
+// w -= sum_{i<cnt} V_i h[i*nseg + s] on each system s
+void launch_mupdate(int n, int nrhs, const Segs &g, int cnt, const c128 *V, long stride,
+                    const c128 *h, c128 *w, hipStream_t st);
+// norms[s] = ||w on system s||_2
+void launch_norms(int n, int nrhs, const Segs &g, const c128 *w, double *norms, double *partial,
+                  int nblk, hipStream_t st);
+// out = in / scale[s] on system s (zero when scale[s] == 0)
+void launch_scale(int n, int nrhs, const Segs &g, const c128 *in, const double *scale, c128 *out,
                   hipStream_t st);
-// out[k, r] = in[k, r] * scale[r]^-1 (scale real; zero when scale == 0)
-void launch_scale(int n, int nrhs, const c128 *in, const double *scale, c128 *out,
-                  hipStream_t st);
-// y[k, r] = a[k, r] - b[k, r]
+// y = a - b
 void launch_sub(int n, int nrhs, const c128 *a, long lda, const c128 *b, long ldb, c128 *y,
                 long ldy, hipStream_t st);
-// x[k, r] += sum_{i<cnt[r]} Z_i[k, r] y[i*nrhs + r]
-void launch_xupdate(int n, int nrhs, const int *cnt, int maxcnt, const c128 *Z, long stride,
+// x += sum_{i<cnt[s]} Z_i y[i*nseg + s] on each system s
+void launch_xupdate(int n, int nrhs, const Segs &g, const int *cnt, const c128 *Z, long stride,
                     const c128 *y, c128 *x, long ldx, hipStream_t st);
-// Arnoldi column j bookkeeping for every right-hand side: store h, apply the
-// previous Givens rotations, build the new one, update g; res[r] = |g_{j+1}|.
-void launch_givens(int nrhs, int j, int m, c128 *H, const c128 *hcol, const double *hnext,
+// Arnoldi column j bookkeeping for every system: store h, apply the previous
+// Givens rotations, build the new one, update g; res[s] = |g_{j+1}|.
+void launch_givens(int nseg, int j, int m, c128 *H, const c128 *hcol, const double *hnext,
                    double *cs, c128 *sn, c128 *g, double *res, const int *active,
                    hipStream_t st);
-// back substitution H(0:cnt,0:cnt) y = g per right-hand side
-void launch_hsolve(int nrhs, int m, const c128 *H, const c128 *g, const int *cnt, c128 *y,
+// back substitution H(0:cnt,0:cnt) y = g per system
+void launch_hsolve(int nseg, int m, const c128 *H, const c128 *g, const int *cnt, c128 *y,
                    hipStream_t st);
 void launch_fill(long n, c128 v, c128 *x, hipStream_t st);
 

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
     const int *__restrict__ src_gid, const int *__restrict__ src_child,
     const int *__restrict__ src_pos, const int *__restrict__ rowptr,
     const int *__restrict__ col, const c128 *__restrict__ val,
-    const cplx<Tc> *__restrict__ cpool, cplx<T> *__restrict__ opool, long ooff) {
+    const cplx<Tc> *__restrict__ cpool, cplx<T> *__restrict__ opool) {
   const FrontDesc d = desc[nodes[blockIdx.x]];
   const long f = d.f;
   const long total = f * (f + d.ni);
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
   const int *gid = src_gid + d.src_off;
   const int *chd = src_child + d.src_off;
   const int *pos = src_pos + d.src_off;
-  cplx<T> *F = opool + (ooff >= 0 ? ooff : d.foff);
+  cplx<T> *F = opool + d.foff;
   for (long e = e0 + threadIdx.x; e < e1; e += kThreads) {
     int p = (int)(e % f), q = (int)(e / f);
     cplx<T> v;
@@ -285,14 +285,12 @@ template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
                            const int *src_gid, const int *src_child, const int *src_pos,
                            const int *rowptr, const int *col, const c128 *val,
-                           const cplx<Tc> *cpool, cplx<T> *opool, long ooff, hipStream_t st,
-                           int max_f) {
+                           const cplx<Tc> *cpool, cplx<T> *opool, hipStream_t st, int max_f) {
   if (count <= 0) return;
   long per = (long)kThreads * 16;
   int ny = ceil_div((long)max_f * (2L * max_f), per);
   hipLaunchKernelGGL((front_assemble_kernel<T, Tc>), dim3(count, ny), dim3(kThreads), 0, st,
-                     nodes, desc, src_gid, src_child, src_pos, rowptr, col, val, cpool, opool,
-                     ooff);
+                     nodes, desc, src_gid, src_child, src_pos, rowptr, col, val, cpool, opool);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -329,7 +327,7 @@ void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipS
   template void launch_front_assemble<T, Tc>(int, const int *, const FrontDesc *, const int *, \
                                              const int *, const int *, const int *,           \
                                              const int *, const c128 *, const cplx<Tc> *,     \
-                                             cplx<T> *, long, hipStream_t, int);
+                                             cplx<T> *, hipStream_t, int);
 HSSX_ASM(double, double)
 HSSX_ASM(float, float)
 HSSX_ASM(double, float)

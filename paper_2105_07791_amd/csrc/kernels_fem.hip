@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *_
 // dA/ds_l = -omega^2 * 2 s_l * Mtri_l - i omega * Gedge_l where Mtri_l(a,b) =
 // sum_{T ni l,a,b} int l_l l_a l_b and Gedge_l likewise on boundary edges.
 __global__ void dads_kernel(int N, double omega, const double *__restrict__ s, int nrhs,
-                            const c128 *__restrict__ lam, const c128 *__restrict__ x,
+                            const c128 *__restrict__ lam, const c128 *__restrict__ x, long ld,
                             double *__restrict__ grad) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   int n = N * N;
@@ -190,8 +190,8 @@ __global__ void dads_kernel(int N, double omega, const double *__restrict__ s, i
   int xl = l % N, yl = l / N;
   double total = 0.0;
   for (int r = 0; r < nrhs; ++r) {
-    const c128 *lr = lam + (long)r * n;
-    const c128 *xr = x + (long)r * n;
+    const c128 *lr = lam + (long)r * ld;
+    const c128 *xr = x + (long)r * ld;
     c128 accT = czero<double>();   // sum_T 2|T| sum_ab c(l,a,b) lam_a x_b
     for (int cy = yl - 1; cy <= yl; ++cy)
       for (int cx = xl - 1; cx <= xl; ++cx) {
@@ -264,10 +264,10 @@ void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 
 }
 
 void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
-                 const c128 *x, double *grad, hipStream_t st) {
+                 const c128 *x, long ld, double *grad, hipStream_t st) {
   int n = N * N;
   hipLaunchKernelGGL(dads_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, N, omega, s, nrhs,
-                     lam, x, grad);
+                     lam, x, ld, grad);
   HSSX_HIP(hipGetLastError());
 }
 

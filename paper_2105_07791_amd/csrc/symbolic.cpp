@@ -200,6 +200,34 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
   return s;
 }
 
+Symbolic merge_forest(const std::vector<Symbolic> &parts, const std::vector<int> &dof_off) {
+  Symbolic f;
+  if (parts.empty()) return f;
+  f.leaf_dofs = parts[0].leaf_dofs;
+  f.beta = parts[0].beta;
+  const int n = dof_off.back();
+  f.perm.reserve(n);
+  f.iperm.assign(n, -1);
+  for (size_t q = 0; q < parts.size(); ++q) {
+    const Symbolic &s = parts[q];
+    const int base = (int)f.nodes.size(), o = dof_off[q];
+    auto shift = [o](std::vector<int> &v) { for (int &x : v) x += o; };
+    for (NDNode nd : s.nodes) {
+      if (nd.lo >= 0) { nd.lo += base; nd.hi += base; }
+      if (nd.parent >= 0) nd.parent += base;
+      shift(nd.bd);
+      shift(nd.I);
+      shift(nd.B);
+      nd.offset += o;
+      f.nodes.push_back(std::move(nd));
+    }
+    for (int v : s.perm) f.perm.push_back(v + o);
+    for (size_t k = 0; k < s.iperm.size(); ++k) f.iperm[k + o] = s.iperm[k] + o;
+    f.max_depth = std::max(f.max_depth, s.max_depth);
+  }
+  return f;
+}
+
 ClusterTree interior_subtree(const NDNode &nd) {
   const ClusterTree &ct = nd.ct;
   if (ct.count() == 0 || nd.p0 == 0) return ClusterTree();   // no P0 part

@@ -39,10 +39,15 @@ struct Symbolic {
   std::vector<int> perm;       // perm[k] = node id eliminated at position k
   std::vector<int> iperm;      // iperm[node id] = position
   int max_depth = 0;
-  int root() const { return (int)nodes.size() - 1; }
 };
 
 Symbolic build_symbolic(int N, int leaf_dofs, int beta);
+
+// Forest of independent problems: the trees of `parts` side by side, with
+// node ids, DOF ids and permutation positions shifted so that part p's DOFs
+// are [dof_off[p], dof_off[p+1]) of one block-diagonal system.  Every tree
+// keeps its own depths, so depth 0 holds all roots.
+Symbolic merge_forest(const std::vector<Symbolic> &parts, const std::vector<int> &dof_off);
 
 // Cluster tree of the P0 block of a node's boundary: the left subtree of the
 // top split, the whole tree when the node has no P1 part, empty without P0.  Positions are

@@ -12,7 +12,7 @@ from . import _lib
 from ._lib import check, lib
 from .symbolic import read_perm, read_tree
 
-__all__ = ["Operator", "Factor", "assemble", "factor", "gmres_solve"]
+__all__ = ["Operator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"]
 
 
 def _stream(stream=None):
@@ -31,19 +31,8 @@ def _col_major(x, dtype):
     return t, x.shape[0], x.shape[1]
 
 
-class Operator:
-    """A(s) = K - omega^2 M[s^2] - i omega G[s] on the N x N P1 grid."""
-
-    def __init__(self, N, omega, slowness, device=0, stream=None):
-        s = torch.as_tensor(slowness, dtype=torch.float64, device=f"cuda:{device}").contiguous()
-        assert s.numel() == N * N
-        self.N, self.omega, self.n, self.device = N, float(omega), N * N, device
-        self.slowness = s
-        h = C.c_void_p()
-        desc = _lib.ProblemDesc(N, float(omega))
-        check(lib().hssx_assemble(device, C.byref(desc), C.c_void_p(s.data_ptr()),
-                                  _stream(stream), C.byref(h)))
-        self.handle = h
+class _OperatorBase:
+    """Calls shared by single-problem and batch operators (handle, n, device)."""
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib._LIB is not None:
@@ -52,7 +41,7 @@ class Operator:
 
     def load(self, f, stream=None):
         """b = M f for nodal source samples f (n,) or (n, nrhs) float64."""
-        f = torch.as_tensor(f, dtype=torch.float64, device=self.slowness.device)
+        f = torch.as_tensor(f, dtype=torch.float64, device=f"cuda:{self.device}")
         ft, n, nrhs = _col_major(f, torch.float64)
         b = torch.empty((nrhs, n), dtype=torch.complex128, device=f.device)
         check(lib().hssx_load(self.handle, nrhs, C.c_void_p(ft.data_ptr()), n,
@@ -89,6 +78,46 @@ class Operator:
                                        _stream(stream)))
         return grad
 
+
+class Operator(_OperatorBase):
+    """A(s) = K - omega^2 M[s^2] - i omega G[s] on the N x N P1 grid."""
+    parts = 1
+
+    def __init__(self, N, omega, slowness, device=0, stream=None):
+        s = torch.as_tensor(slowness, dtype=torch.float64, device=f"cuda:{device}").contiguous()
+        assert s.numel() == N * N
+        self.N, self.omega, self.n, self.device = N, float(omega), N * N, device
+        self.slowness = s
+        self.part_off = [0, self.n]
+        h = C.c_void_p()
+        desc = _lib.ProblemDesc(N, float(omega))
+        check(lib().hssx_assemble(device, C.byref(desc), C.c_void_p(s.data_ptr()),
+                                  _stream(stream), C.byref(h)))
+        self.handle = h
+
+
+class BatchOperator(_OperatorBase):
+    """Independent problems as one block-diagonal operator (hssx_op_batch):
+    vectors are the parts' vectors stacked, part p at rows part_off[p]:part_off[p+1]."""
+
+    def __init__(self, operators, stream=None):
+        ops = list(operators)
+        arr = (C.c_void_p * len(ops))(*[o.handle for o in ops])
+        h = C.c_void_p()
+        check(lib().hssx_op_batch(len(ops), arr, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.device = ops[0].device
+        n, np_ = C.c_int(), C.c_int()
+        check(lib().hssx_op_info(h, C.byref(n), C.byref(np_), None))
+        off = np.empty(np_.value + 1, dtype=np.int32)
+        check(lib().hssx_op_info(h, None, None, off.ctypes.data_as(_lib._ip)))
+        self.n, self.parts, self.part_off = n.value, np_.value, [int(v) for v in off]
+        self.Ns = [o.N for o in ops]
+        self.omegas = [o.omega for o in ops]
+
+    def split(self, x):
+        """Views of the parts of a stacked vector (n,) or (n, nrhs)."""
+        return [x[self.part_off[p]:self.part_off[p + 1]] for p in range(self.parts)]
 
 class Factor:
     """Approximate factorization P = LDR of an Operator (Algorithm 3.4)."""
@@ -136,11 +165,12 @@ class Factor:
 
 
 def gmres_solve(A, P, b, m=50, tol=1e-8, maxit=1000, flexible=False, trans=False, stream=None):
-    """Preconditioned restarted GMRES; returns (x, list of per-rhs stats)."""
+    """Preconditioned restarted GMRES; returns (x, list of per-system stats).
+    A system is one right-hand side of one problem: entry r * A.parts + p."""
     bt, n, nrhs = _col_major(b, torch.complex128)
     x = torch.empty((nrhs, n), dtype=torch.complex128, device=b.device)
     opts = _lib.GmresOpts(m, tol, maxit, int(flexible))
-    stats = (_lib.GmresStats * nrhs)()
+    stats = (_lib.GmresStats * (nrhs * A.parts))()
     code = lib().hssx_gmres_solve(A.handle, P.handle if P is not None else None, int(trans), nrhs,
                                   C.c_void_p(bt.data_ptr()), n, C.c_void_p(x.data_ptr()), n,
                                   C.byref(opts), stats, _stream(stream))

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "node_coords", "source_centers", "gaussian_sources",
-    "random_field", "speed_field", "make_problem", "CONFIGS",
+    "random_field", "speed_field", "make_problem", "CONFIGS", "make_batch", "BATCHES",
     "receiver_nodes", "batch_grid_sizes",
 ]
 
@@ -135,3 +135,43 @@ def make_problem(name, **overrides):
     seed = cfg.pop("seed")
     nsrc = cfg.pop("nsrc")
     return _helmholtz(name, N, omega, seed, nsrc, **cfg)
+
+
+@dataclass
+class BatchProblem:
+    """Uneven-sized independent problems solved together, each with its own
+    seeded speed field, one Gaussian source, receivers and observed data."""
+    name: str
+    problems: list
+    receivers: list               # per problem: int64 node ids
+    data: list                    # per problem: complex128 (count, nrhs)
+
+
+#: Batches of uneven problems.  The frequency of a grid of side N is
+#: omega = kh (N - 1), so every problem resolves its shortest wavelength with
+#: the same number of points (the speed is at least 1, so k h <= kh).
+BATCHES = {
+    "helmholtz_p1_batch256": dict(count=256, lo=65, hi=513, seed=7, kh=0.2, receivers=8),
+    # reduced batches for parity tests
+    "helmholtz_p1_batch8": dict(count=8, lo=9, hi=65, seed=8, kh=0.3, receivers=8),
+    "helmholtz_p1_batch32": dict(count=32, lo=65, hi=129, seed=9, kh=0.2, receivers=8),
+}
+
+
+def make_batch(name, **overrides):
+    cfg = dict(BATCHES[name])
+    cfg.update(overrides)
+    count, seed = cfg["count"], cfg["seed"]
+    Ns = batch_grid_sizes(seed, count, cfg["lo"], cfg["hi"])
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    problems, receivers, data = [], [], []
+    for q, N in enumerate(int(v) for v in Ns):
+        s = 1.0 / speed_field(N, seed * 100003 + q)
+        f = gaussian_sources(N, source_centers(seed * 100003 + q, 1))
+        problems.append(Problem(name=f"{name}[{q}]", N=N, omega=cfg["kh"] * (N - 1),
+                                slowness=s, f=f, factor_dtype="c64"))
+        receivers.append(receiver_nodes(N, seed * 100003 + q, cfg["receivers"]))
+        d = rng.standard_normal((cfg["receivers"], 1)) + 1j * rng.standard_normal(
+            (cfg["receivers"], 1))
+        data.append(1e-4 * d)
+    return BatchProblem(name=name, problems=problems, receivers=receivers, data=data)
