@@ -15,6 +15,14 @@ GMRES, right-hand sides solved one at a time) for comparison, the roofline
 of the dominant kernel from HIP events, and the oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+With --workload helmholtz_p1_batch256 (or a smaller batch) one step is the
+batching form instead: 256 independent problems of uneven sizes (grids of
+65..513 nodes per side, 27.3M DOFs in total, each with its own seeded speed
+field and one source) assembled, factored as one forest (complex64) and
+solved with one GMRES that keeps a Krylov basis per problem, followed by the
+misfit J = 1/2 sum ||R x - d||^2 over 8 receivers per problem and its
+slowness gradient through one batched adjoint solve.
 """
 import argparse
 import json
@@ -83,6 +91,128 @@ def run_cpu_baseline(workload):
                       f"{d['cpu']} (true residual {d['true_res']:.1e})"}
 
 
+def batch_cpu_child(workload, budget_s=15.0):
+    """Oracle forward + adjoint solves (exact factor) on the first problems of
+    the batch until about budget_s of CPU time; prints a JSON line."""
+    import numpy as np
+    from oracle import exact, fem, nd
+    from synth import make_batch
+    from threadpoolctl import threadpool_info, threadpool_limits
+    bp = make_batch(workload, count=8)
+    done_n, sec, count = 0, 0.0, 0
+    with threadpool_limits(limits=1):
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        for q, p in enumerate(bp.problems):
+            A = fem.assemble_helmholtz(p.N, p.omega, p.slowness)
+            t = nd.build_nd(p.N, p.leaf_dofs, p.beta)
+            b = (fem.mass_matrix(p.N) @ p.f).astype(np.complex128)
+            t0 = time.perf_counter()
+            f = exact.factor_exact(A, t, keep_S=False)
+            x = f.apply(b)
+            g = np.zeros_like(x)
+            g[bp.receivers[q]] = x[bp.receivers[q]] - bp.data[q]
+            f.apply_t(np.conj(g))
+            sec += time.perf_counter() - t0
+            done_n += p.n
+            count += 1
+            if sec >= budget_s:
+                break
+    print(json.dumps({"seconds": sec, "dofs": done_n, "problems": count, "threads": threads}))
+
+
+def run_batch(args):
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2105_07791_amd import _lib
+    from paper_2105_07791_amd.autograd import solve
+    from synth import make_batch
+
+    dev = torch.device("cuda:0")
+    t_in = time.perf_counter()
+    bp = make_batch(args.workload, device=dev)
+    Ns = [p.N for p in bp.problems]
+    om = [p.omega for p in bp.problems]
+    n = sum(N * N for N in Ns)
+    s_all = torch.cat([p.slowness for p in bp.problems]).contiguous()
+    offs = np.cumsum([0] + [N * N for N in Ns])
+    f_all = torch.cat([torch.tensor(p.f[:, 0], device=dev) for p in bp.problems])
+    rec = torch.tensor(np.concatenate([bp.receivers[q] + offs[q] for q in range(len(Ns))]),
+                       device=dev)
+    d = torch.tensor(np.concatenate([bp.data[q][:, 0] for q in range(len(Ns))]), device=dev)
+    torch.cuda.synchronize()
+    print(f"[bench] {args.workload}: {len(Ns)} problems, n={n}, inputs {time.perf_counter() - t_in:.1f}s",
+          file=sys.stderr, flush=True)
+    tol = args.tol if args.tol is not None else 1e-6
+    opts = dict(tol=tol, h_sw=4, dtype="c64", flexible=True, seed=1)
+    L = _lib.lib()
+
+    # b = M f (M the plain mass matrix, independent of the slowness): an input
+    from paper_2105_07791_amd.hssx import BatchOperator, Operator
+    parts = [Operator(Ns[q], om[q], s_all[offs[q]:offs[q + 1]]) for q in range(len(Ns))]
+    b = BatchOperator(parts).load(f_all)
+    del parts
+    torch.cuda.synchronize()
+
+    def step():
+        st = s_all.detach().clone().requires_grad_(True)
+        x = solve(st, b, Ns, om, **opts)
+        r = x[rec] - d
+        J = 0.5 * (r.abs() ** 2).sum()
+        J.backward()
+        return J.detach(), st.grad, x.detach()
+
+    for w in range(args.warmup):
+        step()
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    _lib.check(L.hssx_prof_enable(1))
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        J, g, x = step()
+        torch.cuda.synchronize()
+        print(f"[bench] step {k} {time.perf_counter() - ts:.3f}s", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    kern = {}
+    for name in KERNELS:
+        ms, nl, work = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
+        _lib.check(L.hssx_prof_query(name.encode(), ctypes.byref(ms), ctypes.byref(nl),
+                                     ctypes.byref(work)))
+        kern[name] = (ms.value, nl.value, work.value)
+    _lib.check(L.hssx_prof_enable(0))
+    sec = (t1 - t0) / args.steps
+    out = {
+        "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 factor / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "problems": len(Ns), "n": n,
+                   "N_min": min(Ns), "N_max": max(Ns), "factor_dtype": "c64", "hss_tol": tol,
+                   "step": "assemble + factor + flexible GMRES + misfit + adjoint gradient"},
+        "J": J.item(), "grad_norm": torch.linalg.vector_norm(g).item(),
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+                   MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                            "--workload", args.workload], capture_output=True, text=True,
+                           env=env, timeout=900)
+        if r.returncode == 0:
+            c = json.loads(r.stdout.strip().splitlines()[-1])
+            out["cpu_baseline"] = {
+                "value": c["seconds"] * n / c["dofs"], "unit": "s", "cores": c["threads"],
+                "kind": "oracle",
+                "sample": f"first {c['problems']} problems ({c['dofs']} DOFs): exact factor, "
+                          f"forward and adjoint solves in {c['seconds']:.1f}s, scaled by DOFs "
+                          f"to the batch's {n}"}
+        else:
+            out["cpu_baseline"] = {"error": r.stderr[-400:]}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,13 +230,19 @@ def main():
     ap.add_argument("--alt-tol", type=float, default=1e-4,
                     help="also time the complex64 form at this HSS tolerance (0: skip)")
     args = ap.parse_args()
+    from synth import BATCHES
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.workload)
+        if args.workload in BATCHES:
+            batch_cpu_child(args.workload)
+        else:
+            cpu_baseline_child(args.workload)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
+    if args.workload in BATCHES:
+        return run_batch(args)
 
     import ctypes
     import torch

@@ -2,8 +2,12 @@
 // its arguments, runs under the handle's device, converts exceptions into a
 // status code and records the message for hssx_last_error().
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "engine.h"
 #include "prof.h"
@@ -219,8 +223,26 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     if (A->part_N.size() == 1) {
       P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta);
     } else {
-      std::vector<Symbolic> parts;
-      for (int N : A->part_N) parts.push_back(build_symbolic(N, leaf_size, o.beta));
+      // the problems' analyses are independent: run them on host threads
+      const int np = (int)A->part_N.size();
+      std::vector<Symbolic> parts(np);
+      std::atomic<int> next{0};
+      std::exception_ptr fail;
+      std::mutex mu;
+      auto work = [&] {
+        try {
+          for (int q; (q = next++) < np;) parts[q] = build_symbolic(A->part_N[q], leaf_size, o.beta);
+        } catch (...) {
+          std::lock_guard<std::mutex> g(mu);
+          fail = std::current_exception();
+        }
+      };
+      const int nt = std::max(1, std::min(np, std::min(16, (int)std::thread::hardware_concurrency())));
+      std::vector<std::thread> pool;
+      for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+      work();
+      for (auto &t : pool) t.join();
+      if (fail) std::rethrow_exception(fail);
       P->sym = merge_forest(parts, A->part_off);
     }
     const Symbolic &sym = P->sym;

@@ -47,13 +47,26 @@ def gaussian_sources(N, centers, width=0.02):
     return f
 
 
-def random_field(N, seed, ell=0.1, n_features=1024):
+def random_field(N, seed, ell=0.1, n_features=1024, device=None):
     """Random-feature Gaussian field g(x) = sqrt(2/M) sum_m cos(w_m.x + b_m),
-    w_m ~ N(0, ell^-2 I), b_m ~ U[0, 2pi); unit variance, correlation ell."""
+    w_m ~ N(0, ell^-2 I), b_m ~ U[0, 2pi); unit variance, correlation ell.
+    With a torch device the sum is evaluated there (float64) and a tensor is
+    returned; the draws are the same."""
     rng = np.random.Generator(np.random.PCG64(seed))
     w = rng.normal(0.0, 1.0 / ell, size=(n_features, 2))
     b = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
     x, y = node_coords(N)
+    if device is not None:
+        import torch
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
+        xt, yt, wt, bt = t(x), t(y), t(w), t(b)
+        g = torch.zeros(N * N, dtype=torch.float64, device=device)
+        chunk = 1 << 16
+        for s in range(0, N * N, chunk):
+            ph = (torch.outer(xt[s:s + chunk], wt[:, 0]) + torch.outer(yt[s:s + chunk], wt[:, 1])
+                  + bt)
+            g[s:s + chunk] = torch.cos(ph).sum(dim=1)
+        return g * np.sqrt(2.0 / n_features)
     g = np.zeros(N * N)
     chunk = 4096
     for s in range(0, N * N, chunk):
@@ -62,9 +75,12 @@ def random_field(N, seed, ell=0.1, n_features=1024):
     return g * np.sqrt(2.0 / n_features)
 
 
-def speed_field(N, seed, ell=0.1):
+def speed_field(N, seed, ell=0.1, device=None):
     """c(x) = 1 + 2*sigmoid(g(x)) in (1, 3)."""
-    g = random_field(N, seed, ell)
+    g = random_field(N, seed, ell, device=device)
+    if device is not None:
+        import torch
+        return 1.0 + 2.0 * torch.sigmoid(g)
     return 1.0 + 2.0 / (1.0 + np.exp(-g))
 
 
@@ -158,7 +174,10 @@ BATCHES = {
 }
 
 
-def make_batch(name, **overrides):
+def make_batch(name, device=None, **overrides):
+    """The named batch; with a torch device the slowness fields are evaluated
+    there and returned as tensors (the large batches would take minutes on
+    the host)."""
     cfg = dict(BATCHES[name])
     cfg.update(overrides)
     count, seed = cfg["count"], cfg["seed"]
@@ -166,7 +185,7 @@ def make_batch(name, **overrides):
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     problems, receivers, data = [], [], []
     for q, N in enumerate(int(v) for v in Ns):
-        s = 1.0 / speed_field(N, seed * 100003 + q)
+        s = 1.0 / speed_field(N, seed * 100003 + q, device=device)
         f = gaussian_sources(N, source_centers(seed * 100003 + q, 1))
         problems.append(Problem(name=f"{name}[{q}]", N=N, omega=cfg["kh"] * (N - 1),
                                 slowness=s, f=f, factor_dtype="c64"))
