@@ -182,6 +182,41 @@ def run_batch(args):
         kern[name] = (ms.value, nl.value, work.value)
     _lib.check(L.hssx_prof_enable(0))
     sec = (t1 - t0) / args.steps
+
+    # phase breakdown of one more (untimed) step, through the same calls
+    from paper_2105_07791_amd.hssx import Factor, gmres_solve
+    ph = {}
+
+    def mark(name, t):
+        torch.cuda.synchronize()
+        ph[name] = round(time.perf_counter() - t, 3)
+        return time.perf_counter()
+
+    tp = time.perf_counter()
+    parts = [Operator(Ns[q], om[q], s_all[offs[q]:offs[q + 1]]) for q in range(len(Ns))]
+    tp = mark("assemble", tp)
+    Ab = BatchOperator(parts)
+    del parts
+    tp = mark("batch_operator", tp)
+    fo = {k: v for k, v in opts.items() if k != "flexible"}
+    Pb = Factor(Ab, **fo)
+    fst = Pb.stats()
+    tp = mark("factor", tp)
+    ph["factor_symbolic_host"] = round(fst["ms_symbolic"] / 1e3, 3)
+    ph["factor_numeric"] = round(fst["ms_numeric"] / 1e3, 3)
+    xb, stf = gmres_solve(Ab, Pb, b, flexible=True)
+    tp = mark("gmres_forward", tp)
+    gx = torch.zeros_like(xb)
+    gx[rec] = xb[rec] - d
+    lam, stb = gmres_solve(Ab, Pb, gx.conj(), flexible=True, trans=True)
+    tp = mark("gmres_adjoint", tp)
+    Ab.dAds_contract(lam, xb)
+    tp = mark("dAds", tp)
+    ph["gmres_iters_forward_max"] = max(v["iters"] for v in stf)
+    ph["gmres_iters_adjoint_max"] = max(v["iters"] for v in stb)
+    ph["true_res_forward_max"] = max(v["true_res"] for v in stf)
+    print(f"[bench] phases {ph}", file=sys.stderr, flush=True)
+    del Pb, Ab
     out = {
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
@@ -190,7 +225,7 @@ def run_batch(args):
         "config": {"workload": args.workload, "problems": len(Ns), "n": n,
                    "N_min": min(Ns), "N_max": max(Ns), "factor_dtype": "c64", "hss_tol": tol,
                    "step": "assemble + factor + flexible GMRES + misfit + adjoint gradient"},
-        "J": J.item(), "grad_norm": torch.linalg.vector_norm(g).item(),
+        "J": J.item(), "grad_norm": torch.linalg.vector_norm(g).item(), "phases_s": ph,
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kern.items()},
     }
     if not args.no_cpu_baseline:

@@ -98,6 +98,116 @@ __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   __syncthreads();
 }
 
+// Small dense products inside one kTC-thread workgroup: C (M x N) =
+// op(A) B, or C = C0 - op(A) B, with op(A) = A (M x K, ld lda) or A^T (A
+// stored K x M).  (32 RU) x 128 output tiles, each thread an RU x 4 block
+// (RU = 4 for complex64, 2 for complex128); K in chunks of 16 staged through
+// LDS (As, Bs: 16 x 128 each).  Every thread of the workgroup must call it
+// (it synchronises).
+template <typename T, bool TA, bool SUB>
+__device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+                        const cplx<T> *__restrict__ B, long ldb, const cplx<T> *C0, long ldc0,
+                        cplx<T> *C, long ldc, cplx<T> (*As)[128], cplx<T> (*Bs)[128]) {
+  constexpr int RU = sizeof(T) == sizeof(float) ? 4 : 2, TM = 32 * RU;
+  const int tid = threadIdx.x, tx = tid % 32, ty = tid / 32;
+  for (int i0 = 0; i0 < M; i0 += TM)
+    for (int j0 = 0; j0 < N; j0 += 128) {
+      cplx<T> acc[RU][4];
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = czero<T>();
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < 16 * TM; e += kTC) {
+          int kk, i;
+          if (TA) { kk = e % 16; i = e / 16; }
+          else { i = e % TM; kk = e / TM; }
+          const int gi = i0 + i, gk = k0 + kk;
+          cplx<T> a = czero<T>();
+          if (gi < M && gk < K) a = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
+          As[kk][i] = a;
+        }
+        for (int e = tid; e < 16 * 128; e += kTC) {
+          const int kk = e % 16, j = e / 16, gk = k0 + kk, gj = j0 + j;
+          Bs[kk][j] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : czero<T>();
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+          cplx<T> a[RU], b[4];
+#pragma unroll
+          for (int u = 0; u < RU; ++u) a[u] = As[kk][ty + 32 * u];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) b[v] = Bs[kk][tx + 32 * v];
+#pragma unroll
+          for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cfma(acc[u][v], a[u], b[v]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = i0 + ty + 32 * u, gj = j0 + tx + 32 * v;
+          if (gi < M && gj < N) {
+            if (SUB) C[gi + (long)gj * ldc] = C0[gi + (long)gj * ldc0] - acc[u][v];
+            else C[gi + (long)gj * ldc] = acc[u][v];
+          }
+        }
+    }
+  __syncthreads();
+}
+
+// Interpolation coefficients T = R11^-1 R12 of the pivoted QR, written as
+// U(row, b) for every non-pivot row: R(b, row) = Rm[b + row * ldr] (pivot
+// index b, original row), R11(b, a) = R(b, perm[a]).  kG lanes per column
+// hold its kXU-strided entries in registers; back substitution over a, the
+// new entry broadcast to the column's lanes by a shuffle.  rk <= kG * kXU.
+constexpr int kG = 32, kXU = 6;
+template <typename T>
+__device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *__restrict__ Rm,
+                              long ldr, cplx<T> *__restrict__ U) {
+  const int tid = threadIdx.x, sub = tid % kG, col = tid / kG;
+  const int base = (tid % 64) & ~(kG - 1);
+  const int nc = rows - rk;
+  for (int c0 = 0; c0 < nc; c0 += kTC / kG) {
+    const int ci = c0 + col;
+    const bool act = ci < nc;
+    const long pr = act ? (long)perm[rk + ci] * ldr : 0;
+    cplx<T> x[kXU];
+#pragma unroll
+    for (int u = 0; u < kXU; ++u) {
+      const int b = sub + kG * u;
+      x[u] = (act && b < rk) ? Rm[b + pr] : czero<T>();
+    }
+#pragma unroll
+    for (int u = kXU - 1; u >= 0; --u) {
+      for (int la = kG - 1; la >= 0; --la) {
+        const int a = u * kG + la;
+        if (a >= rk) continue;
+        const long pa = (long)perm[a] * ldr;
+        cplx<T> v = x[u] * cinv(Rm[a + pa]);
+        v.re = __shfl(v.re, base + la);
+        v.im = __shfl(v.im, base + la);
+        if (sub == la) x[u] = v;
+#pragma unroll
+        for (int w = 0; w < u; ++w) cfms(x[w], Rm[sub + kG * w + pa], v);
+        if (sub < la) cfms(x[u], Rm[sub + kG * u + pa], v);
+      }
+    }
+    if (act) {
+      const int row = perm[rk + ci];
+#pragma unroll
+      for (int u = 0; u < kXU; ++u) {
+        const int b = sub + kG * u;
+        if (b < rk) U[row + (long)b * rows] = x[u];
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTC) void compress_level_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
@@ -111,6 +221,7 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   __shared__ int si[kTC / 64];
   __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
+  __shared__ cplx<T> As[16][128], Bs[16][128];
   const HssItem it = items[blockIdx.x];
   const HssInstance I = insts[it.inst];
   const int cg = I.cl_off + it.cl;
@@ -174,20 +285,11 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
       const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
       for (int e = tid; e < rows * s; e += kTC) {
         int i = e % rows, j = e / rows;
-        cplx<T> v, o;
-        if (i < kl) {
-          v = Srl[i + (long)j * kl];
-          for (int b = 0; b < kr; ++b) cfms(v, B12[i + (long)b * kl], Omr[b + (long)j * kr]);
-          o = Oml[i + (long)j * kl];
-        } else {
-          int a = i - kl;
-          v = Srr[a + (long)j * kr];
-          for (int b = 0; b < kl; ++b) cfms(v, B21[a + (long)b * kr], Oml[b + (long)j * kl]);
-          o = Omr[a + (long)j * kr];
-        }
-        Sloc[i + (long)j * rcap] = v;
-        Oloc[i + (long)j * rcap] = o;
+        Oloc[i + (long)j * rcap] = i < kl ? Oml[i + (long)j * kl] : Omr[(i - kl) + (long)j * kr];
       }
+      // S_loc = [Sr_l - B12 Om_r ; Sr_r - B21 Om_l]
+      wg_gemm<T, false, true>(kl, s, kr, B12, kl, Omr, kr, Srl, kl, Sloc, rcap, As, Bs);
+      wg_gemm<T, false, true>(kr, s, kl, B21, kr, Oml, kl, Srr, kr, Sloc + kl, rcap, As, Bs);
     }
   }
   __syncthreads();
@@ -365,14 +467,18 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   for (int e = tid; e < rows * rk; e += kTC) U[e] = czero<T>();
   __syncthreads();
   for (int a = tid; a < rk; a += kTC) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
-  for (int c2 = tid; c2 < rows - rk; c2 += kTC) {
-    int row = perm[rk + c2];
-    // back substitution, solution written straight into U(row, :)
-    for (int a = rk - 1; a >= 0; --a) {
-      cplx<T> v = Rm[a + (long)row * C.k_cap];
-      for (int b = a + 1; b < rk; ++b)
-        cfms(v, Rm[a + (long)perm[b] * C.k_cap], U[row + (long)b * rows]);
-      U[row + (long)a * rows] = v * cinv(Rm[a + (long)perm[a] * C.k_cap]);
+  if (rk <= kG * kXU) {
+    interp_coeffs<T>(rows, rk, perm, Rm, C.k_cap, U);
+  } else {
+    for (int c2 = tid; c2 < rows - rk; c2 += kTC) {
+      int row = perm[rk + c2];
+      // back substitution, solution written straight into U(row, :)
+      for (int a = rk - 1; a >= 0; --a) {
+        cplx<T> v = Rm[a + (long)row * C.k_cap];
+        for (int b = a + 1; b < rk; ++b)
+          cfms(v, Rm[a + (long)perm[b] * C.k_cap], U[row + (long)b * rows]);
+        U[row + (long)a * rows] = v * cinv(Rm[a + (long)perm[a] * C.k_cap]);
+      }
     }
   }
   __syncthreads();
@@ -381,11 +487,10 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   cplx<T> *Omc = P + C.Om, *Src = P + C.Sr;
   for (int e = tid; e < rk * s; e += kTC) {
     int a = e % rk, j = e / rk;
-    cplx<T> o = czero<T>();
-    for (int i = 0; i < rows; ++i) cfma(o, U[i + (long)a * rows], Oloc[i + (long)j * rcap]);
-    Omc[a + (long)j * rk] = o;
     Src[a + (long)j * rk] = Sloc[perm[a] + (long)j * rcap];
   }
+  // Om_c = U^T Om_loc
+  wg_gemm<T, true, false>(rk, s, rows, U, rows, Oloc, rcap, nullptr, 0, Omc, rk, As, Bs);
   if (tid == 0) rank[cg] = rk;
 }
 
