@@ -331,7 +331,9 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
 // blocked sequence, all fronts of the batch advancing together.
 template <typename T>
 void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) {
-  constexpr int NB = 32, kSmall = 64;
+  // panel width: the register-resident panel holds 32 complex64 or 16
+  // complex128 columns per row
+  constexpr int NB = sizeof(T) == sizeof(float) ? 32 : 16, kSmall = 64;
   const hipStream_t st = sg.stream();
   std::vector<ElimJob<T>> small, big;
   for (const auto &j : jobs) (j.ne < kSmall ? small : big).push_back(j);
@@ -355,7 +357,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) 
   W.alloc(wsz * sizeof(cplx<T>));
   for (int k = 0; k < steps; ++k) {
     std::vector<PanelJob<T>> pj;
-    int mm = 0, mc = 0;
+    int mm = 0, mc = 0, mp = 0, mnb = 0;
     for (size_t a = 0; a < big.size(); ++a) {
       const auto &j = big[a];
       int p0 = k * NB;
@@ -376,8 +378,10 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) 
       pj.push_back(q);
       mm = std::max(mm, j.m);
       mc = std::max(mc, j.ncols - p0);
+      mp = std::max(mp, j.ne - p0);
+      mnb = std::max(mnb, q.nb);
     }
-    launch_panel_step<T>((int)pj.size(), sg.put(pj), mm, mc, err, st);
+    launch_panel_step<T>((int)pj.size(), sg.put(pj), mm, mc, mp, mnb, err, st);
   }
   // R = -(A_ii^-1 A_ib): negate the block F(0:ne, ne:m)
   std::vector<AxpbyJob<T>> neg;

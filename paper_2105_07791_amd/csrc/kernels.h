@@ -76,9 +76,12 @@ template <typename T> struct PanelJob {
   cplx<T> *W;      // (ne - p0) x nb
   int node;
 };
+// max_prows = largest ne - p0, max_nb = largest nb of the launch; the panel
+// runs register-resident when nb <= 32 (complex64) or 16 (complex128) and
+// ne - p0 <= 1536, else from the scratch W.
 template <typename T>
 void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_cols,
-                       int *err_node, hipStream_t st);
+                       int max_prows, int max_nb, int *err_node, hipStream_t st);
 
 // dst(i,j) += a * src1(i,j) + b * src2(i,j) for an m x n block (all column-major)
 template <typename T> struct AxpbyJob {

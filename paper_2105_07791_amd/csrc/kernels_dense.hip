@@ -194,6 +194,126 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(const PanelJob<T> *__re
   }
 }
 
+// Register-resident panel factorization: 512 threads, thread tid owns panel
+// rows tid + 512 q (q < RQ) across all NBW columns; pivot search by
+// wavefront shuffles, the pivot row broadcast and row exchanges through LDS.
+// Same results as panel_kernel (cabs1 pivots, lowest row on ties).
+constexpr int kPT = 512;
+template <typename T, int NBW, int RQ>
+__global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__restrict__ jobs,
+                                                        int *__restrict__ err_node) {
+  __shared__ T sv[kPT / 64];
+  __shared__ int si[kPT / 64];
+  __shared__ cplx<T> prow[NBW], trow[NBW];
+  __shared__ cplx<T> LU[NBW][NBW + 1], Z[NBW][NBW + 1];
+  const PanelJob<T> jb = jobs[blockIdx.x];
+  const int rows = jb.ne - jb.p0, nb = jb.nb, tid = threadIdx.x;
+  const long ld = jb.ld;
+  cplx<T> w[RQ][NBW];
+#pragma unroll
+  for (int q = 0; q < RQ; ++q) {
+    const int i = tid + kPT * q;
+#pragma unroll
+    for (int c = 0; c < NBW; ++c)
+      w[q][c] = (i < rows && c < nb) ? jb.F[(jb.p0 + i) + (long)(jb.p0 + c) * ld] : czero<T>();
+  }
+  // the pivot step t is a runtime index; every register access goes through
+  // compile-time column indices with predicates
+  for (int t = 0; t < nb; ++t) {
+    T best = (T)-1;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kPT * q;
+      cplx<T> wt = czero<T>();
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        if (c == t) wt = w[q][c];
+      const T a = cabs1(wt);
+      if (i >= t && i < rows && (a > best || (a == best && i < bi))) { best = a; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      T ov = __shfl_xor(best, off);
+      int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((tid & 63) == 0) { sv[tid / 64] = best; si[tid / 64] = bi; }
+    __syncthreads();
+    best = sv[0];
+    bi = si[0];
+#pragma unroll
+    for (int k = 1; k < kPT / 64; ++k)
+      if (sv[k] > best || (sv[k] == best && si[k] < bi)) { best = sv[k]; bi = si[k]; }
+    const bool zero = !(best > (T)0);
+    if (zero && tid == 0) atomicCAS(err_node, -1, jb.node);
+    const int pv = zero ? t : bi;
+    if (tid == 0) jb.piv[t] = jb.p0 + pv;
+    // exchange rows t and pv; the pivot row ends in prow
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kPT * q;
+      if (i == pv) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) prow[c] = w[q][c];
+      }
+      if (i == t) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) trow[c] = w[q][c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kPT * q;
+      if (i == t) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) w[q][c] = prow[c];
+      } else if (i == pv) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) w[q][c] = trow[c];
+      }
+    }
+    const cplx<T> inv = zero ? czero<T>() : cinv(prow[t]);
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kPT * q;
+      if (i > t && i < rows) {
+        cplx<T> l = czero<T>();
+#pragma unroll
+        for (int c = 0; c < NBW; ++c)
+          if (c == t) l = w[q][c];
+        l = l * inv;
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) {
+          if (c == t) w[q][c] = l;
+          else if (c > t) cfms(w[q][c], l, prow[c]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // L11 U11 to LDS, then G = (L11 U11)^-1, one column per thread (in LDS)
+  if (tid < nb) {
+#pragma unroll
+    for (int c = 0; c < NBW; ++c) LU[tid][c] = w[0][c];
+  }
+  __syncthreads();
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; ++i) {
+      cplx<T> v = mk((T)(i == c ? 1 : 0), (T)0);
+      for (int j = 0; j < i; ++j) cfms(v, LU[i][j], Z[j][c]);
+      Z[i][c] = v;
+    }
+    for (int i = nb - 1; i >= 0; --i) {
+      cplx<T> v = Z[i][c];
+      for (int j = i + 1; j < nb; ++j) cfms(v, LU[i][j], Z[j][c]);
+      Z[i][c] = v * cinv(LU[i][i]);
+    }
+    for (int i = 0; i < nb; ++i) jb.G[i + (long)c * nb] = Z[i][c];
+  }
+}
+
 template <typename T>
 __global__ void swap_kernel(const PanelJob<T> *__restrict__ jobs) {
   const PanelJob<T> jb = jobs[blockIdx.y];
@@ -304,9 +424,17 @@ void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStrea
 
 template <typename T>
 void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_cols,
-                       int *err_node, hipStream_t st) {
+                       int max_prows, int max_nb, int *err_node, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(panel_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
+  constexpr int NBW = sizeof(T) == sizeof(float) ? 32 : 16;
+  if (max_nb <= NBW && max_prows <= kPT)
+    hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 1>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= 2 * kPT)
+    hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 2>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= 3 * kPT)
+    hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 3>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
+  else
+    hipLaunchKernelGGL(panel_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
   hipLaunchKernelGGL(swap_kernel<T>, dim3(ceil_div(max_cols, 256), count), dim3(256), 0, st, jobs);
   hipLaunchKernelGGL(gemm_a_kernel<T>, dim3(ceil_div((long)max_cols * kNB, 256), count), dim3(256),
                      0, st, jobs);
@@ -335,7 +463,8 @@ HSSX_ASM(double, float)
 
 #define HSSX_INST(T)                                                                        \
   template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
-  template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int *, hipStream_t); \
+  template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
+                                     hipStream_t);                                          \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)
