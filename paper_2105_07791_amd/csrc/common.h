@@ -154,12 +154,57 @@ inline void upload(DevBuf &d, const std::vector<T> &h) {
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Device scratch arena: bump allocation from chunks that stay allocated and
+// are reused.  release(mark) frees everything allocated after the mark; call
+// it only once the stream has finished every use of that memory.
+class Arena {
+ public:
+  struct Mark {
+    size_t chunk, off;
+  };
+  Mark mark() const { return Mark{cur_, off_}; }
+  void release(Mark m) {
+    cur_ = m.chunk;
+    off_ = m.off;
+  }
+  template <typename T> T *get(size_t count) {
+    size_t need = ((std::max<size_t>(1, count * sizeof(T)) + 255) / 256) * 256;
+    while (cur_ < chunks_.size() && off_ + need > chunks_[cur_]->bytes) {
+      ++cur_;
+      off_ = 0;
+    }
+    if (cur_ == chunks_.size()) {
+      auto c = std::make_unique<DevBuf>();
+      c->alloc(std::max(need, size_t(64) << 20));
+      chunks_.push_back(std::move(c));
+      off_ = 0;
+    }
+    T *p = reinterpret_cast<T *>(static_cast<char *>(chunks_[cur_]->p) + off_);
+    off_ += need;
+    return p;
+  }
+
+ private:
+  std::vector<std::unique_ptr<DevBuf>> chunks_;
+  size_t cur_ = 0, off_ = 0;
+};
+
+// Arenas kept per device between factorizations (a factorization takes one
+// for its duration and returns it, so concurrent calls never share one).
+std::unique_ptr<Arena> acquire_arena(int device);
+void return_arena(int device, std::unique_ptr<Arena> a);
+
 // Stream-ordered upload of small descriptor arrays: host data is copied into
 // pinned chunks and sent with hipMemcpyAsync on the work stream, so uploads
 // block neither the host nor the device.  Chunks are never freed or
 // overwritten while their device copies may still be read; recycle() reuses
 // them and may only be called after the stream has been synchronised and
 // once no pointer returned by put() is used again.
+class Staging;
+// Pinned staging areas kept per device between factorizations, like arenas.
+std::unique_ptr<Staging> acquire_staging(int device, hipStream_t st);
+void return_staging(int device, std::unique_ptr<Staging> s);
+
 class Staging {
  public:
   explicit Staging(hipStream_t st) : st_(st) {}
@@ -200,6 +245,7 @@ class Staging {
     cur_ = 0;
     off_ = 0;
   }
+  void set_stream(hipStream_t st) { st_ = st; }
   hipStream_t stream() const { return st_; }
 
  private:

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "engine.h"
@@ -105,7 +107,7 @@ inline double compress_flops(const HssCluster &c, const HssInstance &I) {
 
 template <typename T>
 void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts &o, double tol,
-                    double id_tol, Staging &sg) {
+                    double id_tol, Staging &sg, Arena &ar) {
   if (tasks.empty()) return;
   const hipStream_t st = sg.stream();
   const int k0 = o.k0, r = o.r;
@@ -125,11 +127,11 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     HSSX_CHECK(t.cap <= 1024, HSSX_EINVAL, "sample block wider than the compression kernel holds");
     HSSX_CHECK(t.m <= 1 << 24, HSSX_EINVAL, "compression size");
   }
-  DevBuf Om, Y, errs;
-  Om.alloc(osz * sizeof(double));
-  Y.alloc(ysz * sizeof(cplx<T>));
-  errs.alloc(2 * tasks.size() * sizeof(double));
-  double *d_err = errs.as<double>();
+  // sketches and samples live until the last round; each round's generator
+  // pools are released once the round has been synchronised
+  double *Om = ar.get<double>(osz);
+  cplx<T> *Y = ar.get<cplx<T>>(ysz);
+  double *d_err = ar.get<double>(2 * tasks.size());
 
   auto gen_and_sample = [&](const std::vector<int> &ids, bool probe) {
     std::vector<GaussJob> gj;
@@ -138,9 +140,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     for (int i : ids) {
       auto &t = tasks[i];
       int c0 = probe ? t.s : 0, nc = probe ? r : t.s;
-      GaussJob g{Om.as<double>() + t.ooff, t.m, t.m, c0, nc, 0, (uint32_t)(4 * t.node + t.kind)};
+      GaussJob g{Om + t.ooff, t.m, t.m, c0, nc, 0, (uint32_t)(4 * t.node + t.kind)};
       gj.push_back(g);
-      SampleJob<T> s{t.S, Om.as<double>() + t.ooff + (long)c0 * t.m, Y.as<cplx<T>>() + t.yoff + (long)c0 * t.m,
+      SampleJob<T> s{t.S, Om + t.ooff + (long)c0 * t.m, Y + t.yoff + (long)c0 * t.m,
                      t.ldS, t.m, t.m, t.m, nc};
       sj.push_back(s);
       mm = std::max(mm, t.m);
@@ -162,6 +164,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
 
   std::vector<int> active = all;
   while (!active.empty()) {
+    const Arena::Mark round_mark = ar.mark();
     // ---- layout of the active instances
     std::vector<HssInstance> inst;
     std::vector<HssCluster> cls;
@@ -203,14 +206,13 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     const cplx<T> *base = tasks[active[0]].S;
     for (size_t a = 0; a < active.size(); ++a) inst[a].soff = tasks[active[a]].S - base;
 
-    DevBuf d_pool, d_ipool, d_rank, d_scr;
     HssInstance *d_inst = sg.put(inst);
     HssCluster *d_cls = sg.put(cls);
-    d_pool.alloc(std::max(1L, pool) * sizeof(cplx<T>));
-    d_ipool.alloc(std::max(1L, ipool) * sizeof(int));
-    d_rank.alloc(std::max<size_t>(1, cls.size()) * sizeof(int));
-    d_scr.alloc(std::max(1L, scratch) * sizeof(cplx<T>));
-    HSSX_HIP(hipMemsetAsync(d_rank.p, 0, cls.size() * sizeof(int), st));
+    cplx<T> *d_pool = ar.get<cplx<T>>(pool);
+    int *d_ipool = ar.get<int>(ipool);
+    int *d_rank = ar.get<int>(cls.size());
+    cplx<T> *d_scr = ar.get<cplx<T>>(scratch);
+    HSSX_HIP(hipMemsetAsync(d_rank, 0, cls.size() * sizeof(int), st));
 
     // ---- bottom-up compression, one launch per cluster-tree level
     for (int lev = maxlev; lev >= 0; --lev) {
@@ -225,9 +227,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       double cflops = 0;
       for (const auto &it : items) cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
       hipEvent_t pc = prof_begin(st);
-      launch_compress_level<T>((int)items.size(), d_items, d_inst, d_cls, d_pool.as<cplx<T>>(),
-                               d_ipool.as<int>(), d_rank.as<int>(), base, Y.as<cplx<T>>(),
-                               Om.as<double>(), d_scr.as<cplx<T>>(), id_tol, st);
+      launch_compress_level<T>((int)items.size(), d_items, d_inst, d_cls, d_pool,
+                               d_ipool, d_rank, base, Y,
+                               Om, d_scr, id_tol, st);
       prof_end("compress_level", st, pc, cflops);
     }
 
@@ -238,32 +240,31 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       auto &t = tasks[active[a]];
       MatvecJob<T> j{};
       j.inst = (int)a;
-      j.X = Om.as<double>() + t.ooff + (long)t.s * t.m;
+      j.X = Om + t.ooff + (long)t.s * t.m;
       j.ldX = t.m;
       j.nc = r;
       j.c0 = 0;
       j.out = nullptr;
       j.ldO = 0;
-      j.Yref = Y.as<cplx<T>>() + t.yoff + (long)t.s * t.m;
+      j.Yref = Y + t.yoff + (long)t.s * t.m;
       j.ldR = t.m;
       j.err2 = d_err + 2 * active[a];
       j.ref2 = d_err + 2 * active[a] + 1;
       j.woff = (long)a * xh_per_job_max;
       mj.push_back(j);
     }
-    DevBuf d_xh;
     MatvecJob<T> *d_mj = sg.put(mj);
-    d_xh.alloc(std::max(1L, (long)mj.size() * xh_per_job_max) * sizeof(cplx<T>));
+    cplx<T> *d_xh = ar.get<cplx<T>>((long)mj.size() * xh_per_job_max);
     HSSX_CHECK(r <= 64, HSSX_EINVAL, "probe block wider than 64 columns");
     hipEvent_t pm = prof_begin(st);
-    launch_hss_matvec<T>((int)mj.size(), d_mj, d_inst, d_cls, d_pool.as<cplx<T>>(),
-                         d_rank.as<int>(), d_xh.as<cplx<T>>(), st);
+    launch_hss_matvec<T>((int)mj.size(), d_mj, d_inst, d_cls, d_pool,
+                         d_rank, d_xh, st);
     prof_end("hss_matvec", st, pm, 0.0);
     std::vector<double> h_err(2 * tasks.size());
     std::vector<int> h_rank(cls.size());
     HSSX_HIP(hipMemcpyAsync(h_err.data(), d_err, h_err.size() * sizeof(double),
                             hipMemcpyDeviceToHost, st));
-    HSSX_HIP(hipMemcpyAsync(h_rank.data(), d_rank.p, h_rank.size() * sizeof(int),
+    HSSX_HIP(hipMemcpyAsync(h_rank.data(), d_rank, h_rank.size() * sizeof(int),
                             hipMemcpyDeviceToHost, st));
     HSSX_HIP(hipStreamSynchronize(st));
 
@@ -304,16 +305,16 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       }
     }
     if (!ej.empty()) {
-      DevBuf d_xh2;
       MatvecJob<T> *d_ej = sg.put(ej);
-      d_xh2.alloc(std::max(1L, (long)ej.size() * xh_per_job_max) * sizeof(cplx<T>));
+      cplx<T> *d_xh2 = ar.get<cplx<T>>((long)ej.size() * xh_per_job_max);
       hipEvent_t pm2 = prof_begin(st);
-      launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool.as<cplx<T>>(),
-                           d_rank.as<int>(), d_xh2.as<cplx<T>>(), st);
+      launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool,
+                           d_rank, d_xh2, st);
       prof_end("hss_matvec", st, pm2, 0.0);
-      // the round's pools are freed below; wait for the expansion first
+      // the round's pools are released below; wait for the expansion first
       HSSX_HIP(hipStreamSynchronize(st));
     }
+    ar.release(round_mark);
     active.swap(next);
   }
 }
@@ -330,7 +331,7 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
 // one workgroup each; larger ones go panel by panel (32 columns) through the
 // blocked sequence, all fronts of the batch advancing together.
 template <typename T>
-void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) {
+void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, Arena &ar) {
   // panel width: the register-resident panel holds 32 complex64 or 16
   // complex128 columns per row
   constexpr int NB = sizeof(T) == sizeof(float) ? 32 : 16, kSmall = 64;
@@ -350,11 +351,14 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) 
     wsz += (long)j.ne * NB;
     steps = std::max(steps, ceil_div(j.ne, NB));
   }
-  DevBuf piv, G, Y, W;
-  piv.alloc(big.size() * NB * sizeof(int));
-  G.alloc(big.size() * NB * NB * sizeof(cplx<T>));
-  Y.alloc(ysz * sizeof(cplx<T>));
-  W.alloc(wsz * sizeof(cplx<T>));
+  const Arena::Mark mk0 = ar.mark();
+  int *piv = ar.get<int>(big.size() * NB);
+  cplx<T> *G = ar.get<cplx<T>>(big.size() * NB * NB);
+  cplx<T> *Y = ar.get<cplx<T>>(ysz);
+  // the panel copy W is only read when a panel is too tall for registers
+  int maxne = 0;
+  for (const auto &j : big) maxne = std::max(maxne, j.ne);
+  cplx<T> *W = maxne > 1536 ? ar.get<cplx<T>>(wsz) : nullptr;
   for (int k = 0; k < steps; ++k) {
     std::vector<PanelJob<T>> pj;
     int mm = 0, mc = 0, mp = 0, mnb = 0;
@@ -370,10 +374,10 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) 
       q.ne = j.ne;
       q.p0 = p0;
       q.nb = std::min(NB, j.ne - p0);
-      q.piv = piv.as<int>() + a * NB;
-      q.G = G.as<cplx<T>>() + a * NB * NB;
-      q.Y = Y.as<cplx<T>>() + yo[a];
-      q.W = W.as<cplx<T>>() + wo[a];
+      q.piv = piv + a * NB;
+      q.G = G + a * NB * NB;
+      q.Y = Y + yo[a];
+      q.W = W ? W + wo[a] : nullptr;
       q.node = j.node;
       pj.push_back(q);
       mm = std::max(mm, j.m);
@@ -394,12 +398,13 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg) 
     nn = std::max(nn, j.m - j.ne);
   }
   if (!neg.empty()) launch_axpby<T>((int)neg.size(), sg.put(neg), nm, nn, st);
-  // the panel scratch is freed on return
+  // the panel scratch is released on return
   HSSX_HIP(hipStreamSynchronize(st));
+  ar.release(mk0);
 }
 
 template <typename T>
-void factor_impl(hssx_fact_ &P, hipStream_t st) {
+void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   hssx_op_ &A = *P.A;
   const Symbolic &sym = P.sym;
   cplx<T> *F = P.front.as<cplx<T>>();
@@ -409,11 +414,9 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
   const double eps = sizeof(T) == sizeof(float) ? 1.1920929e-7 : 2.220446049250313e-16;
   const double id_tol =
       P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : std::max(1e-2 * P.tol, 4.0 * eps);
-  Staging sg(st);
-  DevBuf err;
-  err.alloc(sizeof(int));
+  int *err = ar.get<int>(1);
   int *d_err = sg.put(std::vector<int>{-1});
-  HSSX_HIP(hipMemcpyAsync(err.p, d_err, sizeof(int), hipMemcpyDeviceToDevice, st));
+  HSSX_HIP(hipMemcpyAsync(err, d_err, sizeof(int), hipMemcpyDeviceToDevice, st));
   int kmax = 0, rounds_max = 0, ncomp = 0;
   double est_max = 0;
   // accepted rank cap k of each node's Schur-complement compression; a
@@ -448,7 +451,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         rj.push_back(ElimJob<double>{F64 + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
       }
       hipEvent_t pe = prof_begin(st);
-      eliminate_jobs<double>(rj, err.as<int>(), sg);
+      eliminate_jobs<double>(rj, err, sg, ar);
       prof_end("front_eliminate", st, pe, elim_flops(rj));
       HSSX_HIP(hipStreamSynchronize(st));
       sg.recycle();
@@ -464,7 +467,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     std::vector<int> hn;
     for (int k : nodes)
       if (P.arith[k] && sym.nodes[k].parent >= 0 && P.h_desc[k].ni > 0) hn.push_back(k);
-    DevBuf G, H;
+    const Arena::Mark depth_mark = ar.mark();
     if (!hn.empty()) {
       long gsz = 0, hsz = 0;
       std::vector<long> goff, hoff;
@@ -475,8 +478,8 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         gsz += (long)ni * ni;
         hsz += (long)(ni - p) * (ni - p);
       }
-      G.alloc(std::max(1L, gsz) * sizeof(cplx<T>));
-      H.alloc(std::max(1L, hsz) * sizeof(cplx<T>));
+      cplx<T> *G = ar.get<cplx<T>>(gsz);
+      cplx<T> *H = ar.get<cplx<T>>(hsz);
       std::vector<AxpbyJob<T>> cp;
       std::vector<ElimJob<T>> ej;
       std::vector<CompressTask<T>> tasks;
@@ -485,7 +488,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         int k = hn[a];
         const FrontDesc &fd = P.h_desc[k];
         int ni = fd.ni, p = sym.nodes[sym.nodes[k].lo].p0;
-        cplx<T> *g = G.as<cplx<T>>() + goff[a];
+        cplx<T> *g = G + goff[a];
         cp.push_back(AxpbyJob<T>{g, F + fd.foff, nullptr, ni, fd.f, 0, ni, ni, (T)1, (T)0});
         mm = std::max(mm, ni);
         ej.push_back(ElimJob<T>{g, ni, ni, ni, p, 0, k});
@@ -498,18 +501,18 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
           t.ct = interior_subtree(sym.nodes[sym.nodes[k].hi]);
           t.S = g + p + (long)p * ni;
           t.ldS = ni;
-          t.target = H.as<cplx<T>>() + hoff[a];
+          t.target = H + hoff[a];
           t.ldT = ni - p;
           tasks.push_back(std::move(t));
         }
       }
       // G := 0 then G += A_ii; eliminate mu's block: G(p:, p:) = S~
-      HSSX_HIP(hipMemsetAsync(G.p, 0, G.bytes, st));
+      HSSX_HIP(hipMemsetAsync(G, 0, gsz * sizeof(cplx<T>), st));
       launch_axpby<T>((int)cp.size(), sg.put(cp), mm, mm, st);
       hipEvent_t pe = prof_begin(st);
-      eliminate_jobs<T>(ej, err.as<int>(), sg);
+      eliminate_jobs<T>(ej, err, sg, ar);
       prof_end("front_eliminate", st, pe, elim_flops(ej));
-      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg);
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg, ar);
       std::vector<AxpbyJob<T>> fix;
       int fm = 0;
       size_t ti = 0;
@@ -522,7 +525,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
         record(t);
         // F(p:ni, p:ni) += S~_HSS - S~
         fix.push_back(AxpbyJob<T>{F + fd.foff + p + (long)p * fd.f, t.target,
-                                  G.as<cplx<T>>() + goff[a] + p + (long)p * ni, fd.f, ni - p,
+                                  G + goff[a] + p + (long)p * ni, fd.f, ni - p,
                                   ni, ni - p, ni - p, (T)1, (T)-1});
         fm = std::max(fm, ni - p);
       }
@@ -536,7 +539,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       jobs.push_back(ElimJob<T>{F + fd.foff, fd.f, fd.f, fd.f + fd.ni, fd.ni, 1, k});
     }
     hipEvent_t pe = prof_begin(st);
-    eliminate_jobs<T>(jobs, err.as<int>(), sg);
+    eliminate_jobs<T>(jobs, err, sg, ar);
     prof_end("front_eliminate", st, pe, elim_flops(jobs));
 
     // ---- compress the Schur complements the parents will use in HSS form
@@ -558,7 +561,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
       tasks.push_back(std::move(t));
     }
     if (!tasks.empty()) {
-      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg);
+      compress_batch<T>(tasks, P.opts, P.tol, id_tol, sg, ar);
       for (auto &t : tasks) {
         record(t);
         kfin[t.node] = t.k;
@@ -569,10 +572,11 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
     // (G, H) and the staged descriptors are released
     HSSX_HIP(hipStreamSynchronize(st));
     sg.recycle();
+    ar.release(depth_mark);
   }
   int bad = -1;
   HSSX_HIP(hipStreamSynchronize(st));
-  HSSX_HIP(hipMemcpy(&bad, err.p, sizeof(int), hipMemcpyDeviceToHost));
+  HSSX_HIP(hipMemcpy(&bad, err, sizeof(int), hipMemcpyDeviceToHost));
   HSSX_CHECK(bad < 0, HSSX_ESINGULAR, "zero pivot in the dense block of tree node " + std::to_string(bad));
   P.stats.k_max = kmax;
   P.stats.max_rounds_used = rounds_max;
@@ -582,13 +586,70 @@ void factor_impl(hssx_fact_ &P, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+std::mutex g_pool_mu;
+std::map<int, std::vector<std::unique_ptr<Arena>>> g_arenas;
+std::map<int, std::vector<std::unique_ptr<Staging>>> g_stagings;
+}  // namespace
+
+std::unique_ptr<Arena> acquire_arena(int device) {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  auto &v = g_arenas[device];
+  if (v.empty()) return std::make_unique<Arena>();
+  auto a = std::move(v.back());
+  v.pop_back();
+  return a;
+}
+
+void return_arena(int device, std::unique_ptr<Arena> a) {
+  a->release(Arena::Mark{0, 0});
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_arenas[device].push_back(std::move(a));
+}
+
+std::unique_ptr<Staging> acquire_staging(int device, hipStream_t st) {
+  std::unique_ptr<Staging> s;
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    auto &v = g_stagings[device];
+    if (!v.empty()) {
+      s = std::move(v.back());
+      v.pop_back();
+    }
+  }
+  if (!s) s = std::make_unique<Staging>(st);
+  s->set_stream(st);
+  return s;
+}
+
+void return_staging(int device, std::unique_ptr<Staging> s) {
+  s->recycle();
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_stagings[device].push_back(std::move(s));
+}
+
 void factor_numeric(hssx_fact_ &P, hipStream_t st) {
   hipEvent_t e0, e1;
   HSSX_HIP(hipEventCreate(&e0));
   HSSX_HIP(hipEventCreate(&e1));
   HSSX_HIP(hipEventRecord(e0, st));
-  if (P.dtype == HSSX_C128) factor_impl<double>(P, st);
-  else factor_impl<float>(P, st);
+  // scratch arena and pinned staging are taken from per-device caches and
+  // returned afterwards (also on error), so repeated factorizations reuse them
+  int dev = 0;
+  HSSX_HIP(hipGetDevice(&dev));
+  std::unique_ptr<Arena> ar = acquire_arena(dev);
+  std::unique_ptr<Staging> sg = acquire_staging(dev, st);
+  try {
+    if (P.dtype == HSSX_C128) factor_impl<double>(P, st, *sg, *ar);
+    else factor_impl<float>(P, st, *sg, *ar);
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    return_arena(dev, std::move(ar));
+    return_staging(dev, std::move(sg));
+    throw;
+  }
+  return_arena(dev, std::move(ar));
+  return_staging(dev, std::move(sg));
   HSSX_HIP(hipEventRecord(e1, st));
   HSSX_HIP(hipEventSynchronize(e1));
   float ms = 0;

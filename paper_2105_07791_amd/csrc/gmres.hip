@@ -19,8 +19,17 @@
 
 namespace hssx {
 
-void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb, c128 *x,
-           long ldx, const hssx_gmres_opts &o, hssx_gmres_stats *stats, hipStream_t st) {
+namespace {
+
+// scratch taken from the arena for the duration of one solve
+struct Scr {
+  void *p = nullptr;
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+void gmres_impl(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb,
+                c128 *x, long ldx, const hssx_gmres_opts &o, hssx_gmres_stats *stats,
+                hipStream_t st, Arena &ar, Staging &stg) {
   const int n = A.n, m = o.m;
   const bool left = !o.flexible;
   const long blk = (long)n * nrhs;
@@ -38,37 +47,37 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
     // CSR values + column indices once, row pointers, x read and y written per rhs
     prof_end("spmv", st, pe, A.nnz * 20.0 + (n + 1) * 4.0 + 2.0 * blk * sizeof(c128));
   };
-  DevBuf V, Z, w, t1, H, cs, sn, g, y, hcol, h2, hn, res, cnt, act, part, partd, nrm, xc, bc;
-  V.alloc((size_t)(m + 1) * blk * sizeof(c128));
-  if (!left) Z.alloc((size_t)m * blk * sizeof(c128));
-  w.alloc(blk * sizeof(c128));
-  t1.alloc(blk * sizeof(c128));
-  xc.alloc(blk * sizeof(c128));
-  bc.alloc(blk * sizeof(c128));
-  H.alloc((size_t)(m + 1) * m * nseg * sizeof(c128));
-  cs.alloc((size_t)m * nseg * sizeof(double));
-  sn.alloc((size_t)m * nseg * sizeof(c128));
-  g.alloc((size_t)(m + 1) * nseg * sizeof(c128));
-  y.alloc((size_t)m * nseg * sizeof(c128));
-  hcol.alloc((size_t)(m + 1) * nseg * sizeof(c128));
-  h2.alloc((size_t)(m + 1) * nseg * sizeof(c128));
-  hn.alloc(nseg * sizeof(double));
-  res.alloc(nseg * sizeof(double));
-  nrm.alloc(nseg * sizeof(double));
-  cnt.alloc(nseg * sizeof(int));
-  act.alloc(nseg * sizeof(int));
+  auto take = [&](size_t bytes) {
+    Scr q;
+    q.p = ar.get<char>(bytes);
+    return q;
+  };
+  Scr V = take((size_t)(m + 1) * blk * sizeof(c128));
+  Scr Z = left ? Scr{} : take((size_t)m * blk * sizeof(c128));
+  Scr w = take(blk * sizeof(c128)), t1 = take(blk * sizeof(c128));
+  Scr xc = take(blk * sizeof(c128)), bc = take(blk * sizeof(c128));
+  Scr H = take((size_t)(m + 1) * m * nseg * sizeof(c128));
+  Scr cs = take((size_t)m * nseg * sizeof(double));
+  Scr sn = take((size_t)m * nseg * sizeof(c128));
+  Scr g = take((size_t)(m + 1) * nseg * sizeof(c128));
+  Scr y = take((size_t)m * nseg * sizeof(c128));
+  Scr hcol = take((size_t)(m + 1) * nseg * sizeof(c128));
+  Scr h2 = take((size_t)(m + 1) * nseg * sizeof(c128));
+  Scr hn = take(nseg * sizeof(double)), res = take(nseg * sizeof(double));
+  Scr nrm = take(nseg * sizeof(double));
+  Scr cnt = take(nseg * sizeof(int)), act = take(nseg * sizeof(int));
   const int nblk = std::max(1, std::min(64, ceil_div(maxlen, 256 * 8)));
-  part.alloc((size_t)nblk * (m + 1) * nseg * sizeof(c128));
-  partd.alloc((size_t)nblk * nseg * sizeof(double));
+  Scr part = take((size_t)nblk * (m + 1) * nseg * sizeof(c128));
+  Scr partd = take((size_t)nblk * nseg * sizeof(double));
 
   // hcol += h2 for Arnoldi step j, one descriptor per step, uploaded once
-  DevBuf cgs_job;
+  const AxpbyJob<double> *cgs_job;
   {
     std::vector<AxpbyJob<double>> aj;
     for (int j = 0; j < m; ++j)
       aj.push_back(AxpbyJob<double>{hcol.as<c128>(), h2.as<c128>(), nullptr, (j + 1) * nseg,
                                     (j + 1) * nseg, 0, (j + 1) * nseg, 1, 1.0, 0.0});
-    upload(cgs_job, aj);
+    cgs_job = stg.put(aj);
   }
 
   // contiguous copies of b and x
@@ -159,7 +168,7 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
                   nblk, st);
       launch_mupdate(n, nrhs, sg, j + 1, Vp, stride, h2.as<c128>(), w.as<c128>(), st);
       // hcol += h2 (the second Gram-Schmidt pass's coefficients)
-      launch_axpby<double>(1, cgs_job.as<AxpbyJob<double>>() + j, (j + 1) * nseg, 1, st);
+      launch_axpby<double>(1, cgs_job + j, (j + 1) * nseg, 1, st);
       launch_norms(n, nrhs, sg, w.as<c128>(), hn.as<double>(), partd.as<double>(), nblk, st);
       launch_scale(n, nrhs, sg, w.as<c128>(), hn.as<double>(), Vp + (j + 1) * stride, st);
       launch_givens(nseg, j, m, H.as<c128>(), hcol.as<c128>(), hn.as<double>(), cs.as<double>(),
@@ -196,6 +205,26 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
       stats[r].true_res = true_rel[r];
     }
   (void)total;
+}
+
+}  // namespace
+
+void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb, c128 *x,
+           long ldx, const hssx_gmres_opts &o, hssx_gmres_stats *stats, hipStream_t st) {
+  int dev = 0;
+  HSSX_HIP(hipGetDevice(&dev));
+  std::unique_ptr<Arena> ar = acquire_arena(dev);
+  std::unique_ptr<Staging> stg = acquire_staging(dev, st);
+  try {
+    gmres_impl(A, P, trans, nrhs, b, ldb, x, ldx, o, stats, st, *ar, *stg);
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    return_arena(dev, std::move(ar));
+    return_staging(dev, std::move(stg));
+    throw;
+  }
+  return_arena(dev, std::move(ar));
+  return_staging(dev, std::move(stg));
 }
 
 }  // namespace hssx
