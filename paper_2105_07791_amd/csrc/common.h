@@ -170,6 +170,12 @@ class Arena {
   template <typename T> T *get(size_t count) {
     size_t need = ((std::max<size_t>(1, count * sizeof(T)) + 255) / 256) * 256;
     while (cur_ < chunks_.size() && off_ + need > chunks_[cur_]->bytes) {
+      if (off_ == 0) {
+        // an unused chunk that is too small: give its memory back (every
+        // chunk from cur_ on is unused, and released memory is idle)
+        chunks_.erase(chunks_.begin() + cur_);
+        continue;
+      }
       ++cur_;
       off_ = 0;
     }

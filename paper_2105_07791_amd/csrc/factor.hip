@@ -49,7 +49,10 @@ template <typename T> struct CompressTask {
 
 struct Layout {
   std::vector<HssCluster> cl;
-  long pool = 0, ipool = 0, scratch = 0, xh = 0;
+  long pool = 0, ipool = 0, xh = 0;
+  // compression scratch per tree level: a cluster's local samples are only
+  // used while its own level runs, so the levels share one region
+  std::vector<long> level_scratch;
 };
 
 // cluster capacities and pool offsets of one instance for rank cap k and s columns
@@ -86,8 +89,10 @@ Layout layout_instance(const ClusterTree &ct, int k, int s) {
       h.B12 = h.B21 = 0;
     }
     h.sk = (int)L.ipool; L.ipool += std::max(1L, kk);
-    h.W = L.scratch; L.scratch += 3 * r * s + std::max(1L, kk) * std::max(1L, r);
-    h.XH = L.xh; L.xh += 2 * std::max(1L, kk) * 64;
+    if ((int)L.level_scratch.size() <= h.level) L.level_scratch.resize(h.level + 1, 0);
+    h.W = L.level_scratch[h.level];
+    L.level_scratch[h.level] += 3 * r * s + std::max(1L, kk) * std::max(1L, r);
+    h.XH = L.xh; L.xh += 2 * std::max(1L, kk) * kXC;
   }
   return L;
 }
@@ -169,11 +174,17 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     std::vector<HssInstance> inst;
     std::vector<HssCluster> cls;
     std::vector<Layout> lay;
-    long pool = 0, ipool = 0, scratch = 0, xh_per_job_max = 0;
+    long pool = 0, ipool = 0;
+    int max_width = 0, max_ncl = 0;
+    std::vector<long> xh_of;     // matvec scratch per job of each instance
+    std::vector<long> lev_scr;   // running scratch offset per tree level
     int maxlev = 0;
     for (int i : active) {
       auto &t = tasks[i];
       Layout L = layout_instance(t.ct, t.k, t.s);
+      if (lev_scr.size() < L.level_scratch.size()) lev_scr.resize(L.level_scratch.size(), 0);
+      for (auto &c : L.cl) c.W += lev_scr[c.level];
+      for (size_t l = 0; l < L.level_scratch.size(); ++l) lev_scr[l] += L.level_scratch[l];
       for (const auto &c : L.cl)
         HSSX_CHECK(c.rows_cap <= 1024, HSSX_EINVAL,
                    "local sample block taller than the compression kernel holds");
@@ -190,11 +201,19 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       h.yoff = t.yoff;
       h.ooff = t.ooff;
       h.ldY = t.m;
-      h.woff = scratch;
+      h.woff = 0;
+      // clusters are numbered level by level
+      h.nlev = t.ct.depth() + 1;
+      HSSX_CHECK(h.nlev <= kMaxLev, HSSX_EINVAL, "cluster tree deeper than the matvec supports");
+      for (int l = 0, c = 0; l <= h.nlev; ++l) {
+        while (c < h.ncl && t.ct.level[c] < l) ++c;
+        h.lev_off[l] = c;
+      }
+      for (int l = 0; l < h.nlev; ++l) max_width = std::max(max_width, h.lev_off[l + 1] - h.lev_off[l]);
+      max_ncl = std::max(max_ncl, h.ncl);
       pool += L.pool;
       ipool += L.ipool;
-      scratch += L.scratch;
-      xh_per_job_max = std::max(xh_per_job_max, L.xh);
+      xh_of.push_back(L.xh);
       cls.insert(cls.end(), L.cl.begin(), L.cl.end());
       inst.push_back(h);
       maxlev = std::max(maxlev, t.ct.depth());
@@ -211,6 +230,8 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     cplx<T> *d_pool = ar.get<cplx<T>>(pool);
     int *d_ipool = ar.get<int>(ipool);
     int *d_rank = ar.get<int>(cls.size());
+    long scratch = 0;
+    for (long v : lev_scr) scratch = std::max(scratch, v);
     cplx<T> *d_scr = ar.get<cplx<T>>(scratch);
     HSSX_HIP(hipMemsetAsync(d_rank, 0, cls.size() * sizeof(int), st));
 
@@ -233,32 +254,36 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       prof_end("compress_level", st, pc, cflops);
     }
 
-    // ---- error estimate with r fresh probes (eq. 2.7)
+    // ---- error estimate with r fresh probes (eq. 2.7), kXC columns per job
     gen_and_sample(active, true);
     std::vector<MatvecJob<T>> mj;
+    long xh_total = 0;
     for (size_t a = 0; a < active.size(); ++a) {
       auto &t = tasks[active[a]];
-      MatvecJob<T> j{};
-      j.inst = (int)a;
-      j.X = Om + t.ooff + (long)t.s * t.m;
-      j.ldX = t.m;
-      j.nc = r;
-      j.c0 = 0;
-      j.out = nullptr;
-      j.ldO = 0;
-      j.Yref = Y + t.yoff + (long)t.s * t.m;
-      j.ldR = t.m;
-      j.err2 = d_err + 2 * active[a];
-      j.ref2 = d_err + 2 * active[a] + 1;
-      j.woff = (long)a * xh_per_job_max;
-      mj.push_back(j);
+      for (int c0 = 0; c0 < r; c0 += kXC) {
+        MatvecJob<T> j{};
+        j.inst = (int)a;
+        j.X = Om + t.ooff + (long)(t.s + c0) * t.m;
+        j.ldX = t.m;
+        j.nc = std::min(kXC, r - c0);
+        j.c0 = 0;
+        j.out = nullptr;
+        j.ldO = 0;
+        j.Yref = Y + t.yoff + (long)(t.s + c0) * t.m;
+        j.ldR = t.m;
+        j.err2 = d_err + 2 * active[a];
+        j.ref2 = d_err + 2 * active[a] + 1;
+        j.woff = xh_total;
+        xh_total += xh_of[a];
+        mj.push_back(j);
+      }
     }
     MatvecJob<T> *d_mj = sg.put(mj);
-    cplx<T> *d_xh = ar.get<cplx<T>>((long)mj.size() * xh_per_job_max);
-    HSSX_CHECK(r <= 64, HSSX_EINVAL, "probe block wider than 64 columns");
+    cplx<T> *d_xh = ar.get<cplx<T>>(xh_total);
+    HSSX_HIP(hipMemsetAsync(d_err, 0, 2 * tasks.size() * sizeof(double), st));
     hipEvent_t pm = prof_begin(st);
-    launch_hss_matvec<T>((int)mj.size(), d_mj, d_inst, d_cls, d_pool,
-                         d_rank, d_xh, st);
+    launch_hss_matvec<T>((int)mj.size(), d_mj, d_inst, d_cls, d_pool, d_rank, d_xh, maxlev + 1,
+                         max_width, max_ncl, st);
     prof_end("hss_matvec", st, pm, 0.0);
     std::vector<double> h_err(2 * tasks.size());
     std::vector<int> h_rank(cls.size());
@@ -271,6 +296,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     // ---- decisions; expand the accepted instances into their targets
     std::vector<int> next;
     std::vector<MatvecJob<T>> ej;
+    long xh2_total = 0;
     for (size_t a = 0; a < active.size(); ++a) {
       auto &t = tasks[active[a]];
       t.rounds += 1;
@@ -289,27 +315,27 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
         continue;
       }
       t.done = true;
-      // expansion H I in 16-column blocks: more workgroups for the few large
-      // instances near the root
-      for (int c0 = 0; c0 < t.m; c0 += 16) {
+      // expansion H I in kXC-column blocks
+      for (int c0 = 0; c0 < t.m; c0 += kXC) {
         MatvecJob<T> j{};
         j.inst = (int)a;
         j.X = nullptr;
         j.c0 = c0;
-        j.nc = std::min(16, t.m - c0);
+        j.nc = std::min(kXC, t.m - c0);
         j.out = t.target + (long)c0 * t.ldT;
         j.ldO = t.ldT;
         j.Yref = nullptr;
-        j.woff = (long)ej.size() * xh_per_job_max;
+        j.woff = xh2_total;
+        xh2_total += xh_of[a];
         ej.push_back(j);
       }
     }
     if (!ej.empty()) {
       MatvecJob<T> *d_ej = sg.put(ej);
-      cplx<T> *d_xh2 = ar.get<cplx<T>>((long)ej.size() * xh_per_job_max);
+      cplx<T> *d_xh2 = ar.get<cplx<T>>(xh2_total);
       hipEvent_t pm2 = prof_begin(st);
-      launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool,
-                           d_rank, d_xh2, st);
+      launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool, d_rank, d_xh2,
+                           maxlev + 1, max_width, max_ncl, st);
       prof_end("hss_matvec", st, pm2, 0.0);
       // the round's pools are released below; wait for the expansion first
       HSSX_HIP(hipStreamSynchronize(st));

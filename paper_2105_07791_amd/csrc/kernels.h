@@ -128,9 +128,13 @@ struct HssCluster {
   long W;               // compression scratch offset (relative to the instance)
   long XH;              // matvec scratch offset (relative to the job)
 };
+constexpr int kMaxLev = 24;   // cluster-tree levels of one instance
+constexpr int kXC = 16;       // columns of one HSS matvec job
 struct HssInstance {
   int m;                // matrix size
   int ncl;              // clusters (level order, root = 0)
+  int nlev;             // tree levels; level l holds clusters [lev_off[l], lev_off[l+1])
+  int lev_off[kMaxLev + 1];
   int cl_off;           // first cluster in the global cluster array
   int s;                // sample columns (k + r)
   int k;                // rank cap of this round
@@ -151,9 +155,12 @@ void launch_compress_level(int count, const HssItem *items, const HssInstance *i
                            const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
                            const cplx<T> *front, const cplx<T> *Y, const double *Om,
                            cplx<T> *scratch, double id_tol, hipStream_t st);
-// Per instance (one workgroup each): out = H X for the compressed H, with X
-// given (ldX) or the identity when X is null; if Yref is given, accumulate
-// err2 = ||Yref - H X||_F^2 and ref2 = ||Yref||_F^2 instead of writing out.
+// Per job (nc <= kXC columns of one instance): out = H X for the compressed
+// H, with X given (ldX) or the identity columns c0.. when X is null; if Yref
+// is given, add ||Yref - H X||_F^2 to *err2 and ||Yref||_F^2 to *ref2 (both
+// zeroed by the caller) instead of writing out.  Scratch per job: 2 k_cap
+// kXC per cluster at XH.  nlev, max_width, max_ncl: the largest level count,
+// clusters in one level and clusters of the launch's instances.
 template <typename T> struct MatvecJob {
   int inst;
   const double *X;      // real input (m x nc), or null for identity columns c0..
@@ -168,7 +175,7 @@ template <typename T> struct MatvecJob {
 template <typename T>
 void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *inst,
                        const HssCluster *cl, const cplx<T> *pool, const int *rank,
-                       cplx<T> *scratch, hipStream_t st);
+                       cplx<T> *scratch, int nlev, int max_width, int max_ncl, hipStream_t st);
 
 // ------------------------------------------------------------ apply (Alg. 3.1)
 // y = x(perm) (inverse = 0) or y(perm) = x (inverse = 1), n x nrhs

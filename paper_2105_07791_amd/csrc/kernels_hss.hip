@@ -19,9 +19,10 @@
 //           T = R11^-1 R12, U(J, :) = I, U(rest, :) = T^T.  The cluster keeps
 //           Om_c = U^T Om_loc, Sr_c = S_loc(J, :), skeleton I_loc(J).  The
 //           root only reads its B blocks.
-// hss_matvec: telescoping product (eqs. 2.5-2.6) by one workgroup per job,
-//           used both for the error estimate of eq. 2.7 and to expand the
-//           compressed matrix column block by column block.
+// hss_matvec: telescoping product (eqs. 2.5-2.6), one launch per tree level
+//           and phase, one workgroup per (job, cluster); used both for the
+//           error estimate of eq. 2.7 and to expand the compressed matrix
+//           column block by column block.
 #include "common.h"
 #include "kernels.h"
 
@@ -29,7 +30,6 @@ namespace hssx {
 
 namespace {
 
-constexpr int kT = 1024;         // threads per workgroup of the HSS matvec
 constexpr int kTC = 1024;        // threads per workgroup of the compression
 constexpr int kTPR = 4;          // lanes per row in the global-memory pivoted QR
 // register-resident pivoted QR (complex64): 16 lanes per row, 64 row slots,
@@ -494,148 +494,221 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   if (tid == 0) rank[cg] = rk;
 }
 
-// Telescoping product out = H X by one workgroup.
+// ---------------------------------------------------------------- matvec
+// Telescoping product out = H X (eqs. 2.5-2.6) for a batch of jobs (one
+// instance, up to kXC columns each), one launch per tree level and phase:
+// up-sweep xh_c = U_c^T [X rows | children's xh], sibling couplings
+// yh_l = B12 xh_r, yh_r = B21 xh_l, down-sweep [yh_l; yh_r] += U_c yh_c, and
+// the leaves out = D X + U yh.  Every (job, cluster) pair is one workgroup.
+constexpr int kMT = 256;
+
+// out(M x nc) = op(A) X for one workgroup: A(m, k) from aload, X(k, j) from
+// xin, results handed to put(m, j, value).  64 output rows at a time, K in
+// chunks of 32; A and X tiles staged through LDS.  TA selects the loading
+// order (k fastest when A is stored K x M).
+template <typename T, bool TA, typename AF, typename XF, typename PF>
+__device__ void mv_block(int M, int K, int nc, AF aload, XF xin, PF put, cplx<T> (*As)[65],
+                         cplx<T> (*Xs)[kXC]) {
+  const int tid = threadIdx.x, jj = tid % kXC, ab = tid / kXC;
+  for (int a0 = 0; a0 < M; a0 += 64) {
+    cplx<T> acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = czero<T>();
+    for (int i0 = 0; i0 < K; i0 += 32) {
+      __syncthreads();
+      for (int e = tid; e < 32 * 64; e += kMT) {
+        int ii, aa;
+        if (TA) { ii = e % 32; aa = e / 32; }
+        else { aa = e % 64; ii = e / 64; }
+        const int gi = i0 + ii, ga = a0 + aa;
+        As[ii][aa] = (gi < K && ga < M) ? aload(ga, gi) : czero<T>();
+      }
+      for (int e = tid; e < 32 * kXC; e += kMT) {
+        const int ii = e % 32, j = e / 32, gi = i0 + ii;
+        Xs[ii][j] = (gi < K && j < nc) ? xin(gi, j) : czero<T>();
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int ii = 0; ii < 32; ++ii) {
+        const cplx<T> x = Xs[ii][jj];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cfma(acc[u], As[ii][ab + 16 * u], x);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = a0 + ab + 16 * u;
+      if (a < M && jj < nc) put(a, jj, acc[u]);
+    }
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(kT) void hss_matvec_kernel(
-    const MatvecJob<T> *__restrict__ jobs, const HssInstance *__restrict__ insts,
-    const HssCluster *__restrict__ cls, const cplx<T> *__restrict__ pool,
-    const int *__restrict__ rank, cplx<T> *__restrict__ scratch) {
-  __shared__ double red[2][kT];
+__global__ __launch_bounds__(kMT) void mv_up_kernel(int lev, const MatvecJob<T> *__restrict__ jobs,
+                                                    const HssInstance *__restrict__ insts,
+                                                    const HssCluster *__restrict__ cls,
+                                                    const cplx<T> *__restrict__ pool,
+                                                    const int *__restrict__ rank,
+                                                    cplx<T> *__restrict__ scratch) {
+  __shared__ cplx<T> As[32][65];
+  __shared__ cplx<T> Xs[32][kXC];
   const MatvecJob<T> jb = jobs[blockIdx.x];
-  const HssInstance I = insts[jb.inst];
-  const HssCluster *C = cls + I.cl_off;
-  const int *rk = rank + I.cl_off;
-  const cplx<T> *P = pool + I.pool;
-  const int nc = jb.nc, tid = threadIdx.x;
+  const HssInstance &I = insts[jb.inst];
+  if (lev >= I.nlev) return;
+  const int c = I.lev_off[lev] + blockIdx.y;
+  if (c >= I.lev_off[lev + 1]) return;
+  const HssCluster cc = cls[I.cl_off + c];
+  const int k = rank[I.cl_off + c], nc = jb.nc;
   cplx<T> *W = scratch + jb.woff;
-  auto X = [&](int i, int j) -> T {
-    if (!jb.X) return (i == jb.c0 + j) ? (T)1 : (T)0;
-    return (T)jb.X[i + (long)j * jb.ldX];
-  };
-  int maxlev = 0;
-  for (int c = 0; c < I.ncl; ++c) maxlev = C[c].level > maxlev ? C[c].level : maxlev;
-  // up-sweep: xh_c = U_c^T (X rows | stacked children)
-  for (int lev = maxlev; lev >= 1; --lev) {
-    for (int c = 0; c < I.ncl; ++c) {
-      const HssCluster cc = C[c];
-      if (cc.level != lev) continue;
-      const int k = rk[c];
-      const cplx<T> *U = P + cc.U;
-      cplx<T> *xh = W + cc.XH;
-      if (!jb.X && (cc.start + cc.size <= jb.c0 || cc.start >= jb.c0 + nc)) {
-        // identity columns outside this cluster: its up-sweep vector is zero
-        for (int e = tid; e < k * nc; e += kT) xh[e] = czero<T>();
-      } else if (cc.left < 0) {
-        for (int e = tid; e < k * nc; e += kT) {
-          int a = e % k, j = e / k;
-          cplx<T> v = czero<T>();
-          for (int i = 0; i < cc.size; ++i) {
-            cplx<T> u = U[i + (long)a * cc.size];
-            T x = X(cc.start + i, j);
-            v.re += u.re * x;
-            v.im += u.im * x;
-          }
-          xh[a + (long)j * k] = v;
-        }
-      } else {
-        const int kl = rk[cc.left], kr = rk[cc.right], rows = kl + kr;
-        const cplx<T> *xl = W + C[cc.left].XH, *xr = W + C[cc.right].XH;
-        for (int e = tid; e < k * nc; e += kT) {
-          int a = e % k, j = e / k;
-          cplx<T> v = czero<T>();
-          for (int i = 0; i < kl; ++i) cfma(v, U[i + (long)a * rows], xl[i + (long)j * kl]);
-          for (int i = 0; i < kr; ++i) cfma(v, U[kl + i + (long)a * rows], xr[i + (long)j * kr]);
-          xh[a + (long)j * k] = v;
-        }
-      }
-    }
-    __syncthreads();
+  cplx<T> *xh = W + cc.XH;
+  if (!jb.X && (cc.start + cc.size <= jb.c0 || cc.start >= jb.c0 + nc)) {
+    // identity columns outside this cluster: its up-sweep vector is zero
+    for (int e = threadIdx.x; e < k * nc; e += kMT) xh[e] = czero<T>();
+    return;
   }
-  // couplings: yh_l = B12 xh_r, yh_r = B21 xh_l (yh stored after xh: XH + k_cap*64)
-  for (int c = 0; c < I.ncl; ++c) {
-    const HssCluster cc = C[c];
-    if (cc.left < 0) continue;
-    const int kl = rk[cc.left], kr = rk[cc.right];
-    const HssCluster L = C[cc.left], R = C[cc.right];
-    const cplx<T> *B12 = P + cc.B12, *B21 = P + cc.B21;
-    cplx<T> *yl = W + L.XH + (long)L.k_cap * 64, *yr = W + R.XH + (long)R.k_cap * 64;
-    const cplx<T> *xl = W + L.XH, *xr = W + R.XH;
-    for (int e = tid; e < (kl + kr) * nc; e += kT) {
-      int a = e % (kl + kr), j = e / (kl + kr);
-      cplx<T> v = czero<T>();
-      if (a < kl) {
-        for (int b = 0; b < kr; ++b) cfma(v, B12[a + (long)b * kl], xr[b + (long)j * kr]);
-        yl[a + (long)j * kl] = v;
-      } else {
-        a -= kl;
-        for (int b = 0; b < kl; ++b) cfma(v, B21[a + (long)b * kr], xl[b + (long)j * kl]);
-        yr[a + (long)j * kr] = v;
-      }
-    }
+  const cplx<T> *U = pool + I.pool + cc.U;
+  auto put = [&](int a, int j, cplx<T> v) { xh[a + (long)j * k] = v; };
+  if (cc.left < 0) {
+    const int rows = cc.size;
+    auto aload = [&](int a, int i) { return U[i + (long)a * rows]; };
+    auto xin = [&](int i, int j) {
+      const int gi = cc.start + i;
+      const T v = jb.X ? (T)jb.X[gi + (long)j * jb.ldX] : (T)(gi == jb.c0 + j ? 1 : 0);
+      return mk(v, (T)0);
+    };
+    mv_block<T, true>(k, rows, nc, aload, xin, put, As, Xs);
+  } else {
+    const int kl = rank[I.cl_off + cc.left], kr = rank[I.cl_off + cc.right], rows = kl + kr;
+    const cplx<T> *xl = W + cls[I.cl_off + cc.left].XH, *xr = W + cls[I.cl_off + cc.right].XH;
+    auto aload = [&](int a, int i) { return U[i + (long)a * rows]; };
+    auto xin = [&](int i, int j) {
+      return i < kl ? xl[i + (long)j * kl] : xr[(i - kl) + (long)j * kr];
+    };
+    mv_block<T, true>(k, rows, nc, aload, xin, put, As, Xs);
   }
-  __syncthreads();
-  // down-sweep through internal non-root clusters
-  for (int lev = 1; lev <= maxlev; ++lev) {
-    for (int c = 0; c < I.ncl; ++c) {
-      const HssCluster cc = C[c];
-      if (cc.level != lev || cc.left < 0) continue;
-      const int k = rk[c], kl = rk[cc.left], kr = rk[cc.right], rows = kl + kr;
-      const cplx<T> *U = P + cc.U;
-      const cplx<T> *yh = W + cc.XH + (long)cc.k_cap * 64;
-      cplx<T> *yl = W + C[cc.left].XH + (long)C[cc.left].k_cap * 64;
-      cplx<T> *yr = W + C[cc.right].XH + (long)C[cc.right].k_cap * 64;
-      for (int e = tid; e < rows * nc; e += kT) {
-        int i = e % rows, j = e / rows;
-        cplx<T> v = czero<T>();
-        for (int a = 0; a < k; ++a) cfma(v, U[i + (long)a * rows], yh[a + (long)j * k]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMT) void mv_couple_kernel(const MatvecJob<T> *__restrict__ jobs,
+                                                        const HssInstance *__restrict__ insts,
+                                                        const HssCluster *__restrict__ cls,
+                                                        const cplx<T> *__restrict__ pool,
+                                                        const int *__restrict__ rank,
+                                                        cplx<T> *__restrict__ scratch) {
+  __shared__ cplx<T> As[32][65];
+  __shared__ cplx<T> Xs[32][kXC];
+  const MatvecJob<T> jb = jobs[blockIdx.x];
+  const HssInstance &I = insts[jb.inst];
+  const int c = blockIdx.y;
+  if (c >= I.ncl) return;
+  const HssCluster cc = cls[I.cl_off + c];
+  if (cc.left < 0) return;
+  const int kl = rank[I.cl_off + cc.left], kr = rank[I.cl_off + cc.right], nc = jb.nc;
+  const HssCluster L = cls[I.cl_off + cc.left], R = cls[I.cl_off + cc.right];
+  const cplx<T> *B12 = pool + I.pool + cc.B12, *B21 = pool + I.pool + cc.B21;
+  cplx<T> *W = scratch + jb.woff;
+  cplx<T> *yl = W + L.XH + (long)L.k_cap * kXC, *yr = W + R.XH + (long)R.k_cap * kXC;
+  const cplx<T> *xl = W + L.XH, *xr = W + R.XH;
+  mv_block<T, false>(
+      kl, kr, nc, [&](int a, int b) { return B12[a + (long)b * kl]; },
+      [&](int b, int j) { return xr[b + (long)j * kr]; },
+      [&](int a, int j, cplx<T> v) { yl[a + (long)j * kl] = v; }, As, Xs);
+  mv_block<T, false>(
+      kr, kl, nc, [&](int a, int b) { return B21[a + (long)b * kr]; },
+      [&](int b, int j) { return xl[b + (long)j * kl]; },
+      [&](int a, int j, cplx<T> v) { yr[a + (long)j * kr] = v; }, As, Xs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMT) void mv_down_kernel(int lev, const MatvecJob<T> *__restrict__ jobs,
+                                                      const HssInstance *__restrict__ insts,
+                                                      const HssCluster *__restrict__ cls,
+                                                      const cplx<T> *__restrict__ pool,
+                                                      const int *__restrict__ rank,
+                                                      cplx<T> *__restrict__ scratch) {
+  __shared__ cplx<T> As[32][65];
+  __shared__ cplx<T> Xs[32][kXC];
+  const MatvecJob<T> jb = jobs[blockIdx.x];
+  const HssInstance &I = insts[jb.inst];
+  if (lev >= I.nlev) return;
+  const int c = I.lev_off[lev] + blockIdx.y;
+  if (c >= I.lev_off[lev + 1]) return;
+  const HssCluster cc = cls[I.cl_off + c];
+  if (cc.left < 0) return;
+  const int k = rank[I.cl_off + c], kl = rank[I.cl_off + cc.left],
+            kr = rank[I.cl_off + cc.right], rows = kl + kr, nc = jb.nc;
+  const cplx<T> *U = pool + I.pool + cc.U;
+  cplx<T> *W = scratch + jb.woff;
+  const cplx<T> *yh = W + cc.XH + (long)cc.k_cap * kXC;
+  const HssCluster L = cls[I.cl_off + cc.left], R = cls[I.cl_off + cc.right];
+  cplx<T> *yl = W + L.XH + (long)L.k_cap * kXC, *yr = W + R.XH + (long)R.k_cap * kXC;
+  mv_block<T, false>(
+      rows, k, nc, [&](int i, int a) { return U[i + (long)a * rows]; },
+      [&](int a, int j) { return yh[a + (long)j * k]; },
+      [&](int i, int j, cplx<T> v) {
         if (i < kl) yl[i + (long)j * kl] = yl[i + (long)j * kl] + v;
         else yr[(i - kl) + (long)j * kr] = yr[(i - kl) + (long)j * kr] + v;
-      }
-    }
-    __syncthreads();
-  }
-  // leaves
+      },
+      As, Xs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMT) void mv_leaf_kernel(const MatvecJob<T> *__restrict__ jobs,
+                                                      const HssInstance *__restrict__ insts,
+                                                      const HssCluster *__restrict__ cls,
+                                                      const cplx<T> *__restrict__ pool,
+                                                      const int *__restrict__ rank,
+                                                      cplx<T> *__restrict__ scratch) {
+  __shared__ cplx<T> As[32][65];
+  __shared__ cplx<T> Xs[32][kXC];
+  __shared__ double red[2][kMT];
+  const MatvecJob<T> jb = jobs[blockIdx.x];
+  const HssInstance &I = insts[jb.inst];
+  const int c = blockIdx.y;
+  if (c >= I.ncl) return;
+  const HssCluster cc = cls[I.cl_off + c];
+  if (cc.left >= 0) return;
+  const int k = c == 0 ? 0 : rank[I.cl_off + c], rows = cc.size, nc = jb.nc;
+  const cplx<T> *U = pool + I.pool + cc.U, *D = pool + I.pool + cc.D;
+  const cplx<T> *yh = scratch + jb.woff + cc.XH + (long)cc.k_cap * kXC;
   double e2 = 0.0, r2 = 0.0;
-  for (int c = 0; c < I.ncl; ++c) {
-    const HssCluster cc = C[c];
-    if (cc.left >= 0) continue;
-    const int k = c == 0 ? 0 : rk[c];
-    const cplx<T> *U = P + cc.U, *D = P + cc.D;
-    const cplx<T> *yh = W + cc.XH + (long)cc.k_cap * 64;
-    for (int e = tid; e < cc.size * nc; e += kT) {
-      int i = e % cc.size, j = e / cc.size;
-      cplx<T> v = czero<T>();
-      if (!jb.X) {
-        const int l = jb.c0 + j - cc.start;     // identity column inside the leaf?
-        if (l >= 0 && l < cc.size) v = D[i + (long)l * cc.size];
-      } else {
-        for (int l = 0; l < cc.size; ++l) {
-          cplx<T> d = D[i + (long)l * cc.size];
-          T x = X(cc.start + l, j);
-          v.re += d.re * x;
-          v.im += d.im * x;
+  // out = [D U] [X rows; yh]
+  mv_block<T, false>(
+      rows, rows + k, nc,
+      [&](int i, int l) { return l < rows ? D[i + (long)l * rows] : U[i + (long)(l - rows) * rows]; },
+      [&](int l, int j) {
+        if (l >= rows) return yh[(l - rows) + (long)j * k];
+        const int gl = cc.start + l;
+        const T v = jb.X ? (T)jb.X[gl + (long)j * jb.ldX] : (T)(gl == jb.c0 + j ? 1 : 0);
+        return mk(v, (T)0);
+      },
+      [&](int i, int j, cplx<T> v) {
+        const long gi = cc.start + i;
+        if (jb.Yref) {
+          const cplx<T> y = jb.Yref[gi + (long)j * jb.ldR];
+          e2 += (double)abs2(y - v);
+          r2 += (double)abs2(y);
+        } else {
+          jb.out[gi + (long)j * jb.ldO] = v;
         }
-      }
-      for (int a = 0; a < k; ++a) cfma(v, U[i + (long)a * cc.size], yh[a + (long)j * k]);
-      int gi = cc.start + i;
-      if (jb.Yref) {
-        cplx<T> yr = jb.Yref[gi + (long)j * jb.ldR];
-        e2 += (double)abs2(yr - v);
-        r2 += (double)abs2(yr);
-      } else {
-        jb.out[gi + (long)j * jb.ldO] = v;
-      }
-    }
-  }
+      },
+      As, Xs);
   if (jb.Yref) {
+    const int tid = threadIdx.x;
     red[0][tid] = e2;
     red[1][tid] = r2;
     __syncthreads();
-    for (int w = kT / 2; w > 0; w >>= 1) {
-      if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+    for (int w = kMT / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] += red[0][tid + w];
+        red[1][tid] += red[1][tid + w];
+      }
       __syncthreads();
     }
-    if (tid == 0) { *jb.err2 = red[0][0]; *jb.ref2 = red[1][0]; }
+    if (tid == 0) {
+      atomicAdd(jb.err2, red[0][0]);
+      atomicAdd(jb.ref2, red[1][0]);
+    }
   }
 }
 
@@ -671,10 +744,18 @@ void launch_compress_level(int count, const HssItem *items, const HssInstance *i
 template <typename T>
 void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *inst,
                        const HssCluster *cl, const cplx<T> *pool, const int *rank,
-                       cplx<T> *scratch, hipStream_t st) {
+                       cplx<T> *scratch, int nlev, int max_width, int max_ncl, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(hss_matvec_kernel<T>, dim3(count), dim3(kT), 0, st, jobs, inst, cl, pool,
-                     rank, scratch);
+  for (int lev = nlev - 1; lev >= 1; --lev)
+    hipLaunchKernelGGL(mv_up_kernel<T>, dim3(count, max_width), dim3(kMT), 0, st, lev, jobs, inst,
+                       cl, pool, rank, scratch);
+  hipLaunchKernelGGL(mv_couple_kernel<T>, dim3(count, max_ncl), dim3(kMT), 0, st, jobs, inst, cl,
+                     pool, rank, scratch);
+  for (int lev = 1; lev < nlev; ++lev)
+    hipLaunchKernelGGL(mv_down_kernel<T>, dim3(count, max_width), dim3(kMT), 0, st, lev, jobs,
+                       inst, cl, pool, rank, scratch);
+  hipLaunchKernelGGL(mv_leaf_kernel<T>, dim3(count, max_ncl), dim3(kMT), 0, st, jobs, inst, cl,
+                     pool, rank, scratch);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -686,7 +767,7 @@ void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *i
                                          cplx<T> *, double, hipStream_t);                     \
   template void launch_hss_matvec<T>(int, const MatvecJob<T> *, const HssInstance *,          \
                                      const HssCluster *, const cplx<T> *, const int *,        \
-                                     cplx<T> *, hipStream_t);
+                                     cplx<T> *, int, int, int, hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)
 #undef HSSX_INST
