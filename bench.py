@@ -423,6 +423,7 @@ def main():
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
         "gmres_iters_max": max(iters), "gmres_iters_mean": sum(iters) / len(iters),
         "true_res_max": true_res, "factor_ms": fstats["ms_numeric"],
+        "symbolic_ms": fstats["ms_symbolic"],
         "k_max": fstats["k_max"], "factor_bytes": fstats["factor_bytes"],
         "compressions": fstats["n_compressed"], "max_rank_rounds": fstats["max_rounds_used"],
         "max_estimate": fstats["max_estimate"], "hss_nodes": fstats["n_hss_nodes"],

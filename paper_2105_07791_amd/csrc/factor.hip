@@ -363,7 +363,10 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   constexpr int NB = sizeof(T) == sizeof(float) ? 32 : 16, kSmall = 64;
   const hipStream_t st = sg.stream();
   std::vector<ElimJob<T>> small, big;
-  for (const auto &j : jobs) (j.ne < kSmall ? small : big).push_back(j);
+  // single-workgroup elimination for fronts with few pivots and few rows;
+  // the blocked path spreads the trailing update of larger fronts over many
+  // workgroups
+  for (const auto &j : jobs) (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
   if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
   if (big.empty()) return;
   // scratch per job: pivots, G, Y, W

@@ -22,37 +22,36 @@ namespace hssx {
 namespace {
 
 struct CNode {
-  std::vector<int> ids;  // leaf payload
   std::unique_ptr<CNode> l, r;
+  int start = 0, stop = 0;  // range in the leaf order
 };
 
-std::unique_ptr<CNode> bisect(std::vector<int> ids, int N, int beta) {
+// Geometric bisection of ids[0, n) in place; the final array is the leaf
+// order (in-order concatenation of the leaves), node ranges are offsets.
+std::unique_ptr<CNode> bisect(int *ids, int n, int offset, int N, int beta,
+                              std::vector<long> &key) {
   auto node = std::make_unique<CNode>();
-  if ((int)ids.size() <= beta) {
-    node->ids = std::move(ids);
-    return node;
-  }
+  node->start = offset;
+  node->stop = offset + n;
+  if (n <= beta) return node;
   int xmin = N, xmax = -1, ymin = N, ymax = -1;
-  for (int v : ids) {
-    int x = v % N, y = v / N;
+  for (int k = 0; k < n; ++k) {
+    int x = ids[k] % N, y = ids[k] / N;
     xmin = std::min(xmin, x); xmax = std::max(xmax, x);
     ymin = std::min(ymin, y); ymax = std::max(ymax, y);
   }
-  bool by_x = (xmax - xmin) >= (ymax - ymin);
-  std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
-    int ax = a % N, ay = a / N, bx = b % N, by = b / N;
-    if (by_x) {
-      if (ax != bx) return ax < bx;
-      if (ay != by) return ay < by;
-    } else {
-      if (ay != by) return ay < by;
-      if (ax != bx) return ax < bx;
-    }
-    return a < b;
-  });
-  size_t h = ids.size() / 2;
-  node->l = bisect(std::vector<int>(ids.begin(), ids.begin() + h), N, beta);
-  node->r = bisect(std::vector<int>(ids.begin() + h, ids.end()), N, beta);
+  const bool by_x = (xmax - xmin) >= (ymax - ymin);
+  // order by the split axis, then the other coordinate (unique per node)
+  key.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const long x = ids[k] % N, y = ids[k] / N;
+    key[k] = by_x ? ((x * N + y) << 32 | (unsigned)ids[k]) : ((y * N + x) << 32 | (unsigned)ids[k]);
+  }
+  std::sort(key.begin(), key.begin() + n);
+  for (int k = 0; k < n; ++k) ids[k] = (int)(key[k] & 0xffffffffL);
+  const int h = n / 2;
+  node->l = bisect(ids, h, offset, N, beta, key);
+  node->r = bisect(ids + h, n - h, offset + h, N, beta, key);
   return node;
 }
 
@@ -61,36 +60,21 @@ void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
                        int N, int beta, ClusterTree &ct, std::vector<int> &order) {
   ct = ClusterTree();
   order.clear();
+  if (P0.empty() && P1.empty()) return;
+  order = P0;
+  order.insert(order.end(), P1.begin(), P1.end());
+  std::vector<long> key;
   std::unique_ptr<CNode> root;
-  if (!P0.empty() && !P1.empty()) {
+  const int n0 = (int)P0.size(), n1 = (int)P1.size();
+  if (n0 && n1) {
     root = std::make_unique<CNode>();
-    root->l = bisect(P0, N, beta);
-    root->r = bisect(P1, N, beta);
-  } else if (!P0.empty()) {
-    root = bisect(P0, N, beta);
-  } else if (!P1.empty()) {
-    root = bisect(P1, N, beta);
+    root->start = 0;
+    root->stop = n0 + n1;
+    root->l = bisect(order.data(), n0, 0, N, beta, key);
+    root->r = bisect(order.data() + n0, n1, n0, N, beta, key);
   } else {
-    return;
+    root = bisect(order.data(), n0 + n1, 0, N, beta, key);
   }
-  // in-order ranges
-  std::vector<std::pair<const CNode *, std::pair<int, int>>> rng;
-  std::function<void(const CNode *)> walk = [&](const CNode *t) {
-    int st = (int)order.size();
-    if (!t->l) {
-      order.insert(order.end(), t->ids.begin(), t->ids.end());
-    } else {
-      walk(t->l.get());
-      walk(t->r.get());
-    }
-    rng.push_back({t, {st, (int)order.size()}});
-  };
-  walk(root.get());
-  auto range_of = [&](const CNode *t) {
-    for (auto &p : rng)
-      if (p.first == t) return p.second;
-    return std::make_pair(0, 0);
-  };
   // breadth-first numbering
   std::vector<std::pair<const CNode *, int>> q{{root.get(), 0}};
   for (size_t k = 0; k < q.size(); ++k) {
@@ -104,9 +88,8 @@ void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
   ct.start.resize(nc); ct.size.resize(nc); ct.left.assign(nc, -1);
   ct.right.assign(nc, -1); ct.level.resize(nc);
   for (int k = 0, child = 1; k < nc; ++k) {
-    auto r = range_of(q[k].first);
-    ct.start[k] = r.first;
-    ct.size[k] = r.second - r.first;
+    ct.start[k] = q[k].first->start;
+    ct.size[k] = q[k].first->stop - q[k].first->start;
     ct.level[k] = q[k].second;
     if (q[k].first->l) {
       // children of the k-th node were appended in order; locate them
@@ -153,9 +136,11 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
 
   static const int dx[6] = {1, -1, 0, 0, 1, -1};
   static const int dy[6] = {0, 0, 1, -1, 1, -1};
+  // a node with a neighbour outside the box lies on the box's border, so
+  // only border cells are tested (row-major, so the ids come out sorted)
   for (auto &b : nodes) {
     for (int y = b.y0; y < b.y1; ++y)
-      for (int x = b.x0; x < b.x1; ++x) {
+      for (int x = b.x0; x < b.x1; x = (y == b.y0 || y == b.y1 - 1 || x == b.x1 - 1) ? x + 1 : b.x1 - 1) {
         bool out = false;
         for (int d = 0; d < 6 && !out; ++d) {
           int u = x + dx[d], v = y + dy[d];
