@@ -236,22 +236,27 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     HSSX_HIP(hipMemsetAsync(d_rank, 0, cls.size() * sizeof(int), st));
 
     // ---- bottom-up compression, one launch per cluster-tree level
+    // (clusters of at most 64 rows in small workgroups, the others in large)
     for (int lev = maxlev; lev >= 0; --lev) {
-      std::vector<HssItem> items;
+      std::vector<HssItem> items[2];
       for (size_t a = 0; a < active.size(); ++a) {
         const auto &ct = tasks[active[a]].ct;
-        for (int c = 0; c < ct.count(); ++c)
-          if (ct.level[c] == lev) items.push_back(HssItem{(int)a, c});
+        for (int c = inst[a].lev_off[std::min(lev, inst[a].nlev)];
+             c < inst[a].lev_off[std::min(lev + 1, inst[a].nlev)]; ++c)
+          items[cls[inst[a].cl_off + c].rows_cap <= 64 ? 0 : 1].push_back(HssItem{(int)a, c});
+        (void)ct;
       }
-      if (items.empty()) continue;
-      HssItem *d_items = sg.put(items);
-      double cflops = 0;
-      for (const auto &it : items) cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
-      hipEvent_t pc = prof_begin(st);
-      launch_compress_level<T>((int)items.size(), d_items, d_inst, d_cls, d_pool,
-                               d_ipool, d_rank, base, Y,
-                               Om, d_scr, id_tol, st);
-      prof_end("compress_level", st, pc, cflops);
+      for (int sz = 0; sz < 2; ++sz) {
+        if (items[sz].empty()) continue;
+        HssItem *d_items = sg.put(items[sz]);
+        double cflops = 0;
+        for (const auto &it : items[sz])
+          cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
+        hipEvent_t pc = prof_begin(st);
+        launch_compress_level<T>((int)items[sz].size(), d_items, d_inst, d_cls, d_pool, d_ipool,
+                                 d_rank, base, Y, Om, d_scr, id_tol, sz == 0, st);
+        prof_end("compress_level", st, pc, cflops);
+      }
     }
 
     // ---- error estimate with r fresh probes (eq. 2.7), kXC columns per job

@@ -30,11 +30,14 @@ namespace hssx {
 
 namespace {
 
-constexpr int kTC = 1024;        // threads per workgroup of the compression
 constexpr int kTPR = 4;          // lanes per row in the global-memory pivoted QR
-// register-resident pivoted QR (complex64): 16 lanes per row, 64 row slots,
-// 4 rows per slot, 12 columns per lane -> rows <= 256, sample columns <= 192
-constexpr int kRT = 16, kRS = kTC / kRT, kRPT = 4, kRSEG = 12;
+// Workgroup sizes of the compression kernel: NT = 1024 for clusters of more
+// than 64 rows, 256 below.  The register-resident pivoted QR (complex64)
+// uses RT lanes per row, NT / RT row slots, RPT rows per slot and RSEG
+// columns per lane: rows <= NT / RT * RPT, sample columns <= RT * RSEG.
+template <int NT> struct CCfg;
+template <> struct CCfg<1024> { static constexpr int RT = 16, RPT = 4, RSEG = 12; };
+template <> struct CCfg<256> { static constexpr int RT = 8, RPT = 2, RSEG = 24; };
 constexpr int kMaxRows = 1024;   // rows of one local sample block (LDS index arrays)
 constexpr int kMaxS = 1024;      // sample columns held in LDS for the projector
 
@@ -98,17 +101,17 @@ __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   __syncthreads();
 }
 
-// Small dense products inside one kTC-thread workgroup: C (M x N) =
+// Small dense products inside one NT-thread workgroup: C (M x N) =
 // op(A) B, or C = C0 - op(A) B, with op(A) = A (M x K, ld lda) or A^T (A
-// stored K x M).  (32 RU) x 128 output tiles, each thread an RU x 4 block
+// stored K x M).  (NT/32 RU) x 128 output tiles, each thread an RU x 4 block
 // (RU = 4 for complex64, 2 for complex128); K in chunks of 16 staged through
 // LDS (As, Bs: 16 x 128 each).  Every thread of the workgroup must call it
 // (it synchronises).
-template <typename T, bool TA, bool SUB>
+template <typename T, int NT, bool TA, bool SUB>
 __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
                         const cplx<T> *__restrict__ B, long ldb, const cplx<T> *C0, long ldc0,
                         cplx<T> *C, long ldc, cplx<T> (*As)[128], cplx<T> (*Bs)[128]) {
-  constexpr int RU = sizeof(T) == sizeof(float) ? 4 : 2, TM = 32 * RU;
+  constexpr int RU = sizeof(T) == sizeof(float) ? 4 : 2, TY = NT / 32, TM = TY * RU;
   const int tid = threadIdx.x, tx = tid % 32, ty = tid / 32;
   for (int i0 = 0; i0 < M; i0 += TM)
     for (int j0 = 0; j0 < N; j0 += 128) {
@@ -119,7 +122,7 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
         for (int v = 0; v < 4; ++v) acc[u][v] = czero<T>();
       for (int k0 = 0; k0 < K; k0 += 16) {
         __syncthreads();
-        for (int e = tid; e < 16 * TM; e += kTC) {
+        for (int e = tid; e < 16 * TM; e += NT) {
           int kk, i;
           if (TA) { kk = e % 16; i = e / 16; }
           else { i = e % TM; kk = e / TM; }
@@ -128,7 +131,7 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
           if (gi < M && gk < K) a = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
           As[kk][i] = a;
         }
-        for (int e = tid; e < 16 * 128; e += kTC) {
+        for (int e = tid; e < 16 * 128; e += NT) {
           const int kk = e % 16, j = e / 16, gk = k0 + kk, gj = j0 + j;
           Bs[kk][j] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : czero<T>();
         }
@@ -137,7 +140,7 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
         for (int kk = 0; kk < 16; ++kk) {
           cplx<T> a[RU], b[4];
 #pragma unroll
-          for (int u = 0; u < RU; ++u) a[u] = As[kk][ty + 32 * u];
+          for (int u = 0; u < RU; ++u) a[u] = As[kk][ty + TY * u];
 #pragma unroll
           for (int v = 0; v < 4; ++v) b[v] = Bs[kk][tx + 32 * v];
 #pragma unroll
@@ -150,7 +153,7 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
       for (int u = 0; u < RU; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int gi = i0 + ty + 32 * u, gj = j0 + tx + 32 * v;
+          const int gi = i0 + ty + TY * u, gj = j0 + tx + 32 * v;
           if (gi < M && gj < N) {
             if (SUB) C[gi + (long)gj * ldc] = C0[gi + (long)gj * ldc0] - acc[u][v];
             else C[gi + (long)gj * ldc] = acc[u][v];
@@ -166,13 +169,13 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
 // hold its kXU-strided entries in registers; back substitution over a, the
 // new entry broadcast to the column's lanes by a shuffle.  rk <= kG * kXU.
 constexpr int kG = 32, kXU = 6;
-template <typename T>
+template <typename T, int NT>
 __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *__restrict__ Rm,
                               long ldr, cplx<T> *__restrict__ U) {
   const int tid = threadIdx.x, sub = tid % kG, col = tid / kG;
   const int base = (tid % 64) & ~(kG - 1);
   const int nc = rows - rk;
-  for (int c0 = 0; c0 < nc; c0 += kTC / kG) {
+  for (int c0 = 0; c0 < nc; c0 += NT / kG) {
     const int ci = c0 + col;
     const bool act = ci < nc;
     const long pr = act ? (long)perm[rk + ci] * ldr : 0;
@@ -208,8 +211,8 @@ __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTC) void compress_level_kernel(
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void compress_level_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
     const HssCluster *__restrict__ cls, cplx<T> *__restrict__ pool, int *__restrict__ ipool,
     int *__restrict__ rank, const cplx<T> *__restrict__ front, const cplx<T> *__restrict__ Yall,
@@ -217,10 +220,11 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   __shared__ int I_loc[kMaxRows];
   __shared__ int perm[kMaxRows];
   __shared__ cplx<T> q[kMaxS];
-  __shared__ T sv[kTC / 64];
-  __shared__ int si[kTC / 64];
+  __shared__ T sv[NT / 64];
+  __shared__ int si[NT / 64];
   __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
+  constexpr int kRT = CCfg<NT>::RT, kRS = NT / kRT, kRPT = CCfg<NT>::RPT, kRSEG = CCfg<NT>::RSEG;
   __shared__ cplx<T> As[16][128], Bs[16][128];
   const HssItem it = items[blockIdx.x];
   const HssInstance I = insts[it.inst];
@@ -245,15 +249,15 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   const bool leaf = C.left < 0;
   if (leaf) {
     rows = C.size;
-    for (int i = tid; i < rows; i += kTC) I_loc[i] = C.start + i;
+    for (int i = tid; i < rows; i += NT) I_loc[i] = C.start + i;
     __syncthreads();
     cplx<T> *D = P + C.D;
-    for (int e = tid; e < rows * rows; e += kTC) {
+    for (int e = tid; e < rows * rows; e += NT) {
       int i = e % rows, l = e / rows;
       D[e] = S[(C.start + i) + (long)(C.start + l) * ldS];
     }
     __syncthreads();
-    for (int e = tid; e < rows * s; e += kTC) {
+    for (int e = tid; e < rows * s; e += NT) {
       int i = e % rows, j = e / rows;
       cplx<T> v = Y[(C.start + i) + (long)j * ldY];
       for (int l = 0; l < rows; ++l) {
@@ -270,26 +274,26 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
     const int kl = rank[I.cl_off + C.left], kr = rank[I.cl_off + C.right];
     rows = kl + kr;
     const int *skl = IP + L.sk, *skr = IP + R.sk;
-    for (int i = tid; i < rows; i += kTC) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
+    for (int i = tid; i < rows; i += NT) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
     cplx<T> *B12 = P + C.B12, *B21 = P + C.B21;
-    for (int e = tid; e < kl * kr; e += kTC) {
+    for (int e = tid; e < kl * kr; e += NT) {
       int a = e % kl, b = e / kl;
       B12[a + (long)b * kl] = S[skl[a] + (long)skr[b] * ldS];
     }
-    for (int e = tid; e < kr * kl; e += kTC) {
+    for (int e = tid; e < kr * kl; e += NT) {
       int a = e % kr, b = e / kr;
       B21[a + (long)b * kr] = S[skr[a] + (long)skl[b] * ldS];
     }
     __syncthreads();
     if (it.cl != 0) {
       const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
-      for (int e = tid; e < rows * s; e += kTC) {
+      for (int e = tid; e < rows * s; e += NT) {
         int i = e % rows, j = e / rows;
         Oloc[i + (long)j * rcap] = i < kl ? Oml[i + (long)j * kl] : Omr[(i - kl) + (long)j * kr];
       }
       // S_loc = [Sr_l - B12 Om_r ; Sr_r - B21 Om_l]
-      wg_gemm<T, false, true>(kl, s, kr, B12, kl, Omr, kr, Srl, kl, Sloc, rcap, As, Bs);
-      wg_gemm<T, false, true>(kr, s, kl, B21, kr, Oml, kl, Srr, kr, Sloc + kl, rcap, As, Bs);
+      wg_gemm<T, NT, false, true>(kl, s, kr, B12, kl, Omr, kr, Srl, kl, Sloc, rcap, As, Bs);
+      wg_gemm<T, NT, false, true>(kr, s, kl, B21, kr, Oml, kl, Srr, kr, Sloc + kl, rcap, As, Bs);
     }
   }
   __syncthreads();
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
           w[r][c] = (row < rows && j < s) ? Sloc[row + (long)j * rcap] : czero<T>();
         }
       }
-      for (int i = tid; i < rows; i += kTC) sel[i] = 0;
+      for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
       for (; t < kmax; ++t) {
         T best = (T)-1;
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
             bi = row;
           }
         }
-        block_argmax<kTC>(best, bi, sv, si);
+        block_argmax<NT>(best, bi, sv, si);
         const T pn = sqrt(best);
         if (t == 0) first = pn;
         if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
@@ -400,13 +404,13 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
     }
   }
   if (!reg_done) {
-  for (int e = tid; e < rows * s; e += kTC) {
+  for (int e = tid; e < rows * s; e += NT) {
     int i = e % rows, j = e / rows;
     Wm[i + (long)j * rcap] = Sloc[i + (long)j * rcap];
   }
-  for (int i = tid; i < rows; i += kTC) perm[i] = i;
+  for (int i = tid; i < rows; i += NT) perm[i] = i;
   __syncthreads();
-  const int sub = tid % kTPR, slot = tid / kTPR, nslot = kTC / kTPR;
+  const int sub = tid % kTPR, slot = tid / kTPR, nslot = NT / kTPR;
   for (; t < kmax; ++t) {
     // residual row norms: kTPR lanes per row, reduced by shuffles
     T best = (T)-1;
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
       for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
       if (pp < rows && sub == 0 && (nrm > best || (nrm == best && pp < bi))) { best = nrm; bi = pp; }
     }
-    block_argmax<kTC>(best, bi, sv, si);
+    block_argmax<NT>(best, bi, sv, si);
     T pn = sqrt(best);
     if (t == 0) first = pn;
     if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
     __syncthreads();
     const int prow = perm[t];
     T inv = (T)1 / pn;
-    for (int j = tid; j < s; j += kTC) q[j] = inv * Wm[prow + (long)j * rcap];
+    for (int j = tid; j < s; j += NT) q[j] = inv * Wm[prow + (long)j * rcap];
     if (tid == 0) Rm[t + (long)prow * C.k_cap] = mk(pn, (T)0);
     __syncthreads();
     for (int pp0 = t + 1; pp0 < rows; pp0 += nslot) {
@@ -464,13 +468,13 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
 
   // U (rows x rk): identity rows at the skeleton, T^T = (R11^-1 R12)^T elsewhere
   cplx<T> *U = P + C.U;
-  for (int e = tid; e < rows * rk; e += kTC) U[e] = czero<T>();
+  for (int e = tid; e < rows * rk; e += NT) U[e] = czero<T>();
   __syncthreads();
-  for (int a = tid; a < rk; a += kTC) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
+  for (int a = tid; a < rk; a += NT) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
   if (rk <= kG * kXU) {
-    interp_coeffs<T>(rows, rk, perm, Rm, C.k_cap, U);
+    interp_coeffs<T, NT>(rows, rk, perm, Rm, C.k_cap, U);
   } else {
-    for (int c2 = tid; c2 < rows - rk; c2 += kTC) {
+    for (int c2 = tid; c2 < rows - rk; c2 += NT) {
       int row = perm[rk + c2];
       // back substitution, solution written straight into U(row, :)
       for (int a = rk - 1; a >= 0; --a) {
@@ -483,14 +487,14 @@ __global__ __launch_bounds__(kTC) void compress_level_kernel(
   }
   __syncthreads();
   int *sk = IP + C.sk;
-  for (int a = tid; a < rk; a += kTC) sk[a] = I_loc[perm[a]];
+  for (int a = tid; a < rk; a += NT) sk[a] = I_loc[perm[a]];
   cplx<T> *Omc = P + C.Om, *Src = P + C.Sr;
-  for (int e = tid; e < rk * s; e += kTC) {
+  for (int e = tid; e < rk * s; e += NT) {
     int a = e % rk, j = e / rk;
     Src[a + (long)j * rk] = Sloc[perm[a] + (long)j * rcap];
   }
   // Om_c = U^T Om_loc
-  wg_gemm<T, true, false>(rk, s, rows, U, rows, Oloc, rcap, nullptr, 0, Omc, rk, As, Bs);
+  wg_gemm<T, NT, true, false>(rk, s, rows, U, rows, Oloc, rcap, nullptr, 0, Omc, rk, As, Bs);
   if (tid == 0) rank[cg] = rk;
 }
 
@@ -734,10 +738,14 @@ template <typename T>
 void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
                            const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
                            const cplx<T> *front, const cplx<T> *Y, const double *Om,
-                           cplx<T> *scratch, double id_tol, hipStream_t st) {
+                           cplx<T> *scratch, double id_tol, bool small, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(compress_level_kernel<T>, dim3(count), dim3(kTC), 0, st, items, inst, cl,
-                     pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  if (small)
+    hipLaunchKernelGGL((compress_level_kernel<T, 256>), dim3(count), dim3(256), 0, st, items, inst,
+                       cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  else
+    hipLaunchKernelGGL((compress_level_kernel<T, 1024>), dim3(count), dim3(1024), 0, st, items,
+                       inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -764,7 +772,7 @@ void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *i
   template void launch_compress_level<T>(int, const HssItem *, const HssInstance *,           \
                                          const HssCluster *, cplx<T> *, int *, int *,         \
                                          const cplx<T> *, const cplx<T> *, const double *,    \
-                                         cplx<T> *, double, hipStream_t);                     \
+                                         cplx<T> *, double, bool, hipStream_t);               \
   template void launch_hss_matvec<T>(int, const MatvecJob<T> *, const HssInstance *,          \
                                      const HssCluster *, const cplx<T> *, const int *,        \
                                      cplx<T> *, int, int, int, hipStream_t);
