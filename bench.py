@@ -42,8 +42,8 @@ PEAKS = {  # MI355X published peaks
     "alu_f64": (78.6, "TFLOP/s"),
 }
 KERNELS = ["front_eliminate", "front_assemble", "compress_level", "hss_matvec", "sample",
-           "apply_up", "apply_down", "spmv"]
-BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "spmv"}
+           "apply_up", "apply_down", "apply_graph", "spmv"]
+BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "apply_graph", "spmv"}
 
 
 def cpu_baseline_child(workload):

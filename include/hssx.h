@@ -57,8 +57,8 @@ typedef enum { HSSX_C128 = 0, HSSX_C64 = 1 } hssx_dtype;
 typedef struct hssx_op_ *hssx_op;      /* assembled operator A */
 typedef struct hssx_fact_ *hssx_fact;  /* approximate factorization P */
 
-/* Problem description (Sec. 4.2; the paper's Dirichlet data replaced by the
- * absorbing condition, see DESIGN). */
+/* Problem description (Sec. 4.2), with a first-order absorbing condition on
+ * all four sides of the unit square. */
 typedef struct {
   int N;          /* nodes per side, N >= 2 */
   double omega;   /* angular frequency; wavenumber k(x) = omega * s(x) */
@@ -78,6 +78,15 @@ typedef struct {
   double id_rel_tol;/* relative pivot threshold of the interpolative
                        decomposition; <= 0 selects max(1e-2 * tol,
                        4 * unit roundoff of the factor dtype) */
+  int apply_graph;  /* nonzero: the apply sweeps are captured once per
+                       (right-hand-side count, transpose) and replayed as a
+                       HIP graph; default 1 */
+  int autotune;     /* nonzero: the apply tile shape of every tree depth is
+                       measured on first use per (precision, sweep, size
+                       bucket) and cached for the process; default 1 */
+  int sample_bf16;  /* nonzero (complex64 factors only): the sampling
+                       products Y = S Omega take bf16 operands with fp32
+                       accumulation; default 0 */
 } hssx_factor_opts;
 
 typedef struct {

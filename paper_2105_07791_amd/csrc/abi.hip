@@ -47,6 +47,11 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+hssx_fact_::~hssx_fact_() {
+  hssx::destroy_graphs(*this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
 extern "C" {
 
 const char *hssx_last_error(void) { return g_err.c_str(); }
@@ -206,11 +211,13 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(tol > 0 && tol < 1, HSSX_EINVAL, "tol must lie in (0, 1)");
     HSSX_CHECK(leaf_size >= 1, HSSX_EINVAL, "leaf_size must be >= 1");
     *P_out = nullptr;
-    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0};
+    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0};
     if (opts) o = *opts;
     HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
                HSSX_EINVAL, "invalid factor options");
     HSSX_CHECK(o.dtype == HSSX_C128 || o.dtype == HSSX_C64, HSSX_EINVAL, "dtype");
+    HSSX_CHECK(!o.sample_bf16 || o.dtype == HSSX_C64, HSSX_EINVAL,
+               "bf16 sampling needs a complex64 factor");
     DeviceScope ds(A->device);
     hipStream_t st = S(stream);
     auto P = std::make_unique<hssx_fact_>();
@@ -508,7 +515,15 @@ hssx_status hssx_prof_query(const char *kernel, double *ms, long *launches, doub
   });
 }
 
-void hssx_fact_destroy(hssx_fact P) { delete P; }
+void hssx_fact_destroy(hssx_fact P) {
+  if (P) {
+    int prev = 0;
+    const bool dev = P->A && hipGetDevice(&prev) == hipSuccess;
+    if (dev) (void)hipSetDevice(P->A->device);
+    delete P;
+    if (dev) (void)hipSetDevice(prev);
+  }
+}
 void hssx_op_destroy(hssx_op A) { delete A; }
 
 }  // extern "C"

@@ -1,6 +1,7 @@
 // Handles behind the C ABI and the host drivers that sequence the kernels.
 #pragma once
 
+#include <map>
 #include <memory>
 
 #include "common.h"
@@ -51,11 +52,23 @@ struct hssx_fact_ {
   std::vector<int> node_rank;   // largest compressed rank per node (stats)
   hssx::DevBuf work;            // apply workspace (elimination-order vectors)
   size_t work_cols = 0;
+  // apply: tile configuration per depth (by right-hand-side count) and the
+  // sweeps captured as graphs (by right-hand-side count and transpose)
+  std::map<int, std::vector<int>> cfg_up, cfg_down;
+  struct SweepGraph {
+    int nrhs, trans;
+    hipGraphExec_t exec;
+  };
+  std::vector<SweepGraph> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool capturing = false;
+  ~hssx_fact_();
 };
 
 namespace hssx {
 
 void factor_numeric(hssx_fact_ &P, hipStream_t st);
+void destroy_graphs(hssx_fact_ &P);
 void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
            hipStream_t st);
 void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb, c128 *x,

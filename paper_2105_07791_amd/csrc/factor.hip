@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <array>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -693,52 +694,188 @@ void factor_numeric(hssx_fact_ &P, hipStream_t st) {
   (void)hipEventDestroy(e1);
 }
 
+namespace {
+
+// ---- apply tile autotuner: tile configuration per (factor precision,
+// sweep, right-hand-side bucket, size bucket, node-count bucket), measured
+// once per process on scratch vectors and shared by all factors
+std::mutex g_tune_mu;
+std::map<std::array<int, 5>, int> g_tuned;
+
+int log2_bucket(long v) {
+  int b = 0;
+  while ((1L << b) < v) ++b;
+  return b;
+}
+
+// launches one depth's up (or down) step with tile configuration cfg
+void sweep_step(hssx_fact_ &P, int d, bool up, int trans, int nrhs, c128 *w, c128 *tb, int cfg,
+                hipStream_t st) {
+  const int n = P.A->n, cnt = (int)P.depth_nodes[d].size();
+  const FrontDesc *desc = P.desc.as<FrontDesc>();
+  const int *nodes = P.depth_dev[d].as<int>();
+  const bool f64 = P.dtype == HSSX_C128 || d == 0;
+  const c128 *pool64 = P.dtype == HSSX_C64 ? P.front64.as<c128>() : P.front.as<c128>();
+  if (up) {
+    if (f64)
+      launch_apply_up<double>(cnt, nodes, desc, pool64, P.bpos.as<int>(), tb, w, n, nrhs, trans,
+                              P.depth_max_ni[d], P.depth_max_f[d], cfg, st);
+    else
+      launch_apply_up<float>(cnt, nodes, desc, P.front.as<c64>(), P.bpos.as<int>(), tb, w, n,
+                             nrhs, trans, P.depth_max_ni[d], P.depth_max_f[d], cfg, st);
+  } else {
+    if (f64)
+      launch_apply_down<double>(cnt, nodes, desc, pool64, P.bpos.as<int>(), w, n, nrhs, trans,
+                                P.depth_max_nb[d], P.depth_max_ni[d], cfg, st);
+    else
+      launch_apply_down<float>(cnt, nodes, desc, P.front.as<c64>(), P.bpos.as<int>(), w, n, nrhs,
+                               trans, P.depth_max_nb[d], P.depth_max_ni[d], cfg, st);
+  }
+}
+
+std::array<int, 5> tune_key(const hssx_fact_ &P, int d, bool up, int nrhs) {
+  const bool f64 = P.dtype == HSSX_C128 || d == 0;
+  const int size = up ? P.depth_max_f[d] : P.depth_max_ni[d];
+  return {f64 ? 0 : 1, up ? 0 : 1, log2_bucket(nrhs), log2_bucket(size),
+          log2_bucket((long)P.depth_nodes[d].size())};
+}
+
+// tile configuration of every depth and sweep for nrhs right-hand sides;
+// missing entries of the process cache are measured (events, best of 2)
+void tune_apply(hssx_fact_ &P, int nrhs, hipStream_t st) {
+  if (P.cfg_up.count(nrhs)) return;
+  const int D = P.sym.max_depth, n = P.A->n;
+  std::vector<int> up(D + 1, 2), down(D + 1, 2);
+  if (!P.opts.autotune) {
+    P.cfg_up[nrhs] = up;
+    P.cfg_down[nrhs] = down;
+    return;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  DevBuf x2, t2;
+  hipEvent_t e0, e1;
+  bool have_bufs = false;
+  for (int d = 0; d <= D; ++d) {
+    if (P.depth_nodes[d].empty()) continue;
+    for (int u = 0; u < 2; ++u) {
+      const auto key = tune_key(P, d, u == 0, nrhs);
+      auto it = g_tuned.find(key);
+      if (it != g_tuned.end()) {
+        (u == 0 ? up : down)[d] = it->second;
+        continue;
+      }
+      if (!have_bufs) {
+        x2.alloc((size_t)n * nrhs * sizeof(c128));
+        t2.alloc((size_t)n * nrhs * sizeof(c128));
+        HSSX_HIP(hipMemsetAsync(x2.p, 0, x2.bytes, st));
+        HSSX_HIP(hipMemsetAsync(t2.p, 0, t2.bytes, st));
+        HSSX_HIP(hipEventCreate(&e0));
+        HSSX_HIP(hipEventCreate(&e1));
+        have_bufs = true;
+      }
+      int best = 2;
+      float best_ms = 1e30f;
+      for (int c = 0; c < kNumApplyCfgs; ++c) {
+        sweep_step(P, d, u == 0, 0, nrhs, x2.as<c128>(), t2.as<c128>(), c, st);
+        for (int rep = 0; rep < 2; ++rep) {
+          HSSX_HIP(hipEventRecord(e0, st));
+          sweep_step(P, d, u == 0, 0, nrhs, x2.as<c128>(), t2.as<c128>(), c, st);
+          HSSX_HIP(hipEventRecord(e1, st));
+          HSSX_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          HSSX_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+      }
+      g_tuned[key] = best;
+      (u == 0 ? up : down)[d] = best;
+    }
+  }
+  if (have_bufs) {
+    HSSX_HIP(hipStreamSynchronize(st));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  P.cfg_up[nrhs] = up;
+  P.cfg_down[nrhs] = down;
+}
+
+// Algorithm 3.1 on vectors in elimination order: up-sweep with the fused
+// block solve depth by depth from the leaves, then the down-sweep
+void sweeps(hssx_fact_ &P, int trans, int nrhs, c128 *w, c128 *tb, hipStream_t st) {
+  const int D = P.sym.max_depth;
+  const auto &cu = P.cfg_up.at(nrhs), &cd = P.cfg_down.at(nrhs);
+  const bool prof = prof_on() && !P.capturing;
+  for (int d = D; d >= 0; --d) {
+    if (P.depth_nodes[d].empty()) continue;
+    hipEvent_t pu = prof ? prof_begin(st) : nullptr;
+    sweep_step(P, d, true, trans, nrhs, w, tb, cu[d], st);
+    if (prof) prof_end("apply_up", st, pu, P.up_fbytes[d] + P.up_velems[d] * nrhs * sizeof(c128));
+  }
+  for (int d = 0; d <= D; ++d) {
+    if (P.depth_nodes[d].empty()) continue;
+    hipEvent_t pd = prof ? prof_begin(st) : nullptr;
+    sweep_step(P, d, false, trans, nrhs, w, tb, cd[d], st);
+    if (prof)
+      prof_end("apply_down", st, pd, P.down_fbytes[d] + P.down_velems[d] * nrhs * sizeof(c128));
+  }
+}
+
+}  // namespace
+
+void destroy_graphs(hssx_fact_ &P) {
+  for (auto &g : P.graphs) (void)hipGraphExecDestroy(g.exec);
+  P.graphs.clear();
+}
+
 void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
            hipStream_t st) {
   const int n = P.A->n;
   if (P.work_cols < (size_t)nrhs) {
     HSSX_HIP(hipStreamSynchronize(st));
+    destroy_graphs(P);   // they hold the old workspace's addresses
     P.work.alloc((size_t)2 * n * nrhs * sizeof(c128));
     P.work_cols = nrhs;
   }
   c128 *w = P.work.as<c128>();
   c128 *tb = w + (size_t)n * nrhs;
+  tune_apply(P, nrhs, st);
   launch_permute(n, nrhs, P.perm.as<int>(), x, ldx, w, n, 0, st);
-  const FrontDesc *desc = P.desc.as<FrontDesc>();
-  const int D = P.sym.max_depth;
-  for (int d = D; d >= 0; --d) {
-    int cnt = (int)P.depth_nodes[d].size();
-    if (!cnt) continue;
-    hipEvent_t pu = prof_begin(st);
-    if (P.dtype == HSSX_C64 && d == 0)
-      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front64.as<c128>(), P.bpos.as<int>(), tb, w, n, nrhs, trans,
-                              P.depth_max_ni[d], P.depth_max_f[d], st);
-    else if (P.dtype == HSSX_C128)
-      launch_apply_up<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
-                              P.bpos.as<int>(), tb, w, n, nrhs, trans, P.depth_max_ni[d],
-                              P.depth_max_f[d], st);
-    else
-      launch_apply_up<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
-                             P.bpos.as<int>(), tb, w, n, nrhs, trans, P.depth_max_ni[d],
-                             P.depth_max_f[d], st);
-    prof_end("apply_up", st, pu, P.up_fbytes[d] + P.up_velems[d] * nrhs * sizeof(c128));
-  }
-  for (int d = 0; d <= D; ++d) {
-    int cnt = (int)P.depth_nodes[d].size();
-    if (!cnt) continue;
-    hipEvent_t pd = prof_begin(st);
-    if (P.dtype == HSSX_C64 && d == 0)
-      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front64.as<c128>(), P.bpos.as<int>(), w, n, nrhs, trans,
-                                P.depth_max_nb[d], P.depth_max_ni[d], st);
-    else if (P.dtype == HSSX_C128)
-      launch_apply_down<double>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c128>(),
-                                P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d],
-                                P.depth_max_ni[d], st);
-    else
-      launch_apply_down<float>(cnt, P.depth_dev[d].as<int>(), desc, P.front.as<c64>(),
-                               P.bpos.as<int>(), w, n, nrhs, trans, P.depth_max_nb[d],
-                               P.depth_max_ni[d], st);
-    prof_end("apply_down", st, pd, P.down_fbytes[d] + P.down_velems[d] * nrhs * sizeof(c128));
+  if (P.opts.apply_graph) {
+    // the sweeps on the internal workspace replayed as one graph per
+    // (right-hand-side count, transpose)
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : P.graphs)
+      if (g.nrhs == nrhs && g.trans == trans) exec = g.exec;
+    if (!exec) {
+      if (!P.cap_stream) HSSX_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+      HSSX_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+      hipGraph_t graph = nullptr;
+      P.capturing = true;
+      try {
+        sweeps(P, trans, nrhs, w, tb, P.cap_stream);
+      } catch (...) {
+        P.capturing = false;
+        (void)hipStreamEndCapture(P.cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      P.capturing = false;
+      HSSX_HIP(hipStreamEndCapture(P.cap_stream, &graph));
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HSSX_HIP(e);
+      P.graphs.push_back(hssx_fact_::SweepGraph{nrhs, trans, exec});
+    }
+    hipEvent_t pg = prof_begin(st);
+    HSSX_HIP(hipGraphLaunch(exec, st));
+    double bytes = 0;
+    for (int d = 0; d <= P.sym.max_depth; ++d)
+      bytes += P.up_fbytes[d] + P.down_fbytes[d] +
+               (P.up_velems[d] + P.down_velems[d]) * nrhs * sizeof(c128);
+    prof_end("apply_graph", st, pg, bytes);
+  } else {
+    sweeps(P, trans, nrhs, w, tb, st);
   }
   launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);
 }

@@ -182,18 +182,26 @@ void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *i
 // y = x(perm) (inverse = 0) or y(perm) = x (inverse = 1), n x nrhs
 void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c128 *y,
                     long ldy, int inverse, hipStream_t st);
+// Tile shapes of the (non-transposed) apply sweeps: rows of the output per
+// 256-thread workgroup and right-hand sides per thread.
+struct ApplyCfg {
+  int rows, rb;
+};
+constexpr int kNumApplyCfgs = 6;
+extern const ApplyCfg kApplyCfgs[kNumApplyCfgs];
 // Up-sweep of one tree depth: t = x(I); x(I) = A_ii^-1 t; x(B) += L t
 // (trans: A_ii^-T t and R^T t).  x is in elimination order (ld n); tb is an
-// n x nrhs staging buffer that receives a copy of the I blocks first.
+// n x nrhs staging buffer that receives a copy of the I blocks first.  cfg
+// indexes kApplyCfgs (ignored for trans).
 template <typename T>
 void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
                      const int *bpos, c128 *tb, c128 *x, int n, int nrhs, int trans, int max_ni,
-                     int max_f, hipStream_t st);
+                     int max_f, int cfg, hipStream_t st);
 // Down-sweep of one tree depth: x(I) += R x(B) (trans: L^T x(B)).
 template <typename T>
 void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
                        const int *bpos, c128 *x, int n, int nrhs, int trans, int max_nb,
-                       int max_ni, hipStream_t st);
+                       int max_ni, int cfg, hipStream_t st);
 
 // ------------------------------------------------------------ Krylov
 // Systems of a vector block (n rows x nrhs columns): the rows split into np

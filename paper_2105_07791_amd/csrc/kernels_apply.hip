@@ -12,7 +12,8 @@
 // sweep b(I) += R b(B) reads ancestors' blocks only.
 //
 // The transposed apply (P^-T) uses R^T in the up-sweep, A_ii^-T for the
-// solve and L^T in the down-sweep.
+// solve and L^T in the down-sweep.  The plain apply runs tiled products whose
+// tile shape (one of kApplyCfgs) is chosen per tree depth by the caller.
 #include "common.h"
 #include "kernels.h"
 
@@ -134,6 +135,104 @@ __global__ __launch_bounds__(kT) void apply_down_kernel(const int *__restrict__ 
   }
 }
 
+// Tiled forms of the two sweeps (no transpose): out(i, r) = sum_l F(i, l)
+// t(l, r) as a product over 32-entry chunks of l staged in LDS.  ROWS output
+// rows per workgroup, 256 / ROWS right-hand-side groups, RB right-hand sides
+// per thread held in registers, so every factor entry is read once per
+// workgroup.
+template <typename T, int ROWS, int RB>
+__global__ __launch_bounds__(kT) void apply_up_tiled(const int *__restrict__ nodes,
+                                                     const FrontDesc *__restrict__ desc,
+                                                     const cplx<T> *__restrict__ pool,
+                                                     const int *__restrict__ bpos,
+                                                     const c128 *__restrict__ tb,
+                                                     c128 *__restrict__ x, int n, int nrhs) {
+  constexpr int G = kT / ROWS, RC = G * RB, KC = 32;
+  __shared__ c128 ts[KC][RC];
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  const int ni = d.ni, f = d.f;
+  const int i0 = blockIdx.y * ROWS, r0 = blockIdx.z * RC;
+  if (ni == 0 || i0 >= f || r0 >= nrhs) return;
+  const cplx<T> *F = pool + d.foff + (long)f * f;   // [A_ii^-1 ; L] = F(:, f:f+ni)
+  const int tid = threadIdx.x, g = tid / ROWS, i = i0 + tid % ROWS;
+  c128 acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = czero<double>();
+  for (int l0 = 0; l0 < ni; l0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < KC * RC; e += kT) {
+      const int ll = e % KC, rr = e / KC, l = l0 + ll, r = r0 + rr;
+      ts[ll][rr] = (l < ni && r < nrhs) ? tb[d.ioff + l + (long)r * n] : czero<double>();
+    }
+    __syncthreads();
+    if (i < f) {
+      const int lm = min(KC, ni - l0);
+      for (int ll = 0; ll < lm; ++ll) {
+        const c128 fv = ccast<double>(F[i + (long)(l0 + ll) * f]);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) cfma(acc[q], fv, ts[ll][g + G * q]);
+      }
+    }
+  }
+  if (i >= f) return;
+  const int *bp = bpos + d.bpos_off;
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int r = r0 + g + G * q;
+    if (r >= nrhs) continue;
+    if (i < ni) {
+      x[d.ioff + i + (long)r * n] = acc[q];
+    } else {
+      const long pos = bp[i - ni] + (long)r * n;
+      x[pos] = x[pos] + acc[q];
+    }
+  }
+}
+
+template <typename T, int ROWS, int RB>
+__global__ __launch_bounds__(kT) void apply_down_tiled(const int *__restrict__ nodes,
+                                                       const FrontDesc *__restrict__ desc,
+                                                       const cplx<T> *__restrict__ pool,
+                                                       const int *__restrict__ bpos,
+                                                       c128 *__restrict__ x, int n, int nrhs) {
+  constexpr int G = kT / ROWS, RC = G * RB, KC = 32;
+  __shared__ c128 ts[KC][RC];
+  const FrontDesc d = desc[nodes[blockIdx.x]];
+  const int ni = d.ni, nb = d.nb, f = d.f;
+  const int i0 = blockIdx.y * ROWS, r0 = blockIdx.z * RC;
+  if (ni == 0 || nb == 0 || i0 >= ni || r0 >= nrhs) return;
+  const cplx<T> *F = pool + d.foff + (long)ni * f;   // R = F(0:ni, ni:f)
+  const int *bp = bpos + d.bpos_off;
+  const int tid = threadIdx.x, g = tid / ROWS, i = i0 + tid % ROWS;
+  c128 acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = czero<double>();
+  for (int b0 = 0; b0 < nb; b0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < KC * RC; e += kT) {
+      const int bb = e % KC, rr = e / KC, b = b0 + bb, r = r0 + rr;
+      ts[bb][rr] = (b < nb && r < nrhs) ? x[bp[b] + (long)r * n] : czero<double>();
+    }
+    __syncthreads();
+    if (i < ni) {
+      const int bm = min(KC, nb - b0);
+      for (int bb = 0; bb < bm; ++bb) {
+        const c128 fv = ccast<double>(F[i + (long)(b0 + bb) * f]);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) cfma(acc[q], fv, ts[bb][g + G * q]);
+      }
+    }
+  }
+  if (i >= ni) return;
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int r = r0 + g + G * q;
+    if (r >= nrhs) continue;
+    const long pos = d.ioff + i + (long)r * n;
+    x[pos] = x[pos] + acc[q];
+  }
+}
+
 int rhs_chunk(int nrhs, int rows) {
   // stage at most 4096 complex doubles (64 KiB) of the input block in LDS
   int rc = rows > 0 ? 4096 / rows : nrhs;
@@ -151,40 +250,89 @@ void launch_permute(int n, int nrhs, const int *perm, const c128 *x, long ldx, c
   HSSX_HIP(hipGetLastError());
 }
 
+// tile configurations of the tiled sweeps: output rows per workgroup and
+// right-hand sides per thread
+const ApplyCfg kApplyCfgs[kNumApplyCfgs] = {{256, 1}, {128, 2}, {64, 4}, {64, 8}, {64, 16},
+                                             {32, 8}};
+
+namespace {
+
+template <typename T, int ROWS, int RB>
+void up_tiled(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+              const int *bpos, const c128 *tb, c128 *x, int n, int nrhs, int max_f,
+              hipStream_t st) {
+  constexpr int RC = (kT / ROWS) * RB;
+  hipLaunchKernelGGL((apply_up_tiled<T, ROWS, RB>), dim3(count, ceil_div(max_f, ROWS),
+                     ceil_div(nrhs, RC)), dim3(kT), 0, st, nodes, desc, pool, bpos, tb, x, n, nrhs);
+}
+
+template <typename T, int ROWS, int RB>
+void down_tiled(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
+                const int *bpos, c128 *x, int n, int nrhs, int max_ni, hipStream_t st) {
+  constexpr int RC = (kT / ROWS) * RB;
+  hipLaunchKernelGGL((apply_down_tiled<T, ROWS, RB>), dim3(count, ceil_div(max_ni, ROWS),
+                     ceil_div(nrhs, RC)), dim3(kT), 0, st, nodes, desc, pool, bpos, x, n, nrhs);
+}
+
+}  // namespace
+
 template <typename T>
 void launch_apply_up(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
                      const int *bpos, c128 *tb, c128 *x, int n, int nrhs, int trans, int max_ni,
-                     int max_f, hipStream_t st) {
+                     int max_f, int cfg, hipStream_t st) {
   if (count <= 0 || max_ni <= 0) return;
-  HSSX_CHECK(max_ni <= 4096, HSSX_EINVAL, "interior block larger than the apply kernel stages");
   hipLaunchKernelGGL(stage_kernel, dim3(count, ceil_div((long)max_ni * nrhs, 256)), dim3(256), 0,
                      st, nodes, desc, x, tb, n, nrhs);
-  int rc = rhs_chunk(nrhs, max_ni);
-  size_t lds = (size_t)rc * max_ni * sizeof(c128);
-  hipLaunchKernelGGL(apply_up_kernel<T>, dim3(count, ceil_div(max_f, kRows), ceil_div(nrhs, rc)),
-                     dim3(kT), lds, st, nodes, desc, pool, bpos, tb, x, n, nrhs, trans, rc);
+  if (!trans) {
+    switch (cfg) {
+      case 0: up_tiled<T, 256, 1>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+      case 1: up_tiled<T, 128, 2>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+      case 2: up_tiled<T, 64, 4>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+      case 3: up_tiled<T, 64, 8>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+      case 4: up_tiled<T, 64, 16>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+      default: up_tiled<T, 32, 8>(count, nodes, desc, pool, bpos, tb, x, n, nrhs, max_f, st); break;
+    }
+  } else {
+    HSSX_CHECK(max_ni <= 4096, HSSX_EINVAL, "interior block larger than the apply kernel stages");
+    int rc = rhs_chunk(nrhs, max_ni);
+    size_t lds = (size_t)rc * max_ni * sizeof(c128);
+    hipLaunchKernelGGL(apply_up_kernel<T>, dim3(count, ceil_div(max_f, kRows), ceil_div(nrhs, rc)),
+                       dim3(kT), lds, st, nodes, desc, pool, bpos, tb, x, n, nrhs, trans, rc);
+  }
   HSSX_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_apply_down(int count, const int *nodes, const FrontDesc *desc, const cplx<T> *pool,
                        const int *bpos, c128 *x, int n, int nrhs, int trans, int max_nb,
-                       int max_ni, hipStream_t st) {
+                       int max_ni, int cfg, hipStream_t st) {
   if (count <= 0 || max_nb <= 0 || max_ni <= 0) return;
-  HSSX_CHECK(max_nb <= 4096, HSSX_EINVAL, "boundary block larger than the apply kernel stages");
-  int rc = rhs_chunk(nrhs, max_nb);
-  size_t lds = (size_t)rc * max_nb * sizeof(c128);
-  hipLaunchKernelGGL(apply_down_kernel<T>, dim3(count, ceil_div(max_ni, kRows), ceil_div(nrhs, rc)),
-                     dim3(kT), lds, st, nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  if (!trans) {
+    switch (cfg) {
+      case 0: down_tiled<T, 256, 1>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+      case 1: down_tiled<T, 128, 2>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+      case 2: down_tiled<T, 64, 4>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+      case 3: down_tiled<T, 64, 8>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+      case 4: down_tiled<T, 64, 16>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+      default: down_tiled<T, 32, 8>(count, nodes, desc, pool, bpos, x, n, nrhs, max_ni, st); break;
+    }
+  } else {
+    HSSX_CHECK(max_nb <= 4096, HSSX_EINVAL, "boundary block larger than the apply kernel stages");
+    int rc = rhs_chunk(nrhs, max_nb);
+    size_t lds = (size_t)rc * max_nb * sizeof(c128);
+    hipLaunchKernelGGL(apply_down_kernel<T>, dim3(count, ceil_div(max_ni, kRows), ceil_div(nrhs, rc)),
+                       dim3(kT), lds, st, nodes, desc, pool, bpos, x, n, nrhs, trans, rc);
+  }
   HSSX_HIP(hipGetLastError());
 }
 
 #define HSSX_INST(T)                                                                          \
   template void launch_apply_up<T>(int, const int *, const FrontDesc *, const cplx<T> *,      \
-                                   const int *, c128 *, c128 *, int, int, int, int, int,      \
+                                   const int *, c128 *, c128 *, int, int, int, int, int, int, \
                                    hipStream_t);                                              \
   template void launch_apply_down<T>(int, const int *, const FrontDesc *, const cplx<T> *,    \
-                                     const int *, c128 *, int, int, int, int, int, hipStream_t);
+                                     const int *, c128 *, int, int, int, int, int, int,       \
+                                     hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)
 #undef HSSX_INST

@@ -123,11 +123,13 @@ class Factor:
     """Approximate factorization P = LDR of an Operator (Algorithm 3.4)."""
 
     def __init__(self, A, tol=1e-6, leaf_size=32, beta=16, h_sw=4, k0=32, r=16,
-                 max_rounds=32, dtype="c128", seed=0, id_rel_tol=0.0, stream=None):
+                 max_rounds=32, dtype="c128", seed=0, id_rel_tol=0.0, apply_graph=True,
+                 autotune=True, sample_bf16=False, stream=None):
         self.A = A
         opts = _lib.FactorOpts(beta, h_sw, k0, r, max_rounds,
                                _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64,
-                               seed, id_rel_tol)
+                               seed, id_rel_tol, int(apply_graph), int(autotune),
+                               int(sample_bf16))
         h = C.c_void_p()
         check(lib().hssx_factor(A.handle, float(tol), int(leaf_size), C.byref(opts),
                                 _stream(stream), C.byref(h)))
