@@ -114,6 +114,10 @@ template <typename T> struct SampleJob {
 };
 template <typename T>
 void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, hipStream_t st);
+// the same product for complex64 S with bf16 operands and fp32 accumulation
+// (matrix cores)
+void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc,
+                        hipStream_t st);
 
 // One cluster of one compression instance at the current tree level.
 // Layout of an instance's HSS generators: per cluster offsets (elements of

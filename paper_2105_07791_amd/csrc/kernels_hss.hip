@@ -82,6 +82,50 @@ __global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
   jb.Y[i + (long)j * jb.ldY] = acc;
 }
 
+// bf16 sampling (complex64 only): the complex-times-real product in its real
+// view, Y_r (2m x nc) = S_r (2m x m) Omega (m x nc) with the re/im parts of S
+// as interleaved rows, on the 16x16x16 bf16 matrix cores with fp32
+// accumulation.  Operands are rounded to bf16 (nearest even) on load.  One
+// wavefront per 16 x 16 output tile; four wavefronts per workgroup stack
+// their tiles over rows.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void sample_bf16_kernel(const SampleJob<float> *__restrict__ jobs) {
+  const SampleJob<float> jb = jobs[blockIdx.z];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int R = 2 * jb.m;                               // real rows
+  const int row0 = (blockIdx.x * 4 + wave) * 16, col0 = blockIdx.y * 16;
+  if (row0 >= R || col0 >= jb.nc) return;
+  const float *Sr = reinterpret_cast<const float *>(jb.S);
+  const long ldS = 2L * jb.ldS;
+  const int ai = row0 + lane % 16, bj = col0 + lane % 16, kq = 4 * (lane / 16);
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < jb.m; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + kq + q;
+      a[q] = to_bf16((ai < R && k < jb.m) ? Sr[ai + (long)k * ldS] : 0.f);
+      b[q] = to_bf16((bj < jb.nc && k < jb.m) ? (float)jb.Om[k + (long)bj * jb.ldO] : 0.f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  float *Yr = reinterpret_cast<float *>(jb.Y);
+  const long ldY = 2L * jb.ldY;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = row0 + kq + q, j = col0 + lane % 16;
+    if (i < R && j < jb.nc) Yr[i + (long)j * ldY] = acc[q];
+  }
+}
+
 template <int NT, typename T>
 __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -731,6 +775,14 @@ void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, h
   if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
   hipLaunchKernelGGL(sample_kernel<T>, dim3(ceil_div(max_m, 256), max_nc, count), dim3(256), 0,
                      st, jobs);
+  HSSX_HIP(hipGetLastError());
+}
+
+void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc,
+                        hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
+  hipLaunchKernelGGL(sample_bf16_kernel, dim3(ceil_div(2L * max_m, 64), ceil_div(max_nc, 16), count),
+                     dim3(256), 0, st, jobs);
   HSSX_HIP(hipGetLastError());
 }
 

@@ -69,3 +69,38 @@ def test_graph_apply_through_gmres_matches_oracle():
     xg = x.cpu().numpy().reshape(pr.n, -1)
     assert st[0]["converged"]
     assert np.linalg.norm(xg - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_bf16_sampling_form():
+    """Sampling products on bf16 matrix cores (fp32 accumulation): the
+    adaptive compression still meets its estimate at a tolerance above the
+    bf16 rounding level, and flexible GMRES reaches the oracle solution."""
+    hx = _hx()
+    dev = torch.device("cuda:0")
+    pr = make_problem("helmholtz_p1_65")
+    A = hx.Operator(pr.N, pr.omega, pr.slowness)
+    P16 = hx.Factor(A, tol=1e-2, h_sw=2, dtype="c64", seed=5, sample_bf16=True)
+    P32 = hx.Factor(A, tol=1e-2, h_sw=2, dtype="c64", seed=5, sample_bf16=False)
+    s16, s32 = P16.stats(), P32.stats()
+    assert s16["n_compressed"] > 0
+    assert s16["max_estimate"] <= 1e-2 and s16["max_rounds_used"] < 32
+    assert s16["k_max"] <= 2 * max(s32["k_max"], 16)
+    b = A.load(torch.tensor(pr.f, device=dev))
+    y16 = P16.apply(b).cpu().numpy()
+    y32 = P32.apply(b).cpu().numpy()
+    assert np.linalg.norm(y16 - y32) <= 5e-2 * np.linalg.norm(y32)
+    x, st = hx.gmres_solve(A, P16, b, flexible=True)
+    Ao = fem.assemble_helmholtz(pr.N, pr.omega, pr.slowness)
+    bo = fem.mass_matrix(pr.N) @ pr.f + 0j
+    xo = exact.factor_exact(Ao, nd.build_nd(pr.N, 32, 16), keep_S=False).apply(bo)
+    assert st[0]["converged"]
+    assert np.linalg.norm(x.cpu().numpy().reshape(pr.n, -1) - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_bf16_sampling_needs_complex64():
+    hx = _hx()
+    from paper_2105_07791_amd._lib import HssxError
+    pr = make_problem("helmholtz_p1_17")
+    A = hx.Operator(pr.N, pr.omega, pr.slowness)
+    with pytest.raises(HssxError):
+        hx.Factor(A, dtype="c128", sample_bf16=True)
