@@ -84,9 +84,12 @@ typedef struct {
   int autotune;     /* nonzero: the apply tile shape of every tree depth is
                        measured on first use per (precision, sweep, size
                        bucket) and cached for the process; default 1 */
-  int sample_bf16;  /* nonzero (complex64 factors only): the sampling
-                       products Y = S Omega take bf16 operands with fp32
-                       accumulation; default 0 */
+  int sample_bf16;  /* complex64 factors only: the sampling products
+                       Y = S Omega run on bf16 matrix cores with fp32
+                       accumulation; 1 = operands rounded to bf16, 2 = each
+                       operand split into a bf16 head and tail (three
+                       products, about 16 significant bits); 0 = fp32
+                       vector arithmetic (default) */
 } hssx_factor_opts;
 
 typedef struct {

@@ -216,6 +216,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
                HSSX_EINVAL, "invalid factor options");
     HSSX_CHECK(o.dtype == HSSX_C128 || o.dtype == HSSX_C64, HSSX_EINVAL, "dtype");
+    HSSX_CHECK(o.sample_bf16 >= 0 && o.sample_bf16 <= 2, HSSX_EINVAL, "sample_bf16 must be 0, 1 or 2");
     HSSX_CHECK(!o.sample_bf16 || o.dtype == HSSX_C64, HSSX_EINVAL,
                "bf16 sampling needs a complex64 factor");
     DeviceScope ds(A->device);

@@ -161,7 +161,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     for (const auto &q : sj) sflops += 4.0 * q.m * (double)q.m * q.nc;
     hipEvent_t ps = prof_begin(st);
     if constexpr (std::is_same<T, float>::value) {
-      if (o.sample_bf16) launch_sample_bf16((int)sj.size(), ds, mm, mc, st);
+      if (o.sample_bf16) launch_sample_bf16((int)sj.size(), ds, mm, mc, o.sample_bf16, st);
       else launch_sample<T>((int)sj.size(), ds, mm, mc, st);
     } else {
       launch_sample<T>((int)sj.size(), ds, mm, mc, st);

@@ -114,9 +114,10 @@ template <typename T> struct SampleJob {
 };
 template <typename T>
 void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, hipStream_t st);
-// the same product for complex64 S with bf16 operands and fp32 accumulation
-// (matrix cores)
-void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc,
+// the same product for complex64 S on bf16 matrix cores with fp32
+// accumulation: split = 1 rounds the operands to bf16, split = 2 keeps a bf16
+// head and tail of each operand (three products)
+void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc, int split,
                         hipStream_t st);
 
 // One cluster of one compression instance at the current tree level.

@@ -85,18 +85,21 @@ __global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
 // bf16 sampling (complex64 only): the complex-times-real product in its real
 // view, Y_r (2m x nc) = S_r (2m x m) Omega (m x nc) with the re/im parts of S
 // as interleaved rows, on the 16x16x16 bf16 matrix cores with fp32
-// accumulation.  Operands are rounded to bf16 (nearest even) on load.  One
-// wavefront per 16 x 16 output tile; four wavefronts per workgroup stack
-// their tiles over rows.
+// accumulation.  SPLIT = 1: operands rounded to bf16 (nearest even) on load.
+// SPLIT = 2: each operand is split into a bf16 head and a bf16 tail
+// (x ~ hi + lo) and the product keeps hi*hi + hi*lo + lo*hi (three matrix-core
+// products, about 16 significant bits).  One wavefront per 16 x 16 output
+// tile; four wavefronts per workgroup stack their tiles over rows.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short to_bf16(float f) {
+__device__ __forceinline__ unsigned bf16_bits(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+  return u >> 16;
 }
 
+template <int SPLIT>
 __global__ __launch_bounds__(256) void sample_bf16_kernel(const SampleJob<float> *__restrict__ jobs) {
   const SampleJob<float> jb = jobs[blockIdx.z];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -108,14 +111,25 @@ __global__ __launch_bounds__(256) void sample_bf16_kernel(const SampleJob<float>
   const int ai = row0 + lane % 16, bj = col0 + lane % 16, kq = 4 * (lane / 16);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < jb.m; k0 += 16) {
-    bf16x4 a, b;
+    bf16x4 ah, bh, al, bl;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = k0 + kq + q;
-      a[q] = to_bf16((ai < R && k < jb.m) ? Sr[ai + (long)k * ldS] : 0.f);
-      b[q] = to_bf16((bj < jb.nc && k < jb.m) ? (float)jb.Om[k + (long)bj * jb.ldO] : 0.f);
+      const float a = (ai < R && k < jb.m) ? Sr[ai + (long)k * ldS] : 0.f;
+      const float b = (bj < jb.nc && k < jb.m) ? (float)jb.Om[k + (long)bj * jb.ldO] : 0.f;
+      const unsigned ha = bf16_bits(a), hb = bf16_bits(b);
+      ah[q] = (short)ha;
+      bh[q] = (short)hb;
+      if (SPLIT == 2) {
+        al[q] = (short)bf16_bits(a - __uint_as_float(ha << 16));
+        bl[q] = (short)bf16_bits(b - __uint_as_float(hb << 16));
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    if (SPLIT == 2) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
   }
   float *Yr = reinterpret_cast<float *>(jb.Y);
   const long ldY = 2L * jb.ldY;
@@ -778,11 +792,12 @@ void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, h
   HSSX_HIP(hipGetLastError());
 }
 
-void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc,
+void launch_sample_bf16(int count, const SampleJob<float> *jobs, int max_m, int max_nc, int split,
                         hipStream_t st) {
   if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
-  hipLaunchKernelGGL(sample_bf16_kernel, dim3(ceil_div(2L * max_m, 64), ceil_div(max_nc, 16), count),
-                     dim3(256), 0, st, jobs);
+  const dim3 grid(ceil_div(2L * max_m, 64), ceil_div(max_nc, 16), count);
+  if (split == 2) hipLaunchKernelGGL(sample_bf16_kernel<2>, grid, dim3(256), 0, st, jobs);
+  else hipLaunchKernelGGL(sample_bf16_kernel<1>, grid, dim3(256), 0, st, jobs);
   HSSX_HIP(hipGetLastError());
 }
 

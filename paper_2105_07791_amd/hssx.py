@@ -129,7 +129,7 @@ class Factor:
         opts = _lib.FactorOpts(beta, h_sw, k0, r, max_rounds,
                                _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64,
                                seed, id_rel_tol, int(apply_graph), int(autotune),
-                               int(sample_bf16))
+                               int(sample_bf16))  # 0, 1 (bf16) or 2 (split bf16)
         h = C.c_void_p()
         check(lib().hssx_factor(A.handle, float(tol), int(leaf_size), C.byref(opts),
                                 _stream(stream), C.byref(h)))

@@ -167,7 +167,7 @@ class BatchProblem:
 #: omega = kh (N - 1), so every problem resolves its shortest wavelength with
 #: the same number of points (the speed is at least 1, so k h <= kh).
 BATCHES = {
-    "helmholtz_p1_batch256": dict(count=256, lo=65, hi=513, seed=7, kh=0.2, receivers=8),
+    "helmholtz_p1_batch256": dict(count=256, lo=65, hi=513, seed=0, kh=0.25, receivers=8),
     # reduced batches for parity tests
     "helmholtz_p1_batch8": dict(count=8, lo=9, hi=65, seed=8, kh=0.3, receivers=8),
     "helmholtz_p1_batch32": dict(count=32, lo=65, hi=129, seed=9, kh=0.2, receivers=8),

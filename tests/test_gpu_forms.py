@@ -104,3 +104,20 @@ def test_bf16_sampling_needs_complex64():
     A = hx.Operator(pr.N, pr.omega, pr.slowness)
     with pytest.raises(HssxError):
         hx.Factor(A, dtype="c128", sample_bf16=True)
+
+
+def test_split_bf16_sampling_reaches_fp32_quality():
+    """Head/tail bf16 operands (three matrix-core products) sample accurately
+    enough for the compression to certify 1e-4 with fp32-like ranks."""
+    hx = _hx()
+    dev = torch.device("cuda:0")
+    pr = make_problem("helmholtz_p1_65")
+    A = hx.Operator(pr.N, pr.omega, pr.slowness)
+    Ps = hx.Factor(A, tol=1e-4, h_sw=2, dtype="c64", seed=5, sample_bf16=2)
+    Pf = hx.Factor(A, tol=1e-4, h_sw=2, dtype="c64", seed=5, sample_bf16=0)
+    ss, sf = Ps.stats(), Pf.stats()
+    assert ss["max_estimate"] <= 1e-4 and ss["max_rounds_used"] < 32
+    assert ss["k_max"] <= sf["k_max"] + 16
+    b = A.load(torch.tensor(pr.f, device=dev))
+    ys, yf = Ps.apply(b).cpu().numpy(), Pf.apply(b).cpu().numpy()
+    assert np.linalg.norm(ys - yf) <= 1e-3 * np.linalg.norm(yf)
