@@ -119,8 +119,10 @@ typedef struct {
   double max_estimate;  /* largest accepted relative error estimate (eq. 2.7) */
   double factor_bytes;  /* bytes the apply reads (LU blocks, pivots, R) */
   double factor_flops;  /* nominal flops of the numeric factorization */
-  double ms_symbolic;   /* host symbolic analysis */
+  double ms_symbolic;   /* host symbolic analysis (trees, orders) */
   double ms_numeric;    /* numeric factorization (device, hipEvents) */
+  double ms_setup;      /* front descriptors, their upload and the front
+                           pool allocation (host) */
 } hssx_factor_stats;
 
 /* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for

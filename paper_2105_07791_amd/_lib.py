@@ -38,7 +38,8 @@ class FactorStats(C.Structure):
                 ("n_hss_nodes", C.c_int), ("n_compressed", C.c_int), ("k_max", C.c_int),
                 ("max_rounds_used", C.c_int), ("max_estimate", C.c_double),
                 ("factor_bytes", C.c_double), ("factor_flops", C.c_double),
-                ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double)]
+                ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
+                ("ms_setup", C.c_double)]
 
 
 _vp = C.c_void_p

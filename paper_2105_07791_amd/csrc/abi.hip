@@ -255,6 +255,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     }
     const Symbolic &sym = P->sym;
     const int nn = (int)sym.nodes.size();
+    auto ts = std::chrono::steady_clock::now();
     P->arith.assign(nn, 0);
     P->comp.assign(nn, 0);
     for (int k = 0; k < nn; ++k) P->arith[k] = o.h_sw >= 0 && sym.nodes[k].height > o.h_sw;
@@ -349,7 +350,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->front.alloc(std::max(1L, foff) * esz_pool);
     if (split_roots) P->front64.alloc(std::max(1L, roff) * sizeof(c128));
     auto t1 = std::chrono::steady_clock::now();
-    P->stats.ms_symbolic = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    P->stats.ms_symbolic = std::chrono::duration<double, std::milli>(ts - t0).count();
+    P->stats.ms_setup = std::chrono::duration<double, std::milli>(t1 - ts).count();
     P->stats.n = A->n;
     P->stats.nodes = nn;
     P->stats.depth = sym.max_depth;
