@@ -251,7 +251,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       work();
       for (auto &t : pool) t.join();
       if (fail) std::rethrow_exception(fail);
-      P->sym = merge_forest(parts, A->part_off);
+      P->sym = merge_forest(std::move(parts), A->part_off);
     }
     const Symbolic &sym = P->sym;
     const int nn = (int)sym.nodes.size();
@@ -262,14 +262,12 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     for (int k = 0; k < nn; ++k) P->comp[k] = sym.nodes[k].parent >= 0 && P->arith[sym.nodes[k].parent];
     P->node_rank.assign(nn, 0);
 
-    // descriptors and front-entry sources
+    // descriptors (sizes and offsets, one pass over the nodes)
     std::vector<FrontDesc> dsc(nn);
-    std::vector<int> bpos, sg, sc, sp;
-    std::vector<int> owner(A->n, -1), opos(A->n, -1);
     // complex64 factors keep the roots' fronts in complex128, in a buffer of
     // their own (offsets roff)
     const bool split_roots = o.dtype == HSSX_C64;
-    long foff = 0, roff = 0;
+    long foff = 0, roff = 0, boff = 0, soff = 0;
     double fbytes = 0, flops = 0;
     const size_t esz_pool = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
     for (int k = 0; k < nn; ++k) {
@@ -283,41 +281,81 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       d.foff = off;
       off += (long)d.f * (d.f + d.ni);
       d.ioff = nd.offset;
-      d.bpos_off = (int)bpos.size();
-      for (int v : nd.B) bpos.push_back(sym.iperm[v]);
-      d.src_off = (int)sg.size();
+      d.bpos_off = (int)boff;
+      boff += d.nb;
+      HSSX_CHECK(soff + d.f < (1L << 31), HSSX_EINVAL, "front index space exceeds 32 bits");
+      d.src_off = (int)soff;
+      soff += d.f;
       d.lo = nd.lo;
       d.hi = nd.hi;
-      if (!nd.leafnode()) {
-        const NDNode &lo = sym.nodes[nd.lo], &hi = sym.nodes[nd.hi];
-        for (size_t b = 0; b < lo.B.size(); ++b) { owner[lo.B[b]] = 0; opos[lo.B[b]] = (int)b; }
-        for (size_t b = 0; b < hi.B.size(); ++b) { owner[hi.B[b]] = 1; opos[hi.B[b]] = (int)b; }
-      }
-      auto push = [&](int v) {
-        sg.push_back(v);
-        if (nd.leafnode()) { sc.push_back(-1); sp.push_back(0); }
-        else {
-          HSSX_CHECK(owner[v] >= 0, HSSX_EINVAL, "front entry outside the children's boundaries");
-          sc.push_back(owner[v]);
-          sp.push_back(opos[v]);
+      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * (in64 ? sizeof(c128) : esz_pool);
+      // Gauss-Jordan on f rows x (f + ni) columns, complex multiply-add = 8 flops:
+      // sum over pivots p < ni of (f - 1)(f + ni - p - 1)
+      flops += 8.0 * (d.f - 1) * ((double)d.ni * (d.f + d.ni - 1) - 0.5 * d.ni * (d.ni - 1.0));
+    }
+    // front-entry sources: node id, and (child, position in the child's B)
+    // packed as 2 pos + child (-1: entry of A); parts filled on host threads
+    std::vector<int> bpos(boff), sg(soff), scode(soff);
+    const int nparts = (int)sym.part_nodes.size() - 1;
+    {
+      std::atomic<int> next{0};
+      std::exception_ptr fail;
+      std::mutex mu;
+      auto work = [&] {
+        try {
+          std::vector<int> owner, opos;
+          for (int q; (q = next++) < nparts;) {
+            const int k0 = sym.part_nodes[q], k1 = sym.part_nodes[q + 1];
+            const int v0 = A->part_off[q], nv = A->part_off[q + 1] - v0;
+            owner.assign(nv, -1);
+            opos.assign(nv, -1);
+            for (int k = k0; k < k1; ++k) {
+              const NDNode &nd = sym.nodes[k];
+              const FrontDesc &d = dsc[k];
+              for (int b = 0; b < d.nb; ++b) bpos[d.bpos_off + b] = sym.iperm[nd.B[b]];
+              const bool leaf = nd.leafnode();
+              if (!leaf) {
+                const NDNode &lo = sym.nodes[nd.lo], &hi = sym.nodes[nd.hi];
+                for (size_t b = 0; b < lo.B.size(); ++b) { owner[lo.B[b] - v0] = 0; opos[lo.B[b] - v0] = (int)b; }
+                for (size_t b = 0; b < hi.B.size(); ++b) { owner[hi.B[b] - v0] = 1; opos[hi.B[b] - v0] = (int)b; }
+              }
+              long e = d.src_off;
+              auto put = [&](int v) {
+                sg[e] = v;
+                if (leaf) {
+                  scode[e] = -1;
+                } else {
+                  HSSX_CHECK(owner[v - v0] >= 0, HSSX_EINVAL,
+                             "front entry outside the children's boundaries");
+                  scode[e] = 2 * opos[v - v0] + owner[v - v0];
+                }
+                ++e;
+              };
+              for (int v : nd.I) put(v);
+              for (int v : nd.B) put(v);
+              if (!leaf) {
+                for (int v : sym.nodes[nd.lo].B) owner[v - v0] = -1;
+                for (int v : sym.nodes[nd.hi].B) owner[v - v0] = -1;
+              }
+            }
+          }
+        } catch (...) {
+          std::lock_guard<std::mutex> g(mu);
+          fail = std::current_exception();
         }
       };
-      for (int v : nd.I) push(v);
-      for (int v : nd.B) push(v);
-      if (!nd.leafnode()) {
-        for (int v : sym.nodes[nd.lo].B) owner[v] = -1;
-        for (int v : sym.nodes[nd.hi].B) owner[v] = -1;
-      }
-      fbytes += ((double)d.ni * d.ni + 2.0 * d.ni * d.nb) * (in64 ? sizeof(c128) : esz_pool);
-      // Gauss-Jordan on f rows x (f + ni) columns, complex multiply-add = 8 flops
-      for (int p = 0; p < d.ni; ++p) flops += 8.0 * (d.f - 1) * (d.f + d.ni - p - 1);
+      const int nt = std::max(1, std::min(nparts, std::min(16, (int)std::thread::hardware_concurrency())));
+      std::vector<std::thread> pool;
+      for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+      work();
+      for (auto &t : pool) t.join();
+      if (fail) std::rethrow_exception(fail);
     }
     P->h_desc = dsc;
     upload(P->desc, dsc);
     upload(P->bpos, bpos);
     upload(P->src_gid, sg);
-    upload(P->src_child, sc);
-    upload(P->src_pos, sp);
+    upload(P->src_code, scode);
     upload(P->perm, sym.perm);
     P->depth_nodes.assign(sym.max_depth + 1, {});
     for (int k = 0; k < nn; ++k) P->depth_nodes[sym.nodes[k].depth].push_back(k);

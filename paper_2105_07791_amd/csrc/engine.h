@@ -38,7 +38,7 @@ struct hssx_fact_ {
   hssx::Symbolic sym;
   std::vector<int> arith, comp; // per node: HSS arithmetic, compressed S
   std::vector<hssx::FrontDesc> h_desc;
-  hssx::DevBuf desc, bpos, src_gid, src_child, src_pos, perm, front;
+  hssx::DevBuf desc, bpos, src_gid, src_code, perm, front;
   // complex64 factors keep the roots (top separators) in complex128: their
   // fronts live in front64, at the roots' foff
   hssx::DevBuf front64;

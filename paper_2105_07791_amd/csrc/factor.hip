@@ -481,7 +481,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
       c128 *F64 = P.front64.as<c128>();
       hipEvent_t pa = prof_begin(st);
       launch_front_assemble<double, T>(cnt, P.depth_dev[0].as<int>(), desc, P.src_gid.as<int>(),
-                                       P.src_child.as<int>(), P.src_pos.as<int>(),
+                                       P.src_code.as<int>(),
                                        A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), F,
                                        F64, st, P.depth_max_f[0]);
       prof_end("front_assemble", st, pa, P.asm_bytes[0]);
@@ -499,7 +499,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
     }
     hipEvent_t pa = prof_begin(st);
     launch_front_assemble<T, T>(cnt, P.depth_dev[d].as<int>(), desc, P.src_gid.as<int>(),
-                                P.src_child.as<int>(), P.src_pos.as<int>(), A.rowptr.as<int>(),
+                                P.src_code.as<int>(), A.rowptr.as<int>(),
                                 A.col.as<int>(), A.val.as<c128>(), F, F, st, P.depth_max_f[d]);
     prof_end("front_assemble", st, pa, P.asm_bytes[d]);
 

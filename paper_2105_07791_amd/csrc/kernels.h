@@ -42,7 +42,7 @@ struct FrontDesc {
 // are kept in complex128).
 template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
-                           const int *src_gid, const int *src_child, const int *src_pos,
+                           const int *src_gid, const int *src_code,
                            const int *rowptr, const int *col, const c128 *val,
                            const cplx<Tc> *cpool, cplx<T> *opool, hipStream_t st, int max_f);
 

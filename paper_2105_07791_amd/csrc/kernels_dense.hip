@@ -1,7 +1,7 @@
 // Dense fronts of the nested-dissection elimination (eqs. 3.2-3.5).
 //
 // front_assemble: F(p, q) = S_child(p, q) when both front entries belong to
-// the same child's boundary (the child's Schur complement, held in the
+// the same child's boundary (entry source code 2 pos + child, -1 for none) (the child's Schur complement, held in the
 // trailing block of the child's front), else A(p, q) from the CSR (eq. 3.4);
 // the appended ni columns start as [I; 0].
 //
@@ -23,8 +23,8 @@ constexpr int kThreads = 256;
 template <typename T, typename Tc>
 __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
     const int *__restrict__ nodes, const FrontDesc *__restrict__ desc,
-    const int *__restrict__ src_gid, const int *__restrict__ src_child,
-    const int *__restrict__ src_pos, const int *__restrict__ rowptr,
+    const int *__restrict__ src_gid, const int *__restrict__ src_code,
+    const int *__restrict__ rowptr,
     const int *__restrict__ col, const c128 *__restrict__ val,
     const cplx<Tc> *__restrict__ cpool, cplx<T> *__restrict__ opool) {
   const FrontDesc d = desc[nodes[blockIdx.x]];
@@ -35,8 +35,7 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
   if (e0 >= total) return;
   long e1 = e0 + per < total ? e0 + per : total;
   const int *gid = src_gid + d.src_off;
-  const int *chd = src_child + d.src_off;
-  const int *pos = src_pos + d.src_off;
+  const int *code = src_code + d.src_off;
   cplx<T> *F = opool + d.foff;
   for (long e = e0 + threadIdx.x; e < e1; e += kThreads) {
     int p = (int)(e % f), q = (int)(e / f);
@@ -44,10 +43,10 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
     if (q >= f) {
       v = mk((T)(p == q - f ? 1 : 0), (T)0);
     } else {
-      int cp = chd[p], cq = chd[q];
-      if (cp >= 0 && cp == cq) {
-        const FrontDesc c = desc[cp == 0 ? d.lo : d.hi];
-        v = ccast<T>(cpool[c.foff + (long)(c.ni + pos[p]) + (long)(c.ni + pos[q]) * c.f]);
+      const int ep = code[p], eq = code[q];
+      if (ep >= 0 && eq >= 0 && (ep & 1) == (eq & 1)) {
+        const FrontDesc c = desc[(ep & 1) == 0 ? d.lo : d.hi];
+        v = ccast<T>(cpool[c.foff + (long)(c.ni + (ep >> 1)) + (long)(c.ni + (eq >> 1)) * c.f]);
       } else {
         int gi = gid[p], gj = gid[q];
         c128 a = czero<double>();
@@ -403,14 +402,14 @@ __global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
 
 template <typename T, typename Tc>
 void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
-                           const int *src_gid, const int *src_child, const int *src_pos,
+                           const int *src_gid, const int *src_code,
                            const int *rowptr, const int *col, const c128 *val,
                            const cplx<Tc> *cpool, cplx<T> *opool, hipStream_t st, int max_f) {
   if (count <= 0) return;
   long per = (long)kThreads * 16;
   int ny = ceil_div((long)max_f * (2L * max_f), per);
   hipLaunchKernelGGL((front_assemble_kernel<T, Tc>), dim3(count, ny), dim3(kThreads), 0, st,
-                     nodes, desc, src_gid, src_child, src_pos, rowptr, col, val, cpool, opool);
+                     nodes, desc, src_gid, src_code, rowptr, col, val, cpool, opool);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -454,8 +453,8 @@ void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipS
 #define HSSX_ASM(T, Tc)                                                                      \
   template void launch_front_assemble<T, Tc>(int, const int *, const FrontDesc *, const int *, \
                                              const int *, const int *, const int *,           \
-                                             const int *, const c128 *, const cplx<Tc> *,     \
-                                             cplx<T> *, hipStream_t, int);
+                                             const c128 *, const cplx<Tc> *, cplx<T> *,       \
+                                             hipStream_t, int);
 HSSX_ASM(double, double)
 HSSX_ASM(float, float)
 HSSX_ASM(double, float)

@@ -182,22 +182,27 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
   }
   s.iperm.assign((size_t)N * N, -1);
   for (size_t k = 0; k < s.perm.size(); ++k) s.iperm[s.perm[k]] = (int)k;
+  s.part_nodes = {0, (int)nodes.size()};
   return s;
 }
 
-Symbolic merge_forest(const std::vector<Symbolic> &parts, const std::vector<int> &dof_off) {
+Symbolic merge_forest(std::vector<Symbolic> &&parts, const std::vector<int> &dof_off) {
   Symbolic f;
   if (parts.empty()) return f;
   f.leaf_dofs = parts[0].leaf_dofs;
   f.beta = parts[0].beta;
   const int n = dof_off.back();
+  size_t total = 0;
+  for (const auto &s : parts) total += s.nodes.size();
+  f.nodes.reserve(total);
   f.perm.reserve(n);
   f.iperm.assign(n, -1);
+  f.part_nodes.push_back(0);
   for (size_t q = 0; q < parts.size(); ++q) {
-    const Symbolic &s = parts[q];
+    Symbolic &s = parts[q];
     const int base = (int)f.nodes.size(), o = dof_off[q];
     auto shift = [o](std::vector<int> &v) { for (int &x : v) x += o; };
-    for (NDNode nd : s.nodes) {
+    for (NDNode &nd : s.nodes) {
       if (nd.lo >= 0) { nd.lo += base; nd.hi += base; }
       if (nd.parent >= 0) nd.parent += base;
       shift(nd.bd);
@@ -209,6 +214,8 @@ Symbolic merge_forest(const std::vector<Symbolic> &parts, const std::vector<int>
     for (int v : s.perm) f.perm.push_back(v + o);
     for (size_t k = 0; k < s.iperm.size(); ++k) f.iperm[k + o] = s.iperm[k] + o;
     f.max_depth = std::max(f.max_depth, s.max_depth);
+    f.part_nodes.push_back((int)f.nodes.size());
+    Symbolic().nodes.swap(s.nodes);   // release the part's storage
   }
   return f;
 }

@@ -39,6 +39,8 @@ struct Symbolic {
   std::vector<int> perm;       // perm[k] = node id eliminated at position k
   std::vector<int> iperm;      // iperm[node id] = position
   int max_depth = 0;
+  // forests: nodes of part q are [part_nodes[q], part_nodes[q+1])
+  std::vector<int> part_nodes;
 };
 
 Symbolic build_symbolic(int N, int leaf_dofs, int beta);
@@ -47,7 +49,7 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta);
 // node ids, DOF ids and permutation positions shifted so that part p's DOFs
 // are [dof_off[p], dof_off[p+1]) of one block-diagonal system.  Every tree
 // keeps its own depths, so depth 0 holds all roots.
-Symbolic merge_forest(const std::vector<Symbolic> &parts, const std::vector<int> &dof_off);
+Symbolic merge_forest(std::vector<Symbolic> &&parts, const std::vector<int> &dof_off);
 
 // Cluster tree of the P0 block of a node's boundary: the left subtree of the
 // top split, the whole tree when the node has no P1 part, empty without P0.  Positions are
