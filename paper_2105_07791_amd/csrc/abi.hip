@@ -229,7 +229,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->opts = o;
     auto t0 = std::chrono::steady_clock::now();
     if (A->part_N.size() == 1) {
-      P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta);
+      P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta,
+                              std::min(16, (int)std::thread::hardware_concurrency()));
     } else {
       // the problems' analyses are independent: run them on host threads
       const int np = (int)A->part_N.size();
@@ -457,7 +458,7 @@ hssx_status hssx_analyze(int N, int leaf_size, int beta, hssx_fact *P_out) {
     auto P = std::make_unique<hssx_fact_>();
     P->leaf = leaf_size;
     P->opts.beta = beta;
-    P->sym = build_symbolic(N, leaf_size, beta);
+    P->sym = build_symbolic(N, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()));
     *P_out = P.release();
   });
 }

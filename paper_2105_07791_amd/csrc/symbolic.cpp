@@ -14,8 +14,10 @@
 #include "symbolic.h"
 
 #include <algorithm>
+#include <atomic>
 #include <functional>
 #include <memory>
+#include <thread>
 
 namespace hssx {
 
@@ -99,9 +101,27 @@ void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
   }
 }
 
+// fn(k) for k in [0, n) on up to `threads` host threads
+template <typename F> void parallel_for(int n, int threads, F fn) {
+  threads = std::max(1, std::min(threads, n / 64));
+  if (threads <= 1) {
+    for (int k = 0; k < n; ++k) fn(k);
+    return;
+  }
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int k; (k = next.fetch_add(64)) < n;)
+      for (int j = k; j < std::min(n, k + 64); ++j) fn(j);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+}
+
 }  // namespace
 
-Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads) {
   Symbolic s;
   s.N = N;
   s.leaf_dofs = leaf_dofs;
@@ -136,9 +156,11 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
 
   static const int dx[6] = {1, -1, 0, 0, 1, -1};
   static const int dy[6] = {0, 0, 1, -1, 1, -1};
+  const int nn = (int)nodes.size();
   // a node with a neighbour outside the box lies on the box's border, so
   // only border cells are tested (row-major, so the ids come out sorted)
-  for (auto &b : nodes) {
+  parallel_for(nn, threads, [&](int k) {
+    auto &b = nodes[k];
     for (int y = b.y0; y < b.y1; ++y)
       for (int x = b.x0; x < b.x1; x = (y == b.y0 || y == b.y1 - 1 || x == b.x1 - 1) ? x + 1 : b.x1 - 1) {
         bool out = false;
@@ -149,19 +171,21 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
         }
         if (out) b.bd.push_back(y * N + x);     // row-major scan = sorted ids
       }
-  }
+  });
 
-  for (auto &b : nodes) {
-    if (b.parent < 0) continue;
+  parallel_for(nn, threads, [&](int k) {
+    auto &b = nodes[k];
+    if (b.parent < 0) return;
     const auto &pbd = nodes[b.parent].bd;
     std::vector<int> P0, P1;
     for (int v : b.bd)
       (std::binary_search(pbd.begin(), pbd.end(), v) ? P1 : P0).push_back(v);
     make_cluster_tree(P0, P1, N, beta, b.ct, b.B);
     b.p0 = (int)P0.size();
-  }
+  });
 
-  for (auto &b : nodes) {
+  parallel_for(nn, threads, [&](int k) {
+    auto &b = nodes[k];
     if (b.leafnode()) {
       for (int y = b.y0; y < b.y1; ++y)
         for (int x = b.x0; x < b.x1; ++x) {
@@ -173,7 +197,7 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta) {
       b.I.assign(mu.B.begin(), mu.B.begin() + mu.p0);
       b.I.insert(b.I.end(), nu.B.begin(), nu.B.begin() + nu.p0);
     }
-  }
+  });
 
   s.perm.reserve((size_t)N * N);
   for (auto &b : nodes) {

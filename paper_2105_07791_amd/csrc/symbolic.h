@@ -43,7 +43,9 @@ struct Symbolic {
   std::vector<int> part_nodes;
 };
 
-Symbolic build_symbolic(int N, int leaf_dofs, int beta);
+// threads: host threads for the per-node work (boundary sets, cluster
+// trees, interiors); the result does not depend on it
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads = 1);
 
 // Forest of independent problems: the trees of `parts` side by side, with
 // node ids, DOF ids and permutation positions shifted so that part p's DOFs
