@@ -12,7 +12,9 @@
 //           Sr_r - B21 Om_l], B12 = S(sk_l, sk_r), B21 = S(sk_r, sk_l).  The
 //           interpolative decomposition S_loc ~ U S_loc(J, :) comes from a
 //           pivoted Gram-Schmidt QR of S_loc^T (pivot = largest remaining row
-//           norm, lowest row index on ties; each projection applied twice;
+//           norm, lowest row index on ties; one projection per pivot: the
+//           rounding it leaves along the pivot direction is far below the
+//           ID threshold of at least 4 unit roundoffs;
 //           for complex64 and blocks up to 256 x 192 the rows stay in
 //           registers, 16 lanes per row), rank =
 //           min(k, rows, s) reduced to the pivots above id_tol * first pivot;
@@ -31,6 +33,7 @@ namespace hssx {
 namespace {
 
 constexpr int kTPR = 4;          // lanes per row in the global-memory pivoted QR
+constexpr int kPasses = 1;       // projections per pivot step
 // Workgroup sizes of the compression kernel: NT = 1024 for clusters of more
 // than 64 rows, 256 below.  The register-resident pivoted QR (complex64)
 // uses RT lanes per row, NT / RT row slots, RPT rows per slot and RSEG
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           const int row = slot + kRS * r;
           const bool act = row < rows && !sel[row];
           cplx<T> rr = czero<T>();
-          for (int pass = 0; pass < 2; ++pass) {
+          for (int pass = 0; pass < kPasses; ++pass) {
             cplx<T> d = czero<T>();
 #pragma unroll
             for (int c = 0; c < kRSEG; ++c) {
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       const bool act = pp < rows;
       const int row = act ? perm[pp] : 0;
       cplx<T> rr = czero<T>();
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < kPasses; ++pass) {
         cplx<T> d = czero<T>();
         if (act)
           for (int j = sub; j < s; j += kTPR) cfma(d, conj(q[j]), Wm[row + (long)j * rcap]);
