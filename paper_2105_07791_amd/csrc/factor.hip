@@ -106,7 +106,7 @@ inline double compress_flops(const HssCluster &c, const HssInstance &I) {
   double f = 0;
   if (c.left < 0) f += 4.0 * rows * rows * s;                 // D Omega
   else f += 8.0 * rows * rows * s / 2;                        // B12 Om_r, B21 Om_l
-  f += k * rows * s * (3.0 + 32.0);                           // norms + 2 x (dot, axpy)
+  f += k * rows * s * (3.0 + 16.0);                           // norms + dot + axpy per pivot
   f += 4.0 * (rows - k) * k * k + 8.0 * k * rows * s;         // T and U^T Omega
   return f;
 }
