@@ -201,9 +201,11 @@ constexpr int kPT = 512;
 template <typename T, int NBW, int RQ>
 __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__restrict__ jobs,
                                                         int *__restrict__ err_node) {
-  __shared__ T sv[kPT / 64];
-  __shared__ int si[kPT / 64];
-  __shared__ cplx<T> prow[NBW], trow[NBW];
+  // wavefront maxima and exchanged rows, double-buffered by step parity so
+  // that a step needs two barriers
+  __shared__ T sv[2][kPT / 64];
+  __shared__ int si[2][kPT / 64];
+  __shared__ cplx<T> prowb[2][NBW], trowb[2][NBW];
   __shared__ cplx<T> LU[NBW][NBW + 1], Z[NBW][NBW + 1];
   const PanelJob<T> jb = jobs[blockIdx.x];
   const int rows = jb.ne - jb.p0, nb = jb.nb, tid = threadIdx.x;
@@ -219,6 +221,8 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
   // the pivot step t is a runtime index; every register access goes through
   // compile-time column indices with predicates
   for (int t = 0; t < nb; ++t) {
+    const int par = t & 1;
+    cplx<T> *prow = prowb[par], *trow = trowb[par];
     T best = (T)-1;
     int bi = 0x7fffffff;
 #pragma unroll
@@ -236,13 +240,16 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
       int oi = __shfl_xor(bi, off);
       if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
     }
-    if ((tid & 63) == 0) { sv[tid / 64] = best; si[tid / 64] = bi; }
+    if ((tid & 63) == 0) { sv[par][tid / 64] = best; si[par][tid / 64] = bi; }
     __syncthreads();
-    best = sv[0];
-    bi = si[0];
+    best = sv[par][0];
+    bi = si[par][0];
 #pragma unroll
     for (int k = 1; k < kPT / 64; ++k)
-      if (sv[k] > best || (sv[k] == best && si[k] < bi)) { best = sv[k]; bi = si[k]; }
+      if (sv[par][k] > best || (sv[par][k] == best && si[par][k] < bi)) {
+        best = sv[par][k];
+        bi = si[par][k];
+      }
     const bool zero = !(best > (T)0);
     if (zero && tid == 0) atomicCAS(err_node, -1, jb.node);
     const int pv = zero ? t : bi;
@@ -289,7 +296,6 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
         }
       }
     }
-    __syncthreads();
   }
   // L11 U11 to LDS, then G = (L11 U11)^-1, one column per thread (in LDS)
   if (tid < nb) {

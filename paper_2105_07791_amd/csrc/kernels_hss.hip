@@ -143,6 +143,26 @@ __global__ __launch_bounds__(256) void sample_bf16_kernel(const SampleJob<float>
   }
 }
 
+// Block-wide argmax with one barrier: wavefront maxima go to LDS slot set
+// `par` (alternate between calls), then every thread reduces all of them in
+// the same order, so all threads agree without a second barrier.  Ties keep
+// the smaller index.
+template <int NT, typename T>
+__device__ void block_argmax_1b(T &v, int &idx, T (*sv)[NT / 64], int (*si)[NT / 64], int par) {
+  for (int off = 32; off > 0; off >>= 1) {
+    T ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  if ((threadIdx.x & 63) == 0) { sv[par][threadIdx.x / 64] = v; si[par][threadIdx.x / 64] = idx; }
+  __syncthreads();
+  v = sv[par][0];
+  idx = si[par][0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k)
+    if (sv[par][k] > v || (sv[par][k] == v && si[par][k] < idx)) { v = sv[par][k]; idx = si[par][k]; }
+}
+
 template <int NT, typename T>
 __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -286,6 +306,11 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
   constexpr int kRT = CCfg<NT>::RT, kRS = NT / kRT, kRPT = CCfg<NT>::RPT, kRSEG = CCfg<NT>::RSEG;
+  // pivot rows and wavefront maxima of the register path, double-buffered by
+  // step parity
+  __shared__ cplx<T> qb[2][kRT * kRSEG];
+  __shared__ T sv2[2][NT / 64];
+  __shared__ int si2[2][NT / 64];
   __shared__ cplx<T> As[16][128], Bs[16][128];
   const HssItem it = items[blockIdx.x];
   const HssInstance I = insts[it.inst];
@@ -387,7 +412,11 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       }
       for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
+      // two barriers per pivot: after the wavefront maxima and after the
+      // pivot row; LDS buffers alternate between steps
       for (; t < kmax; ++t) {
+        const int par = t & 1;
+        cplx<T> *q = qb[par];
         T best = (T)-1;
         int bi = 0x7fffffff;
 #pragma unroll
@@ -402,7 +431,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             bi = row;
           }
         }
-        block_argmax<NT>(best, bi, sv, si);
+        block_argmax_1b<NT>(best, bi, sv2, si2, par);
         const T pn = sqrt(best);
         if (t == 0) first = pn;
         if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
@@ -452,8 +481,8 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           }
           if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
         }
-        __syncthreads();
       }
+      __syncthreads();
       // the unselected rows follow the pivots in ascending order
       if (tid == 0) {
         int pos = t;
