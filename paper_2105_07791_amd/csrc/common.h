@@ -112,6 +112,16 @@ __host__ __device__ __forceinline__ cplx<T> czero() {
   return mk((T)0, (T)0);
 }
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads()
+// it does not wait for the workgroup's outstanding global stores, so loops
+// that write results to global memory every step do not stall on them.  Use
+// it only where the other threads read nothing but LDS after the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- memory
 // Device buffer owned by the library (RAII, not copyable).
 struct DevBuf {

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
       if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
     }
     if ((tid & 63) == 0) { sv[par][tid / 64] = best; si[par][tid / 64] = bi; }
-    __syncthreads();
+    lds_barrier();
     best = sv[par][0];
     bi = si[par][0];
 #pragma unroll
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
         for (int c = 0; c < NBW; ++c) trow[c] = w[q][c];
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
       const int i = tid + kPT * q;

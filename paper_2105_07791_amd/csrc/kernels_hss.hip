@@ -155,7 +155,7 @@ __device__ void block_argmax_1b(T &v, int &idx, T (*sv)[NT / 64], int (*si)[NT /
     if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
   }
   if ((threadIdx.x & 63) == 0) { sv[par][threadIdx.x / 64] = v; si[par][threadIdx.x / 64] = idx; }
-  __syncthreads();
+  lds_barrier();
   v = sv[par][0];
   idx = si[par][0];
 #pragma unroll
@@ -453,7 +453,9 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           sel[bi] = 1;
           Rm[t + (long)bi * C.k_cap] = mk(pn, (T)0);
         }
-        __syncthreads();
+        // LDS-only barrier: the R coefficients go to global memory and are
+        // read after the loop's closing full barrier
+        lds_barrier();
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
           const int row = slot + kRS * r;
