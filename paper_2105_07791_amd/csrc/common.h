@@ -122,6 +122,44 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Cross-lane moves within rows of 16 lanes on the VALU (DPP) instead of the
+// LDS crossbar: xor 1 and xor 2 inside quads, the reversal of 8 lanes and the
+// reversal of 16 lanes.  A sum or an argmax over a group of 8 or 16
+// consecutive lanes is the quad butterflies followed by the reversals.
+enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ int dpp(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16), result in every lane
+template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
+  if (G >= 2) v += dpp<kDppXor1>(v);
+  if (G >= 4) v += dpp<kDppXor2>(v);
+  if (G >= 8) v += dpp<kDppHalfMirror>(v);
+  if (G >= 16) v += dpp<kDppMirror>(v);
+  return v;
+}
+// argmax (ties: smaller index) over the whole wavefront, result in every lane
+template <typename T> __device__ __forceinline__ void wave_argmax(T &v, int &idx) {
+  auto step = [&](T ov, int oi) {
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  };
+  step(dpp<kDppXor1>(v), dpp<kDppXor1>(idx));
+  step(dpp<kDppXor2>(v), dpp<kDppXor2>(idx));
+  step(dpp<kDppHalfMirror>(v), dpp<kDppHalfMirror>(idx));
+  step(dpp<kDppMirror>(v), dpp<kDppMirror>(idx));
+  step(__shfl_xor(v, 16), __shfl_xor(idx, 16));
+  step(__shfl_xor(v, 32), __shfl_xor(idx, 32));
+}
+
 // ---------------------------------------------------------------- memory
 // Device buffer owned by the library (RAII, not copyable).
 struct DevBuf {

@@ -235,11 +235,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
       const T a = cabs1(wt);
       if (i >= t && i < rows && (a > best || (a == best && i < bi))) { best = a; bi = i; }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      T ov = __shfl_xor(best, off);
-      int oi = __shfl_xor(bi, off);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
+    wave_argmax(best, bi);
     if ((tid & 63) == 0) { sv[par][tid / 64] = best; si[par][tid / 64] = bi; }
     lds_barrier();
     best = sv[par][0];

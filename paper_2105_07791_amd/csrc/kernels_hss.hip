@@ -149,11 +149,7 @@ __global__ __launch_bounds__(256) void sample_bf16_kernel(const SampleJob<float>
 // the smaller index.
 template <int NT, typename T>
 __device__ void block_argmax_1b(T &v, int &idx, T (*sv)[NT / 64], int (*si)[NT / 64], int par) {
-  for (int off = 32; off > 0; off >>= 1) {
-    T ov = __shfl_xor(v, off);
-    int oi = __shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
+  wave_argmax(v, idx);
   if ((threadIdx.x & 63) == 0) { sv[par][threadIdx.x / 64] = v; si[par][threadIdx.x / 64] = idx; }
   lds_barrier();
   v = sv[par][0];
@@ -425,7 +421,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           T nrm = 0;
 #pragma unroll
           for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
-          for (int o = 1; o < kRT; o <<= 1) nrm += __shfl_xor(nrm, o);
+          nrm = group_sum<kRT>(nrm);
           if (row < rows && !sel[row] && (nrm > best || (nrm == best && row < bi))) {
             best = nrm;
             bi = row;
@@ -468,10 +464,8 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
               const int j = sub + kRT * c;
               if (j < s) cfma(d, conj(q[j]), w[r][c]);
             }
-            for (int o = 1; o < kRT; o <<= 1) {
-              d.re += __shfl_xor(d.re, o);
-              d.im += __shfl_xor(d.im, o);
-            }
+            d.re = group_sum<kRT>(d.re);
+            d.im = group_sum<kRT>(d.im);
             if (act) {
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
