@@ -408,9 +408,6 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       }
       for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
-      // row slots and column segments in use (uniform), so that the unused
-      // register blocks are skipped rather than masked
-      const int nseg = (s + kRT - 1) / kRT, nrpt = (rows + kRS - 1) / kRS;
       // two barriers per pivot: after the wavefront maxima and after the
       // pivot row; LDS buffers alternate between steps
       for (; t < kmax; ++t) {
@@ -420,12 +417,10 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         int bi = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
-          if (r >= nrpt) break;
           const int row = slot + kRS * r;
           T nrm = 0;
 #pragma unroll
-          for (int c = 0; c < kRSEG; ++c)
-            if (c < nseg) nrm += abs2(w[r][c]);
+          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
           nrm = group_sum<kRT>(nrm);
           if (row < rows && !sel[row] && (nrm > best || (nrm == best && row < bi))) {
             best = nrm;
@@ -459,7 +454,6 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         lds_barrier();
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
-          if (r >= nrpt) break;
           const int row = slot + kRS * r;
           const bool act = row < rows && !sel[row];
           cplx<T> rr = czero<T>();
@@ -468,7 +462,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
 #pragma unroll
             for (int c = 0; c < kRSEG; ++c) {
               const int j = sub + kRT * c;
-              if (c < nseg && j < s) cfma(d, conj(q[j]), w[r][c]);
+              if (j < s) cfma(d, conj(q[j]), w[r][c]);
             }
             d.re = group_sum<kRT>(d.re);
             d.im = group_sum<kRT>(d.im);
@@ -476,7 +470,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
                 const int j = sub + kRT * c;
-                if (c < nseg && j < s) cfms(w[r][c], d, q[j]);
+                if (j < s) cfms(w[r][c], d, q[j]);
               }
             }
             rr = rr + d;
