@@ -124,7 +124,7 @@ def _front(A, tree, k, child_S):
     front = np.concatenate([bx.I, bx.B])
     F = A[front][:, front].toarray().astype(np.complex128)
     if not bx.is_leaf:
-        pos = np.full(tree.N * tree.N, -1, dtype=np.int64)
+        pos = np.full(tree.perm.size, -1, dtype=np.int64)
         pos[front] = np.arange(front.size)
         for c in (bx.lo, bx.hi):
             p = pos[tree.boxes[c].B]

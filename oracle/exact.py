@@ -75,7 +75,7 @@ def front_matrix(A, tree, k, S):
     if not bx.is_leaf:
         for c in (bx.lo, bx.hi):
             cb = tree.boxes[c].B
-            pos = np.full(tree.N * tree.N, -1, dtype=np.int64)
+            pos = np.full(tree.perm.size, -1, dtype=np.int64)
             pos[front] = np.arange(front.size)
             p = pos[cb]
             assert (p >= 0).all()

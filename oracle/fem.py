@@ -30,7 +30,8 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["triangles", "boundary_edges", "assemble_helmholtz", "mass_matrix",
-           "stencil_nnz", "element_terms", "assemble_parts"]
+           "stencil_nnz", "element_terms", "assemble_parts", "assemble_elastic",
+           "assemble_elastic_parts", "mass_matrix_vec"]
 
 
 def triangles(N):
@@ -188,3 +189,121 @@ def mass_matrix(N):
 def stencil_nnz(N):
     """Structural nonzeros of the 7-point P1 stencil on this mesh."""
     return N * N + 2 * (2 * N * (N - 1) + (N - 1) ** 2)
+
+
+# ---------------------------------------------------------------- elastic
+#
+# Time-harmonic linear elasticity, P1 vector elements on the same mesh
+# (the elastic workload of the paper's numerical section):
+#
+#     -div sigma(u) - omega^2 rho u = f,   sigma(u) = lam (div u) I + mu (grad u + grad u^T),
+#
+# with the first-order absorbing (Lysmer-Kuhlemeyer) traction
+# sigma(u) n = i omega rho (c_p (u.n) n + c_s (u.t) t) on the boundary,
+# c_p = sqrt((lam + 2 mu) / rho), c_s = sqrt(mu / rho).  Bilinear pairing:
+#
+#     A = K[lam, mu] - omega^2 M[rho] - i omega C,
+#
+#     K_(a,i),(b,j) = int lam d_i phi_a d_j phi_b + mu (delta_ij grad phi_a . grad phi_b
+#                                                       + d_j phi_a d_i phi_b)
+#     M[rho]_(a,i),(b,j) = delta_ij sum_l rho_l int phi_l phi_a phi_b
+#     C_(a,i),(b,j) = sum_l int_e phi_l phi_a phi_b (zp_l n_i n_j + zs_l t_i t_j),
+#                     zp = rho c_p, zs = rho c_s (nodal values interpolated as P1)
+#
+# lam, mu enter K through their element means (P1 interpolation, constant
+# gradients).  DOF id = 2 * node + component.
+
+def _edge_normals(N):
+    """Per boundary edge (same order as boundary_edges): n n^T and t t^T."""
+    k = N - 1
+    nn = np.zeros((4 * k, 2, 2))
+    tt = np.zeros((4 * k, 2, 2))
+    nn[:k, 1, 1] = 1.0          # south, n = (0, -1)
+    tt[:k, 0, 0] = 1.0
+    nn[k:2 * k, 0, 0] = 1.0     # east, n = (1, 0)
+    tt[k:2 * k, 1, 1] = 1.0
+    nn[2 * k:3 * k, 1, 1] = 1.0  # north
+    tt[2 * k:3 * k, 0, 0] = 1.0
+    nn[3 * k:, 0, 0] = 1.0       # west
+    tt[3 * k:, 1, 1] = 1.0
+    return nn, tt
+
+
+def assemble_elastic_parts(N, lam, mu, rho):
+    """Unordered DOF pairs (rows <= cols) with float64 values of K, M[rho],
+    M[1] (plain vector mass) and C; each element adds its local pairs once in
+    a fixed order, so mirroring gives a bitwise symmetric matrix."""
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    h = 1.0 / (N - 1)
+    tris = triangles(N)
+    xy = np.stack([(tris % N) * h, (tris // N) * h], axis=-1)
+    e1 = xy[:, 1] - xy[:, 0]
+    e2 = xy[:, 2] - xy[:, 0]
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    area = 0.5 * np.abs(det)
+    g = np.empty((tris.shape[0], 3, 2))
+    for a in range(3):
+        d = xy[:, (a + 2) % 3] - xy[:, (a + 1) % 3]
+        g[:, a, 0] = d[:, 1] / det
+        g[:, a, 1] = -d[:, 0] / det
+    lam_t = lam[tris].mean(axis=1) * area
+    mu_t = mu[tris].mean(axis=1) * area
+    eye = np.eye(2)
+    # Kl[t, a, i, b, j]
+    gg = np.einsum("tad,tbd->tab", g, g)
+    Kl = (lam_t[:, None, None, None, None] * np.einsum("tai,tbj->taibj", g, g)
+          + mu_t[:, None, None, None, None] * (np.einsum("tab,ij->taibj", gg, eye)
+                                               + np.einsum("taj,tbi->taibj", g, g)))
+    Ms = 2.0 * area[:, None, None] * np.einsum("tl,lij->tij", rho[tris], _T3)
+    M1s = 2.0 * area[:, None, None] * _T2[None, :, :]
+    Ml = np.einsum("tab,ij->taibj", Ms, eye)
+    M1l = np.einsum("tab,ij->taibj", M1s, eye)
+    edges = boundary_edges(N)
+    zp = np.sqrt(rho * (lam + 2.0 * mu))
+    zs = np.sqrt(rho * mu)
+    nn, tt = _edge_normals(N)
+    Ep = h * np.einsum("el,lab->eab", zp[edges], _E3)
+    Es = h * np.einsum("el,lab->eab", zs[edges], _E3)
+    Cl = (np.einsum("eab,eij->eaibj", Ep, nn) + np.einsum("eab,eij->eaibj", Es, tt))
+
+    n = 2 * N * N
+    # local DOF lists: triangle (3 nodes x 2) and edge (2 nodes x 2)
+    tdof = (2 * tris[:, :, None] + np.arange(2)[None, None, :]).reshape(-1, 6)
+    edof = (2 * edges[:, :, None] + np.arange(2)[None, None, :]).reshape(-1, 4)
+    ta, tb = np.triu_indices(6)
+    ea, eb = np.triu_indices(4)
+    r = np.concatenate([tdof[:, ta].ravel(), edof[:, ea].ravel()])
+    c = np.concatenate([tdof[:, tb].ravel(), edof[:, eb].ravel()])
+    lo = np.minimum(r, c)
+    hi = np.maximum(r, c)
+    uniq, inv = np.unique(lo * n + hi, return_inverse=True)
+    nt = tris.shape[0] * ta.size
+    vals = {}
+    for name, loc_t, loc_e in (("K", Kl, None), ("M", Ml, None), ("M1", M1l, None),
+                               ("C", None, Cl)):
+        acc = np.zeros(uniq.size)
+        if loc_t is not None:
+            np.add.at(acc, inv[:nt], loc_t.reshape(-1, 6, 6)[:, ta, tb].ravel())
+        if loc_e is not None:
+            np.add.at(acc, inv[nt:], loc_e.reshape(-1, 4, 4)[:, ea, eb].ravel())
+        vals[name] = acc
+    return uniq // n, uniq % n, vals
+
+
+def assemble_elastic(N, omega, lam, mu, rho):
+    """A = K - omega^2 M[rho] - i omega C (complex128 CSR, sorted columns) on
+    DOF ids 2 * node + component.  Structural zeros of the 14-entry block
+    pattern are kept as explicit entries."""
+    n = 2 * N * N
+    rows, cols, v = assemble_elastic_parts(N, lam, mu, rho)
+    val = v["K"] - omega * omega * v["M"] - 1j * omega * v["C"]
+    return _mirror_csr(n, rows, cols, val.astype(np.complex128))
+
+
+def mass_matrix_vec(N):
+    """Plain vector mass matrix (DOF ids 2 * node + component)."""
+    n = 2 * N * N
+    rows, cols, v = assemble_elastic_parts(N, np.ones(N * N), np.ones(N * N), np.ones(N * N))
+    return _mirror_csr(n, rows, cols, v["M1"])

@@ -28,6 +28,9 @@ Rules (Sec. 3.1 Def. 3.1 and Fig. 3; Sec. 3.2 Fig. 4; Sec. 3.3):
 * Order of I(sigma): a leaf sorts its nodes by (y, x); a non-leaf lists mu's P0
   then nu's P0 (the block layout of eq. 3.4).
 * The elimination permutation concatenates I(sigma) over the post-order.
+* With several unknowns per node (vector problems) every node contributes its
+  components consecutively (DOF id = dofs * node + component); boxes and
+  clusters are formed on nodes with sizes counted in DOFs.
 """
 from dataclasses import dataclass, field
 
@@ -257,13 +260,30 @@ def build_nd(N, leaf_dofs=32, beta=16, dofs=1):
             b.I = np.concatenate([mu.B[:mu.p0], nu.B[:nu.p0]])
         del b._nodes
 
+    if dofs > 1:
+        _expand_dofs(boxes, dofs)
     perm = np.concatenate([b.I for b in boxes]).astype(np.int64)
     off = 0
     for b in boxes:
         b.offset = off
         off += b.I.size
-    iperm = np.empty(n, dtype=np.int64)
-    iperm[perm] = np.arange(n)
+    n_dof = n * dofs
+    iperm = np.empty(n_dof, dtype=np.int64)
+    iperm[perm] = np.arange(n_dof)
     t = NDTree(N=N, leaf_dofs=leaf_dofs, beta=beta, dofs=dofs, boxes=boxes,
                perm=perm, iperm=iperm)
     return t
+
+
+def _expand_dofs(boxes, dofs):
+    """Node lists -> DOF lists for `dofs` unknowns per node (DOF id =
+    dofs * node + component): every node becomes its consecutive components,
+    cluster ranges and P0 sizes scale by `dofs`."""
+    comp = np.arange(dofs, dtype=np.int64)
+    ex = lambda v: (np.asarray(v, dtype=np.int64)[:, None] * dofs + comp[None, :]).ravel()  # noqa: E731
+    for b in boxes:
+        b.I = ex(b.I)
+        b.B = ex(b.B)
+        b.p0 = b.p0 * dofs
+        ct = b.ctree
+        b.ctree = ClusterTree(ct.start * dofs, ct.size * dofs, ct.left, ct.right, ct.level)

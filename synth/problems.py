@@ -18,7 +18,8 @@ import numpy as np
 __all__ = [
     "Problem", "node_coords", "source_centers", "gaussian_sources",
     "random_field", "speed_field", "make_problem", "CONFIGS", "make_batch", "BATCHES",
-    "receiver_nodes", "batch_grid_sizes",
+    "receiver_nodes", "batch_grid_sizes", "ElasticProblem", "lame_fields",
+    "make_elastic", "ELASTIC",
 ]
 
 
@@ -194,3 +195,69 @@ def make_batch(name, device=None, **overrides):
             (cfg["receivers"], 1))
         data.append(1e-4 * d)
     return BatchProblem(name=name, problems=problems, receivers=receivers, data=data)
+
+
+def lame_fields(N, seed, ell=0.1, device=None):
+    """Smooth Lame fields lam = 1 + 3*sigmoid(g1) in (1, 4) and
+    mu = 0.5 + 1.5*sigmoid(g2) in (0.5, 2), g1, g2 the random fields of seeds
+    seed and seed + 1; density rho = 1."""
+    g1 = random_field(N, seed, ell, device=device)
+    g2 = random_field(N, seed + 1, ell, device=device)
+    if device is not None:
+        import torch
+        return (1.0 + 3.0 * torch.sigmoid(g1), 0.5 + 1.5 * torch.sigmoid(g2),
+                torch.ones(N * N, dtype=torch.float64, device=device))
+    sig = lambda g: 1.0 / (1.0 + np.exp(-g))  # noqa: E731
+    return 1.0 + 3.0 * sig(g1), 0.5 + 1.5 * sig(g2), np.ones(N * N)
+
+
+@dataclass
+class ElasticProblem:
+    """One seeded time-harmonic P1 elastic workload on [0,1]^2 with the
+    first-order absorbing traction on all four sides.  Vectors hold
+    2 * N * N entries, DOF id 2 * node + component (x, y)."""
+    name: str
+    N: int
+    omega: float
+    lam: np.ndarray               # (N*N,) nodal Lame lambda
+    mu: np.ndarray                # (N*N,) nodal Lame mu
+    rho: np.ndarray               # (N*N,) nodal density
+    f: np.ndarray                 # (2*N*N, nrhs) nodal body-force samples
+    leaf_dofs: int = 64
+    beta: int = 32
+    tol: float = 1e-6
+    h_sw: int = 4
+    factor_dtype: str = "c64"
+
+    @property
+    def n(self):
+        return 2 * self.N * self.N
+
+    @property
+    def nrhs(self):
+        return self.f.shape[1]
+
+
+#: Elastic workloads: the 2.1M-DOF case at N = 1025 and small parity cases.
+ELASTIC = {
+    "elastic_p1_1025": dict(N=1025, omega=60.0, seed=0, nsrc=1),
+    "elastic_p1_33": dict(N=33, omega=6.0, seed=2, nsrc=2),
+    "elastic_p1_65": dict(N=65, omega=12.0, seed=4, nsrc=2),
+    "elastic_p1_129": dict(N=129, omega=20.0, seed=6, nsrc=2),
+}
+
+
+def make_elastic(name, device=None, **overrides):
+    """The named elastic workload: Lame fields from seeds (seed, seed + 1),
+    vertical body forces (0, 1) times Gaussian bumps (width 0.02) at nsrc
+    centres drawn with seed + 2.  With a torch device the Lame fields are
+    evaluated there and returned as tensors."""
+    cfg = dict(ELASTIC[name])
+    cfg.update(overrides)
+    N, seed, nsrc = cfg.pop("N"), cfg.pop("seed"), cfg.pop("nsrc")
+    omega = float(cfg.pop("omega"))
+    lam, mu, rho = lame_fields(N, seed, device=device)
+    g = gaussian_sources(N, source_centers(seed + 2, nsrc))
+    f = np.zeros((2 * N * N, nsrc))
+    f[1::2] = g
+    return ElasticProblem(name=name, N=N, omega=omega, lam=lam, mu=mu, rho=rho, f=f, **cfg)
