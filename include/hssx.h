@@ -127,9 +127,28 @@ typedef struct {
 
 /* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for
  * the slowness field s (device, float64[N*N], caller-owned, read during the
- * call).  Sec. 4.2 eq. 4.2 with the closed-form P1 integrals. */
+ * call).  Sec. 4.2 eq. 4.2 with the closed-form P1 integrals.  EINVAL for N
+ * outside [2, 17000] (32-bit CSR offsets), a non-finite or negative omega or
+ * null arguments. */
 hssx_status hssx_assemble(int device, const hssx_problem_desc *desc,
                           const double *s_dev, void *stream, hssx_op *A_out);
+
+/* Build the time-harmonic P1 elastic operator A = K[lam, mu] - omega^2
+ * M[rho] - i omega C on the N x N grid (the elastic workload of Sec. 4):
+ * displacement DOFs 2 * node + component, stiffness from the Lame fields
+ * lam, mu (element means of their P1 interpolants), mass with density rho,
+ * and the first-order absorbing traction rho (c_p u_n n + c_s u_t t) on all
+ * four sides (c_p = sqrt((lam + 2 mu)/rho), c_s = sqrt(mu/rho)).  lam, mu,
+ * rho: device float64[N*N], caller-owned, read during the call.  Pattern:
+ * 2 x 2 blocks of the 7-point node stencil, columns sorted.  The operator
+ * works with hssx_load (vector mass), hssx_matvec, hssx_factor, hssx_apply
+ * and hssx_gmres_solve; not with hssx_dAds_contract or in batches.
+ * EINVAL for N outside [2, 8500] (32-bit CSR offsets), a non-finite or
+ * negative omega, or null fields. */
+hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc,
+                                  const double *lam_dev, const double *mu_dev,
+                                  const double *rho_dev, void *stream,
+                                  hssx_op *A_out);
 
 /* Batch of independent problems as one block-diagonal operator (the
  * batching form: fronts of one tree depth, across all problems, are
@@ -210,11 +229,13 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev,
                                void *stream);
 
 /* Symbolic analysis only (box nested dissection, elimination tree, cluster
- * trees; Sec. 3.1 Def. 3.1, Fig. 3, Fig. 4) for an N x N grid with leaf boxes
- * of at most leaf_size DOFs and HSS leaves of at most beta DOFs.  Host-only:
+ * trees; Sec. 3.1 Def. 3.1, Fig. 3, Fig. 4) for an N x N grid with dofs
+ * unknowns per grid node (1: Helmholtz, 2: elastic, DOF dofs * node + c),
+ * leaf boxes of at most leaf_size DOFs and HSS leaves of at most beta DOFs
+ * (both >= dofs; a node's unknowns are never split).  Host-only:
  * makes no HIP call, so it runs without a GPU.  The handle supports
  * hssx_get_perm, hssx_get_tree and hssx_fact_destroy only. */
-hssx_status hssx_analyze(int N, int leaf_size, int beta, hssx_fact *P_out);
+hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_out);
 
 /* Elimination permutation (host int32[n]): perm[k] = node id eliminated at
  * position k (concatenation of I(sigma) over the post-order). */

@@ -52,6 +52,8 @@ _dp = C.POINTER(C.c_double)
 
 SIGNATURES = {
     "hssx_assemble": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, C.POINTER(_vp)]),
+    "hssx_assemble_elastic": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, _vp, _vp,
+                                   C.POINTER(_vp)]),
     "hssx_op_batch": (_i, [_i, C.POINTER(_vp), _vp, C.POINTER(_vp)]),
     "hssx_op_info": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), _ip]),
     "hssx_load": (_i, [_vp, _i, _vp, _l, _vp, _l, _vp]),
@@ -62,7 +64,7 @@ SIGNATURES = {
     "hssx_gmres_solve": (_i, [_vp, _vp, _i, _i, _vp, _l, _vp, _l, C.POINTER(GmresOpts),
                               C.POINTER(GmresStats), _vp]),
     "hssx_dAds_contract": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
-    "hssx_analyze": (_i, [_i, _i, _i, C.POINTER(_vp)]),
+    "hssx_analyze": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
     "hssx_get_perm": (_i, [_vp, _ip, _l]),
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),

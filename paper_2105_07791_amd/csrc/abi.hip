@@ -60,7 +60,8 @@ hssx_status hssx_assemble(int device, const hssx_problem_desc *desc, const doubl
                           void *stream, hssx_op *A_out) {
   return guarded([&] {
     HSSX_CHECK(desc && A_out && s_dev, HSSX_EINVAL, "null argument");
-    HSSX_CHECK(desc->N >= 2 && desc->N <= 46000, HSSX_EINVAL, "N out of range");
+    // 32-bit CSR offsets: nnz < 7 N^2 must stay below 2^31
+    HSSX_CHECK(desc->N >= 2 && desc->N <= 17000, HSSX_EINVAL, "N out of range");
     HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
     *A_out = nullptr;
     DeviceScope ds(device);
@@ -101,6 +102,62 @@ hssx_status hssx_assemble(int device, const hssx_problem_desc *desc, const doubl
   });
 }
 
+hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc, const double *lam_dev,
+                                  const double *mu_dev, const double *rho_dev, void *stream,
+                                  hssx_op *A_out) {
+  return guarded([&] {
+    HSSX_CHECK(desc && A_out && lam_dev && mu_dev && rho_dev, HSSX_EINVAL, "null argument");
+    // 32-bit CSR offsets: nnz < 28 N^2 must stay below 2^31
+    HSSX_CHECK(desc->N >= 2 && desc->N <= 8500, HSSX_EINVAL, "N out of range");
+    HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
+    *A_out = nullptr;
+    DeviceScope ds(device);
+    hipStream_t st = S(stream);
+    auto A = std::make_unique<hssx_op_>();
+    A->device = device;
+    A->N = desc->N;
+    A->omega = desc->omega;
+    A->dofs = 2;
+    const int N = desc->N, nn = N * N, n = 2 * nn;
+    A->n = n;
+    // 2 x 2 blocks of the 7-point node stencil, columns sorted
+    A->h_rowptr.resize(n + 1);
+    A->h_col.reserve((size_t)14 * n);
+    A->h_rowptr[0] = 0;
+    static const int ox[7] = {-1, 0, -1, 0, 1, 0, 1}, oy[7] = {-1, -1, 0, 0, 0, 1, 1};
+    for (int r = 0; r < n; ++r) {
+      const int v = r / 2, x = v % N, y = v / N;
+      for (int t = 0; t < 7; ++t) {
+        int u = x + ox[t], w = y + oy[t];
+        if (u >= 0 && w >= 0 && u < N && w < N) {
+          A->h_col.push_back(2 * (w * N + u));
+          A->h_col.push_back(2 * (w * N + u) + 1);
+        }
+      }
+      A->h_rowptr[r + 1] = (int)A->h_col.size();
+    }
+    A->nnz = (long)A->h_col.size();
+    upload(A->rowptr, A->h_rowptr);
+    upload(A->col, A->h_col);
+    A->val.alloc(A->nnz * sizeof(c128));
+    A->mval.alloc(A->nnz * sizeof(double));
+    // material fields kept as [lam; mu; rho]
+    A->s.alloc((size_t)3 * nn * sizeof(double));
+    double *f = A->s.as<double>();
+    HSSX_HIP(hipMemcpyAsync(f, lam_dev, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HSSX_HIP(hipMemcpyAsync(f + nn, mu_dev, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HSSX_HIP(hipMemcpyAsync(f + 2 * nn, rho_dev, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_assemble_elastic(N, desc->omega, f, f + nn, f + 2 * nn, A->rowptr.as<int>(),
+                            A->col.as<int>(), A->val.as<c128>(), A->mval.as<double>(), st);
+    A->part_N = {N};
+    A->part_omega = {desc->omega};
+    A->part_off = {0, n};
+    upload(A->part_off_dev, A->part_off);
+    HSSX_HIP(hipStreamSynchronize(st));
+    *A_out = A.release();
+  });
+}
+
 hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op *A_out) {
   return guarded([&] {
     HSSX_CHECK(parts && A_out && count >= 1, HSSX_EINVAL, "invalid argument");
@@ -110,6 +167,7 @@ hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op
       HSSX_CHECK(parts[q] && parts[q]->part_N.size() == 1, HSSX_EINVAL,
                  "batch parts must be single-problem operators");
       HSSX_CHECK(parts[q]->device == parts[0]->device, HSSX_EINVAL, "parts on different devices");
+      HSSX_CHECK(parts[q]->dofs == 1, HSSX_EINVAL, "batches hold scalar (Helmholtz) problems");
       n += parts[q]->n;
       nnz += parts[q]->nnz;
     }
@@ -187,7 +245,7 @@ hssx_status hssx_matvec(hssx_op A, int trans, int nrhs, const void *x_dev, long 
     (void)trans;   // A^T = A
     DeviceScope ds(A->device);
     launch_spmv(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->val.as<c128>(),
-                (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, S(stream));
+                (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, 7 * A->dofs, S(stream));
   });
 }
 
@@ -217,6 +275,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
                HSSX_EINVAL, "invalid factor options");
     HSSX_CHECK(o.dtype == HSSX_C128 || o.dtype == HSSX_C64, HSSX_EINVAL, "dtype");
     HSSX_CHECK(o.sample_bf16 >= 0 && o.sample_bf16 <= 2, HSSX_EINVAL, "sample_bf16 must be 0, 1 or 2");
+    HSSX_CHECK(leaf_size >= A->dofs && o.beta >= A->dofs, HSSX_EINVAL,
+               "leaf and HSS leaf sizes must hold one grid node's unknowns");
     HSSX_CHECK(!o.sample_bf16 || o.dtype == HSSX_C64, HSSX_EINVAL,
                "bf16 sampling needs a complex64 factor");
     DeviceScope ds(A->device);
@@ -230,7 +290,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     auto t0 = std::chrono::steady_clock::now();
     if (A->part_N.size() == 1) {
       P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta,
-                              std::min(16, (int)std::thread::hardware_concurrency()));
+                              std::min(16, (int)std::thread::hardware_concurrency()), A->dofs);
     } else {
       // the problems' analyses are independent: run them on host threads
       const int np = (int)A->part_N.size();
@@ -440,6 +500,7 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, cons
                                double *grad_dev, void *stream) {
   return guarded([&] {
     HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
+    HSSX_CHECK(A->dofs == 1, HSSX_EINVAL, "the slowness gradient is defined for Helmholtz operators");
     DeviceScope ds(A->device);
     for (size_t q = 0; q < A->part_N.size(); ++q) {
       const int o = A->part_off[q];
@@ -450,15 +511,17 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, cons
   });
 }
 
-hssx_status hssx_analyze(int N, int leaf_size, int beta, hssx_fact *P_out) {
+hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_out) {
   return guarded([&] {
-    HSSX_CHECK(P_out && N >= 2 && N <= 46000 && leaf_size >= 1 && beta >= 1, HSSX_EINVAL,
-               "invalid argument");
+    HSSX_CHECK(P_out && N >= 2 && (dofs == 1 || dofs == 2) && (long)N * N * dofs < (1L << 31) &&
+                   leaf_size >= dofs && beta >= dofs,
+               HSSX_EINVAL, "invalid argument");
     *P_out = nullptr;
     auto P = std::make_unique<hssx_fact_>();
     P->leaf = leaf_size;
     P->opts.beta = beta;
-    P->sym = build_symbolic(N, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()));
+    P->sym = build_symbolic(N, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()),
+                            dofs);
     *P_out = P.release();
   });
 }

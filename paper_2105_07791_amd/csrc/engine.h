@@ -14,6 +14,7 @@ struct hssx_op_ {
   int N = 0;          // grid side (0 for a batch of problems)
   double omega = 0;
   int n = 0;
+  int dofs = 1;       // unknowns per grid node (2 for the elastic operator)
   long nnz = 0;
   hssx::DevBuf rowptr, col, val, mval, s;
   std::vector<int> h_rowptr, h_col;

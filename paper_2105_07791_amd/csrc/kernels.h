@@ -10,10 +10,15 @@ namespace hssx {
 // ------------------------------------------------------------ FEM / SpMV
 void launch_assemble(int N, double omega, const double *s, const int *rowptr, const int *col,
                      c128 *val, double *mval, hipStream_t st);
+// elastic operator on DOFs 2 v + c (pattern: 2 x 2 blocks of the 7-point node stencil)
+void launch_assemble_elastic(int N, double omega, const double *lam, const double *mu,
+                             const double *rho, const int *rowptr, const int *col, c128 *val,
+                             double *mval, hipStream_t st);
 void launch_load(int n, int nrhs, const int *rowptr, const int *col, const double *mval,
                  const double *f, long ldf, c128 *b, long ldb, hipStream_t st);
+// row_max: longest row (7 for the scalar stencil, 14 for 2 x 2 blocks)
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
-                 const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st);
+                 const c128 *x, long ldx, c128 *y, long ldy, int row_max, hipStream_t st);
 void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
                  const c128 *x, long ld, double *grad, hipStream_t st);
 

@@ -140,6 +140,110 @@ __global__ void assemble_kernel(int N, double omega, const double *__restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- elastic
+// Time-harmonic P1 elasticity (DOF 2 v + c): A = K[lam, mu] - omega^2 M[rho]
+// - i omega C with the Lysmer-Kuhlemeyer boundary term.  Per triangle and
+// local vertices a, b, components i, j:
+//   K = lam_T g_a[i] g_b[j] + mu_T (delta_ij g_a.g_b + g_a[j] g_b[i]),
+//   lam_T, mu_T = area times the vertex mean; M = delta_ij 2|T| sum_l rho_l
+//   int l_l l_a l_b; on boundary edges C = delta_ij h sum_l z_l int l_l l_a l_b
+//   with z = rho c_p for the normal component and rho c_s for the tangential.
+__device__ void tri_terms_el(int N, double h, const Tri &T, int a, int i, int b, int j,
+                             const double *lam, const double *mu, const double *rho,
+                             double &k, double &m, double &m1) {
+  double px[3], py[3];
+  for (int q = 0; q < 3; ++q) {
+    px[q] = (double)(T.v[q] % N) * h;
+    py[q] = (double)(T.v[q] / N) * h;
+  }
+  double det = (px[1] - px[0]) * (py[2] - py[0]) - (py[1] - py[0]) * (px[2] - px[0]);
+  double area = 0.5 * fabs(det);
+  double ga[2], gb[2];
+  ga[0] = (py[(a + 2) % 3] - py[(a + 1) % 3]) / det;
+  ga[1] = -(px[(a + 2) % 3] - px[(a + 1) % 3]) / det;
+  gb[0] = (py[(b + 2) % 3] - py[(b + 1) % 3]) / det;
+  gb[1] = -(px[(b + 2) % 3] - px[(b + 1) % 3]) / det;
+  const double lt = (lam[T.v[0]] + lam[T.v[1]] + lam[T.v[2]]) / 3.0 * area;
+  const double mt = (mu[T.v[0]] + mu[T.v[1]] + mu[T.v[2]]) / 3.0 * area;
+  const double gg = ga[0] * gb[0] + ga[1] * gb[1];
+  k = lt * ga[i] * gb[j] + mt * ((i == j ? gg : 0.0) + ga[j] * gb[i]);
+  m = 0.0;
+  m1 = 0.0;
+  if (i == j) {
+    double acc = 0.0;
+    for (int l = 0; l < 3; ++l) acc += rho[T.v[l]] * tri3(l, a, b);
+    m = 2.0 * area * acc;
+    m1 = 2.0 * area * (a == b ? 1.0 / 12.0 : 1.0 / 24.0);
+  }
+}
+
+// boundary term of the DOF pair (gi, ci), (gj, cj): nonzero for ci == cj only
+__device__ double edge_terms_el(int N, double h, int gi, int gj, int c, const double *lam,
+                                const double *mu, const double *rho) {
+  int xi = gi % N, yi = gi / N;
+  double acc = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    int along;
+    bool on;
+    if (q == 0) { on = yi == 0; along = xi; }
+    else if (q == 1) { on = xi == N - 1; along = yi; }
+    else if (q == 2) { on = yi == N - 1; along = xi; }
+    else { on = xi == 0; along = yi; }
+    if (!on) continue;
+    // normal component: y on the south/north sides, x on east/west
+    const bool normal = (q == 0 || q == 2) ? c == 1 : c == 0;
+    for (int e = along - 1; e <= along; ++e) {
+      if (e < 0 || e >= N - 1) continue;
+      int u, v;
+      side_edge(N, q, e, u, v);
+      bool hi_ = (u == gi || v == gi), hj = (u == gj || v == gj);
+      if (!(hi_ && hj)) continue;
+      int a = (u == gi) ? 0 : 1, b = (u == gj) ? 0 : 1;
+      const double zu = normal ? sqrt(rho[u] * (lam[u] + 2.0 * mu[u])) : sqrt(rho[u] * mu[u]);
+      const double zv = normal ? sqrt(rho[v] * (lam[v] + 2.0 * mu[v])) : sqrt(rho[v] * mu[v]);
+      double t0 = (0 == a && a == b) ? 0.25 : 1.0 / 12.0;
+      double t1 = (1 == a && a == b) ? 0.25 : 1.0 / 12.0;
+      acc += h * (zu * t0 + zv * t1);
+    }
+  }
+  return acc;
+}
+
+__global__ void assemble_elastic_kernel(int N, double omega, const double *__restrict__ lam,
+                                        const double *__restrict__ mu,
+                                        const double *__restrict__ rho,
+                                        const int *__restrict__ rowptr,
+                                        const int *__restrict__ col, c128 *__restrict__ val,
+                                        double *__restrict__ mval) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 2 * N * N) return;
+  double h = 1.0 / (N - 1);
+  for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+    // the ordered DOF pair (lo, hi): bitwise symmetric, no atomics
+    const int lo = min(r, col[p]), hi = max(r, col[p]);
+    const int vl = lo / 2, il = lo % 2, vh = hi / 2, ih = hi % 2;
+    const int xl = vl % N, yl = vl / N;
+    double k = 0.0, m = 0.0, m1 = 0.0;
+    for (int cy = yl - 1; cy <= yl; ++cy)
+      for (int cx = xl - 1; cx <= xl; ++cx) {
+        if (cx < 0 || cy < 0 || cx >= N - 1 || cy >= N - 1) continue;
+        for (int t = 0; t < 2; ++t) {
+          Tri T = cell_tri(N, cx, cy, t);
+          int a = local_index(T, vl), b = local_index(T, vh);
+          if (a < 0 || b < 0) continue;
+          double kk, mm, mm1;
+          tri_terms_el(N, h, T, a, il, b, ih, lam, mu, rho, kk, mm, mm1);
+          k += kk;
+          m += mm;
+          m1 += mm1;
+        }
+      }
+    double g = il == ih ? edge_terms_el(N, h, vl, vh, il, lam, mu, rho) : 0.0;
+    val[p] = mk(k - omega * omega * m, -omega * g);
+    mval[p] = m1;
+  }
+}
+
 // b = M[1] f  (f real n x nrhs, b complex)
 __global__ void load_kernel(int n, int nrhs, const int *__restrict__ rowptr,
                             const int *__restrict__ col, const double *__restrict__ mval,
@@ -155,6 +259,9 @@ __global__ void load_kernel(int n, int nrhs, const int *__restrict__ rowptr,
 // One thread per row: the row's <= 7 entries are read once and reused for
 // every right-hand side; for a fixed rhs a wavefront touches consecutive rows,
 // so x and y accesses stay coalesced.
+// One row per thread, the row's W (7: scalar stencil, 14: 2 x 2 blocks)
+// entries held in registers across the right-hand sides.
+template <int W>
 __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *__restrict__ rowptr,
                                                    const int *__restrict__ col,
                                                    const c128 *__restrict__ val,
@@ -163,16 +270,18 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *_
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int p0 = rowptr[i], cnt = rowptr[i + 1] - p0;
-  int cj[7];
-  c128 a[7];
-  for (int q = 0; q < 7; ++q) {
+  int cj[W];
+  c128 a[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
     cj[q] = q < cnt ? col[p0 + q] : i;
     a[q] = q < cnt ? val[p0 + q] : czero<double>();
   }
   for (int r = 0; r < nrhs; ++r) {
     const c128 *xr = x + r * ldx;
     c128 acc = czero<double>();
-    for (int q = 0; q < 7; ++q) cfma(acc, a[q], xr[cj[q]]);
+#pragma unroll
+    for (int q = 0; q < W; ++q) cfma(acc, a[q], xr[cj[q]]);
     y[i + r * ldy] = acc;
   }
 }
@@ -248,6 +357,15 @@ void launch_assemble(int N, double omega, const double *s, const int *rowptr, co
   HSSX_HIP(hipGetLastError());
 }
 
+void launch_assemble_elastic(int N, double omega, const double *lam, const double *mu,
+                             const double *rho, const int *rowptr, const int *col, c128 *val,
+                             double *mval, hipStream_t st) {
+  int n = 2 * N * N;
+  hipLaunchKernelGGL(assemble_elastic_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, N, omega,
+                     lam, mu, rho, rowptr, col, val, mval);
+  HSSX_HIP(hipGetLastError());
+}
+
 void launch_load(int n, int nrhs, const int *rowptr, const int *col, const double *mval,
                  const double *f, long ldf, c128 *b, long ldb, hipStream_t st) {
   long tot = (long)n * nrhs;
@@ -257,9 +375,15 @@ void launch_load(int n, int nrhs, const int *rowptr, const int *col, const doubl
 }
 
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
-                 const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st) {
-  hipLaunchKernelGGL(spmv_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs, rowptr,
-                     col, val, x, ldx, y, ldy);
+                 const c128 *x, long ldx, c128 *y, long ldy, int row_max, hipStream_t st) {
+  if (row_max <= 7)
+    hipLaunchKernelGGL(spmv_kernel<7>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs, rowptr,
+                       col, val, x, ldx, y, ldy);
+  else if (row_max <= 14)
+    hipLaunchKernelGGL(spmv_kernel<14>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs,
+                       rowptr, col, val, x, ldx, y, ldy);
+  else
+    throw Error(HSSX_EINVAL, "rows longer than 14 entries");
   HSSX_HIP(hipGetLastError());
 }
 

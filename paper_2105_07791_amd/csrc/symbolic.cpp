@@ -11,6 +11,8 @@
 // P0 = Bd \ Bd(parent) from P1 = Bd n Bd(parent) (Fig. 4); each part is
 // bisected geometrically (axis of larger extent, x on ties; order by axis
 // coordinate then the other coordinate; split at count/2) down to <= beta.
+// Vector problems (dofs unknowns per node) apply the same rules on nodes with
+// sizes counted in DOFs; every node's components stay consecutive.
 #include "symbolic.h"
 
 #include <algorithm>
@@ -121,18 +123,23 @@ template <typename F> void parallel_for(int n, int threads, F fn) {
 
 }  // namespace
 
-Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads) {
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
   Symbolic s;
   s.N = N;
   s.leaf_dofs = leaf_dofs;
   s.beta = beta;
+  s.dofs = dofs;
   auto &nodes = s.nodes;
+  // boxes and clusters are formed on grid nodes with sizes counted in DOFs:
+  // nx ny dofs > leaf_dofs  <=>  nx ny > leaf_dofs / dofs (integer division)
+  const int leaf_nodes = leaf_dofs / dofs;
+  beta = beta / dofs;
 
   std::function<int(int, int, int, int, int)> rec = [&](int x0, int x1, int y0, int y1, int depth) {
     NDNode b;
     b.x0 = x0; b.x1 = x1; b.y0 = y0; b.y1 = y1; b.depth = depth;
     int nx = x1 - x0, ny = y1 - y0;
-    if ((long)nx * ny > leaf_dofs) {
+    if ((long)nx * ny > leaf_nodes) {
       int lo, hi;
       if (nx >= ny) {
         int xm = x0 + nx / 2;
@@ -199,12 +206,32 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads) {
     }
   });
 
-  s.perm.reserve((size_t)N * N);
+  // node lists -> DOF lists (DOF id = dofs * node + component)
+  if (dofs > 1) {
+    parallel_for(nn, threads, [&](int k) {
+      auto &b = nodes[k];
+      auto ex = [dofs](std::vector<int> &v) {
+        std::vector<int> o;
+        o.reserve(v.size() * dofs);
+        for (int x : v)
+          for (int c = 0; c < dofs; ++c) o.push_back(dofs * x + c);
+        v.swap(o);
+      };
+      ex(b.I);
+      ex(b.B);
+      b.p0 *= dofs;
+      for (auto &x : b.ct.start) x *= dofs;
+      for (auto &x : b.ct.size) x *= dofs;
+    });
+  }
+  for (auto &b : nodes) std::vector<int>().swap(b.bd);   // only needed above
+  const size_t n = (size_t)N * N * dofs;
+  s.perm.reserve(n);
   for (auto &b : nodes) {
     b.offset = (int)s.perm.size();
     s.perm.insert(s.perm.end(), b.I.begin(), b.I.end());
   }
-  s.iperm.assign((size_t)N * N, -1);
+  s.iperm.assign(n, -1);
   for (size_t k = 0; k < s.perm.size(); ++k) s.iperm[s.perm[k]] = (int)k;
   s.part_nodes = {0, (int)nodes.size()};
   return s;

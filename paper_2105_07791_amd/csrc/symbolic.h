@@ -34,7 +34,7 @@ struct NDNode {
 };
 
 struct Symbolic {
-  int N = 0, leaf_dofs = 0, beta = 0;
+  int N = 0, leaf_dofs = 0, beta = 0, dofs = 1;
   std::vector<NDNode> nodes;   // post-order; root last
   std::vector<int> perm;       // perm[k] = node id eliminated at position k
   std::vector<int> iperm;      // iperm[node id] = position
@@ -44,8 +44,10 @@ struct Symbolic {
 };
 
 // threads: host threads for the per-node work (boundary sets, cluster
-// trees, interiors); the result does not depend on it
-Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads = 1);
+// trees, interiors); the result does not depend on it.  dofs: unknowns per
+// grid node (1 scalar, 2 for the elastic operator); I, B, perm and the
+// cluster ranges are then DOF lists (DOF id = dofs * node + component).
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads = 1, int dofs = 1);
 
 // Forest of independent problems: the trees of `parts` side by side, with
 // node ids, DOF ids and permutation positions shifted so that part p's DOFs

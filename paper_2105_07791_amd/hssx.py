@@ -12,7 +12,7 @@ from . import _lib
 from ._lib import check, lib
 from .symbolic import read_perm, read_tree
 
-__all__ = ["Operator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"]
+__all__ = ["Operator", "ElasticOperator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"]
 
 
 def _stream(stream=None):
@@ -93,6 +93,27 @@ class Operator(_OperatorBase):
         desc = _lib.ProblemDesc(N, float(omega))
         check(lib().hssx_assemble(device, C.byref(desc), C.c_void_p(s.data_ptr()),
                                   _stream(stream), C.byref(h)))
+        self.handle = h
+
+
+class ElasticOperator(_OperatorBase):
+    """A = K[lam, mu] - omega^2 M[rho] - i omega C on the N x N P1 grid,
+    2 unknowns per node (DOF 2 * node + component)."""
+    parts = 1
+
+    def __init__(self, N, omega, lam, mu, rho, device=0, stream=None):
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64,  # noqa: E731
+                                      device=f"cuda:{device}").contiguous()
+        lam, mu, rho = t(lam), t(mu), t(rho)
+        assert lam.numel() == mu.numel() == rho.numel() == N * N
+        self.N, self.omega, self.n, self.device = N, float(omega), 2 * N * N, device
+        self.fields = (lam, mu, rho)
+        self.part_off = [0, self.n]
+        h = C.c_void_p()
+        desc = _lib.ProblemDesc(N, float(omega))
+        check(lib().hssx_assemble_elastic(device, C.byref(desc), C.c_void_p(lam.data_ptr()),
+                                          C.c_void_p(mu.data_ptr()), C.c_void_p(rho.data_ptr()),
+                                          _stream(stream), C.byref(h)))
         self.handle = h
 
 

@@ -32,12 +32,12 @@ def read_tree(handle):
 
 
 class Analysis:
-    """Symbolic analysis of an N x N grid (hssx_analyze)."""
+    """Symbolic analysis of an N x N grid with `dofs` unknowns per node (hssx_analyze)."""
 
-    def __init__(self, N, leaf_size=32, beta=16):
-        self.N, self.n = N, N * N
+    def __init__(self, N, leaf_size=32, beta=16, dofs=1):
+        self.N, self.n, self.dofs = N, N * N * dofs, dofs
         h = C.c_void_p()
-        check(lib().hssx_analyze(int(N), int(leaf_size), int(beta), C.byref(h)))
+        check(lib().hssx_analyze(int(N), int(dofs), int(leaf_size), int(beta), C.byref(h)))
         self.handle = h
 
     def __del__(self):

@@ -30,12 +30,15 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-@pytest.mark.parametrize("N,leaf,beta", [(9, 8, 4), (17, 32, 16), (40, 20, 8), (65, 32, 16),
-                                         (100, 32, 16), (129, 24, 12), (513, 32, 16)])
-def test_symbolic_bit_exact(N, leaf, beta):
+@pytest.mark.parametrize("N,leaf,beta,dofs", [(9, 8, 4, 1), (17, 32, 16, 1), (40, 20, 8, 1),
+                                              (65, 32, 16, 1), (100, 32, 16, 1),
+                                              (129, 24, 12, 1), (513, 32, 16, 1),
+                                              (9, 8, 4, 2), (33, 33, 17, 2), (64, 32, 16, 2),
+                                              (101, 48, 24, 2)])
+def test_symbolic_bit_exact(N, leaf, beta, dofs):
     from paper_2105_07791_amd.symbolic import Analysis
-    an = Analysis(N, leaf, beta)
-    t = nd.build_nd(N, leaf, beta)
+    an = Analysis(N, leaf, beta, dofs=dofs)
+    t = nd.build_nd(N, leaf, beta, dofs=dofs)
     assert np.array_equal(an.perm(), t.perm)
     tr = an.tree()
     assert tr["info"].shape[0] == len(t.boxes)
@@ -56,6 +59,8 @@ def test_invalid_arguments_rejected():
     from paper_2105_07791_amd import _lib
     L = _lib.lib()
     h = ctypes.c_void_p()
-    assert L.hssx_analyze(1, 32, 16, ctypes.byref(h)) == -1
+    assert L.hssx_analyze(1, 1, 32, 16, ctypes.byref(h)) == -1
     assert b"invalid" in L.hssx_last_error()
-    assert L.hssx_analyze(9, 0, 16, ctypes.byref(h)) == -1
+    assert L.hssx_analyze(9, 1, 0, 16, ctypes.byref(h)) == -1
+    assert L.hssx_analyze(9, 2, 1, 16, ctypes.byref(h)) == -1
+    assert L.hssx_analyze(9, 3, 32, 16, ctypes.byref(h)) == -1
