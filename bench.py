@@ -16,6 +16,12 @@ of the dominant kernel from HIP events, and the oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
+With --workload elastic_p1_1025 the operator is the time-harmonic P1 elastic
+one on a 1025 x 1025 node grid (2,101,250 DOFs, omega = 60, smooth seeded Lame
+fields, density 1, absorbing traction, one vertical Gaussian body force); ND
+leaves <= 64 DOFs, HSS leaves 32, HSS tolerance 1e-6, complex64 factors.  The
+oracle line then times a coarser member of the same family (N = 513).
+
 With --workload helmholtz_p1_batch256 (or a smaller batch) one step is the
 batching form instead: 256 independent problems of uneven sizes (grids of
 65..513 nodes per side, about 27M DOFs in total, each with its own seeded speed
@@ -46,16 +52,27 @@ KERNELS = ["front_eliminate", "front_assemble", "compress_level", "hss_matvec", 
 BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "apply_graph", "spmv"}
 
 
+#: elastic workloads too large for the oracle within the time budget are
+#: sampled on a smaller grid of the same family
+ELASTIC_CPU_SAMPLE = {"elastic_p1_1025": "elastic_p1_513"}
+
+
 def cpu_baseline_child(workload):
     """Oracle (exact nested-dissection factor + solve of all right-hand sides)
-    on the same workload; prints a JSON line."""
+    on the same workload, or on its smaller sample; prints a JSON line."""
     import numpy as np
     from oracle import exact, fem, nd
-    from synth import make_problem
-    pr = make_problem(workload)
-    A = fem.assemble_helmholtz(pr.N, pr.omega, pr.slowness)
-    t = nd.build_nd(pr.N, pr.leaf_dofs, pr.beta)
-    b = (fem.mass_matrix(pr.N) @ pr.f).astype(np.complex128)
+    from synth import ELASTIC, make_elastic, make_problem
+    if workload in ELASTIC:
+        pr = make_elastic(ELASTIC_CPU_SAMPLE.get(workload, workload))
+        A = fem.assemble_elastic(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
+        t = nd.build_nd(pr.N, pr.leaf_dofs, pr.beta, dofs=2)
+        b = (fem.mass_matrix_vec(pr.N) @ pr.f).astype(np.complex128)
+    else:
+        pr = make_problem(workload)
+        A = fem.assemble_helmholtz(pr.N, pr.omega, pr.slowness)
+        t = nd.build_nd(pr.N, pr.leaf_dofs, pr.beta)
+        b = (fem.mass_matrix(pr.N) @ pr.f).astype(np.complex128)
     from threadpoolctl import threadpool_info, threadpool_limits
     with threadpool_limits(limits=1):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
@@ -73,7 +90,8 @@ def cpu_baseline_child(workload):
                 break
     except OSError:
         pass
-    print(json.dumps({"seconds": t1 - t0, "true_res": res, "threads": threads, "cpu": cpu}))
+    print(json.dumps({"seconds": t1 - t0, "true_res": res, "threads": threads, "cpu": cpu,
+                      "n": int(A.shape[0]), "N": pr.N}))
 
 
 def run_cpu_baseline(workload):
@@ -85,6 +103,18 @@ def run_cpu_baseline(workload):
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
+    if workload in ELASTIC_CPU_SAMPLE:
+        from synth import ELASTIC
+        n_full = 2 * ELASTIC[workload]["N"] ** 2
+        return {"value": d["seconds"], "unit": "s", "cores": d["threads"], "kind": "oracle",
+                "sample": f"{ELASTIC_CPU_SAMPLE[workload]} (N={d['N']}, n={d['n']}, same "
+                          f"family, not the full {workload}): exact nested-dissection "
+                          f"factorization (no compression) + solve, float64, "
+                          f"{d['threads']} thread(s) on {d['cpu']} (true residual "
+                          f"{d['true_res']:.1e})",
+                "full_size_estimate_s": d["seconds"] * (n_full / d["n"]) ** 1.5,
+                "estimate_rule": "sample seconds x (n_full / n_sample)^1.5 (nested-dissection "
+                                 "cost in 2D)"}
     return {"value": d["seconds"], "unit": "s", "cores": d["threads"], "kind": "oracle",
             "sample": f"full {workload}: exact nested-dissection factorization (no compression) "
                       f"+ solve of all right-hand sides, float64, {d['threads']} thread(s) on "
@@ -305,11 +335,16 @@ def main():
     import ctypes
     import torch
     from paper_2105_07791_amd import _lib, hssx
-    from synth import make_problem
+    from synth import ELASTIC, make_elastic, make_problem
 
-    pr = make_problem(args.workload)
     dev = torch.device("cuda:0")
-    A = hssx.Operator(pr.N, pr.omega, pr.slowness)
+    elastic = args.workload in ELASTIC
+    if elastic:
+        pr = make_elastic(args.workload, device=dev)
+        A = hssx.ElasticOperator(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
+    else:
+        pr = make_problem(args.workload)
+        A = hssx.Operator(pr.N, pr.omega, pr.slowness)
     b = A.load(torch.tensor(pr.f, device=dev))
     torch.cuda.synchronize()
     L = _lib.lib()
@@ -441,6 +476,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "c64 factor / f64 Krylov",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": pr.N, "n": pr.n, "omega": pr.omega,
+                   "operator": "P1 elastic, 2 DOFs per node" if elastic else "P1 Helmholtz",
                    "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": tol_mixed,
                    "nd_leaf_dofs": pr.leaf_dofs, "hss_leaf": pr.beta, "h_sw": pr.h_sw,
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},

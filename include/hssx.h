@@ -192,7 +192,12 @@ hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col,
  * A.1, relative tolerance tol, eq. 2.7), and the HSS-class interior blocks
  * handled by the 2x2 block inverse of Algorithms 3.2/3.3.  With dtype
  * HSSX_C64 every front is stored and eliminated in complex64 except the
- * roots (top separators), which stay complex128.  A batch operator gets one
+ * roots (top separators), which stay complex128.  The rank of a compression
+ * grows by r per round until its estimate meets tol; it also stops, and the
+ * estimate is reported in max_estimate, at max_rounds, at the sample or
+ * local-block capacity (2 (k + r) > 1024 rows), and, for complex64 fronts,
+ * when the estimate is within 10 tol and a round no longer halves it (the
+ * rounding-noise floor of single precision).  A batch operator gets one
  * tree per problem, all processed depth by depth in the same launches.
  * Host-blocking: synchronises stream after every batch of compressions to
  * read the error estimates.  opts may be NULL (defaults). */

@@ -42,7 +42,7 @@ template <typename T> struct CompressTask {
   int ldT = 0;
   // state / results
   int k = 0, s = 0, rounds = 0, cap = 0;
-  double est = 0;
+  double est = 0, est_prev = 0;
   int maxrank = 0;
   bool done = false;
   long ooff = 0, yoff = 0;
@@ -110,6 +110,11 @@ inline double compress_flops(const HssCluster &c, const HssInstance &I) {
   f += 4.0 * (rows - k) * k * k + 8.0 * k * rows * s;         // T and U^T Omega
   return f;
 }
+
+// rows of one local sample block the compression kernel holds
+constexpr int kMaxLocalRows = 1024;
+// acceptance slack of a stalled complex64 estimate, relative to tol
+constexpr double kStallSlack = 10.0;
 
 template <typename T>
 void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts &o, double tol,
@@ -192,7 +197,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       for (auto &c : L.cl) c.W += lev_scr[c.level];
       for (size_t l = 0; l < L.level_scratch.size(); ++l) lev_scr[l] += L.level_scratch[l];
       for (const auto &c : L.cl)
-        HSSX_CHECK(c.rows_cap <= 1024, HSSX_EINVAL,
+        HSSX_CHECK(c.rows_cap <= kMaxLocalRows, HSSX_EINVAL,
                    "local sample block taller than the compression kernel holds");
       HssInstance h{};
       h.m = t.m;
@@ -312,13 +317,21 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       auto &t = tasks[active[a]];
       t.rounds += 1;
       double e2 = h_err[2 * active[a]], r2 = h_err[2 * active[a] + 1];
+      t.est_prev = t.est;
       t.est = r2 > 0 ? std::sqrt(e2 / r2) : 0.0;
       int mr = 0;
       for (int c = 0; c < t.ct.count(); ++c) mr = std::max(mr, h_rank[inst[a].cl_off + c]);
       t.maxrank = mr;
-      // growing needs room for the next round's probes: columns [s + r, s + 2r)
+      // growing needs room for the next round's probes: columns [s + r, s + 2r),
+      // and local blocks of at most 2 (k + r) rows
       bool accept = t.est <= tol || t.k >= t.m || t.rounds >= o.max_rounds ||
-                    t.s + 2 * r > t.cap;
+                    t.s + 2 * r > t.cap || 2 * (t.k + r) > kMaxLocalRows;
+      // complex64 fronts carry rounding noise of relative size ~ eps_fp32
+      // sqrt(m): once the estimate sits within kStallSlack of tol and another
+      // r columns no longer halve it, the rank is chasing that noise
+      if (sizeof(T) == sizeof(float) && t.rounds >= 2 && t.est <= kStallSlack * tol &&
+          t.est > 0.5 * t.est_prev)
+        accept = true;
       if (!accept) {
         t.k += r;
         t.s += r;

@@ -227,6 +227,8 @@ class ElasticProblem:
     beta: int = 32
     tol: float = 1e-6
     h_sw: int = 4
+    gmres_m: int = 50
+    gmres_tol: float = 1e-8
     factor_dtype: str = "c64"
 
     @property
@@ -244,6 +246,9 @@ ELASTIC = {
     "elastic_p1_33": dict(N=33, omega=6.0, seed=2, nsrc=2),
     "elastic_p1_65": dict(N=65, omega=12.0, seed=4, nsrc=2),
     "elastic_p1_129": dict(N=129, omega=20.0, seed=6, nsrc=2),
+    # coarser members of the 1025 family (omega scaled with N - 1)
+    "elastic_p1_257": dict(N=257, omega=15.0, seed=0, nsrc=1),
+    "elastic_p1_513": dict(N=513, omega=30.0, seed=0, nsrc=1),
 }
 
 
