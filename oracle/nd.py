@@ -31,12 +31,15 @@ Rules (Sec. 3.1 Def. 3.1 and Fig. 3; Sec. 3.2 Fig. 4; Sec. 3.3):
 * With several unknowns per node (vector problems) every node contributes its
   components consecutively (DOF id = dofs * node + component); boxes and
   clusters are formed on nodes with sizes counted in DOFs.
+* Discontinuous Galerkin (build_nd_dg): the same rules with boxes over mesh
+  cells and whole triangles as the units (Sec. 3.3, Fig. 5 left), adjacency
+  across faces, and the triangle centroids as cluster coordinates.
 """
 from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Box", "ClusterTree", "NDTree", "build_nd", "grid_pattern"]
+__all__ = ["Box", "ClusterTree", "NDTree", "build_nd", "build_nd_dg", "grid_pattern", "dg_pattern"]
 
 
 def grid_pattern(N):
@@ -107,29 +110,29 @@ class _CNode:
         self.ids, self.left, self.right = ids, left, right
 
 
-def _bisect(nodes, N, beta, dofs):
-    """Recursive geometric bisection of a node-id array into clusters."""
-    if nodes.size * dofs <= beta:
-        return _CNode(ids=nodes)
-    x = nodes % N
-    y = nodes // N
+def _bisect(units, coords, beta, dofs):
+    """Recursive geometric bisection of a unit-id array into clusters;
+    coords(ids) gives integer (x, y) per unit."""
+    if units.size * dofs <= beta:
+        return _CNode(ids=units)
+    x, y = coords(units)
     if (x.max() - x.min()) >= (y.max() - y.min()):
-        order = np.lexsort((nodes, y, x))     # primary x, then y, then id
+        order = np.lexsort((units, y, x))     # primary x, then y, then id
     else:
-        order = np.lexsort((nodes, x, y))     # primary y, then x, then id
-    s = nodes[order]
+        order = np.lexsort((units, x, y))     # primary y, then x, then id
+    s = units[order]
     h = s.size // 2
-    return _CNode(left=_bisect(s[:h], N, beta, dofs),
-                  right=_bisect(s[h:], N, beta, dofs))
+    return _CNode(left=_bisect(s[:h], coords, beta, dofs),
+                  right=_bisect(s[h:], coords, beta, dofs))
 
 
-def _cluster_tree(parts, N, beta, dofs):
+def _cluster_tree(parts, coords, beta, dofs):
     """Cluster tree (level order) and the leaf order of the listed parts.
 
-    parts: list of node-id arrays (P0, P1); empty parts are dropped.  With two
+    parts: list of unit-id arrays (P0, P1); empty parts are dropped.  With two
     non-empty parts the root splits them; otherwise the root is the single
     part's bisection."""
-    subs = [_bisect(p, N, beta, dofs) for p in parts if p.size > 0]
+    subs = [_bisect(p, coords, beta, dofs) for p in parts if p.size > 0]
     empty = np.zeros(0, dtype=np.int64)
     if not subs:
         return ClusterTree(empty, empty, empty, empty, empty), empty
@@ -194,14 +197,79 @@ class NDTree:
 
 
 def build_nd(N, leaf_dofs=32, beta=16, dofs=1):
+    """Nested dissection of the N x N node grid of the continuous P1 mesh;
+    `dofs` unknowns per node (DOF id = dofs * node + component)."""
     indptr, indices = grid_pattern(N)
-    n = N * N
+
+    def units_in(b):
+        xs = np.arange(b.x0, b.x1)
+        ys = np.arange(b.y0, b.y1)
+        return (ys[:, None] * N + xs[None, :]).ravel()      # sorted ids
+
+    coords = lambda u: (u % N, u // N)  # noqa: E731
+    return _build(N, N * N, 1, dofs, leaf_dofs, beta, units_in, indptr, indices, coords)
+
+
+def dg_pattern(Nc):
+    """Face adjacency of the triangles of the Nc x Nc cell mesh (element id
+    2 (j Nc + i) + t, t = 0 lower, 1 upper), including the diagonal: lower
+    (i,j) meets upper (i,j), upper (i,j-1) across its south edge and upper
+    (i+1,j) across its east edge."""
+    ne = 2 * Nc * Nc
+    r, c = [np.arange(ne)], [np.arange(ne)]
+    j, i = np.meshgrid(np.arange(Nc), np.arange(Nc), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    lo = 2 * (j * Nc + i)
+    pairs = [(lo, lo + 1)]
+    m = j > 0
+    pairs.append((lo[m], 2 * ((j[m] - 1) * Nc + i[m]) + 1))
+    m = i < Nc - 1
+    pairs.append((lo[m], 2 * (j[m] * Nc + i[m] + 1) + 1))
+    for a, b in pairs:
+        r += [a, b]
+        c += [b, a]
+    r, c = np.concatenate(r), np.concatenate(c)
+    key = np.unique(r * ne + c)
+    rows, cols = key // ne, key % ne
+    indptr = np.zeros(ne + 1, dtype=np.int64)
+    np.add.at(indptr, rows + 1, 1)
+    return np.cumsum(indptr), cols
+
+
+def build_nd_dg(Nc, leaf_dofs=60, beta=60, dofs=6):
+    """Nested dissection of the discontinuous mesh (Sec. 3.3, Fig. 5 left):
+    boxes are half-open cell ranges of the Nc x Nc cell grid, whole triangles
+    are the units (each cell holds two), two triangles are adjacent when they
+    share a face, and each triangle carries `dofs` unknowns (6 for P2; DOF id
+    = dofs * element + local index).  A box with nx ny 2 dofs <= leaf_dofs is
+    a leaf.  Cluster bisection uses the triangle centroids in units of h/3:
+    (3i + 2, 3j + 1) for the lower and (3i + 1, 3j + 2) for the upper
+    triangle of cell (i, j)."""
+    indptr, indices = dg_pattern(Nc)
+
+    def units_in(b):
+        xs = np.arange(b.x0, b.x1)
+        ys = np.arange(b.y0, b.y1)
+        cells = (ys[:, None] * Nc + xs[None, :]).ravel()
+        return (2 * cells[:, None] + np.arange(2)[None, :]).ravel()   # sorted ids
+
+    def coords(u):
+        cell, t = u // 2, u % 2
+        i, j = cell % Nc, cell // Nc
+        return 3 * i + 2 - t, 3 * j + 1 + t
+
+    return _build(Nc, 2 * Nc * Nc, 2, dofs, leaf_dofs, beta, units_in, indptr, indices, coords)
+
+
+def _build(G, n_units, per_cell, dofs, leaf_dofs, beta, units_in, indptr, indices, coords):
+    """Shared core: boxes over the G x G grid of nodes (CG) or cells (DG)
+    holding per_cell units each; unit adjacency from the CSR pattern."""
     boxes = []
 
     def rec(x0, x1, y0, y1, depth):
         nx, ny = x1 - x0, y1 - y0
         b = Box(x0, x1, y0, y1, depth=depth)
-        if nx * ny * dofs > leaf_dofs:
+        if nx * ny * per_cell * dofs > leaf_dofs:
             if nx >= ny:
                 xm = x0 + nx // 2
                 lo = rec(x0, xm, y0, y1, depth + 1)
@@ -219,46 +287,44 @@ def build_nd(N, leaf_dofs=32, beta=16, dofs=1):
             boxes[b.hi].parent = k
         return k
 
-    rec(0, N, 0, N, 0)
+    rec(0, G, 0, G, 0)
 
-    # Bd(sigma): nodes of the box with a structural neighbour outside the box
-    inbox = np.zeros(n, dtype=bool)
+    # Bd(sigma): units of the box with a structural neighbour outside the box
+    inbox = np.zeros(n_units, dtype=bool)
     for b in boxes:
-        xs = np.arange(b.x0, b.x1)
-        ys = np.arange(b.y0, b.y1)
-        nodes = (ys[:, None] * N + xs[None, :]).ravel()
-        inbox[nodes] = True
-        cnt = indptr[nodes + 1] - indptr[nodes]
-        rows = np.repeat(nodes, cnt)
-        first = np.repeat(indptr[nodes] - np.cumsum(cnt) + cnt, cnt)
+        units = units_in(b)
+        inbox[units] = True
+        cnt = indptr[units + 1] - indptr[units]
+        rows = np.repeat(units, cnt)
+        first = np.repeat(indptr[units] - np.cumsum(cnt) + cnt, cnt)
         nbr = indices[first + np.arange(cnt.sum())]
         outside = ~inbox[nbr]
         b.bd = np.unique(rows[outside])
-        inbox[nodes] = False
-        b._nodes = np.sort(nodes)
+        inbox[units] = False
+        b._units = np.sort(units)
 
     # B order (cluster trees) and P0 sizes; needs the parent's Bd
     for k, b in enumerate(boxes):
         if b.parent < 0:
             b.B = np.zeros(0, dtype=np.int64)
             b.p0 = 0
-            b.ctree, _ = _cluster_tree([], N, beta, dofs)
+            b.ctree, _ = _cluster_tree([], coords, beta, dofs)
             continue
         pbd = boxes[b.parent].bd
         in_pb = np.isin(b.bd, pbd)
         P0 = b.bd[~in_pb]
         P1 = b.bd[in_pb]
-        b.ctree, b.B = _cluster_tree([P0, P1], N, beta, dofs)
+        b.ctree, b.B = _cluster_tree([P0, P1], coords, beta, dofs)
         b.p0 = P0.size
 
     # I order
     for b in boxes:
         if b.is_leaf:
-            b.I = np.setdiff1d(b._nodes, b.bd)          # sorted ids = (y, x) order
+            b.I = np.setdiff1d(b._units, b.bd)          # sorted unit ids
         else:
             mu, nu = boxes[b.lo], boxes[b.hi]
             b.I = np.concatenate([mu.B[:mu.p0], nu.B[:nu.p0]])
-        del b._nodes
+        del b._units
 
     if dofs > 1:
         _expand_dofs(boxes, dofs)
@@ -267,10 +333,10 @@ def build_nd(N, leaf_dofs=32, beta=16, dofs=1):
     for b in boxes:
         b.offset = off
         off += b.I.size
-    n_dof = n * dofs
+    n_dof = n_units * dofs
     iperm = np.empty(n_dof, dtype=np.int64)
     iperm[perm] = np.arange(n_dof)
-    t = NDTree(N=N, leaf_dofs=leaf_dofs, beta=beta, dofs=dofs, boxes=boxes,
+    t = NDTree(N=G, leaf_dofs=leaf_dofs, beta=beta, dofs=dofs, boxes=boxes,
                perm=perm, iperm=iperm)
     return t
 

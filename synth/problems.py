@@ -19,7 +19,7 @@ __all__ = [
     "Problem", "node_coords", "source_centers", "gaussian_sources",
     "random_field", "speed_field", "make_problem", "CONFIGS", "make_batch", "BATCHES",
     "receiver_nodes", "batch_grid_sizes", "ElasticProblem", "lame_fields",
-    "make_elastic", "ELASTIC",
+    "make_elastic", "ELASTIC", "DGProblem", "dg_node_coords", "make_dg", "DG",
 ]
 
 
@@ -266,3 +266,84 @@ def make_elastic(name, device=None, **overrides):
     f = np.zeros((2 * N * N, nsrc))
     f[1::2] = g
     return ElasticProblem(name=name, N=N, omega=omega, lam=lam, mu=mu, rho=rho, f=f, **cfg)
+
+
+def dg_node_coords(Nc):
+    """(x, y) of the DOF nodes of the P2 discontinuous mesh: Nc x Nc cells of
+    side 1/Nc, cell (i, j) split into the lower triangle (i,j), (i+1,j),
+    (i+1,j+1) and the upper triangle (i,j), (i+1,j+1), (i,j+1); element
+    2 (j Nc + i) + t holds its three vertices, then the midpoints of its
+    edges (v0,v1), (v1,v2), (v2,v0).  Arrays of length 12 Nc^2."""
+    h = 1.0 / Nc
+    j, i = np.meshgrid(np.arange(Nc, dtype=np.float64), np.arange(Nc, dtype=np.float64),
+                       indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    lower = [(i, j), (i + 1, j), (i + 1, j + 1)]
+    upper = [(i, j), (i + 1, j + 1), (i, j + 1)]
+    out = np.empty((Nc * Nc, 2, 6, 2))
+    for t, V in enumerate((lower, upper)):
+        pts = V + [((V[0][0] + V[1][0]) / 2, (V[0][1] + V[1][1]) / 2),
+                   ((V[1][0] + V[2][0]) / 2, (V[1][1] + V[2][1]) / 2),
+                   ((V[2][0] + V[0][0]) / 2, (V[2][1] + V[0][1]) / 2)]
+        for a, (px, py) in enumerate(pts):
+            out[:, t, a, 0] = px * h
+            out[:, t, a, 1] = py * h
+    out = out.reshape(-1, 2)
+    return out[:, 0], out[:, 1]
+
+
+@dataclass
+class DGProblem:
+    """One seeded SIPG-P2 Helmholtz workload on [0,1]^2 with the absorbing
+    condition on all four sides: slowness at the (Nc+1)^2 mesh vertices,
+    sources sampled at the 12 Nc^2 DOF nodes."""
+    name: str
+    Nc: int
+    omega: float
+    slowness: np.ndarray          # ((Nc+1)^2,) vertex slowness s = 1/c
+    f: np.ndarray                 # (12 Nc^2, nrhs) nodal source samples
+    leaf_dofs: int = 60           # ND leaves of at most 10 triangles
+    beta: int = 60                # HSS leaves of 10 triangles
+    tol: float = 1e-4
+    h_sw: int = 4
+    gmres_m: int = 50
+    gmres_tol: float = 1e-8
+    factor_dtype: str = "c64"
+
+    @property
+    def n(self):
+        return 12 * self.Nc * self.Nc
+
+    @property
+    def nrhs(self):
+        return self.f.shape[1]
+
+
+#: SIPG-P2 workloads: 256 x 256 x 2 triangles (786,432 DOFs) and parity cases
+#: at the same resolution per cell (omega = 80 Nc / 256).
+DG = {
+    "sipg_p2_256": dict(Nc=256, omega=80.0, seed=0, nsrc=1),
+    "sipg_p2_8": dict(Nc=8, omega=2.5, seed=3, nsrc=2),
+    "sipg_p2_16": dict(Nc=16, omega=5.0, seed=4, nsrc=2),
+    "sipg_p2_32": dict(Nc=32, omega=10.0, seed=5, nsrc=2),
+    "sipg_p2_64": dict(Nc=64, omega=20.0, seed=6, nsrc=2),
+    "sipg_p2_128": dict(Nc=128, omega=40.0, seed=0, nsrc=1),
+}
+
+
+def make_dg(name, device=None, **overrides):
+    """The named SIPG-P2 workload: speed c = 1 + 2 sigmoid(g) (seed) at the
+    mesh vertices, Gaussian sources (width 0.02) at centres drawn with the
+    same seed, sampled at the DOF nodes.  With a torch device the speed
+    field is evaluated there (returned as a tensor)."""
+    cfg = dict(DG[name])
+    cfg.update(overrides)
+    Nc, seed, nsrc = cfg.pop("Nc"), cfg.pop("seed"), cfg.pop("nsrc")
+    omega = float(cfg.pop("omega"))
+    s = 1.0 / speed_field(Nc + 1, seed, device=device)
+    x, y = dg_node_coords(Nc)
+    centers = source_centers(seed, nsrc)
+    f = np.empty((x.size, nsrc))
+    for q, (cx, cy) in enumerate(centers):
+        f[:, q] = np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * 0.02 * 0.02))
+    return DGProblem(name=name, Nc=Nc, omega=omega, slowness=s, f=f, **cfg)
