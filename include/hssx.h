@@ -150,6 +150,25 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc,
                                   const double *rho_dev, void *stream,
                                   hssx_op *A_out);
 
+/* Build the symmetric interior-penalty DG operator with P2 elements for the
+ * Helmholtz problem (the IPDG discretization of Sec. 4.1-4.2) on desc->N x
+ * desc->N cells of side h = 1/N, each split along its SW-NE diagonal into
+ * the lower triangle (element 2 c) and the upper one (2 c + 1), c = j N + i;
+ * DOF 6 e + a over the nodal P2 basis (vertices, then edge midpoints of
+ * (v0,v1), (v1,v2), (v2,v0)).  Form: sum_T int grad u.grad v - k^2 u v, on
+ * interior faces -{grad u.n}[v] - {grad v.n}[u] + 10 p^2/|F| [u][v], and
+ * -i k u v on the absorbing boundary faces; k^2 = omega^2 times the P1
+ * interpolant of s^2, k = omega times that of s.  s_dev: device float64
+ * [(N+1)^2] slowness at the mesh vertices (vertex (i, j) at j (N+1) + i),
+ * caller-owned, read during the call.  Pattern: 6 x 6 blocks of each
+ * triangle with itself and its face neighbours, columns sorted.  Works with
+ * hssx_load (block-diagonal P2 mass), hssx_matvec, hssx_factor, hssx_apply
+ * and hssx_gmres_solve; not with hssx_dAds_contract or in batches.  EINVAL
+ * for N outside [1, 2700] (32-bit CSR offsets), a non-finite or negative
+ * omega, or null arguments. */
+hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc,
+                             const double *s_dev, void *stream, hssx_op *A_out);
+
 /* Batch of independent problems as one block-diagonal operator (the
  * batching form: fronts of one tree depth, across all problems, are
  * eliminated and compressed in the same launches, and GMRES advances every
@@ -241,6 +260,12 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev,
  * makes no HIP call, so it runs without a GPU.  The handle supports
  * hssx_get_perm, hssx_get_tree and hssx_fact_destroy only. */
 hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_out);
+
+/* Symbolic analysis of the discontinuous mesh of hssx_assemble_dg (Nc x Nc
+ * cells, whole triangles of 6 DOFs as units, Sec. 3.3 Fig. 5): boxes of cells,
+ * adjacency across faces, cluster coordinates at the triangle centroids.
+ * leaf_size and beta count DOFs (>= 6).  Host-only, as hssx_analyze. */
+hssx_status hssx_analyze_dg(int Nc, int leaf_size, int beta, hssx_fact *P_out);
 
 /* Elimination permutation (host int32[n]): perm[k] = node id eliminated at
  * position k (concatenation of I(sigma) over the post-order). */

@@ -65,6 +65,8 @@ SIGNATURES = {
                               C.POINTER(GmresStats), _vp]),
     "hssx_dAds_contract": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "hssx_analyze": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
+    "hssx_analyze_dg": (_i, [_i, _i, _i, C.POINTER(_vp)]),
+    "hssx_assemble_dg": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, C.POINTER(_vp)]),
     "hssx_get_perm": (_i, [_vp, _ip, _l]),
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),

@@ -118,6 +118,7 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc, con
     A->N = desc->N;
     A->omega = desc->omega;
     A->dofs = 2;
+    A->row_max = 14;
     const int N = desc->N, nn = N * N, n = 2 * nn;
     A->n = n;
     // 2 x 2 blocks of the 7-point node stencil, columns sorted
@@ -158,6 +159,67 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc, con
   });
 }
 
+hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const double *s_dev,
+                             void *stream, hssx_op *A_out) {
+  return guarded([&] {
+    HSSX_CHECK(desc && A_out && s_dev, HSSX_EINVAL, "null argument");
+    // 32-bit CSR offsets: nnz < 288 Nc^2 must stay below 2^31
+    HSSX_CHECK(desc->N >= 1 && desc->N <= 2700, HSSX_EINVAL, "cell count out of range");
+    HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
+    *A_out = nullptr;
+    DeviceScope ds(device);
+    hipStream_t st = S(stream);
+    auto A = std::make_unique<hssx_op_>();
+    A->device = device;
+    A->N = desc->N;
+    A->omega = desc->omega;
+    A->dofs = 6;
+    A->mesh = kMeshDG;
+    A->row_max = 24;
+    const int Nc = desc->N, ne = 2 * Nc * Nc, n = 6 * ne, nv = (Nc + 1) * (Nc + 1);
+    A->n = n;
+    // 6 x 6 blocks of each triangle with itself and its face neighbours,
+    // neighbour elements in increasing id (columns sorted)
+    A->h_rowptr.resize(n + 1);
+    A->h_col.reserve((size_t)24 * n);
+    A->h_rowptr[0] = 0;
+    for (int e = 0; e < ne; ++e) {
+      const int c = e >> 1, t = e & 1, i = c % Nc, j = c / Nc;
+      int el[4], k = 0;
+      el[k++] = e;
+      el[k++] = t == 0 ? e + 1 : e - 1;
+      if (t == 0) {
+        if (j > 0) el[k++] = 2 * ((j - 1) * Nc + i) + 1;
+        if (i < Nc - 1) el[k++] = 2 * (j * Nc + i + 1) + 1;
+      } else {
+        if (j < Nc - 1) el[k++] = 2 * ((j + 1) * Nc + i);
+        if (i > 0) el[k++] = 2 * (j * Nc + i - 1);
+      }
+      std::sort(el, el + k);
+      for (int a = 0; a < 6; ++a) {
+        for (int q = 0; q < k; ++q)
+          for (int b = 0; b < 6; ++b) A->h_col.push_back(6 * el[q] + b);
+        A->h_rowptr[6 * e + a + 1] = (int)A->h_col.size();
+      }
+    }
+    A->nnz = (long)A->h_col.size();
+    upload(A->rowptr, A->h_rowptr);
+    upload(A->col, A->h_col);
+    A->val.alloc(A->nnz * sizeof(c128));
+    A->mval.alloc(A->nnz * sizeof(double));
+    A->s.alloc((size_t)nv * sizeof(double));
+    HSSX_HIP(hipMemcpyAsync(A->s.p, s_dev, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_assemble_dg(Nc, desc->omega, A->s.as<double>(), A->rowptr.as<int>(), A->col.as<int>(),
+                       A->val.as<c128>(), A->mval.as<double>(), st);
+    A->part_N = {Nc};
+    A->part_omega = {desc->omega};
+    A->part_off = {0, n};
+    upload(A->part_off_dev, A->part_off);
+    HSSX_HIP(hipStreamSynchronize(st));
+    *A_out = A.release();
+  });
+}
+
 hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op *A_out) {
   return guarded([&] {
     HSSX_CHECK(parts && A_out && count >= 1, HSSX_EINVAL, "invalid argument");
@@ -167,7 +229,8 @@ hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op
       HSSX_CHECK(parts[q] && parts[q]->part_N.size() == 1, HSSX_EINVAL,
                  "batch parts must be single-problem operators");
       HSSX_CHECK(parts[q]->device == parts[0]->device, HSSX_EINVAL, "parts on different devices");
-      HSSX_CHECK(parts[q]->dofs == 1, HSSX_EINVAL, "batches hold scalar (Helmholtz) problems");
+      HSSX_CHECK(parts[q]->dofs == 1 && parts[q]->mesh == kMeshCG, HSSX_EINVAL,
+                 "batches hold P1 Helmholtz problems");
       n += parts[q]->n;
       nnz += parts[q]->nnz;
     }
@@ -245,7 +308,7 @@ hssx_status hssx_matvec(hssx_op A, int trans, int nrhs, const void *x_dev, long 
     (void)trans;   // A^T = A
     DeviceScope ds(A->device);
     launch_spmv(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->val.as<c128>(),
-                (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, 7 * A->dofs, S(stream));
+                (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, A->row_max, S(stream));
   });
 }
 
@@ -290,7 +353,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     auto t0 = std::chrono::steady_clock::now();
     if (A->part_N.size() == 1) {
       P->sym = build_symbolic(A->part_N[0], leaf_size, o.beta,
-                              std::min(16, (int)std::thread::hardware_concurrency()), A->dofs);
+                              std::min(16, (int)std::thread::hardware_concurrency()), A->dofs,
+                              A->mesh);
     } else {
       // the problems' analyses are independent: run them on host threads
       const int np = (int)A->part_N.size();
@@ -500,7 +564,8 @@ hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, cons
                                double *grad_dev, void *stream) {
   return guarded([&] {
     HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
-    HSSX_CHECK(A->dofs == 1, HSSX_EINVAL, "the slowness gradient is defined for Helmholtz operators");
+    HSSX_CHECK(A->dofs == 1 && A->mesh == kMeshCG, HSSX_EINVAL,
+               "the slowness gradient is defined for P1 Helmholtz operators");
     DeviceScope ds(A->device);
     for (size_t q = 0; q < A->part_N.size(); ++q) {
       const int o = A->part_off[q];
@@ -522,6 +587,20 @@ hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_
     P->opts.beta = beta;
     P->sym = build_symbolic(N, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()),
                             dofs);
+    *P_out = P.release();
+  });
+}
+
+hssx_status hssx_analyze_dg(int Nc, int leaf_size, int beta, hssx_fact *P_out) {
+  return guarded([&] {
+    HSSX_CHECK(P_out && Nc >= 1 && Nc <= 2700 && leaf_size >= 6 && beta >= 6, HSSX_EINVAL,
+               "invalid argument");
+    *P_out = nullptr;
+    auto P = std::make_unique<hssx_fact_>();
+    P->leaf = leaf_size;
+    P->opts.beta = beta;
+    P->sym = build_symbolic(Nc, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()),
+                            6, kMeshDG);
     *P_out = P.release();
   });
 }

@@ -14,7 +14,9 @@ struct hssx_op_ {
   int N = 0;          // grid side (0 for a batch of problems)
   double omega = 0;
   int n = 0;
-  int dofs = 1;       // unknowns per grid node (2 for the elastic operator)
+  int dofs = 1;       // unknowns per unit (2: elastic node, 6: P2 triangle)
+  int mesh = 0;       // hssx::kMeshCG (grid nodes) or hssx::kMeshDG (triangles)
+  int row_max = 7;    // longest CSR row (7 scalar P1, 14 elastic, 24 SIPG-P2)
   long nnz = 0;
   hssx::DevBuf rowptr, col, val, mval, s;
   std::vector<int> h_rowptr, h_col;

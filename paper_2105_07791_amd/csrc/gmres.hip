@@ -44,7 +44,7 @@ void gmres_impl(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, 
   auto matvec = [&](const c128 *in, c128 *out) {
     hipEvent_t pe = prof_begin(st);
     launch_spmv(n, nrhs, A.rowptr.as<int>(), A.col.as<int>(), A.val.as<c128>(), in, n, out, n,
-                7 * A.dofs, st);
+                A.row_max, st);
     // CSR values + column indices once, row pointers, x read and y written per rhs
     prof_end("spmv", st, pe, A.nnz * 20.0 + (n + 1) * 4.0 + 2.0 * blk * sizeof(c128));
   };

@@ -259,7 +259,8 @@ __global__ void load_kernel(int n, int nrhs, const int *__restrict__ rowptr,
 // One thread per row: the row's <= 7 entries are read once and reused for
 // every right-hand side; for a fixed rhs a wavefront touches consecutive rows,
 // so x and y accesses stay coalesced.
-// One row per thread, the row's W (7: scalar stencil, 14: 2 x 2 blocks)
+// One row per thread, the row's W (7: scalar stencil, 14: 2 x 2 blocks,
+// 24: P2 triangle blocks)
 // entries held in registers across the right-hand sides.
 template <int W>
 __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *__restrict__ rowptr,
@@ -382,8 +383,11 @@ void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 
   else if (row_max <= 14)
     hipLaunchKernelGGL(spmv_kernel<14>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs,
                        rowptr, col, val, x, ldx, y, ldy);
+  else if (row_max <= 24)
+    hipLaunchKernelGGL(spmv_kernel<24>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs,
+                       rowptr, col, val, x, ldx, y, ldy);
   else
-    throw Error(HSSX_EINVAL, "rows longer than 14 entries");
+    throw Error(HSSX_EINVAL, "rows longer than 24 entries");
   HSSX_HIP(hipGetLastError());
 }
 

@@ -13,6 +13,12 @@
 // coordinate then the other coordinate; split at count/2) down to <= beta.
 // Vector problems (dofs unknowns per node) apply the same rules on nodes with
 // sizes counted in DOFs; every node's components stay consecutive.
+// Discontinuous Galerkin meshes (Sec. 3.3, Fig. 5 left) use boxes of cells and
+// whole triangles as the units: cell (i,j) holds the lower triangle 2 c and
+// the upper triangle 2 c + 1 (c = j N + i); the lower one meets the upper one
+// of its own cell, of cell (i,j-1) across its south edge and of cell (i+1,j)
+// across its east edge.  Cluster coordinates are the triangle centroids in
+// units of h/3: (3i+2, 3j+1) lower, (3i+1, 3j+2) upper.
 #include "symbolic.h"
 
 #include <algorithm>
@@ -30,38 +36,58 @@ struct CNode {
   int start = 0, stop = 0;  // range in the leaf order
 };
 
+// Integer unit coordinates (both below M): grid nodes, or triangle
+// centroids in thirds of a cell.
+struct Coords {
+  int N, mesh;
+  int M() const { return mesh == kMeshDG ? 3 * N : N; }
+  void operator()(int u, long &x, long &y) const {
+    if (mesh == kMeshDG) {
+      const int c = u >> 1, t = u & 1;
+      x = 3L * (c % N) + 2 - t;
+      y = 3L * (c / N) + 1 + t;
+    } else {
+      x = u % N;
+      y = u / N;
+    }
+  }
+};
+
 // Geometric bisection of ids[0, n) in place; the final array is the leaf
 // order (in-order concatenation of the leaves), node ranges are offsets.
-std::unique_ptr<CNode> bisect(int *ids, int n, int offset, int N, int beta,
+std::unique_ptr<CNode> bisect(int *ids, int n, int offset, const Coords &cc, int beta,
                               std::vector<long> &key) {
   auto node = std::make_unique<CNode>();
   node->start = offset;
   node->stop = offset + n;
   if (n <= beta) return node;
-  int xmin = N, xmax = -1, ymin = N, ymax = -1;
+  const long M = cc.M();
+  long xmin = M, xmax = -1, ymin = M, ymax = -1;
   for (int k = 0; k < n; ++k) {
-    int x = ids[k] % N, y = ids[k] / N;
+    long x, y;
+    cc(ids[k], x, y);
     xmin = std::min(xmin, x); xmax = std::max(xmax, x);
     ymin = std::min(ymin, y); ymax = std::max(ymax, y);
   }
   const bool by_x = (xmax - xmin) >= (ymax - ymin);
-  // order by the split axis, then the other coordinate (unique per node)
+  // order by the split axis, then the other coordinate, then the id
   key.resize(n);
   for (int k = 0; k < n; ++k) {
-    const long x = ids[k] % N, y = ids[k] / N;
-    key[k] = by_x ? ((x * N + y) << 32 | (unsigned)ids[k]) : ((y * N + x) << 32 | (unsigned)ids[k]);
+    long x, y;
+    cc(ids[k], x, y);
+    key[k] = by_x ? ((x * M + y) << 32 | (unsigned)ids[k]) : ((y * M + x) << 32 | (unsigned)ids[k]);
   }
   std::sort(key.begin(), key.begin() + n);
   for (int k = 0; k < n; ++k) ids[k] = (int)(key[k] & 0xffffffffL);
   const int h = n / 2;
-  node->l = bisect(ids, h, offset, N, beta, key);
-  node->r = bisect(ids + h, n - h, offset + h, N, beta, key);
+  node->l = bisect(ids, h, offset, cc, beta, key);
+  node->r = bisect(ids + h, n - h, offset + h, cc, beta, key);
   return node;
 }
 
 // Level-order cluster tree + leaf order of the given parts.
 void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
-                       int N, int beta, ClusterTree &ct, std::vector<int> &order) {
+                       const Coords &cc, int beta, ClusterTree &ct, std::vector<int> &order) {
   ct = ClusterTree();
   order.clear();
   if (P0.empty() && P1.empty()) return;
@@ -74,10 +100,10 @@ void make_cluster_tree(const std::vector<int> &P0, const std::vector<int> &P1,
     root = std::make_unique<CNode>();
     root->start = 0;
     root->stop = n0 + n1;
-    root->l = bisect(order.data(), n0, 0, N, beta, key);
-    root->r = bisect(order.data() + n0, n1, n0, N, beta, key);
+    root->l = bisect(order.data(), n0, 0, cc, beta, key);
+    root->r = bisect(order.data() + n0, n1, n0, cc, beta, key);
   } else {
-    root = bisect(order.data(), n0 + n1, 0, N, beta, key);
+    root = bisect(order.data(), n0 + n1, 0, cc, beta, key);
   }
   // breadth-first numbering
   std::vector<std::pair<const CNode *, int>> q{{root.get(), 0}};
@@ -123,17 +149,21 @@ template <typename F> void parallel_for(int n, int threads, F fn) {
 
 }  // namespace
 
-Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs, int mesh) {
   Symbolic s;
   s.N = N;
   s.leaf_dofs = leaf_dofs;
   s.beta = beta;
   s.dofs = dofs;
+  s.mesh = mesh;
   auto &nodes = s.nodes;
-  // boxes and clusters are formed on grid nodes with sizes counted in DOFs:
-  // nx ny dofs > leaf_dofs  <=>  nx ny > leaf_dofs / dofs (integer division)
-  const int leaf_nodes = leaf_dofs / dofs;
+  const bool dg = mesh == kMeshDG;
+  const int per_cell = dg ? 2 : 1;   // units per box cell
+  // boxes and clusters are formed on units with sizes counted in DOFs:
+  // nx ny per_cell dofs > leaf_dofs  <=>  nx ny > leaf_dofs / (per_cell dofs)
+  const int leaf_nodes = leaf_dofs / (per_cell * dofs);
   beta = beta / dofs;
+  const Coords cc{N, mesh};
 
   std::function<int(int, int, int, int, int)> rec = [&](int x0, int x1, int y0, int y1, int depth) {
     NDNode b;
@@ -163,19 +193,27 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
 
   static const int dx[6] = {1, -1, 0, 0, 1, -1};
   static const int dy[6] = {0, 0, 1, -1, 1, -1};
+  // face neighbours of the lower (t = 0: south, east) and upper (t = 1:
+  // north, west) triangle of a cell, as cell offsets
+  static const int fx[2][2] = {{0, 1}, {0, -1}}, fy[2][2] = {{-1, 0}, {1, 0}};
   const int nn = (int)nodes.size();
-  // a node with a neighbour outside the box lies on the box's border, so
-  // only border cells are tested (row-major, so the ids come out sorted)
+  // a unit with a neighbour outside the box lies in a border cell, so only
+  // border cells are tested (row-major, so the ids come out sorted)
   parallel_for(nn, threads, [&](int k) {
     auto &b = nodes[k];
+    auto outside = [&](int u, int v) {
+      return u >= 0 && v >= 0 && u < N && v < N && (u < b.x0 || u >= b.x1 || v < b.y0 || v >= b.y1);
+    };
     for (int y = b.y0; y < b.y1; ++y)
       for (int x = b.x0; x < b.x1; x = (y == b.y0 || y == b.y1 - 1 || x == b.x1 - 1) ? x + 1 : b.x1 - 1) {
-        bool out = false;
-        for (int d = 0; d < 6 && !out; ++d) {
-          int u = x + dx[d], v = y + dy[d];
-          if (u < 0 || v < 0 || u >= N || v >= N) continue;
-          if (u < b.x0 || u >= b.x1 || v < b.y0 || v >= b.y1) out = true;
+        if (dg) {
+          for (int t = 0; t < 2; ++t)
+            if (outside(x + fx[t][0], y + fy[t][0]) || outside(x + fx[t][1], y + fy[t][1]))
+              b.bd.push_back(2 * (y * N + x) + t);
+          continue;
         }
+        bool out = false;
+        for (int d = 0; d < 6 && !out; ++d) out = outside(x + dx[d], y + dy[d]);
         if (out) b.bd.push_back(y * N + x);     // row-major scan = sorted ids
       }
   });
@@ -187,7 +225,7 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
     std::vector<int> P0, P1;
     for (int v : b.bd)
       (std::binary_search(pbd.begin(), pbd.end(), v) ? P1 : P0).push_back(v);
-    make_cluster_tree(P0, P1, N, beta, b.ct, b.B);
+    make_cluster_tree(P0, P1, cc, beta, b.ct, b.B);
     b.p0 = (int)P0.size();
   });
 
@@ -195,10 +233,11 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
     auto &b = nodes[k];
     if (b.leafnode()) {
       for (int y = b.y0; y < b.y1; ++y)
-        for (int x = b.x0; x < b.x1; ++x) {
-          int v = y * N + x;
-          if (!std::binary_search(b.bd.begin(), b.bd.end(), v)) b.I.push_back(v);
-        }
+        for (int x = b.x0; x < b.x1; ++x)
+          for (int t = 0; t < per_cell; ++t) {
+            int v = per_cell * (y * N + x) + t;
+            if (!std::binary_search(b.bd.begin(), b.bd.end(), v)) b.I.push_back(v);
+          }
     } else {
       const auto &mu = nodes[b.lo], &nu = nodes[b.hi];
       b.I.assign(mu.B.begin(), mu.B.begin() + mu.p0);
@@ -206,7 +245,7 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
     }
   });
 
-  // node lists -> DOF lists (DOF id = dofs * node + component)
+  // unit lists -> DOF lists (DOF id = dofs * unit + component)
   if (dofs > 1) {
     parallel_for(nn, threads, [&](int k) {
       auto &b = nodes[k];
@@ -225,7 +264,7 @@ Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads, int dofs) {
     });
   }
   for (auto &b : nodes) std::vector<int>().swap(b.bd);   // only needed above
-  const size_t n = (size_t)N * N * dofs;
+  const size_t n = (size_t)N * N * per_cell * dofs;
   s.perm.reserve(n);
   for (auto &b : nodes) {
     b.offset = (int)s.perm.size();

@@ -20,7 +20,7 @@ struct ClusterTree {
 };
 
 struct NDNode {
-  int x0, x1, y0, y1;        // half-open node box
+  int x0, x1, y0, y1;        // half-open box of grid nodes (CG) or cells (DG)
   int lo = -1, hi = -1;      // children (post-order ids), -1 for leaves
   int parent = -1;
   int depth = 0, height = 0;
@@ -33,8 +33,12 @@ struct NDNode {
   bool leafnode() const { return lo < 0; }
 };
 
+// meshes: continuous (units are the N x N grid nodes) or discontinuous
+// (units are the two triangles of each of N x N cells)
+constexpr int kMeshCG = 0, kMeshDG = 1;
+
 struct Symbolic {
-  int N = 0, leaf_dofs = 0, beta = 0, dofs = 1;
+  int N = 0, leaf_dofs = 0, beta = 0, dofs = 1, mesh = kMeshCG;
   std::vector<NDNode> nodes;   // post-order; root last
   std::vector<int> perm;       // perm[k] = node id eliminated at position k
   std::vector<int> iperm;      // iperm[node id] = position
@@ -45,9 +49,11 @@ struct Symbolic {
 
 // threads: host threads for the per-node work (boundary sets, cluster
 // trees, interiors); the result does not depend on it.  dofs: unknowns per
-// grid node (1 scalar, 2 for the elastic operator); I, B, perm and the
-// cluster ranges are then DOF lists (DOF id = dofs * node + component).
-Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads = 1, int dofs = 1);
+// unit (1 scalar, 2 for the elastic operator, 6 for P2 triangles); I, B, perm
+// and the cluster ranges are then DOF lists (DOF id = dofs * unit + c).
+// mesh: kMeshCG (N grid nodes per side) or kMeshDG (N cells per side).
+Symbolic build_symbolic(int N, int leaf_dofs, int beta, int threads = 1, int dofs = 1,
+                        int mesh = kMeshCG);
 
 // Forest of independent problems: the trees of `parts` side by side, with
 // node ids, DOF ids and permutation positions shifted so that part p's DOFs

@@ -12,7 +12,7 @@ from . import _lib
 from ._lib import check, lib
 from .symbolic import read_perm, read_tree
 
-__all__ = ["Operator", "ElasticOperator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"]
+__all__ = ["Operator", "ElasticOperator", "DGOperator", "BatchOperator", "Factor", "assemble", "factor", "gmres_solve"]
 
 
 def _stream(stream=None):
@@ -114,6 +114,24 @@ class ElasticOperator(_OperatorBase):
         check(lib().hssx_assemble_elastic(device, C.byref(desc), C.c_void_p(lam.data_ptr()),
                                           C.c_void_p(mu.data_ptr()), C.c_void_p(rho.data_ptr()),
                                           _stream(stream), C.byref(h)))
+        self.handle = h
+
+
+class DGOperator(_OperatorBase):
+    """SIPG-P2 Helmholtz operator on Nc x Nc x 2 triangles (DOF 6 e + a);
+    slowness given at the (Nc+1)^2 mesh vertices."""
+    parts = 1
+
+    def __init__(self, Nc, omega, slowness, device=0, stream=None):
+        s = torch.as_tensor(slowness, dtype=torch.float64, device=f"cuda:{device}").contiguous()
+        assert s.numel() == (Nc + 1) ** 2
+        self.N, self.omega, self.n, self.device = Nc, float(omega), 12 * Nc * Nc, device
+        self.slowness = s
+        self.part_off = [0, self.n]
+        h = C.c_void_p()
+        desc = _lib.ProblemDesc(Nc, float(omega))
+        check(lib().hssx_assemble_dg(device, C.byref(desc), C.c_void_p(s.data_ptr()),
+                                     _stream(stream), C.byref(h)))
         self.handle = h
 
 

@@ -32,12 +32,18 @@ def read_tree(handle):
 
 
 class Analysis:
-    """Symbolic analysis of an N x N grid with `dofs` unknowns per node (hssx_analyze)."""
+    """Symbolic analysis of an N x N grid with `dofs` unknowns per node
+    (hssx_analyze), or with dg=True of the N x N x 2 triangle mesh of the
+    SIPG-P2 operator (hssx_analyze_dg)."""
 
-    def __init__(self, N, leaf_size=32, beta=16, dofs=1):
-        self.N, self.n, self.dofs = N, N * N * dofs, dofs
+    def __init__(self, N, leaf_size=32, beta=16, dofs=1, dg=False):
         h = C.c_void_p()
-        check(lib().hssx_analyze(int(N), int(dofs), int(leaf_size), int(beta), C.byref(h)))
+        if dg:
+            self.N, self.n, self.dofs = N, 12 * N * N, 6
+            check(lib().hssx_analyze_dg(int(N), int(leaf_size), int(beta), C.byref(h)))
+        else:
+            self.N, self.n, self.dofs = N, N * N * dofs, dofs
+            check(lib().hssx_analyze(int(N), int(dofs), int(leaf_size), int(beta), C.byref(h)))
         self.handle = h
 
     def __del__(self):

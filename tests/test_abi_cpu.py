@@ -55,6 +55,28 @@ def test_symbolic_bit_exact(N, leaf, beta, dofs):
         assert np.array_equal(cl, ref), k
 
 
+@pytest.mark.parametrize("Nc,leaf,beta", [(1, 12, 6), (3, 12, 12), (8, 60, 60), (11, 36, 24),
+                                          (32, 60, 60), (45, 60, 30)])
+def test_symbolic_dg_bit_exact(Nc, leaf, beta):
+    from paper_2105_07791_amd.symbolic import Analysis
+    an = Analysis(Nc, leaf, beta, dg=True)
+    t = nd.build_nd_dg(Nc, leaf, beta)
+    assert np.array_equal(an.perm(), t.perm)
+    tr = an.tree()
+    assert tr["info"].shape[0] == len(t.boxes)
+    for k, b in enumerate(t.boxes):
+        info = tr["info"][k]
+        assert list(info) == [b.x0, b.x1, b.y0, b.y1, b.lo, b.hi, b.parent, b.depth,
+                              b.height, b.p0], k
+        assert np.array_equal(tr["I"][tr["I_ptr"][k]:tr["I_ptr"][k + 1]], b.I), k
+        assert np.array_equal(tr["B"][tr["B_ptr"][k]:tr["B_ptr"][k + 1]], b.B), k
+        cl = tr["clusters"][tr["c_ptr"][k]:tr["c_ptr"][k + 1]]
+        ct = b.ctree
+        ref = np.stack([ct.start, ct.size, ct.left, ct.right, ct.level], axis=1) \
+            if ct.nclusters else np.zeros((0, 5))
+        assert np.array_equal(cl, ref), k
+
+
 def test_invalid_arguments_rejected():
     from paper_2105_07791_amd import _lib
     L = _lib.lib()
@@ -64,3 +86,5 @@ def test_invalid_arguments_rejected():
     assert L.hssx_analyze(9, 1, 0, 16, ctypes.byref(h)) == -1
     assert L.hssx_analyze(9, 2, 1, 16, ctypes.byref(h)) == -1
     assert L.hssx_analyze(9, 3, 32, 16, ctypes.byref(h)) == -1
+    assert L.hssx_analyze_dg(0, 60, 60, ctypes.byref(h)) == -1
+    assert L.hssx_analyze_dg(8, 5, 60, ctypes.byref(h)) == -1

@@ -1,0 +1,128 @@
+"""GPU parity of the SIPG-P2 Helmholtz operator (IPDG of Sec. 4.1-4.2, whole
+triangles as ND units, Sec. 3.3) through the C ABI against the oracle:
+assembly to rounding with the exact block pattern, the exact sparse direct
+solver (compression off) to rounding, the compressed preconditioner within
+its tolerance, and GMRES to a true relative residual of 1e-8 with the
+solution within 1e-6 of the oracle's direct solve."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import approx, exact, fem_dg, nd  # noqa: E402
+from synth import make_dg  # noqa: E402
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+def _op(name, **kw):
+    from paper_2105_07791_amd import hssx
+    pr = make_dg(name, **kw)
+    A = hssx.DGOperator(pr.Nc, pr.omega, pr.slowness)
+    return hssx, pr, A
+
+
+@pytest.mark.parametrize("name,Nc", [("sipg_p2_8", 1), ("sipg_p2_8", 3), ("sipg_p2_16", None),
+                                     ("sipg_p2_32", 37)])
+def test_assembly_load_spmv(name, Nc):
+    dev = _dev()
+    hx, pr, A = _op(name, **({} if Nc is None else {"Nc": Nc}))
+    rp, col, val = A.csr()
+    Ao = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+    assert np.array_equal(rp, Ao.indptr) and np.array_equal(col, Ao.indices)
+    assert np.abs(val - Ao.data).max() <= 1e-13 * np.abs(Ao.data).max()
+    import scipy.sparse as sp
+    Ag = sp.csr_matrix((val, col, rp), shape=Ao.shape)
+    assert (Ag != Ag.T).nnz == 0
+    b = A.load(torch.tensor(pr.f, device=dev)).cpu().numpy()
+    bo = fem_dg.mass_matrix_dg(pr.Nc) @ pr.f
+    # quadrature mass entries: rounding differs from the oracle's sums
+    assert np.abs(b - bo).max() <= 1e-13 * max(np.abs(bo).max(), 1e-300)
+    x = np.random.default_rng(0).standard_normal((A.n, 3)) + 1j
+    y = A.matvec(torch.tensor(x, device=dev)).cpu().numpy()
+    assert np.linalg.norm(y - Ao @ x) <= 1e-13 * np.linalg.norm(Ao @ x)
+
+
+@pytest.mark.parametrize("Nc,leaf,beta", [(8, 60, 60), (13, 36, 24), (16, 60, 30)])
+def test_exact_factor(Nc, leaf, beta):
+    """h_sw < 0: compression off, the factor is the exact sparse direct solver."""
+    dev = _dev()
+    hx, pr, A = _op("sipg_p2_16", Nc=Nc)
+    P = hx.Factor(A, tol=1e-6, leaf_size=leaf, beta=beta, h_sw=-1)
+    Ao = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+    t = nd.build_nd_dg(Nc, leaf, beta)
+    fo = exact.factor_exact(Ao, t)
+    b = fem_dg.mass_matrix_dg(Nc) @ pr.f + 0j
+    y = P.apply(torch.tensor(b, device=dev)).cpu().numpy()
+    yo = fo.apply(b)
+    assert np.linalg.norm(y - yo) <= 1e-11 * np.linalg.norm(yo)
+    yt = P.apply(torch.tensor(b, device=dev), trans=True).cpu().numpy()
+    assert np.linalg.norm(yt - yo) <= 1e-11 * np.linalg.norm(yo)
+    for k in range(0, len(t.boxes) - 1, max(1, len(t.boxes) // 7)):
+        S = P.schur(k, t.boxes[k].B.size)
+        assert np.linalg.norm(S - fo.S[k]) <= 1e-11 * np.linalg.norm(fo.S[k])
+    x, st = hx.gmres_solve(A, P, torch.tensor(b, device=dev))
+    assert all(v["iters"] == 1 and v["true_res"] < 1e-12 for v in st)
+
+
+@pytest.mark.parametrize("name,h_sw", [("sipg_p2_16", 2), ("sipg_p2_32", 3)])
+def test_compressed_factor_matches_oracle(name, h_sw):
+    dev = _dev()
+    hx, pr, A = _op(name)
+    P = hx.Factor(A, tol=1e-6, leaf_size=60, beta=60, h_sw=h_sw, seed=5)
+    st = P.stats()
+    assert st["n_hss_nodes"] > 0 and st["n_compressed"] > 0
+    assert st["max_estimate"] <= 1e-6
+    Ao = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+    t = nd.build_nd_dg(pr.Nc, 60, 60)
+    fa = approx.factor_approx(Ao, t, h_sw=h_sw, tol=1e-6, seed=5)
+    fe = exact.factor_exact(Ao, t, keep_S=False)
+    b = fem_dg.mass_matrix_dg(pr.Nc) @ pr.f + 0j
+    y = P.apply(torch.tensor(b, device=dev)).cpu().numpy()
+    ya, ye = fa.apply(b), fe.apply(b)
+    ea = np.linalg.norm(ya - ye)
+    assert np.linalg.norm(y - ye) <= 1e-4 * np.linalg.norm(ye)
+    assert np.linalg.norm(y - ya) <= 4 * ea + 1e-7 * np.linalg.norm(ye)
+    x, stats = hx.gmres_solve(A, P, torch.tensor(b, device=dev), m=50, tol=1e-8)
+    x = x.cpu().numpy()
+    for r in range(b.shape[1]):
+        assert stats[r]["converged"] and stats[r]["true_res"] <= 1e-8
+        assert stats[r]["iters"] <= 6
+        assert np.linalg.norm(x[:, r] - ye[:, r]) <= 1e-6 * np.linalg.norm(ye[:, r])
+
+
+def test_c64_factor_flexible_gmres():
+    """complex64 factor at the workload tolerance 1e-4 inside FP64 flexible
+    GMRES reaches the FP64 target (64 x 64 x 2 triangles, 49,152 DOFs)."""
+    dev = _dev()
+    hx, pr, A = _op("sipg_p2_64")
+    P = hx.Factor(A, tol=1e-4, leaf_size=60, beta=60, h_sw=4, dtype="c64", seed=1)
+    b = A.load(torch.tensor(pr.f, device=dev))
+    x, stats = hx.gmres_solve(A, P, b, flexible=True)
+    Ao = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+    import scipy.sparse.linalg as spla
+    bo, xo = b.cpu().numpy(), x.cpu().numpy()
+    xe = spla.splu(Ao.tocsc()).solve(bo)
+    for r in range(bo.shape[1]):
+        assert stats[r]["converged"]
+        assert np.linalg.norm(Ao @ xo[:, r] - bo[:, r]) <= 1e-8 * np.linalg.norm(bo[:, r])
+        assert np.linalg.norm(xo[:, r] - xe[:, r]) <= 1e-6 * np.linalg.norm(xe[:, r])
+
+
+def test_dg_errors_are_reported():
+    _dev()
+    from paper_2105_07791_amd import hssx
+    from paper_2105_07791_amd._lib import HssxError
+    hx, pr, A = _op("sipg_p2_8", Nc=4)
+    with pytest.raises(HssxError):
+        hx.Factor(A, tol=1e-6, leaf_size=5)
+    with pytest.raises(HssxError):
+        A.dAds_contract(torch.zeros(A.n, dtype=torch.complex128, device="cuda:0"),
+                        torch.zeros(A.n, dtype=torch.complex128, device="cuda:0"))
+    with pytest.raises(HssxError):
+        hssx.BatchOperator([A, A])
