@@ -22,6 +22,13 @@ fields, density 1, absorbing traction, one vertical Gaussian body force); ND
 leaves <= 64 DOFs, HSS leaves 32, HSS tolerance 1e-6, complex64 factors.  The
 oracle line then times a coarser member of the same family (N = 513).
 
+With --workload sipg_p2_256 the operator is the symmetric interior-penalty DG
+discretization with P2 elements on 256 x 256 x 2 triangles (786,432 DOFs,
+omega = 80, speed 1 + 2 sigmoid(g) at the mesh vertices, absorbing faces, one
+Gaussian source); ND leaves <= 10 triangles, HSS leaves of 10 triangles, HSS
+tolerance 1e-4, complex64 factors.  The oracle line times the 128 x 128 x 2
+member of that family.
+
 With --workload helmholtz_p1_batch256 (or a smaller batch) one step is the
 batching form instead: 256 independent problems of uneven sizes (grids of
 65..513 nodes per side, about 27M DOFs in total, each with its own seeded speed
@@ -56,19 +63,24 @@ BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "apply_graph", "spmv
 SINGLE_KERNELS = {"front_assemble", "compress_level", "sample", "spmv"}
 
 
-#: elastic workloads too large for the oracle within the time budget are
-#: sampled on a smaller grid of the same family
-ELASTIC_CPU_SAMPLE = {"elastic_p1_1025": "elastic_p1_513"}
+#: workloads too large for the oracle within the time budget are sampled on
+#: a coarser member of the same family
+CPU_SAMPLE = {"elastic_p1_1025": "elastic_p1_513", "sipg_p2_256": "sipg_p2_128"}
 
 
 def cpu_baseline_child(workload):
     """Oracle (exact nested-dissection factor + solve of all right-hand sides)
     on the same workload, or on its smaller sample; prints a JSON line."""
     import numpy as np
-    from oracle import exact, fem, nd
-    from synth import ELASTIC, make_elastic, make_problem
-    if workload in ELASTIC:
-        pr = make_elastic(ELASTIC_CPU_SAMPLE.get(workload, workload))
+    from oracle import exact, fem, fem_dg, nd
+    from synth import DG, ELASTIC, make_dg, make_elastic, make_problem
+    if workload in DG:
+        pr = make_dg(CPU_SAMPLE.get(workload, workload))
+        A = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+        t = nd.build_nd_dg(pr.Nc, pr.leaf_dofs, pr.beta)
+        b = (fem_dg.mass_matrix_dg(pr.Nc) @ pr.f).astype(np.complex128)
+    elif workload in ELASTIC:
+        pr = make_elastic(CPU_SAMPLE.get(workload, workload))
         A = fem.assemble_elastic(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
         t = nd.build_nd(pr.N, pr.leaf_dofs, pr.beta, dofs=2)
         b = (fem.mass_matrix_vec(pr.N) @ pr.f).astype(np.complex128)
@@ -95,7 +107,7 @@ def cpu_baseline_child(workload):
     except OSError:
         pass
     print(json.dumps({"seconds": t1 - t0, "true_res": res, "threads": threads, "cpu": cpu,
-                      "n": int(A.shape[0]), "N": pr.N}))
+                      "n": int(A.shape[0]), "N": getattr(pr, "N", getattr(pr, "Nc", 0))}))
 
 
 def run_cpu_baseline(workload):
@@ -107,11 +119,12 @@ def run_cpu_baseline(workload):
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
-    if workload in ELASTIC_CPU_SAMPLE:
-        from synth import ELASTIC
-        n_full = 2 * ELASTIC[workload]["N"] ** 2
+    if workload in CPU_SAMPLE:
+        from synth import DG, ELASTIC
+        n_full = 2 * ELASTIC[workload]["N"] ** 2 if workload in ELASTIC else \
+            12 * DG[workload]["Nc"] ** 2
         return {"value": d["seconds"], "unit": "s", "cores": d["threads"], "kind": "oracle",
-                "sample": f"{ELASTIC_CPU_SAMPLE[workload]} (N={d['N']}, n={d['n']}, same "
+                "sample": f"{CPU_SAMPLE[workload]} (N={d['N']}, n={d['n']}, same "
                           f"family, not the full {workload}): exact nested-dissection "
                           f"factorization (no compression) + solve, float64, "
                           f"{d['threads']} thread(s) on {d['cpu']} (true residual "
@@ -339,13 +352,17 @@ def main():
     import ctypes
     import torch
     from paper_2105_07791_amd import _lib, hssx
-    from synth import ELASTIC, make_elastic, make_problem
+    from synth import DG, ELASTIC, make_dg, make_elastic, make_problem
 
     dev = torch.device("cuda:0")
     elastic = args.workload in ELASTIC
+    dg = args.workload in DG
     if elastic:
         pr = make_elastic(args.workload, device=dev)
         A = hssx.ElasticOperator(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
+    elif dg:
+        pr = make_dg(args.workload, device=dev)
+        A = hssx.DGOperator(pr.Nc, pr.omega, pr.slowness)
     else:
         pr = make_problem(args.workload)
         A = hssx.Operator(pr.N, pr.omega, pr.slowness)
@@ -480,8 +497,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "c64 factor / f64 Krylov",
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": pr.N, "n": pr.n, "omega": pr.omega,
-                   "operator": "P1 elastic, 2 DOFs per node" if elastic else "P1 Helmholtz",
+        "config": {"workload": args.workload, "N": A.N, "n": pr.n, "omega": pr.omega,
+                   "operator": ("P1 elastic, 2 DOFs per node" if elastic else
+                                "SIPG-P2 Helmholtz, N x N x 2 triangles" if dg else
+                                "P1 Helmholtz"),
                    "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": tol_mixed,
                    "nd_leaf_dofs": pr.leaf_dofs, "hss_leaf": pr.beta, "h_sw": pr.h_sw,
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
