@@ -388,6 +388,82 @@ __global__ __launch_bounds__(256) void gemm_b_kernel(const PanelJob<T> *__restri
   }
 }
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// complex64 trailing update on the matrix cores.  The tile is computed
+// transposed, D = C^T = Y^T A^T, with v_mfma_f32_16x16x4f32 on the real and
+// imaginary parts (Re D = Yr^T Ar^T - Yi^T Ai^T, Im D = Yi^T Ar^T + Yr^T Ai^T),
+// so each output register of a lane group holds 16 consecutive rows of one
+// column of F and the read-modify-write is coalesced.  Four waves cover the
+// 64 x 64 tile as 2 x 2 blocks of 32 x 32; each wave keeps 2 x 2 blocks of
+// 16 x 16 for both parts (32 accumulator registers).
+__global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<float> *__restrict__ jobs) {
+  __shared__ cplx<float> As[kTile][kNB + 1];
+  __shared__ cplx<float> Ys[kNB][kTile];
+  const PanelJob<float> jb = jobs[blockIdx.z];
+  const int J = jb.ncols - jb.p0 - jb.nb;
+  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  if (i0 >= jb.m || j0 >= J) return;
+  const int nb = jb.nb, tid = threadIdx.x;
+  const long ld = jb.ld;
+  // panel columns beyond nb are zero so that the K loop runs in steps of 4
+  for (int e = tid; e < kTile * kNB; e += 256) {
+    int r = e % kTile, t = e / kTile;
+    int i = i0 + r;
+    As[r][t] = (i < jb.m && t < nb) ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<float>();
+  }
+  for (int e = tid; e < kTile * kNB; e += 256) {
+    int t = e % kNB, c = e / kNB;
+    Ys[t][c] = ((j0 + c) < J && t < nb) ? jb.Y[t + (long)(j0 + c) * nb] : czero<float>();
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
+  const int q = lane & 15, kq = lane >> 4;
+  floatx4_t dr[2][2], di[2][2];
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      dr[bc][bi] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      di[bc][bi] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  const int nbr = (nb + 3) & ~3;
+  for (int t0 = 0; t0 < nbr; t0 += 4) {
+    const int t = t0 + kq;
+    cplx<float> y[2], a[2];
+#pragma unroll
+    for (int bc = 0; bc < 2; ++bc) y[bc] = Ys[t][wc + 16 * bc + q];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) a[bi] = As[wr + 16 * bi + q][t];
+#pragma unroll
+    for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        dr[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].re, a[bi].re, dr[bc][bi], 0, 0, 0);
+        dr[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(-y[bc].im, a[bi].im, dr[bc][bi], 0, 0, 0);
+        di[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].im, a[bi].re, di[bc][bi], 0, 0, 0);
+        di[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].re, a[bi].im, di[bc][bi], 0, 0, 0);
+      }
+  }
+  // lane (q, kq), register r: C row i0 + wr + 16 bi + q, column j0 + wc + 16 bc + 4 kq + r
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cl = wc + 16 * bc + 4 * kq + r, c = j0 + cl;
+      if (c >= J) continue;
+      cplx<float> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int i = i0 + wr + 16 * bi + q;
+        if (i >= jb.m) continue;
+        if (i >= jb.p0 && i < jb.p0 + nb) col[i] = Ys[i - jb.p0][cl];
+        else col[i] = col[i] - mk(dr[bc][bi][r], di[bc][bi][r]);
+      }
+    }
+}
+
 template <typename T>
 __global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
   const AxpbyJob<T> jb = jobs[blockIdx.z];
@@ -439,8 +515,12 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
   hipLaunchKernelGGL(swap_kernel<T>, dim3(ceil_div(max_cols, 256), count), dim3(256), 0, st, jobs);
   hipLaunchKernelGGL(gemm_a_kernel<T>, dim3(ceil_div((long)max_cols * kNB, 256), count), dim3(256),
                      0, st, jobs);
-  hipLaunchKernelGGL(gemm_b_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
-                     dim3(256), 0, st, jobs);
+  if constexpr (std::is_same<T, float>::value)
+    hipLaunchKernelGGL(gemm_b_mfma_kernel, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
+                       dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL(gemm_b_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
+                       dim3(256), 0, st, jobs);
   HSSX_HIP(hipGetLastError());
 }
 
