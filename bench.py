@@ -509,6 +509,7 @@ def main():
         "symbolic_ms": fstats["ms_symbolic"], "setup_ms": fstats["ms_setup"],
         "k_max": fstats["k_max"], "factor_bytes": fstats["factor_bytes"],
         "compressions": fstats["n_compressed"], "max_rank_rounds": fstats["max_rounds_used"],
+        "rounds_total": fstats["rounds_total"],
         "max_estimate": fstats["max_estimate"], "hss_nodes": fstats["n_hss_nodes"],
         "kernel_ms_per_step": kernel_ms,
         "plain_fp64": plain,

@@ -123,6 +123,7 @@ typedef struct {
   double ms_numeric;    /* numeric factorization (device, hipEvents) */
   double ms_setup;      /* front descriptors, their upload and the front
                            pool allocation (host) */
+  int rounds_total;     /* rank-growth rounds summed over all compressions */
 } hssx_factor_stats;
 
 /* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for

@@ -39,7 +39,7 @@ class FactorStats(C.Structure):
                 ("max_rounds_used", C.c_int), ("max_estimate", C.c_double),
                 ("factor_bytes", C.c_double), ("factor_flops", C.c_double),
                 ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
-                ("ms_setup", C.c_double)]
+                ("ms_setup", C.c_double), ("rounds_total", C.c_int)]
 
 
 _vp = C.c_void_p

@@ -470,7 +470,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   int *err = ar.get<int>(1);
   int *d_err = sg.put(std::vector<int>{-1});
   HSSX_HIP(hipMemcpyAsync(err, d_err, sizeof(int), hipMemcpyDeviceToDevice, st));
-  int kmax = 0, rounds_max = 0, ncomp = 0;
+  int kmax = 0, rounds_max = 0, ncomp = 0, rounds_sum = 0;
   double est_max = 0;
   // accepted rank cap k of each node's Schur-complement compression; a
   // parent's compressions start from its children's (Algorithm A.1 takes an
@@ -479,6 +479,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   auto record = [&](const CompressTask<T> &t) {
     kmax = std::max(kmax, t.maxrank);
     rounds_max = std::max(rounds_max, t.rounds);
+    rounds_sum += t.rounds;
     est_max = std::max(est_max, t.est);
     P.node_rank[t.node] = std::max(P.node_rank[t.node], t.maxrank);
   };
@@ -633,6 +634,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   HSSX_CHECK(bad < 0, HSSX_ESINGULAR, "zero pivot in the dense block of tree node " + std::to_string(bad));
   P.stats.k_max = kmax;
   P.stats.max_rounds_used = rounds_max;
+  P.stats.rounds_total = rounds_sum;
   P.stats.max_estimate = est_max;
   P.stats.n_compressed = ncomp;
 }

@@ -6,6 +6,12 @@
   flexible GMRES; the benchmark's launch configuration): every right-hand
   side against the oracle's exact solve (solution error <= 1e-6, true residual
   <= 1e-8 evaluated with the oracle's matrix).
+* sipg_p2_256 (786,432 DOFs) and elastic_p1_1025 (2,101,250 DOFs) in the
+  benchmark's launch configuration: sampled CSR rows against the oracle's
+  full assembly, the load against the oracle's mass matrix, and the true
+  residual of the GPU solution evaluated with the oracle's matrix (<= 1e-8);
+  the oracle's exact solve at these sizes takes minutes on the host, so the
+  solution is checked through its residual.
 * edge cases: a single-node tree, leaf boxes of one node (empty interiors),
   every non-leaf node with HSS arithmetic, vanishing tolerance, ragged grids.
 """
@@ -16,8 +22,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from oracle import approx, exact, fem, nd  # noqa: E402
-from synth import make_problem  # noqa: E402
+from oracle import approx, exact, fem, fem_dg, nd  # noqa: E402
+from synth import make_dg, make_elastic, make_problem  # noqa: E402
 
 
 def _hx():
@@ -63,6 +69,48 @@ def test_helmholtz_p1_513_x64_full_size():
     # noise floor (an estimate that a further round no longer halves)
     assert P.stats()["max_estimate"] <= 10 * pr.tol
     assert max(v["iters"] for v in st) <= 6
+
+
+def _full_size_check(A, Ao, Mo, pr, iters_max):
+    """Sampled rows, load and true residual against the oracle's matrices."""
+    dev = torch.device("cuda:0")
+    rp, col, val = A.csr()
+    assert np.array_equal(rp, Ao.indptr)
+    rows = np.random.default_rng(0).choice(A.n, size=2000, replace=False)
+    for r in rows:
+        a, b = Ao.indptr[r], Ao.indptr[r + 1]
+        assert np.array_equal(col[a:b], Ao.indices[a:b]), r
+        assert np.abs(val[a:b] - Ao.data[a:b]).max() <= 1e-13 * np.abs(Ao.data[a:b]).max(), r
+    del rp, col, val
+    P = _hx().Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
+                     dtype=pr.factor_dtype, seed=1)
+    b = A.load(torch.tensor(pr.f, device=dev))
+    bo = Mo @ pr.f
+    bg = b.cpu().numpy().reshape(A.n, -1)
+    assert np.abs(bg - bo).max() <= 1e-13 * np.abs(bo).max()
+    x, st = _hx().gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol, flexible=True)
+    xg = x.cpu().numpy().reshape(A.n, -1)
+    for r in range(bo.shape[1]):
+        assert st[r]["converged"] and st[r]["iters"] <= iters_max, st[r]
+        assert np.linalg.norm(Ao @ xg[:, r] - bo[:, r]) <= 1e-8 * np.linalg.norm(bo[:, r])
+
+
+def test_sipg_p2_256_full_size():
+    hx = _hx()
+    pr = make_dg("sipg_p2_256")
+    A = hx.DGOperator(pr.Nc, pr.omega, pr.slowness)
+    Ao = fem_dg.assemble_dg(pr.Nc, pr.omega, pr.slowness)
+    _full_size_check(A, Ao, fem_dg.mass_matrix_dg(pr.Nc), pr, iters_max=8)
+
+
+def test_elastic_p1_1025_full_size():
+    hx = _hx()
+    dev = torch.device("cuda:0")
+    pr = make_elastic("elastic_p1_1025", device=dev)   # Lame fields evaluated on the device
+    A = hx.ElasticOperator(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
+    lam, mu, rho = (t.cpu().numpy() for t in (pr.lam, pr.mu, pr.rho))
+    Ao = fem.assemble_elastic(pr.N, pr.omega, lam, mu, rho)
+    _full_size_check(A, Ao, fem.mass_matrix_vec(pr.N), pr, iters_max=8)
 
 
 @pytest.mark.parametrize("N,leaf,h_sw", [(2, 32, 4), (5, 1, -1), (5, 1, 0), (9, 4, 0),
