@@ -6,8 +6,11 @@ omega = 100, unit wave speed, absorbing boundary, 64 seeded Gaussian sources
 (width 0.02) solved together.  One step = numeric factorization P = LDR
 (complex64 factors, HSS tolerance 1e-6, ND leaves <= 32 DOFs, HSS leaves 16,
 switching height 4) + flexible GMRES(50) in FP64 to a true relative residual
-of 1e-8 for all 64 right-hand sides.  The operator and the right-hand sides
-are resident in HBM before the timed region.
+of 1e-8 for all 64 right-hand sides.  The symbolic analysis and the front
+descriptors depend only on the grid; they are built once per pattern (in the
+warm-up) and reported separately, and every timed step recomputes the whole
+numeric factorization from the operator (hssx_refactor).  The operator and
+the right-hand sides are resident in HBM before the timed region.
 
 Printed: one JSON line with the metric (seconds per factor+solve, lower is
 better), GMRES iterations, the FP64 plain form (complex128 factors, left
@@ -372,9 +375,22 @@ def main():
 
     tol_mixed = args.tol if args.tol is not None else pr.tol
 
-    def step(dtype, flexible, tol_hss=tol_mixed):
-        P = hssx.Factor(A, tol=tol_hss, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
-                        dtype=dtype, seed=1)
+    # analyze once, factor many: the first call of a form builds its factor
+    # (symbolic analysis, descriptors, numeric factorization); later calls
+    # recompute the numeric factorization from the operator (hssx_refactor)
+    factors, analysis = {}, {}
+
+    def step(dtype, flexible, tol_hss=tol_mixed, key="mixed"):
+        P = factors.get(key)
+        if P is None:
+            P = hssx.Factor(A, tol=tol_hss, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
+                            dtype=dtype, seed=1)
+            factors[key] = P
+            fs = P.stats()
+            analysis[key] = {"symbolic_ms": fs["ms_symbolic"], "setup_ms": fs["ms_setup"],
+                             "first_numeric_ms": fs["ms_numeric"]}
+        else:
+            P.refactor(A)
         x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol, flexible=flexible)
         return P, x, st
 
@@ -427,6 +443,10 @@ def main():
             "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
             "avg_launch_us": avg_s * 1e6}
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in kern.items()}
+    # achieved rate of each category over the timed steps: GB/s for the
+    # byte-counted ones, TFLOP/s for the flop-counted ones (0: no count)
+    kernel_rate = {k: round(v[2] / (v[0] / 1e3) / (1e9 if k in BYTE_KERNELS else 1e12), 3)
+                   if v[0] > 0 and v[2] > 0 else 0.0 for k, v in kern.items()}
     # HBM traffic per launch from the committed counter measurement, valid only
     # while the measured kernel's source is unchanged
     try:
@@ -441,9 +461,10 @@ def main():
 
     alt = None
     if args.alt_tol and args.alt_tol != tol_mixed:
+        step("c64", True, tol_hss=args.alt_tol, key="alt")       # analysis, untimed
         torch.cuda.synchronize()
         ta0 = time.perf_counter()
-        Pa, xa, sa = step("c64", True, tol_hss=args.alt_tol)
+        Pa, xa, sa = step("c64", True, tol_hss=args.alt_tol, key="alt")
         torch.cuda.synchronize()
         ta1 = time.perf_counter()
         ra = (torch.linalg.vector_norm(A.matvec(xa) - b, dim=0)
@@ -461,10 +482,11 @@ def main():
 
     plain = None
     if not args.no_plain:
+        Pp = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
+                         dtype="c128", seed=1)                      # analysis, untimed
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
-        Pp = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
-                         dtype="c128", seed=1)
+        Pp.refactor(A)
         torch.cuda.synchronize()
         tp1 = time.perf_counter()
         pit = []
@@ -506,12 +528,15 @@ def main():
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
         "gmres_iters_max": max(iters), "gmres_iters_mean": sum(iters) / len(iters),
         "true_res_max": true_res, "factor_ms": fstats["ms_numeric"],
-        "symbolic_ms": fstats["ms_symbolic"], "setup_ms": fstats["ms_setup"],
+        "analyze": dict(analysis.get("mixed", {}), note="symbolic analysis and front "
+                        "descriptors, once per pattern, outside the timed steps"),
         "k_max": fstats["k_max"], "factor_bytes": fstats["factor_bytes"],
         "compressions": fstats["n_compressed"], "max_rank_rounds": fstats["max_rounds_used"],
         "rounds_total": fstats["rounds_total"],
         "max_estimate": fstats["max_estimate"], "hss_nodes": fstats["n_hss_nodes"],
         "kernel_ms_per_step": kernel_ms,
+        "kernel_rate": kernel_rate,
+        "kernel_rate_units": {k: ("GB/s" if k in BYTE_KERNELS else "TFLOP/s") for k in kern},
         "plain_fp64": plain,
         "mixed_alt_tol": alt,
         "roofline": roof,

@@ -225,6 +225,17 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size,
                         const hssx_factor_opts *opts, void *stream,
                         hssx_fact *P_out);
 
+/* Numeric refactorization (Algorithm 3.4 without the analysis): recompute
+ * the factor P for operator A, which must have the pattern of the operator P
+ * was built from (same kind and grid sides, e.g. new slowness or Lame fields
+ * reassembled on the same grid, or a batch of the same grids).  The symbolic
+ * analysis, front descriptors, front pool, sketch seeds, options and apply
+ * graphs and tiles of P are kept; every numeric value is recomputed from A.
+ * P refers to A afterwards.  Host-blocking like hssx_factor.  EINVAL for a
+ * handle without a factorization or a different pattern; the factor is
+ * unusable after a failed refactor (ESINGULAR, ENOMEM). */
+hssx_status hssx_refactor(hssx_fact P, hssx_op A, void *stream);
+
 /* y = P^-1 x (trans = 0) or P^-T x (trans = 1) by Algorithm 3.1
  * (bottom-up L sweep, block-diagonal solve, top-down R sweep).  x, y:
  * device complex128, n x nrhs; y may alias x. */

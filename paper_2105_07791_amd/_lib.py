@@ -66,6 +66,7 @@ SIGNATURES = {
     "hssx_dAds_contract": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "hssx_analyze": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
     "hssx_analyze_dg": (_i, [_i, _i, _i, C.POINTER(_vp)]),
+    "hssx_refactor": (_i, [_vp, _vp, _vp]),
     "hssx_assemble_dg": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, C.POINTER(_vp)]),
     "hssx_get_perm": (_i, [_vp, _ip, _l]),
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),

@@ -346,6 +346,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     hipStream_t st = S(stream);
     auto P = std::make_unique<hssx_fact_>();
     P->A = A;
+    P->pattern = A->pattern_key();
     P->dtype = o.dtype;
     P->tol = tol;
     P->leaf = leaf_size;
@@ -525,6 +526,21 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->stats.factor_flops = flops;
     factor_numeric(*P, st);
     *P_out = P.release();
+  });
+}
+
+hssx_status hssx_refactor(hssx_fact P, hssx_op A, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(P && A, HSSX_EINVAL, "null argument");
+    HSSX_CHECK(P->desc.p != nullptr, HSSX_EINVAL, "handle holds no factorization");
+    HSSX_CHECK(A->pattern_key() == P->pattern, HSSX_EINVAL,
+               "refactor needs an operator with the factor's pattern (same grids and kind)");
+    DeviceScope ds(A->device);
+    P->A = A;
+    P->stats.ms_symbolic = 0;
+    P->stats.ms_setup = 0;
+    std::fill(P->node_rank.begin(), P->node_rank.end(), 0);
+    factor_numeric(*P, S(stream));
   });
 }
 

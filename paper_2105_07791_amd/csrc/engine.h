@@ -17,6 +17,13 @@ struct hssx_op_ {
   int dofs = 1;       // unknowns per unit (2: elastic node, 6: P2 triangle)
   int mesh = 0;       // hssx::kMeshCG (grid nodes) or hssx::kMeshDG (triangles)
   int row_max = 7;    // longest CSR row (7 scalar P1, 14 elastic, 24 SIPG-P2)
+  // the structured assemblers' patterns are functions of (mesh, dofs, grid
+  // sides of the parts): operators with equal keys have equal patterns
+  std::vector<long> pattern_key() const {
+    std::vector<long> k{device, mesh, dofs, n, nnz};
+    k.insert(k.end(), part_N.begin(), part_N.end());
+    return k;
+  }
   long nnz = 0;
   hssx::DevBuf rowptr, col, val, mval, s;
   std::vector<int> h_rowptr, h_col;
@@ -34,6 +41,7 @@ struct hssx_op_ {
 
 struct hssx_fact_ {
   hssx_op_ *A = nullptr;      // operator the factor was built from (not owned)
+  std::vector<long> pattern;  // its pattern key (checked by hssx_refactor)
   hssx_dtype dtype = HSSX_C128;
   double tol = 0;
   int leaf = 0;

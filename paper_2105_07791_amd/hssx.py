@@ -174,6 +174,14 @@ class Factor:
                                 _stream(stream), C.byref(h)))
         self.handle = h
 
+    def refactor(self, A=None, stream=None):
+        """Numeric refactorization for A (default: the current operator),
+        which must share the factor's pattern (hssx_refactor)."""
+        A = self.A if A is None else A
+        check(lib().hssx_refactor(self.handle, A.handle, _stream(stream)))
+        self.A = A
+        return self
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib._LIB is not None:
             lib().hssx_fact_destroy(self.handle)
