@@ -206,9 +206,13 @@ def run_batch(args):
     del parts
     torch.cuda.synchronize()
 
+    # the forest's analysis is built in the warm-up; every step reassembles
+    # A(s) and recomputes the numeric factorization (hssx_refactor)
+    cache = {}
+
     def step():
         st = s_all.detach().clone().requires_grad_(True)
-        x = solve(st, b, Ns, om, **opts)
+        x = solve(st, b, Ns, om, cache=cache, **opts)
         r = x[rec] - d
         J = 0.5 * (r.abs() ** 2).sum()
         J.backward()
@@ -257,6 +261,8 @@ def run_batch(args):
     ph["factor_symbolic_host"] = round(fst["ms_symbolic"] / 1e3, 3)
     ph["factor_setup_host"] = round(fst["ms_setup"] / 1e3, 3)
     ph["factor_numeric"] = round(fst["ms_numeric"] / 1e3, 3)
+    Pb.refactor(Ab)
+    tp = mark("refactor", tp)
     xb, stf = gmres_solve(Ab, Pb, b, flexible=True)
     tp = mark("gmres_forward", tp)
     gx = torch.zeros_like(xb)
@@ -296,7 +302,8 @@ def run_batch(args):
         "config": {"workload": args.workload, "problems": len(Ns), "n": n,
                    "N_min": min(Ns), "N_max": max(Ns), "factor_dtype": "c64", "hss_tol": tol,
                    "sampling": "bf16 matrix cores, split operands, fp32 accumulation",
-                   "step": "assemble + factor + flexible GMRES + misfit + adjoint gradient"},
+                   "step": "assemble + numeric factor (analysis once per forest, in the "
+                           "warm-up) + flexible GMRES + misfit + adjoint gradient"},
         "J": J.item(), "grad_norm": torch.linalg.vector_norm(g).item(), "phases_s": ph,
         "fp32_sampling_tol_1e-6": ref,
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kern.items()},

@@ -11,6 +11,12 @@ g = dL/dRe(x) + i dL/dIm(x), dL = Re(g^H dx) and dx = -A^-1 (dA) x, so
 All three steps run in libhssx.so; this module only marshals tensors.
 A batch of uneven problems (N and omega given as lists) is one
 block-diagonal operator: s, b and x are the parts' vectors stacked.
+
+With a cache (any dict) the factor of a grid configuration is built once and
+later calls on the same grids recompute only its numeric factorization
+(hssx_refactor), as in an inversion loop that reassembles A(s) every step.
+A cached factor is refactored in place: run a call's backward before the
+next forward that reuses the cache.
 """
 import torch
 
@@ -37,8 +43,18 @@ class WaveSolve(torch.autograd.Function):
         opts = dict(opts or {})
         gm = dict(m=opts.pop("gmres_m", 50), tol=opts.pop("gmres_tol", 1e-8),
                   flexible=opts.pop("flexible", False))
+        cache = opts.pop("cache", None)
         A = _operator(s.detach(), N, omega)
-        P = Factor(A, **opts)
+        key = (tuple(N) if isinstance(N, (list, tuple)) else N,
+               tuple(omega) if isinstance(omega, (list, tuple)) else omega,
+               tuple(sorted(opts.items())))
+        P = cache.get(key) if cache is not None else None
+        if P is None:
+            P = Factor(A, **opts)
+            if cache is not None:
+                cache[key] = P
+        else:
+            P.refactor(A)
         x, st = gmres_solve(A, P, b.detach(), **gm)
         ctx.A, ctx.P, ctx.gm, ctx.stats = A, P, gm, st
         ctx.save_for_backward(x)
@@ -54,7 +70,10 @@ class WaveSolve(torch.autograd.Function):
         return gs, gb, None, None, None
 
 
-def solve(s, b, N, omega, **opts):
+def solve(s, b, N, omega, cache=None, **opts):
     """x = A(s)^-1 b, differentiable in the slowness s and the load b.  N and
-    omega may be lists (a batch of problems, vectors stacked part by part)."""
+    omega may be lists (a batch of problems, vectors stacked part by part).
+    cache: optional dict for analysis reuse across calls (see module doc)."""
+    if cache is not None:
+        opts["cache"] = cache
     return WaveSolve.apply(s, b, N, omega, opts)

@@ -95,3 +95,30 @@ def test_refactor_rejects_other_patterns():
         P.refactor(hx.ElasticOperator(pe.N, pe.omega, pe.lam, pe.mu, pe.rho))
     # still usable with its own operator
     P.refactor(A)
+
+
+def test_autograd_cache_matches_fresh_factors():
+    """An inversion-style loop with a factor cache gives the same solutions
+    and slowness gradients as fresh factorizations, step after step."""
+    _hx()
+    from paper_2105_07791_amd.autograd import solve
+    dev = torch.device("cuda:0")
+    Ns = [17, 29]
+    om = [0.25 * (N - 1) for N in Ns]
+    f = torch.randn(sum(N * N for N in Ns), dtype=torch.float64, device=dev)
+    from paper_2105_07791_amd.hssx import BatchOperator, Operator
+    b = BatchOperator([Operator(N, w, np.ones(N * N)) for N, w in zip(Ns, om)]).load(f)
+    opts = dict(tol=1e-6, h_sw=2, dtype="c64", flexible=True, seed=1)
+    cache = {}
+    for seed in (1, 2, 3):
+        s = torch.cat([1.0 / speed_field(N, seed + N, device=dev) for N in Ns])
+        grads, xs = [], []
+        for c in (cache, None):
+            st = s.clone().requires_grad_(True)
+            x = solve(st, b, Ns, om, cache=c, **opts)
+            (0.5 * (x.abs() ** 2).sum()).backward()
+            grads.append(st.grad)
+            xs.append(x.detach())
+        assert torch.equal(xs[0], xs[1])
+        assert torch.equal(grads[0], grads[1])
+    assert len(cache) == 1
