@@ -50,8 +50,17 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
       } else {
         int gi = gid[p], gj = gid[q];
         c128 a = czero<double>();
-        for (int t = rowptr[gi]; t < rowptr[gi + 1]; ++t)
-          if (col[t] == gj) { a = val[t]; break; }
+        // sorted columns: most pairs of a large front lie outside row gi's
+        // column range and are rejected by its two ends; the rest bisect
+        int lo = rowptr[gi], hi = rowptr[gi + 1] - 1;
+        if (lo <= hi && gj >= col[lo] && gj <= col[hi]) {
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (col[mid] < gj) lo = mid + 1;
+            else hi = mid;
+          }
+          if (col[lo] == gj) a = val[lo];
+        }
         v = ccast<T>(a);
       }
     }
@@ -344,94 +353,73 @@ __global__ void gemm_a_kernel(const PanelJob<T> *__restrict__ jobs) {
   jb.Y[t + (long)c * jb.nb] = acc;
 }
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> {
+  using V = floatx4_t;
+  static constexpr int KB = 32;   // panel width
+  __device__ static V fma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row of register r in lane group g (lanes 16 g .. 16 g + 15)
+  __device__ static int drow(int g, int r) { return 4 * g + r; }
+};
+template <> struct MfmaAcc<double> {
+  using V = doublex4_t;
+  static constexpr int KB = 16;
+  __device__ static V fma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int g, int r) { return g + 4 * r; }
+};
+
+// Trailing update on the matrix cores (16x16x4 MFMA in the factor's real
+// precision).  The tile is computed transposed, D = C^T = Y^T A^T, on the
+// real and imaginary parts (Re D = Yr^T Ar^T - Yi^T Ai^T, Im D = Yi^T Ar^T +
+// Yr^T Ai^T), so each output register of a lane group holds 16 consecutive
+// rows of one column of F and the read-modify-write is coalesced.  Four waves
+// cover the 64 x 64 tile as 2 x 2 blocks of 32 x 32; each wave keeps 2 x 2
+// blocks of 16 x 16 for both parts.
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_b_kernel(const PanelJob<T> *__restrict__ jobs) {
-  __shared__ cplx<T> As[kTile][kNB + 1];
-  __shared__ cplx<T> Ys[kNB][kTile];
+__global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<T> *__restrict__ jobs) {
+  using M = MfmaAcc<T>;
+  constexpr int KB = M::KB;
+  __shared__ cplx<T> As[kTile][KB + 1];
+  __shared__ cplx<T> Ys[KB][kTile];
   const PanelJob<T> jb = jobs[blockIdx.z];
   const int J = jb.ncols - jb.p0 - jb.nb;
   const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
   if (i0 >= jb.m || j0 >= J) return;
   const int nb = jb.nb, tid = threadIdx.x;
   const long ld = jb.ld;
-  for (int e = tid; e < kTile * nb; e += 256) {
-    int r = e % kTile, t = e / kTile;
-    int i = i0 + r;
-    As[r][t] = i < jb.m ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<T>();
-  }
-  for (int e = tid; e < kTile * nb; e += 256) {
-    int t = e % nb, c = e / nb;
-    Ys[t][c] = (j0 + c) < J ? jb.Y[t + (long)(j0 + c) * nb] : czero<T>();
-  }
-  __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
-  cplx<T> acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) acc[a][b] = czero<T>();
-  for (int t = 0; t < nb; ++t) {
-    cplx<T> av[4], yv[4];
-    for (int a = 0; a < 4; ++a) av[a] = As[tx + 16 * a][t];
-    for (int b = 0; b < 4; ++b) yv[b] = Ys[t][ty + 16 * b];
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], yv[b]);
-  }
-  for (int b = 0; b < 4; ++b) {
-    int c = j0 + ty + 16 * b;
-    if (c >= J) continue;
-    cplx<T> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
-    for (int a = 0; a < 4; ++a) {
-      int i = i0 + tx + 16 * a;
-      if (i >= jb.m) continue;
-      if (i >= jb.p0 && i < jb.p0 + nb) col[i] = Ys[i - jb.p0][ty + 16 * b];
-      else col[i] = col[i] - acc[a][b];
-    }
-  }
-}
-
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-// complex64 trailing update on the matrix cores.  The tile is computed
-// transposed, D = C^T = Y^T A^T, with v_mfma_f32_16x16x4f32 on the real and
-// imaginary parts (Re D = Yr^T Ar^T - Yi^T Ai^T, Im D = Yi^T Ar^T + Yr^T Ai^T),
-// so each output register of a lane group holds 16 consecutive rows of one
-// column of F and the read-modify-write is coalesced.  Four waves cover the
-// 64 x 64 tile as 2 x 2 blocks of 32 x 32; each wave keeps 2 x 2 blocks of
-// 16 x 16 for both parts (32 accumulator registers).
-__global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<float> *__restrict__ jobs) {
-  __shared__ cplx<float> As[kTile][kNB + 1];
-  __shared__ cplx<float> Ys[kNB][kTile];
-  const PanelJob<float> jb = jobs[blockIdx.z];
-  const int J = jb.ncols - jb.p0 - jb.nb;
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
-  if (i0 >= jb.m || j0 >= J) return;
-  const int nb = jb.nb, tid = threadIdx.x;
-  const long ld = jb.ld;
   // panel columns beyond nb are zero so that the K loop runs in steps of 4
-  for (int e = tid; e < kTile * kNB; e += 256) {
+  for (int e = tid; e < kTile * KB; e += 256) {
     int r = e % kTile, t = e / kTile;
     int i = i0 + r;
-    As[r][t] = (i < jb.m && t < nb) ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<float>();
+    As[r][t] = (i < jb.m && t < nb) ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<T>();
   }
-  for (int e = tid; e < kTile * kNB; e += 256) {
-    int t = e % kNB, c = e / kNB;
-    Ys[t][c] = ((j0 + c) < J && t < nb) ? jb.Y[t + (long)(j0 + c) * nb] : czero<float>();
+  for (int e = tid; e < kTile * KB; e += 256) {
+    int t = e % KB, c = e / KB;
+    Ys[t][c] = ((j0 + c) < J && t < nb) ? jb.Y[t + (long)(j0 + c) * nb] : czero<T>();
   }
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
   const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
   const int q = lane & 15, kq = lane >> 4;
-  floatx4_t dr[2][2], di[2][2];
+  typename M::V dr[2][2], di[2][2];
 #pragma unroll
   for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
-      dr[bc][bi] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-      di[bc][bi] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      dr[bc][bi] = typename M::V{0, 0, 0, 0};
+      di[bc][bi] = typename M::V{0, 0, 0, 0};
     }
   const int nbr = (nb + 3) & ~3;
   for (int t0 = 0; t0 < nbr; t0 += 4) {
     const int t = t0 + kq;
-    cplx<float> y[2], a[2];
+    cplx<T> y[2], a[2];
 #pragma unroll
     for (int bc = 0; bc < 2; ++bc) y[bc] = Ys[t][wc + 16 * bc + q];
 #pragma unroll
@@ -440,20 +428,21 @@ __global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<float> 
     for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        dr[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].re, a[bi].re, dr[bc][bi], 0, 0, 0);
-        dr[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(-y[bc].im, a[bi].im, dr[bc][bi], 0, 0, 0);
-        di[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].im, a[bi].re, di[bc][bi], 0, 0, 0);
-        di[bc][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[bc].re, a[bi].im, di[bc][bi], 0, 0, 0);
+        dr[bc][bi] = M::fma(y[bc].re, a[bi].re, dr[bc][bi]);
+        dr[bc][bi] = M::fma(-y[bc].im, a[bi].im, dr[bc][bi]);
+        di[bc][bi] = M::fma(y[bc].im, a[bi].re, di[bc][bi]);
+        di[bc][bi] = M::fma(y[bc].re, a[bi].im, di[bc][bi]);
       }
   }
-  // lane (q, kq), register r: C row i0 + wr + 16 bi + q, column j0 + wc + 16 bc + 4 kq + r
+  // lane (q, kq), register r: C row i0 + wr + 16 bi + q, column
+  // j0 + wc + 16 bc + drow(kq, r) (the output row of D)
 #pragma unroll
   for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int cl = wc + 16 * bc + 4 * kq + r, c = j0 + cl;
+      const int cl = wc + 16 * bc + M::drow(kq, r), c = j0 + cl;
       if (c >= J) continue;
-      cplx<float> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
+      cplx<T> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
         const int i = i0 + wr + 16 * bi + q;
@@ -515,12 +504,8 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
   hipLaunchKernelGGL(swap_kernel<T>, dim3(ceil_div(max_cols, 256), count), dim3(256), 0, st, jobs);
   hipLaunchKernelGGL(gemm_a_kernel<T>, dim3(ceil_div((long)max_cols * kNB, 256), count), dim3(256),
                      0, st, jobs);
-  if constexpr (std::is_same<T, float>::value)
-    hipLaunchKernelGGL(gemm_b_mfma_kernel, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
-                       dim3(256), 0, st, jobs);
-  else
-    hipLaunchKernelGGL(gemm_b_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
-                       dim3(256), 0, st, jobs);
+  hipLaunchKernelGGL(gemm_b_mfma_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_cols, kTile), count),
+                     dim3(256), 0, st, jobs);
   HSSX_HIP(hipGetLastError());
 }
 
