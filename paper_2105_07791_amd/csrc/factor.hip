@@ -379,7 +379,12 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
 
 // Gauss-Jordan elimination of a batch of jobs: fronts with few pivots run in
 // one workgroup each; larger ones go panel by panel (32 columns) through the
-// blocked sequence, all fronts of the batch advancing together.
+// blocked sequence, all fronts of the batch advancing together.  The blocked
+// path eliminates only the pivot rows [0, ne): they become
+// [I | A_ii^-1 A_ib | A_ii^-1]; the remaining rows are then updated by one
+// product per front, F(ne:m, ne:) -= F(ne:m, 0:ne) F(0:ne, ne:), which gives
+// S = A_bb - A_bi A_ii^-1 A_ib and L = -A_bi A_ii^-1 (eqs. 3.2-3.5) with
+// every entry accumulated once instead of once per panel.
 template <typename T>
 void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, Arena &ar) {
   // panel width: the register-resident panel holds 32 complex64 or 16
@@ -422,7 +427,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       PanelJob<T> q;
       q.F = j.ptr;
       q.ld = j.ld;
-      q.m = j.m;
+      q.m = j.ne;
       q.ncols = j.ncols;
       q.ne = j.ne;
       q.p0 = p0;
@@ -433,13 +438,25 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       q.W = W ? W + wo[a] : nullptr;
       q.node = j.node;
       pj.push_back(q);
-      mm = std::max(mm, j.m);
+      mm = std::max(mm, j.ne);
       mc = std::max(mc, j.ncols - p0);
       mp = std::max(mp, j.ne - p0);
       mnb = std::max(mnb, q.nb);
     }
     launch_panel_step<T>((int)pj.size(), sg.put(pj), mm, mc, mp, mnb, err, st);
   }
+  // non-pivot rows: F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols)
+  std::vector<GemmJob<T>> gj;
+  int gm = 0, gn = 0;
+  for (const auto &j : big) {
+    if (j.m == j.ne || j.ne == 0) continue;
+    const cplx<T> *Abi = j.ptr + j.ne, *Bx = j.ptr + (long)j.ne * j.ld;
+    cplx<T> *C = j.ptr + j.ne + (long)j.ne * j.ld;
+    gj.push_back(GemmJob<T>{Abi, Bx, C, j.ld, j.ld, j.ld, j.m - j.ne, j.ncols - j.ne, j.ne});
+    gm = std::max(gm, j.m - j.ne);
+    gn = std::max(gn, j.ncols - j.ne);
+  }
+  if (!gj.empty()) launch_gemm_sub<T>((int)gj.size(), sg.put(gj), gm, gn, st);
   // R = -(A_ii^-1 A_ib): negate the block F(0:ne, ne:m)
   std::vector<AxpbyJob<T>> neg;
   int nm = 0, nn = 0;

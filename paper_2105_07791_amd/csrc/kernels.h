@@ -85,6 +85,16 @@ template <typename T> struct PanelJob {
   cplx<T> *W;      // (ne - p0) x nb
   int node;
 };
+// C -= A B for a batch of jobs (complex, column-major, each job its own
+// sizes and leading dimensions); K may be 0
+template <typename T> struct GemmJob {
+  const cplx<T> *A, *B;
+  cplx<T> *C;
+  int lda, ldb, ldc, M, N, K;
+};
+template <typename T>
+void launch_gemm_sub(int count, const GemmJob<T> *jobs, int max_m, int max_n, hipStream_t st);
+
 // max_prows = largest ne - p0, max_nb = largest nb of the launch; the panel
 // runs register-resident when nb <= 32 (complex64) or 16 (complex128) and
 // ne - p0 <= 1536, else from the scratch W.

@@ -453,6 +453,75 @@ __global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<T> *__r
     }
 }
 
+// C -= A B on the matrix cores, one 64 x 64 tile of C per workgroup, K in
+// chunks of the panel width staged through LDS; the tile is computed
+// transposed (D = C^T = B^T A^T) as in the trailing update.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_sub_mfma_kernel(const GemmJob<T> *__restrict__ jobs) {
+  using M = MfmaAcc<T>;
+  constexpr int KB = M::KB;
+  __shared__ cplx<T> As[kTile][KB + 1];
+  __shared__ cplx<T> Bs[KB][kTile];
+  const GemmJob<T> jb = jobs[blockIdx.z];
+  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  if (i0 >= jb.M || j0 >= jb.N) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = 32 * (w & 1), wc = 32 * (w >> 1);
+  const int q = lane & 15, kq = lane >> 4;
+  typename M::V dr[2][2], di[2][2];
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      dr[bc][bi] = typename M::V{0, 0, 0, 0};
+      di[bc][bi] = typename M::V{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < jb.K; k0 += KB) {
+    __syncthreads();
+    for (int e = tid; e < kTile * KB; e += 256) {
+      const int r = e % kTile, t = e / kTile, i = i0 + r, k = k0 + t;
+      As[r][t] = (i < jb.M && k < jb.K) ? jb.A[i + (long)k * jb.lda] : czero<T>();
+    }
+    for (int e = tid; e < kTile * KB; e += 256) {
+      const int t = e % KB, c = e / KB, k = k0 + t, j = j0 + c;
+      Bs[t][c] = (j < jb.N && k < jb.K) ? jb.B[k + (long)j * jb.ldb] : czero<T>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t0 = 0; t0 < KB; t0 += 4) {
+      const int t = t0 + kq;
+      cplx<T> y[2], a[2];
+#pragma unroll
+      for (int bc = 0; bc < 2; ++bc) y[bc] = Bs[t][wc + 16 * bc + q];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) a[bi] = As[wr + 16 * bi + q][t];
+#pragma unroll
+      for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+          dr[bc][bi] = M::fma(y[bc].re, a[bi].re, dr[bc][bi]);
+          dr[bc][bi] = M::fma(-y[bc].im, a[bi].im, dr[bc][bi]);
+          di[bc][bi] = M::fma(y[bc].im, a[bi].re, di[bc][bi]);
+          di[bc][bi] = M::fma(y[bc].re, a[bi].im, di[bc][bi]);
+        }
+    }
+  }
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = j0 + wc + 16 * bc + M::drow(kq, r);
+      if (c >= jb.N) continue;
+      cplx<T> *col = jb.C + (long)c * jb.ldc;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int i = i0 + wr + 16 * bi + q;
+        if (i < jb.M) col[i] = col[i] - mk(dr[bc][bi][r], di[bc][bi][r]);
+      }
+    }
+}
+
 template <typename T>
 __global__ void axpby_kernel(const AxpbyJob<T> *__restrict__ jobs) {
   const AxpbyJob<T> jb = jobs[blockIdx.z];
@@ -510,6 +579,14 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
 }
 
 template <typename T>
+void launch_gemm_sub(int count, const GemmJob<T> *jobs, int max_m, int max_n, hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(gemm_sub_mfma_kernel<T>, dim3(ceil_div(max_m, kTile), ceil_div(max_n, kTile), count),
+                     dim3(256), 0, st, jobs);
+  HSSX_HIP(hipGetLastError());
+}
+
+template <typename T>
 void launch_axpby(int count, const AxpbyJob<T> *jobs, int max_m, int max_n, hipStream_t st) {
   if (count <= 0 || max_m <= 0 || max_n <= 0) return;
   hipLaunchKernelGGL(axpby_kernel<T>, dim3(ceil_div(max_m, 256), max_n, count), dim3(256), 0,
@@ -531,7 +608,8 @@ HSSX_ASM(double, float)
   template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
                                      hipStream_t);                                          \
-  template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);
+  template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);           \
+  template void launch_gemm_sub<T>(int, const GemmJob<T> *, int, int, hipStream_t);
 HSSX_INST(double)
 HSSX_INST(float)
 #undef HSSX_INST
