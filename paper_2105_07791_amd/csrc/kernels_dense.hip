@@ -185,20 +185,32 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(const PanelJob<T> *__re
     }
     __syncthreads();
   }
-  // G = (L11 U11)^-1, one column per thread
+  // G = (L11 U11)^-1, one column per thread, the column in registers
+  // (unrolled substitutions; entries beyond nb stay zero)
   for (int c = tid; c < nb; c += kThreads) {
     cplx<T> z[kNB];
-    for (int i = 0; i < nb; ++i) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) {
       cplx<T> v = mk((T)(i == c ? 1 : 0), (T)0);
-      for (int j = 0; j < i; ++j) cfms(v, W[i + (long)j * rows], z[j]);
-      z[i] = v;
+      if (i < nb) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) cfms(v, W[i + (long)j * rows], z[j]);
+      }
+      z[i] = i < nb ? v : czero<T>();
     }
-    for (int i = nb - 1; i >= 0; --i) {
-      cplx<T> v = z[i];
-      for (int j = i + 1; j < nb; ++j) cfms(v, W[i + (long)j * rows], z[j]);
-      z[i] = v * cinv(W[i + (long)i * rows]);
+#pragma unroll
+    for (int i = kNB - 1; i >= 0; --i) {
+      if (i < nb) {
+        cplx<T> v = z[i];
+#pragma unroll
+        for (int j = i + 1; j < kNB; ++j)
+          if (j < nb) cfms(v, W[i + (long)j * rows], z[j]);
+        z[i] = v * cinv(W[i + (long)i * rows]);
+      }
     }
-    for (int i = 0; i < nb; ++i) jb.G[i + (long)c * nb] = z[i];
+#pragma unroll
+    for (int i = 0; i < kNB; ++i)
+      if (i < nb) jb.G[i + (long)c * nb] = z[i];
   }
 }
 
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
   __shared__ T sv[2][kPT / 64];
   __shared__ int si[2][kPT / 64];
   __shared__ cplx<T> prowb[2][NBW], trowb[2][NBW];
-  __shared__ cplx<T> LU[NBW][NBW + 1], Z[NBW][NBW + 1];
+  __shared__ cplx<T> LU[NBW][NBW + 1];
   const PanelJob<T> jb = jobs[blockIdx.x];
   const int rows = jb.ne - jb.p0, nb = jb.nb, tid = threadIdx.x;
   const long ld = jb.ld;
@@ -302,7 +314,9 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
       }
     }
   }
-  // L11 U11 to LDS, then G = (L11 U11)^-1, one column per thread (in LDS)
+  // L11 U11 to LDS, then G = (L11 U11)^-1, one column per thread with the
+  // column in registers (unrolled substitutions; LU read by broadcast).
+  // Entries beyond nb are zero (the panel columns past nb were loaded as 0).
   if (tid < nb) {
 #pragma unroll
     for (int c = 0; c < NBW; ++c) LU[tid][c] = w[0][c];
@@ -310,17 +324,26 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
   __syncthreads();
   if (tid < nb) {
     const int c = tid;
-    for (int i = 0; i < nb; ++i) {
+    cplx<T> z[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
       cplx<T> v = mk((T)(i == c ? 1 : 0), (T)0);
-      for (int j = 0; j < i; ++j) cfms(v, LU[i][j], Z[j][c]);
-      Z[i][c] = v;
+#pragma unroll
+      for (int j = 0; j < i; ++j) cfms(v, LU[i][j], z[j]);
+      z[i] = i < nb ? v : czero<T>();
     }
-    for (int i = nb - 1; i >= 0; --i) {
-      cplx<T> v = Z[i][c];
-      for (int j = i + 1; j < nb; ++j) cfms(v, LU[i][j], Z[j][c]);
-      Z[i][c] = v * cinv(LU[i][i]);
+#pragma unroll
+    for (int i = NBW - 1; i >= 0; --i) {
+      if (i < nb) {
+        cplx<T> v = z[i];
+#pragma unroll
+        for (int j = i + 1; j < NBW; ++j) cfms(v, LU[i][j], z[j]);
+        z[i] = v * cinv(LU[i][i]);
+      }
     }
-    for (int i = 0; i < nb; ++i) jb.G[i + (long)c * nb] = Z[i][c];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+      if (i < nb) jb.G[i + (long)c * nb] = z[i];
   }
 }
 
