@@ -396,7 +396,16 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   // the blocked path spreads the trailing update of larger fronts over many
   // workgroups
   for (const auto &j : jobs) (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
-  if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
+  // small fronts that fit in 64 KiB of LDS are eliminated there
+  std::vector<ElimJob<T>> in_lds, in_mem;
+  size_t lds = 0;
+  for (const auto &j : small) {
+    const size_t b = (size_t)j.m * j.ncols * sizeof(cplx<T>);
+    if (b <= 65536) { in_lds.push_back(j); lds = std::max(lds, b); }
+    else in_mem.push_back(j);
+  }
+  if (!in_lds.empty()) launch_eliminate<T>((int)in_lds.size(), sg.put(in_lds), err, st, lds);
+  if (!in_mem.empty()) launch_eliminate<T>((int)in_mem.size(), sg.put(in_mem), err, st);
   if (big.empty()) return;
   // scratch per job: pivots, G, Y, W
   long ysz = 0, wsz = 0;

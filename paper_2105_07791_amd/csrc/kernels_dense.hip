@@ -68,6 +68,69 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
   }
 }
 
+// Gauss-Jordan of a small front staged in LDS (dynamic shared memory holds
+// the m x ncols front with leading dimension m).  Per pivot: wave 0 finds
+// the pivot (DPP argmax, ties to the lowest row) and its inverse; one pass
+// over the columns exchanges the two rows and scales the pivot row; one pass
+// over (row, column) pairs applies the rank-1 update, every thread busy.
+// The pivot columns are written as the identity at the end (they are never
+// read again), and R = F(0:ne, ne:m) is negated on the way out.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T> *__restrict__ jobs,
+                                                                int *__restrict__ err_node) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T> *Fs = reinterpret_cast<cplx<T> *>(smem_raw);
+  __shared__ int s_piv;
+  __shared__ cplx<T> s_inv;
+  const ElimJob<T> jb = jobs[blockIdx.x];
+  const int m = jb.m, nc = jb.ncols, ne = jb.ne, tid = threadIdx.x;
+  const long ld = jb.ld;
+  for (int e = tid; e < m * nc; e += kThreads) {
+    const int i = e % m, j = e / m;
+    Fs[e] = jb.ptr[i + (long)j * ld];
+  }
+  __syncthreads();
+  for (int p = 0; p < ne; ++p) {
+    if (tid < 64) {
+      T best = (T)-1;
+      int bi = 0x7fffffff;
+      for (int i = p + tid; i < ne; i += 64) {
+        const T a = cabs1(Fs[i + p * m]);
+        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+      }
+      wave_argmax(best, bi);
+      if (tid == 0) {
+        const bool zero = !(best > (T)0);
+        if (zero) atomicCAS(err_node, -1, jb.node);
+        s_piv = zero ? p : bi;
+        s_inv = zero ? czero<T>() : cinv(Fs[bi + p * m]);
+      }
+    }
+    __syncthreads();
+    const int pv = s_piv;
+    const cplx<T> inv = s_inv;
+    for (int j = p + tid; j < nc; j += kThreads) {
+      const cplx<T> a = Fs[p + j * m], b = Fs[pv + j * m];
+      Fs[pv + j * m] = a;
+      Fs[p + j * m] = j == p ? mk((T)1, (T)0) : b * inv;
+    }
+    __syncthreads();
+    const int w = nc - p - 1;
+    for (int e = tid; e < m * w; e += kThreads) {
+      const int i = e % m, j = p + 1 + e / m;
+      if (i != p) cfms(Fs[i + j * m], Fs[i + p * m], Fs[p + j * m]);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * nc; e += kThreads) {
+    const int i = e % m, j = e / m;
+    cplx<T> v = Fs[e];
+    if (j < ne) v = mk((T)(i == j ? 1 : 0), (T)0);
+    else if (jb.negate_r && i < ne && j < m) v = -v;
+    jb.ptr[i + (long)j * ld] = v;
+  }
+}
+
 template <typename T>
 __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   // wave reduction then across waves; ties keep the smaller index
@@ -573,9 +636,14 @@ void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
 }
 
 template <typename T>
-void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st) {
+void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
+                      size_t lds_bytes) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(eliminate_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
+  if (lds_bytes > 0)
+    hipLaunchKernelGGL(eliminate_lds_kernel<T>, dim3(count), dim3(kThreads), lds_bytes, st, jobs,
+                       err_node);
+  else
+    hipLaunchKernelGGL(eliminate_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -628,7 +696,7 @@ HSSX_ASM(double, float)
 #undef HSSX_ASM
 
 #define HSSX_INST(T)                                                                        \
-  template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t);           \
+  template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t, size_t);   \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
                                      hipStream_t);                                          \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);           \
