@@ -395,18 +395,28 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   // single-workgroup elimination for fronts with few pivots and few rows;
   // the blocked path spreads the trailing update of larger fronts over many
   // workgroups
-  for (const auto &j : jobs) (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
-  // small fronts that fit in 64 KiB of LDS are eliminated there
-  std::vector<ElimJob<T>> in_lds, in_mem;
+  // fronts with few pivots whose pivot rows fit in LDS are eliminated there
+  // (pivot rows only; the others follow by the product below), the rest of
+  // the few-pivot fronts in one workgroup from global memory
+  constexpr size_t kLdsMax = 156 * 1024;   // of the 160 KiB per workgroup
+  std::vector<ElimJob<T>> in_lds, rows_done;
   size_t lds = 0;
-  for (const auto &j : small) {
-    const size_t b = (size_t)j.m * j.ncols * sizeof(cplx<T>);
-    if (b <= 65536) { in_lds.push_back(j); lds = std::max(lds, b); }
-    else in_mem.push_back(j);
+  for (const auto &j : jobs) {
+    const size_t b = (size_t)j.ne * j.ncols * sizeof(cplx<T>);
+    if (j.ne < kSmall && j.ne > 0 && b <= kLdsMax) {
+      ElimJob<T> q = j;
+      q.m = j.ne;
+      q.negate_r = 0;
+      in_lds.push_back(q);
+      rows_done.push_back(j);
+      lds = std::max(lds, b);
+    } else {
+      (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
+    }
   }
   if (!in_lds.empty()) launch_eliminate<T>((int)in_lds.size(), sg.put(in_lds), err, st, lds);
-  if (!in_mem.empty()) launch_eliminate<T>((int)in_mem.size(), sg.put(in_mem), err, st);
-  if (big.empty()) return;
+  if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
+  if (big.empty() && rows_done.empty()) return;
   // scratch per job: pivots, G, Y, W
   long ysz = 0, wsz = 0;
   std::vector<long> yo, wo;
@@ -419,9 +429,9 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     steps = std::max(steps, ceil_div(j.ne, NB));
   }
   const Arena::Mark mk0 = ar.mark();
-  int *piv = ar.get<int>(big.size() * NB);
-  cplx<T> *G = ar.get<cplx<T>>(big.size() * NB * NB);
-  cplx<T> *Y = ar.get<cplx<T>>(ysz);
+  int *piv = ar.get<int>(std::max<size_t>(1, big.size()) * NB);
+  cplx<T> *G = ar.get<cplx<T>>(std::max<size_t>(1, big.size()) * NB * NB);
+  cplx<T> *Y = ar.get<cplx<T>>(std::max(1L, ysz));
   // the panel copy W is only read when a panel is too tall for registers
   int maxne = 0;
   for (const auto &j : big) maxne = std::max(maxne, j.ne);
@@ -457,6 +467,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   // non-pivot rows: F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols)
   std::vector<GemmJob<T>> gj;
   int gm = 0, gn = 0;
+  big.insert(big.end(), rows_done.begin(), rows_done.end());
   for (const auto &j : big) {
     if (j.m == j.ne || j.ne == 0) continue;
     const cplx<T> *Abi = j.ptr + j.ne, *Bx = j.ptr + (long)j.ne * j.ld;

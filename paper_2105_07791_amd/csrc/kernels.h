@@ -66,8 +66,8 @@ template <typename T> struct ElimJob {
   int ld, m, ncols, ne, negate_r;
   int node;         // reported on a zero pivot
 };
-// lds_bytes > 0: every job's m x ncols front fits in that much LDS (at most
-// 64 KiB) and runs staged there; 0: in global memory
+// lds_bytes > 0: every job's m x ncols block fits in that much LDS (at most
+// 156 KiB) and runs staged there; 0: in global memory
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                       size_t lds_bytes = 0);

@@ -639,9 +639,13 @@ template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                       size_t lds_bytes) {
   if (count <= 0) return;
-  if (lds_bytes > 0)
+  if (lds_bytes > 0) {
+    if (lds_bytes > 65536)
+      HSSX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&eliminate_lds_kernel<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     hipLaunchKernelGGL(eliminate_lds_kernel<T>, dim3(count), dim3(kThreads), lds_bytes, st, jobs,
                        err_node);
+  }
   else
     hipLaunchKernelGGL(eliminate_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
   HSSX_HIP(hipGetLastError());
