@@ -497,19 +497,27 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   for (int i = tid; i < rows; i += NT) perm[i] = i;
   __syncthreads();
   const int sub = tid % kTPR, slot = tid / kTPR, nslot = NT / kTPR;
+  // residual row norms (kTPR lanes per row, reduced by shuffles), indexed by
+  // original row; after the first they come from the projection pass, which
+  // sums the updated entries, so each pivot reads the block twice, not three
+  // times.  They live in the product staging area As, idle during the ID
+  // (16 x 128 complex >= kMaxRows reals).
+  T *rnorm = reinterpret_cast<T *>(&As[0][0]);
+  for (int pp0 = 0; pp0 < rows; pp0 += nslot) {
+    const int pp = pp0 + slot;
+    T nrm = 0;
+    if (pp < rows)
+      for (int j = sub; j < s; j += kTPR) nrm += abs2(Wm[pp + (long)j * rcap]);
+    for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
+    if (pp < rows && sub == 0) rnorm[pp] = nrm;
+  }
+  __syncthreads();
   for (; t < kmax; ++t) {
-    // residual row norms: kTPR lanes per row, reduced by shuffles
     T best = (T)-1;
     int bi = 0x7fffffff;
-    for (int pp0 = t; pp0 < rows; pp0 += nslot) {
-      const int pp = pp0 + slot;
-      T nrm = 0;
-      if (pp < rows) {
-        const int row = perm[pp];
-        for (int j = sub; j < s; j += kTPR) nrm += abs2(Wm[row + (long)j * rcap]);
-      }
-      for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
-      if (pp < rows && sub == 0 && (nrm > best || (nrm == best && pp < bi))) { best = nrm; bi = pp; }
+    for (int pp = t + tid; pp < rows; pp += NT) {
+      const T nrm = rnorm[perm[pp]];
+      if (nrm > best || (nrm == best && pp < bi)) { best = nrm; bi = pp; }
     }
     block_argmax<NT>(best, bi, sv, si);
     T pn = sqrt(best);
@@ -539,8 +547,16 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           d.re += __shfl_xor(d.re, o);
           d.im += __shfl_xor(d.im, o);
         }
+        T nrm = 0;
         if (act)
-          for (int j = sub; j < s; j += kTPR) cfms(Wm[row + (long)j * rcap], d, q[j]);
+          for (int j = sub; j < s; j += kTPR) {
+            cplx<T> v = Wm[row + (long)j * rcap];
+            cfms(v, d, q[j]);
+            Wm[row + (long)j * rcap] = v;
+            nrm += abs2(v);
+          }
+        for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
+        if (act && sub == 0) rnorm[row] = nrm;
         rr = rr + d;
       }
       if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
