@@ -220,7 +220,9 @@ class Arena {
     while (cur_ < chunks_.size() && off_ + need > chunks_[cur_]->bytes) {
       if (off_ == 0) {
         // an unused chunk that is too small: give its memory back (every
-        // chunk from cur_ on is unused, and released memory is idle)
+        // chunk from cur_ on is unused by the host; kernels queued before a
+        // release may still read it, so the device is drained first)
+        HSSX_HIP(hipDeviceSynchronize());
         chunks_.erase(chunks_.begin() + cur_);
         continue;
       }

@@ -361,9 +361,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool, d_rank, d_xh2,
                            maxlev + 1, max_width, max_ncl, st);
       prof_end("hss_matvec", st, pm2, 0.0);
-      // the round's pools are released below; wait for the expansion first
-      HSSX_HIP(hipStreamSynchronize(st));
     }
+    // the round's pools go back to the arena; later kernels that reuse the
+    // memory are ordered after the expansion on the same stream
     ar.release(round_mark);
     active.swap(next);
   }
@@ -488,8 +488,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     nn = std::max(nn, j.m - j.ne);
   }
   if (!neg.empty()) launch_axpby<T>((int)neg.size(), sg.put(neg), nm, nn, st);
-  // the panel scratch is released on return
-  HSSX_HIP(hipStreamSynchronize(st));
+  // the panel scratch is released on return (stream-ordered reuse)
   ar.release(mk0);
 }
 
