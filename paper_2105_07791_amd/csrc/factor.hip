@@ -414,7 +414,15 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
     }
   }
-  if (!in_lds.empty()) launch_eliminate<T>((int)in_lds.size(), sg.put(in_lds), err, st, lds);
+  if (!in_lds.empty()) {
+    // longest first: GJ work of the pivot rows, about ne^2 ncols
+    std::vector<ElimJob<T>> order = in_lds;
+    std::stable_sort(order.begin(), order.end(), [](const ElimJob<T> &a, const ElimJob<T> &b) {
+      return (long)a.ne * a.ne * a.ncols > (long)b.ne * b.ne * b.ncols;
+    });
+    int *queue = sg.put(std::vector<int>{0});
+    launch_eliminate<T>((int)order.size(), sg.put(order), err, st, lds, queue);
+  }
   if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
   if (big.empty() && rows_done.empty()) return;
   // scratch per job: pivots, G, Y, W

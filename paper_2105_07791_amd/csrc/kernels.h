@@ -67,10 +67,12 @@ template <typename T> struct ElimJob {
   int node;         // reported on a zero pivot
 };
 // lds_bytes > 0: every job's m x ncols block fits in that much LDS (at most
-// 156 KiB) and runs staged there; 0: in global memory
+// 156 KiB) and runs staged there, as a persistent launch whose workgroups
+// take jobs in list order from the device counter *queue (zero before the
+// launch); 0: one workgroup per job from global memory
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
-                      size_t lds_bytes = 0);
+                      size_t lds_bytes = 0, int *queue = nullptr);
 
 // Blocked Gauss-Jordan, one column panel P = [p0, p0 + nb) of one job per
 // entry (jobs of one launch may belong to different fronts):

@@ -75,15 +75,28 @@ __global__ __launch_bounds__(kThreads) void front_assemble_kernel(
 // over (row, column) pairs applies the rank-1 update, every thread busy.
 // The pivot columns are written as the identity at the end (they are never
 // read again), and R = F(0:ne, ne:m) is negated on the way out.
+//
+// Persistent launch over a work queue: the grid holds as many workgroups as
+// fit on the device at once, and each takes the next front from a device
+// counter (jobs are listed by decreasing cost, so the uneven fronts of a
+// level are balanced longest first).  Every workgroup leaves the loop once
+// the counter passes the job count.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T> *__restrict__ jobs,
+                                                                int count, int *__restrict__ queue,
                                                                 int *__restrict__ err_node) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *Fs = reinterpret_cast<cplx<T> *>(smem_raw);
-  __shared__ int s_piv;
+  __shared__ int s_piv, s_job;
   __shared__ cplx<T> s_inv;
-  const ElimJob<T> jb = jobs[blockIdx.x];
-  const int m = jb.m, nc = jb.ncols, ne = jb.ne, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  for (;;) {
+  if (tid == 0) s_job = atomicAdd(queue, 1);
+  __syncthreads();
+  const int job = s_job;
+  if (job >= count) break;
+  const ElimJob<T> jb = jobs[job];
+  const int m = jb.m, nc = jb.ncols, ne = jb.ne;
   const long ld = jb.ld;
   for (int e = tid; e < m * nc; e += kThreads) {
     const int i = e % m, j = e / m;
@@ -128,6 +141,8 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
     if (j < ne) v = mk((T)(i == j ? 1 : 0), (T)0);
     else if (jb.negate_r && i < ne && j < m) v = -v;
     jb.ptr[i + (long)j * ld] = v;
+  }
+  __syncthreads();   // Fs and s_job are reused by the next front
   }
 }
 
@@ -637,14 +652,22 @@ void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
 
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
-                      size_t lds_bytes) {
+                      size_t lds_bytes, int *queue) {
   if (count <= 0) return;
   if (lds_bytes > 0) {
+    HSSX_CHECK(queue != nullptr, HSSX_EINVAL, "LDS elimination needs a work-queue counter");
     if (lds_bytes > 65536)
       HSSX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&eliminate_lds_kernel<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-    hipLaunchKernelGGL(eliminate_lds_kernel<T>, dim3(count), dim3(kThreads), lds_bytes, st, jobs,
-                       err_node);
+    // as many workgroups as are resident at once: LDS (160 KiB per CU) and
+    // 8 workgroups of 256 threads per CU, 256 CUs
+    int dev = 0, cus = 256;
+    HSSX_HIP(hipGetDevice(&dev));
+    HSSX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (lds_bytes + 64))));
+    const int grid = std::max(1, std::min(count, cus * per_cu));
+    hipLaunchKernelGGL(eliminate_lds_kernel<T>, dim3(grid), dim3(kThreads), lds_bytes, st, jobs,
+                       count, queue, err_node);
   }
   else
     hipLaunchKernelGGL(eliminate_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
@@ -700,7 +723,8 @@ HSSX_ASM(double, float)
 #undef HSSX_ASM
 
 #define HSSX_INST(T)                                                                        \
-  template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t, size_t);   \
+  template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t, size_t,    \
+                                    int *);                                                 \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
                                      hipStream_t);                                          \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);           \
