@@ -246,18 +246,28 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     cplx<T> *d_scr = ar.get<cplx<T>>(scratch);
     HSSX_HIP(hipMemsetAsync(d_rank, 0, cls.size() * sizeof(int), st));
 
-    // ---- bottom-up compression, one launch per cluster-tree level
-    // (clusters of at most 64 rows in small workgroups, the others in large)
+    // ---- bottom-up compression, one launch per cluster-tree level and size
+    // class (clusters of at most 64 rows in small workgroups; the larger
+    // ones in large workgroups, split by whether they fit the register path)
     for (int lev = maxlev; lev >= 0; --lev) {
-      std::vector<HssItem> items[2];
+      std::vector<HssItem> items[3];
       for (size_t a = 0; a < active.size(); ++a) {
-        const auto &ct = tasks[active[a]].ct;
         for (int c = inst[a].lev_off[std::min(lev, inst[a].nlev)];
-             c < inst[a].lev_off[std::min(lev + 1, inst[a].nlev)]; ++c)
-          items[cls[inst[a].cl_off + c].rows_cap <= 64 ? 0 : 1].push_back(HssItem{(int)a, c});
-        (void)ct;
+             c < inst[a].lev_off[std::min(lev + 1, inst[a].nlev)]; ++c) {
+          const int rc = cls[inst[a].cl_off + c].rows_cap;
+          const bool reg = rc <= kRegRows && inst[a].s <= kRegCols;
+          items[rc <= 64 ? 0 : reg ? 1 : 2].push_back(HssItem{(int)a, c});
+        }
       }
-      for (int sz = 0; sz < 2; ++sz) {
+      // the one-barrier 1024-thread variant holds one workgroup per CU: used
+      // when the level's large clusters all fit it and do not outnumber the
+      // CUs (otherwise occupancy, or running with the global-memory ones in
+      // one launch, matters more)
+      if (items[1].size() > 256 || !items[2].empty()) {
+        items[2].insert(items[2].end(), items[1].begin(), items[1].end());
+        items[1].clear();
+      }
+      for (int sz = 0; sz < 3; ++sz) {
         if (items[sz].empty()) continue;
         HssItem *d_items = sg.put(items[sz]);
         double cflops = 0;
@@ -265,7 +275,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
           cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
         hipEvent_t pc = prof_begin(st);
         launch_compress_level<T>((int)items[sz].size(), d_items, d_inst, d_cls, d_pool, d_ipool,
-                                 d_rank, base, Y, Om, d_scr, id_tol, sz == 0, st);
+                                 d_rank, base, Y, Om, d_scr, id_tol, sz, st);
         prof_end("compress_level", st, pc, cflops);
       }
     }

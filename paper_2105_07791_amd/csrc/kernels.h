@@ -179,12 +179,15 @@ struct HssInstance {
 struct HssItem {
   int inst, cl;         // instance, cluster id within it
 };
-// small: every item's cluster has at most 64 rows (256-thread workgroups)
+// size_class 0: every item's cluster has at most 64 rows (256-thread
+// workgroups); 1: larger clusters that fit the 1024-thread register path
+// (at most kRegRows rows, s <= kRegCols; complex64); 2: any other cluster
+constexpr int kRegRows = 256, kRegCols = 192;
 template <typename T>
 void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
                            const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
                            const cplx<T> *front, const cplx<T> *Y, const double *Om,
-                           cplx<T> *scratch, double id_tol, bool small, hipStream_t st);
+                           cplx<T> *scratch, double id_tol, int size_class, hipStream_t st);
 // Per job (nc <= kXC columns of one instance): out = H X for the compressed
 // H, with X given (ldX) or the identity columns c0.. when X is null; if Yref
 // is given, add ||Yref - H X||_F^2 to *err2 and ||Yref||_F^2 to *ref2 (both

@@ -288,7 +288,12 @@ __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *
   }
 }
 
-template <typename T, int NT>
+// ONEB: the register path takes one barrier per pivot (each wavefront's best
+// row staged in LDS: in the product staging area for 256 threads, in a
+// buffer of its own for 1024); else two (pivot row broadcast after the
+// maxima).  The 1024-thread one-barrier variant is launched only for
+// clusters that fit the register path, since its buffer costs occupancy.
+template <typename T, int NT, bool ONEB>
 __global__ __launch_bounds__(NT) void compress_level_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
     const HssCluster *__restrict__ cls, cplx<T> *__restrict__ pool, int *__restrict__ ipool,
@@ -302,9 +307,15 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
   constexpr int kRT = CCfg<NT>::RT, kRS = NT / kRT, kRPT = CCfg<NT>::RPT, kRSEG = CCfg<NT>::RSEG;
-  // pivot rows and wavefront maxima of the register path, double-buffered by
-  // step parity
+  // register path: pivot rows (two-barrier steps, 1024 threads) or each
+  // wavefront's best row (one-barrier steps, 256 threads; held in the
+  // product staging area As, idle during the ID), and the wavefront maxima,
+  // double-buffered by step parity
   __shared__ cplx<T> qb[2][kRT * kRSEG];
+  constexpr int kOwnCand = (ONEB && NT != 256 && sizeof(T) == sizeof(float)) ? kRT * kRSEG : 1;
+  static_assert(NT != 1024 || (kRS * kRPT == kRegRows && kRT * kRSEG == kRegCols),
+                "host size classes must match the register-path capacity");
+  __shared__ cplx<T> own_cand[2][NT / 64][kOwnCand];
   __shared__ T sv2[2][NT / 64];
   __shared__ int si2[2][NT / 64];
   __shared__ cplx<T> As[16][128], Bs[16][128];
@@ -406,6 +417,117 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           w[r][c] = (row < rows && j < s) ? Sloc[row + (long)j * rcap] : czero<T>();
         }
       }
+      if constexpr (ONEB) {
+      constexpr int kC = kRT * kRSEG;
+      static_assert(NT != 256 || 2 * (NT / 64) * kC <= 16 * 128,
+                    "candidate rows exceed the staging area");
+      static_assert(NT == 256 || kOwnCand == kC, "one-barrier steps need the candidate buffer");
+      cplx<T>(*cand)[NT / 64][kC] =
+          NT == 256 ? reinterpret_cast<cplx<T>(*)[NT / 64][kC]>(&As[0][0])
+                    : reinterpret_cast<cplx<T>(*)[NT / 64][kC]>(&own_cand[0][0][0]);
+      // one barrier per pivot: every wavefront stages its best row (owner
+      // lanes) and its maximum in LDS before the barrier, so after it all
+      // threads pick the winner and read the pivot row without a second one;
+      // LDS buffers alternate between steps, picked rows are register flags
+      bool pk[kRPT];
+#pragma unroll
+      for (int r = 0; r < kRPT; ++r) pk[r] = false;
+      const int wv = tid / 64;
+      __syncthreads();
+      for (; t < kmax; ++t) {
+        const int par = t & 1;
+        T best = (T)-1;
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int r = 0; r < kRPT; ++r) {
+          const int row = slot + kRS * r;
+          T nrm = 0;
+#pragma unroll
+          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
+          nrm = group_sum<kRT>(nrm);
+          if (row < rows && !pk[r] && (nrm > best || (nrm == best && row < bi))) {
+            best = nrm;
+            bi = row;
+          }
+        }
+        wave_argmax(best, bi);
+        if (bi != 0x7fffffff && slot == bi % kRS) {
+          const int ro = bi / kRS;
+#pragma unroll
+          for (int r = 0; r < kRPT; ++r)
+            if (r == ro) {
+#pragma unroll
+              for (int c = 0; c < kRSEG; ++c) {
+                const int j = sub + kRT * c;
+                if (j < s) cand[par][wv][j] = w[r][c];
+              }
+            }
+        }
+        if ((tid & 63) == 0) { sv2[par][wv] = best; si2[par][wv] = bi; }
+        lds_barrier();
+        T v = sv2[par][0];
+        int vi = si2[par][0], ww = 0;
+#pragma unroll
+        for (int k = 1; k < NT / 64; ++k)
+          if (sv2[par][k] > v || (sv2[par][k] == v && si2[par][k] < vi)) {
+            v = sv2[par][k];
+            vi = si2[par][k];
+            ww = k;
+          }
+        const T pn = sqrt(v);
+        if (t == 0) first = pn;
+        if (!(pn > (T)0) || pn <= (T)id_tol * first) break;
+        const T inv = (T)1 / pn;
+        // pivot row p = cand * pn: q = p / pn is applied as inv * cand
+        const cplx<T> *qr = cand[par][ww];
+        if (slot == vi % kRS) {
+          const int ro = vi / kRS;
+#pragma unroll
+          for (int r = 0; r < kRPT; ++r)
+            if (r == ro) pk[r] = true;
+        }
+        if (tid == 0) {
+          perm[t] = vi;
+          Rm[t + (long)vi * C.k_cap] = mk(pn, (T)0);
+        }
+#pragma unroll
+        for (int r = 0; r < kRPT; ++r) {
+          const int row = slot + kRS * r;
+          const bool act = row < rows && !pk[r];
+          cplx<T> rr = czero<T>();
+          for (int pass = 0; pass < kPasses; ++pass) {
+            cplx<T> d = czero<T>();
+#pragma unroll
+            for (int c = 0; c < kRSEG; ++c) {
+              const int j = sub + kRT * c;
+              if (j < s) cfma(d, conj(qr[j]), w[r][c]);
+            }
+            d.re = inv * group_sum<kRT>(d.re);
+            d.im = inv * group_sum<kRT>(d.im);
+            if (act) {
+              const cplx<T> dq = inv * d;
+#pragma unroll
+              for (int c = 0; c < kRSEG; ++c) {
+                const int j = sub + kRT * c;
+                if (j < s) cfms(w[r][c], dq, qr[j]);
+              }
+            }
+            rr = rr + d;
+          }
+          if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
+        }
+      }
+      __syncthreads();
+      // the unselected rows follow the pivots in ascending order
+      if (tid == 0) {
+        for (int i = 0; i < rows; ++i) sel[i] = 0;
+        for (int a = 0; a < t; ++a) sel[perm[a]] = 1;
+        int pos = t;
+        for (int i = 0; i < rows; ++i)
+          if (!sel[i]) perm[pos++] = i;
+      }
+      __syncthreads();
+      } else {
       for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
       // two barriers per pivot: after the wavefront maxima and after the
@@ -486,6 +608,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           if (!sel[i]) perm[pos++] = i;
       }
       __syncthreads();
+      }
       reg_done = true;
     }
   }
@@ -849,14 +972,18 @@ template <typename T>
 void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
                            const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,
                            const cplx<T> *front, const cplx<T> *Y, const double *Om,
-                           cplx<T> *scratch, double id_tol, bool small, hipStream_t st) {
+                           cplx<T> *scratch, double id_tol, int size_class, hipStream_t st) {
   if (count <= 0) return;
-  if (small)
-    hipLaunchKernelGGL((compress_level_kernel<T, 256>), dim3(count), dim3(256), 0, st, items, inst,
-                       cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
-  else
-    hipLaunchKernelGGL((compress_level_kernel<T, 1024>), dim3(count), dim3(1024), 0, st, items,
+  constexpr bool kF32 = sizeof(T) == sizeof(float);
+  if (size_class == 0)
+    hipLaunchKernelGGL((compress_level_kernel<T, 256, kF32>), dim3(count), dim3(256), 0, st, items,
                        inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  else if (size_class == 1 && kF32)
+    hipLaunchKernelGGL((compress_level_kernel<T, 1024, kF32>), dim3(count), dim3(1024), 0, st,
+                       items, inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  else
+    hipLaunchKernelGGL((compress_level_kernel<T, 1024, false>), dim3(count), dim3(1024), 0, st,
+                       items, inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -883,7 +1010,7 @@ void launch_hss_matvec(int count, const MatvecJob<T> *jobs, const HssInstance *i
   template void launch_compress_level<T>(int, const HssItem *, const HssInstance *,           \
                                          const HssCluster *, cplx<T> *, int *, int *,         \
                                          const cplx<T> *, const cplx<T> *, const double *,    \
-                                         cplx<T> *, double, bool, hipStream_t);               \
+                                         cplx<T> *, double, int, hipStream_t);                \
   template void launch_hss_matvec<T>(int, const MatvecJob<T> *, const HssInstance *,          \
                                      const HssCluster *, const cplx<T> *, const int *,        \
                                      cplx<T> *, int, int, int, hipStream_t);
