@@ -68,21 +68,91 @@ __global__ void gaussian_kernel(const GaussJob *__restrict__ jobs, uint32_t seed
   jb.out[i + (long)(jb.c0 + jj - jb.cbase) * jb.ld] = g;
 }
 
-template <typename T>
-__global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
-  const SampleJob<T> jb = jobs[blockIdx.z];
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y;
-  if (i >= jb.m || j >= jb.nc) return;
-  cplx<T> acc = czero<T>();
-  const double *o = jb.Om + (long)j * jb.ldO;
-  for (int k = 0; k < jb.m; ++k) {
-    cplx<T> s = jb.S[i + (long)k * jb.ldS];
-    T w = (T)o[k];
-    acc.re += s.re * w;
-    acc.im += s.im * w;
+// Sampling on the matrix cores in the factor's real precision: the
+// complex-times-real product in its real view, Yr (2m x nc) = Sr (2m x m)
+// Omega (m x nc) with the re/im parts of S as interleaved rows, computed
+// transposed (D = Yr^T = Omega^T Sr^T) so that each output register of a lane
+// group holds 16 consecutive rows of one column of Y and the stores are
+// coalesced.  Four wavefronts cover a 64 x 64 tile of Yr as 2 x 2 blocks of
+// 32 x 32 and read their operands straight from global memory (the waves of a
+// tile share them through the vector L1).  One step of the K loop takes 16
+// sketch rows: lane group g feeds rows 4 g .. 4 g + 3 to the four 16x16x4
+// products (any split of the rows over the products gives the same sum).
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <typename T> struct SampleMma;
+template <> struct SampleMma<float> {
+  using V = floatx4;
+  __device__ static V fma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  jb.Y[i + (long)j * jb.ldY] = acc;
+  // row of D held by register r of lane group g
+  __device__ static int drow(int g, int r) { return 4 * g + r; }
+};
+template <> struct SampleMma<double> {
+  using V = doublex4;
+  __device__ static V fma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int g, int r) { return g + 4 * r; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
+  using M = SampleMma<T>;
+  const SampleJob<T> jb = jobs[blockIdx.z];
+  const int R = 2 * jb.m, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = blockIdx.x * 64 + 32 * (w & 1), wc = blockIdx.y * 64 + 32 * (w >> 1);
+  if (wr >= R || wc >= jb.nc) return;   // no barriers below: waves leave alone
+  const int q = lane & 15, g = lane >> 4;
+  const T *Sr = reinterpret_cast<const T *>(jb.S);
+  const long ldS = 2L * jb.ldS;
+  int ri[2], cj[2];
+  bool rok[2], cok[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    ri[b] = wr + 16 * b + q;
+    rok[b] = ri[b] < R;
+    cj[b] = wc + 16 * b + q;
+    cok[b] = cj[b] < jb.nc;
+  }
+  typename M::V d[2][2];
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) d[bc][bi] = typename M::V{0, 0, 0, 0};
+  for (int k0 = 0; k0 < jb.m; k0 += 16) {
+    T a[2][4], o[2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * g + u;
+      const bool kok = k < jb.m;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        a[b][u] = (rok[b] && kok) ? Sr[ri[b] + (long)k * ldS] : T(0);
+        o[b][u] = (cok[b] && kok) ? (T)jb.Om[k + (long)cj[b] * jb.ldO] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) d[bc][bi] = M::fma(o[bc][u], a[bi][u], d[bc][bi]);
+  }
+  // lane (q, g), register r: Yr row wr + 16 bi + q, column wc + 16 bc + drow(g, r)
+  T *Yr = reinterpret_cast<T *>(jb.Y);
+  const long ldY = 2L * jb.ldY;
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = wc + 16 * bc + M::drow(g, r);
+      if (j >= jb.nc) continue;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        if (rok[bi]) Yr[ri[bi] + (long)j * ldY] = d[bc][bi][r];
+    }
 }
 
 // bf16 sampling (complex64 only): the complex-times-real product in its real
@@ -94,7 +164,6 @@ __global__ void sample_kernel(const SampleJob<T> *__restrict__ jobs) {
 // products, about 16 significant bits).  One wavefront per 16 x 16 output
 // tile; four wavefronts per workgroup stack their tiles over rows.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned bf16_bits(float f) {
   unsigned u = __float_as_uint(f);
@@ -954,8 +1023,8 @@ void launch_gaussian(int count, const GaussJob *jobs, uint32_t seed, int max_m, 
 template <typename T>
 void launch_sample(int count, const SampleJob<T> *jobs, int max_m, int max_nc, hipStream_t st) {
   if (count <= 0 || max_m <= 0 || max_nc <= 0) return;
-  hipLaunchKernelGGL(sample_kernel<T>, dim3(ceil_div(max_m, 256), max_nc, count), dim3(256), 0,
-                     st, jobs);
+  hipLaunchKernelGGL(sample_kernel<T>, dim3(ceil_div(2L * max_m, 64), ceil_div(max_nc, 64), count),
+                     dim3(256), 0, st, jobs);
   HSSX_HIP(hipGetLastError());
 }
 
