@@ -425,6 +425,150 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
   }
 }
 
+// Tall panels (more rows than the register file of one workgroup holds):
+// the rows stay in the panel copy W (global memory, L2-resident).  Panel row
+// i belongs to thread i mod kTT for the whole panel, so a thread only reads
+// rows it wrote itself; the pivot row and the row it displaces reach the
+// other threads through LDS (double-buffered by step parity: two barriers
+// per step).  The pivot search issues the loads of all of a thread's rows at
+// once; the update then takes the rows one at a time (a whole row per load
+// batch).  Same results as panel_kernel (cabs1 pivots, lowest row on ties).
+constexpr int kTT = 512;
+template <typename T, int NBW, int RQ>
+__global__ __launch_bounds__(kTT) void panel_tall_kernel(const PanelJob<T> *__restrict__ jobs,
+                                                         int *__restrict__ err_node) {
+  __shared__ T sv[2][kTT / 64];
+  __shared__ int si[2][kTT / 64];
+  __shared__ cplx<T> prowb[2][NBW], trowb[2][NBW];
+  __shared__ cplx<T> LU[NBW][NBW + 1];
+  const PanelJob<T> jb = jobs[blockIdx.x];
+  const int rows = jb.ne - jb.p0, nb = jb.nb, tid = threadIdx.x;
+  const long ld = jb.ld;
+  cplx<T> *W = jb.W;
+#pragma unroll 1
+  for (int q = 0; q < RQ; ++q) {
+    const int i = tid + kTT * q;
+    if (i >= rows) break;
+    cplx<T> r[NBW];
+#pragma unroll
+    for (int c = 0; c < NBW; ++c)
+      r[c] = c < nb ? jb.F[(jb.p0 + i) + (long)(jb.p0 + c) * ld] : czero<T>();
+#pragma unroll
+    for (int c = 0; c < NBW; ++c)
+      if (c < nb) W[i + (long)c * rows] = r[c];
+  }
+  for (int t = 0; t < nb; ++t) {
+    const int par = t & 1;
+    cplx<T> *prow = prowb[par], *trow = trowb[par];
+    T best = (T)-1;
+    int bi = 0x7fffffff;
+    T a[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kTT * q;
+      a[q] = (i >= t && i < rows) ? cabs1(W[i + (long)t * rows]) : (T)-1;
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+      if (a[q] > best) { best = a[q]; bi = tid + kTT * q; }   // rows ascend with q
+    wave_argmax(best, bi);
+    if ((tid & 63) == 0) { sv[par][tid / 64] = best; si[par][tid / 64] = bi; }
+    lds_barrier();
+    best = sv[par][0];
+    bi = si[par][0];
+#pragma unroll
+    for (int k = 1; k < kTT / 64; ++k)
+      if (sv[par][k] > best || (sv[par][k] == best && si[par][k] < bi)) {
+        best = sv[par][k];
+        bi = si[par][k];
+      }
+    const bool zero = !(best > (T)0);
+    if (zero && tid == 0) atomicCAS(err_node, -1, jb.node);
+    const int pv = zero ? t : bi;
+    if (tid == 0) jb.piv[t] = jb.p0 + pv;
+    // the owners of rows pv and t publish them
+#pragma unroll 1
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kTT * q;
+      if (i != pv && i != t) continue;
+      cplx<T> r[NBW];
+#pragma unroll
+      for (int c = 0; c < NBW; ++c) r[c] = c < nb ? W[i + (long)c * rows] : czero<T>();
+      if (i == pv) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) prow[c] = r[c];
+      }
+      if (i == t) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) trow[c] = r[c];
+      }
+    }
+    lds_barrier();
+    const cplx<T> inv = zero ? czero<T>() : cinv(prow[t]);
+#pragma unroll 1
+    for (int q = 0; q < RQ; ++q) {
+      const int i = tid + kTT * q;
+      if (i >= rows) break;
+      if (i < t) continue;
+      if (i == t) {
+        // row t takes the pivot row (the U row stays unscaled)
+#pragma unroll
+        for (int c = 0; c < NBW; ++c)
+          if (c < nb) W[i + (long)c * rows] = prow[c];
+        continue;
+      }
+      // row pv takes the displaced row t; every row below t is updated
+      const bool sw = i == pv;
+      cplx<T> r[NBW];
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        r[c] = sw ? trow[c] : ((c >= t && c < nb) ? W[i + (long)c * rows] : czero<T>());
+      cplx<T> l = czero<T>();
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        if (c == t) l = r[c] * inv;
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        if (c > t && c < nb) cfms(r[c], l, prow[c]);
+#pragma unroll
+      for (int c = 0; c < NBW; ++c) {
+        if (c == t) W[i + (long)c * rows] = l;
+        else if ((c > t || sw) && c < nb) W[i + (long)c * rows] = r[c];
+      }
+    }
+  }
+  // L11 U11 (rows 0 .. nb - 1, owned by threads 0 .. nb - 1) to LDS, then
+  // G = (L11 U11)^-1 as in panel_reg_kernel
+  if (tid < nb) {
+#pragma unroll
+    for (int c = 0; c < NBW; ++c) LU[tid][c] = c < nb ? W[tid + (long)c * rows] : czero<T>();
+  }
+  __syncthreads();
+  if (tid < nb) {
+    const int c = tid;
+    cplx<T> z[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      cplx<T> v = mk((T)(i == c ? 1 : 0), (T)0);
+#pragma unroll
+      for (int j = 0; j < i; ++j) cfms(v, LU[i][j], z[j]);
+      z[i] = i < nb ? v : czero<T>();
+    }
+#pragma unroll
+    for (int i = NBW - 1; i >= 0; --i) {
+      if (i < nb) {
+        cplx<T> v = z[i];
+#pragma unroll
+        for (int j = i + 1; j < NBW; ++j) cfms(v, LU[i][j], z[j]);
+        z[i] = v * cinv(LU[i][i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+      if (i < nb) jb.G[i + (long)c * nb] = z[i];
+  }
+}
+
 template <typename T>
 __global__ void swap_kernel(const PanelJob<T> *__restrict__ jobs) {
   const PanelJob<T> jb = jobs[blockIdx.y];
@@ -686,6 +830,12 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
     hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 2>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
   else if (max_nb <= NBW && max_prows <= 3 * kPT)
     hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 3>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= 4 * kTT)
+    hipLaunchKernelGGL((panel_tall_kernel<T, NBW, 4>), dim3(count), dim3(kTT), 0, st, jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= 8 * kTT)
+    hipLaunchKernelGGL((panel_tall_kernel<T, NBW, 8>), dim3(count), dim3(kTT), 0, st, jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= 12 * kTT)
+    hipLaunchKernelGGL((panel_tall_kernel<T, NBW, 12>), dim3(count), dim3(kTT), 0, st, jobs, err_node);
   else
     hipLaunchKernelGGL(panel_kernel<T>, dim3(count), dim3(kThreads), 0, st, jobs, err_node);
   hipLaunchKernelGGL(swap_kernel<T>, dim3(ceil_div(max_cols, 256), count), dim3(256), 0, st, jobs);
