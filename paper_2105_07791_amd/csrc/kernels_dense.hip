@@ -317,9 +317,12 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     for (int c = 0; c < NBW; ++c)
       w[q][c] = (i < rows && c < nb) ? jb.F[(jb.p0 + i) + (long)(jb.p0 + c) * ld] : czero<T>();
   }
-  // the pivot step t is a runtime index; every register access goes through
-  // compile-time column indices with predicates
-  for (int t = 0; t < nb; ++t) {
+  // the pivot steps are unrolled, so t and every column index are
+  // compile-time constants: no per-column predicates on the step, and the
+  // update touches only the columns right of the pivot
+#pragma clang loop unroll(full)
+  for (int t = 0; t < NBW; ++t) {
+    if (t < nb) {
     const int par = t & 1;
     cplx<T> *prow = prowb[par], *trow = trowb[par];
     T best = (T)-1;
@@ -390,6 +393,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
           else if (c > t) cfms(w[q][c], l, prow[c]);
         }
       }
+    }
     }
   }
   // L11 U11 to LDS, then G = (L11 U11)^-1, one column per thread with the
