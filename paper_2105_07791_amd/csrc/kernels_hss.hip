@@ -907,14 +907,27 @@ __global__ __launch_bounds__(kMT) void mv_couple_kernel(const MatvecJob<T> *__re
   cplx<T> *W = scratch + jb.woff;
   cplx<T> *yl = W + L.XH + (long)L.k_cap * kXC, *yr = W + R.XH + (long)R.k_cap * kXC;
   const cplx<T> *xl = W + L.XH, *xr = W + R.XH;
-  mv_block<T, false>(
-      kl, kr, nc, [&](int a, int b) { return B12[a + (long)b * kl]; },
-      [&](int b, int j) { return xr[b + (long)j * kr]; },
-      [&](int a, int j, cplx<T> v) { yl[a + (long)j * kl] = v; }, As, Xs);
-  mv_block<T, false>(
-      kr, kl, nc, [&](int a, int b) { return B21[a + (long)b * kr]; },
-      [&](int b, int j) { return xl[b + (long)j * kl]; },
-      [&](int a, int j, cplx<T> v) { yr[a + (long)j * kr] = v; }, As, Xs);
+  // identity columns outside a child give it a zero up-sweep vector (see
+  // mv_up_kernel), so the sibling's coupling product is zero
+  auto outside = [&](const HssCluster &h) {
+    return !jb.X && (h.start + h.size <= jb.c0 || h.start >= jb.c0 + nc);
+  };
+  if (outside(R)) {
+    for (int e = threadIdx.x; e < kl * nc; e += kMT) yl[e] = czero<T>();
+  } else {
+    mv_block<T, false>(
+        kl, kr, nc, [&](int a, int b) { return B12[a + (long)b * kl]; },
+        [&](int b, int j) { return xr[b + (long)j * kr]; },
+        [&](int a, int j, cplx<T> v) { yl[a + (long)j * kl] = v; }, As, Xs);
+  }
+  if (outside(L)) {
+    for (int e = threadIdx.x; e < kr * nc; e += kMT) yr[e] = czero<T>();
+  } else {
+    mv_block<T, false>(
+        kr, kl, nc, [&](int a, int b) { return B21[a + (long)b * kr]; },
+        [&](int b, int j) { return xl[b + (long)j * kl]; },
+        [&](int a, int j, cplx<T> v) { yr[a + (long)j * kr] = v; }, As, Xs);
+  }
 }
 
 template <typename T>
@@ -970,11 +983,17 @@ __global__ __launch_bounds__(kMT) void mv_leaf_kernel(const MatvecJob<T> *__rest
   const cplx<T> *U = pool + I.pool + cc.U, *D = pool + I.pool + cc.D;
   const cplx<T> *yh = scratch + jb.woff + cc.XH + (long)cc.k_cap * kXC;
   double e2 = 0.0, r2 = 0.0;
-  // out = [D U] [X rows; yh]
+  // out = [D U] [X rows; yh]; identity columns outside the leaf make its X
+  // rows zero, and the product starts at the U block (lo = rows)
+  const int lo = (!jb.X && (cc.start + rows <= jb.c0 || cc.start >= jb.c0 + nc)) ? rows : 0;
   mv_block<T, false>(
-      rows, rows + k, nc,
-      [&](int i, int l) { return l < rows ? D[i + (long)l * rows] : U[i + (long)(l - rows) * rows]; },
+      rows, rows + k - lo, nc,
+      [&](int i, int l) {
+        l += lo;
+        return l < rows ? D[i + (long)l * rows] : U[i + (long)(l - rows) * rows];
+      },
       [&](int l, int j) {
+        l += lo;
         if (l >= rows) return yh[(l - rows) + (long)j * k];
         const int gl = cc.start + l;
         const T v = jb.X ? (T)jb.X[gl + (long)j * jb.ldX] : (T)(gl == jb.c0 + j ? 1 : 0);
