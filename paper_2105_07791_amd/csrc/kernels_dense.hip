@@ -643,15 +643,25 @@ __global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<T> *__r
   if (i0 >= jb.m || j0 >= J) return;
   const int nb = jb.nb, tid = threadIdx.x;
   const long ld = jb.ld;
-  // panel columns beyond nb are zero so that the K loop runs in steps of 4
-  for (int e = tid; e < kTile * KB; e += 256) {
-    int r = e % kTile, t = e / kTile;
-    int i = i0 + r;
-    As[r][t] = (i < jb.m && t < nb) ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<T>();
+  // panel columns beyond nb are zero so that the K loop runs in steps of 4.
+  // All global loads are issued before the LDS writes: the loads go through
+  // generic pointers that may alias LDS, so interleaving them with the
+  // writes would wait out each load before the next.
+  constexpr int kPE = kTile * KB / 256;
+  cplx<T> ra[kPE], ry[kPE];
+#pragma unroll
+  for (int u = 0; u < kPE; ++u) {
+    const int e = tid + 256 * u;
+    const int r = e % kTile, t = e / kTile, i = i0 + r;
+    ra[u] = (i < jb.m && t < nb) ? jb.F[i + (long)(jb.p0 + t) * ld] : czero<T>();
+    const int ty = e % KB, c = e / KB;
+    ry[u] = ((j0 + c) < J && ty < nb) ? jb.Y[ty + (long)(j0 + c) * nb] : czero<T>();
   }
-  for (int e = tid; e < kTile * KB; e += 256) {
-    int t = e % KB, c = e / KB;
-    Ys[t][c] = ((j0 + c) < J && t < nb) ? jb.Y[t + (long)(j0 + c) * nb] : czero<T>();
+#pragma unroll
+  for (int u = 0; u < kPE; ++u) {
+    const int e = tid + 256 * u;
+    As[e % kTile][e / kTile] = ra[u];
+    Ys[e % KB][e / KB] = ry[u];
   }
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
@@ -684,7 +694,22 @@ __global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<T> *__r
       }
   }
   // lane (q, kq), register r: C row i0 + wr + 16 bi + q, column
-  // j0 + wc + 16 bc + drow(kq, r) (the output row of D)
+  // j0 + wc + 16 bc + drow(kq, r) (the output row of D).  The tile of C is
+  // read completely before the first store (see the staging above).
+  cplx<T> cv[2][4][2];
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = j0 + wc + 16 * bc + M::drow(kq, r);
+      const cplx<T> *col = jb.F + (long)(jb.p0 + nb + c) * ld;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int i = i0 + wr + 16 * bi + q;
+        const bool upd = c < J && i < jb.m && !(i >= jb.p0 && i < jb.p0 + nb);
+        cv[bc][r][bi] = upd ? col[i] : czero<T>();
+      }
+    }
 #pragma unroll
   for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
@@ -697,7 +722,7 @@ __global__ __launch_bounds__(256) void gemm_b_mfma_kernel(const PanelJob<T> *__r
         const int i = i0 + wr + 16 * bi + q;
         if (i >= jb.m) continue;
         if (i >= jb.p0 && i < jb.p0 + nb) col[i] = Ys[i - jb.p0][cl];
-        else col[i] = col[i] - mk(dr[bc][bi][r], di[bc][bi][r]);
+        else col[i] = cv[bc][r][bi] - mk(dr[bc][bi][r], di[bc][bi][r]);
       }
     }
 }
@@ -726,15 +751,25 @@ __global__ __launch_bounds__(256) void gemm_sub_mfma_kernel(const GemmJob<T> *__
       dr[bc][bi] = typename M::V{0, 0, 0, 0};
       di[bc][bi] = typename M::V{0, 0, 0, 0};
     }
+  constexpr int kPE = kTile * KB / 256;
   for (int k0 = 0; k0 < jb.K; k0 += KB) {
-    __syncthreads();
-    for (int e = tid; e < kTile * KB; e += 256) {
+    // all global loads of the chunk before its LDS writes (generic pointers
+    // may alias LDS: interleaved, each load would be waited out)
+    cplx<T> ra[kPE], rb[kPE];
+#pragma unroll
+    for (int u = 0; u < kPE; ++u) {
+      const int e = tid + 256 * u;
       const int r = e % kTile, t = e / kTile, i = i0 + r, k = k0 + t;
-      As[r][t] = (i < jb.M && k < jb.K) ? jb.A[i + (long)k * jb.lda] : czero<T>();
+      ra[u] = (i < jb.M && k < jb.K) ? jb.A[i + (long)k * jb.lda] : czero<T>();
+      const int tb = e % KB, c = e / KB, kb = k0 + tb, j = j0 + c;
+      rb[u] = (j < jb.N && kb < jb.K) ? jb.B[kb + (long)j * jb.ldb] : czero<T>();
     }
-    for (int e = tid; e < kTile * KB; e += 256) {
-      const int t = e % KB, c = e / KB, k = k0 + t, j = j0 + c;
-      Bs[t][c] = (j < jb.N && k < jb.K) ? jb.B[k + (long)j * jb.ldb] : czero<T>();
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPE; ++u) {
+      const int e = tid + 256 * u;
+      As[e % kTile][e / kTile] = ra[u];
+      Bs[e % KB][e / KB] = rb[u];
     }
     __syncthreads();
 #pragma unroll
@@ -756,6 +791,20 @@ __global__ __launch_bounds__(256) void gemm_sub_mfma_kernel(const GemmJob<T> *__
         }
     }
   }
+  // the tile of C is read completely before the first store
+  cplx<T> cv[2][4][2];
+#pragma unroll
+  for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = j0 + wc + 16 * bc + M::drow(kq, r);
+      const cplx<T> *col = jb.C + (long)c * jb.ldc;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int i = i0 + wr + 16 * bi + q;
+        cv[bc][r][bi] = (c < jb.N && i < jb.M) ? col[i] : czero<T>();
+      }
+    }
 #pragma unroll
   for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
@@ -766,7 +815,7 @@ __global__ __launch_bounds__(256) void gemm_sub_mfma_kernel(const GemmJob<T> *__
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
         const int i = i0 + wr + 16 * bi + q;
-        if (i < jb.M) col[i] = col[i] - mk(dr[bc][bi][r], di[bc][bi][r]);
+        if (i < jb.M) col[i] = cv[bc][r][bi] - mk(dr[bc][bi][r], di[bc][bi][r]);
       }
     }
 }

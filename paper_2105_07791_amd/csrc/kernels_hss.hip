@@ -258,6 +258,7 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
                         const cplx<T> *__restrict__ B, long ldb, const cplx<T> *C0, long ldc0,
                         cplx<T> *C, long ldc, cplx<T> (*As)[128], cplx<T> (*Bs)[128]) {
   constexpr int RU = sizeof(T) == sizeof(float) ? 4 : 2, TY = NT / 32, TM = TY * RU;
+  static_assert((16 * TM) % NT == 0 && (16 * 128) % NT == 0, "staging loads per thread");
   const int tid = threadIdx.x, tx = tid % 32, ty = tid / 32;
   for (int i0 = 0; i0 < M; i0 += TM)
     for (int j0 = 0; j0 < N; j0 += 128) {
@@ -267,19 +268,37 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = czero<T>();
       for (int k0 = 0; k0 < K; k0 += 16) {
-        __syncthreads();
-        for (int e = tid; e < 16 * TM; e += NT) {
+        // the chunk's global loads all go out before its LDS writes, so they
+        // are not waited out one by one
+        constexpr int kA = 16 * TM / NT, kB = 16 * 128 / NT;
+        cplx<T> ra[kA], rb[kB];
+#pragma unroll
+        for (int u = 0; u < kA; ++u) {
+          const int e = tid + NT * u;
           int kk, i;
           if (TA) { kk = e % 16; i = e / 16; }
           else { i = e % TM; kk = e / TM; }
           const int gi = i0 + i, gk = k0 + kk;
-          cplx<T> a = czero<T>();
-          if (gi < M && gk < K) a = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
-          As[kk][i] = a;
+          ra[u] = czero<T>();
+          if (gi < M && gk < K) ra[u] = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
         }
-        for (int e = tid; e < 16 * 128; e += NT) {
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int e = tid + NT * u;
           const int kk = e % 16, j = e / 16, gk = k0 + kk, gj = j0 + j;
-          Bs[kk][j] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : czero<T>();
+          rb[u] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : czero<T>();
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kA; ++u) {
+          const int e = tid + NT * u;
+          if (TA) As[e % 16][e / 16] = ra[u];
+          else As[e / TM][e % TM] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int e = tid + NT * u;
+          Bs[e % 16][e / 16] = rb[u];
         }
         __syncthreads();
 #pragma unroll 4
@@ -295,15 +314,27 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
             for (int v = 0; v < 4; ++v) cfma(acc[u][v], a[u], b[v]);
         }
       }
+      if (SUB) {
+        // C0 read completely before the first store of C
+        cplx<T> c0v[RU][4];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gi = i0 + ty + TY * u, gj = j0 + tx + 32 * v;
+            c0v[u][v] = (gi < M && gj < N) ? C0[gi + (long)gj * ldc0] : czero<T>();
+          }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = c0v[u][v] - acc[u][v];
+      }
 #pragma unroll
       for (int u = 0; u < RU; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int gi = i0 + ty + TY * u, gj = j0 + tx + 32 * v;
-          if (gi < M && gj < N) {
-            if (SUB) C[gi + (long)gj * ldc] = C0[gi + (long)gj * ldc0] - acc[u][v];
-            else C[gi + (long)gj * ldc] = acc[u][v];
-          }
+          if (gi < M && gj < N) C[gi + (long)gj * ldc] = acc[u][v];
         }
     }
   __syncthreads();
@@ -807,23 +838,42 @@ constexpr int kMT = 256;
 template <typename T, bool TA, typename AF, typename XF, typename PF>
 __device__ void mv_block(int M, int K, int nc, AF aload, XF xin, PF put, cplx<T> (*As)[65],
                          cplx<T> (*Xs)[kXC]) {
+  static_assert((32 * 64) % kMT == 0 && (32 * kXC) % kMT == 0, "staging loads per thread");
   const int tid = threadIdx.x, jj = tid % kXC, ab = tid / kXC;
   for (int a0 = 0; a0 < M; a0 += 64) {
     cplx<T> acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = czero<T>();
     for (int i0 = 0; i0 < K; i0 += 32) {
-      __syncthreads();
-      for (int e = tid; e < 32 * 64; e += kMT) {
+      // the chunk's global loads all go out before its LDS writes
+      constexpr int kA = 32 * 64 / kMT, kX = 32 * kXC / kMT;
+      cplx<T> ra[kA], rx[kX];
+#pragma unroll
+      for (int u = 0; u < kA; ++u) {
+        const int e = tid + kMT * u;
         int ii, aa;
         if (TA) { ii = e % 32; aa = e / 32; }
         else { aa = e % 64; ii = e / 64; }
         const int gi = i0 + ii, ga = a0 + aa;
-        As[ii][aa] = (gi < K && ga < M) ? aload(ga, gi) : czero<T>();
+        ra[u] = (gi < K && ga < M) ? aload(ga, gi) : czero<T>();
       }
-      for (int e = tid; e < 32 * kXC; e += kMT) {
+#pragma unroll
+      for (int u = 0; u < kX; ++u) {
+        const int e = tid + kMT * u;
         const int ii = e % 32, j = e / 32, gi = i0 + ii;
-        Xs[ii][j] = (gi < K && j < nc) ? xin(gi, j) : czero<T>();
+        rx[u] = (gi < K && j < nc) ? xin(gi, j) : czero<T>();
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kA; ++u) {
+        const int e = tid + kMT * u;
+        if (TA) As[e % 32][e / 32] = ra[u];
+        else As[e / 64][e % 64] = ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kX; ++u) {
+        const int e = tid + kMT * u;
+        Xs[e % 32][e / 32] = rx[u];
       }
       __syncthreads();
 #pragma unroll 8
