@@ -713,9 +713,22 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
     }
   }
   if (!reg_done) {
-  for (int e = tid; e < rows * s; e += NT) {
-    int i = e % rows, j = e / rows;
-    Wm[i + (long)j * rcap] = Sloc[i + (long)j * rcap];
+  // copies and row sweeps below take kGB elements per lane per batch, all
+  // loads of a batch before its stores: the pointers may alias, so a store
+  // between two loads would make each load wait for the previous one
+  constexpr int kGB = 8;
+  for (int e0 = tid; e0 < rows * s; e0 += NT * kGB) {
+    cplx<T> v[kGB];
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int e = e0 + NT * u;
+      v[u] = e < rows * s ? Sloc[e % rows + (long)(e / rows) * rcap] : czero<T>();
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int e = e0 + NT * u;
+      if (e < rows * s) Wm[e % rows + (long)(e / rows) * rcap] = v[u];
+    }
   }
   for (int i = tid; i < rows; i += NT) perm[i] = i;
   __syncthreads();
@@ -730,7 +743,17 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
     const int pp = pp0 + slot;
     T nrm = 0;
     if (pp < rows)
-      for (int j = sub; j < s; j += kTPR) nrm += abs2(Wm[pp + (long)j * rcap]);
+      for (int j0 = sub; j0 < s; j0 += kTPR * kGB) {
+        cplx<T> v[kGB];
+#pragma unroll
+        for (int u = 0; u < kGB; ++u) {
+          const int j = j0 + kTPR * u;
+          v[u] = j < s ? Wm[pp + (long)j * rcap] : czero<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < kGB; ++u)
+          if (j0 + kTPR * u < s) nrm += abs2(v[u]);
+      }
     for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
     if (pp < rows && sub == 0) rnorm[pp] = nrm;
   }
@@ -765,18 +788,41 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       for (int pass = 0; pass < kPasses; ++pass) {
         cplx<T> d = czero<T>();
         if (act)
-          for (int j = sub; j < s; j += kTPR) cfma(d, conj(q[j]), Wm[row + (long)j * rcap]);
+          for (int j0 = sub; j0 < s; j0 += kTPR * kGB) {
+            cplx<T> v[kGB];
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+              const int j = j0 + kTPR * u;
+              v[u] = j < s ? Wm[row + (long)j * rcap] : czero<T>();
+            }
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+              const int j = j0 + kTPR * u;
+              if (j < s) cfma(d, conj(q[j]), v[u]);
+            }
+          }
         for (int o = 1; o < kTPR; o <<= 1) {
           d.re += __shfl_xor(d.re, o);
           d.im += __shfl_xor(d.im, o);
         }
         T nrm = 0;
         if (act)
-          for (int j = sub; j < s; j += kTPR) {
-            cplx<T> v = Wm[row + (long)j * rcap];
-            cfms(v, d, q[j]);
-            Wm[row + (long)j * rcap] = v;
-            nrm += abs2(v);
+          for (int j0 = sub; j0 < s; j0 += kTPR * kGB) {
+            cplx<T> v[kGB];
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+              const int j = j0 + kTPR * u;
+              v[u] = j < s ? Wm[row + (long)j * rcap] : czero<T>();
+            }
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+              const int j = j0 + kTPR * u;
+              if (j < s) {
+                cfms(v[u], d, q[j]);
+                Wm[row + (long)j * rcap] = v[u];
+                nrm += abs2(v[u]);
+              }
+            }
           }
         for (int o = 1; o < kTPR; o <<= 1) nrm += __shfl_xor(nrm, o);
         if (act && sub == 0) rnorm[row] = nrm;
@@ -814,9 +860,18 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   int *sk = IP + C.sk;
   for (int a = tid; a < rk; a += NT) sk[a] = I_loc[perm[a]];
   cplx<T> *Omc = P + C.Om, *Src = P + C.Sr;
-  for (int e = tid; e < rk * s; e += NT) {
-    int a = e % rk, j = e / rk;
-    Src[a + (long)j * rk] = Sloc[perm[a] + (long)j * rcap];
+  for (int e0 = tid; e0 < rk * s; e0 += NT * 8) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u;
+      v[u] = e < rk * s ? Sloc[perm[e % rk] + (long)(e / rk) * rcap] : czero<T>();
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + NT * u;
+      if (e < rk * s) Src[e % rk + (long)(e / rk) * rk] = v[u];
+    }
   }
   // Om_c = U^T Om_loc
   wg_gemm<T, NT, true, false>(rk, s, rows, U, rows, Oloc, rcap, nullptr, 0, Omc, rk, As, Bs);
