@@ -445,23 +445,36 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
     for (int i = tid; i < rows; i += NT) I_loc[i] = C.start + i;
     __syncthreads();
     cplx<T> *D = P + C.D;
-    for (int e = tid; e < rows * rows; e += NT) {
-      int i = e % rows, l = e / rows;
-      D[e] = S[(C.start + i) + (long)(C.start + l) * ldS];
+    // D = S(I, I) and Om_loc = Om(I, :) (the real sketch as complex), copied
+    // in batches of loads ahead of their stores; then S_loc = Y(I, :) - D Om_loc
+    for (int e0 = tid; e0 < rows * rows; e0 += NT * 8) {
+      cplx<T> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + NT * u;
+        v[u] = e < rows * rows ? S[(C.start + e % rows) + (long)(C.start + e / rows) * ldS]
+                               : czero<T>();
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + NT * u < rows * rows) D[e0 + NT * u] = v[u];
+    }
+    for (int e0 = tid; e0 < rows * s; e0 += NT * 8) {
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + NT * u;
+        w[u] = e < rows * s ? Om[(C.start + e % rows) + (long)(e / rows) * ldO] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + NT * u;
+        if (e < rows * s) Oloc[e % rows + (long)(e / rows) * rcap] = mk((T)w[u], (T)0);
+      }
     }
     __syncthreads();
-    for (int e = tid; e < rows * s; e += NT) {
-      int i = e % rows, j = e / rows;
-      cplx<T> v = Y[(C.start + i) + (long)j * ldY];
-      for (int l = 0; l < rows; ++l) {
-        T w = (T)Om[(C.start + l) + (long)j * ldO];
-        cplx<T> d = D[i + (long)l * rows];
-        v.re -= d.re * w;
-        v.im -= d.im * w;
-      }
-      Sloc[i + (long)j * rcap] = v;
-      Oloc[i + (long)j * rcap] = mk((T)Om[(C.start + i) + (long)j * ldO], (T)0);
-    }
+    wg_gemm<T, NT, false, true>(rows, s, rows, D, rows, Oloc, rcap, Y + C.start, ldY, Sloc, rcap,
+                                As, Bs);
   } else {
     const HssCluster L = cls[I.cl_off + C.left], R = cls[I.cl_off + C.right];
     const int kl = rank[I.cl_off + C.left], kr = rank[I.cl_off + C.right];
@@ -469,20 +482,46 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
     const int *skl = IP + L.sk, *skr = IP + R.sk;
     for (int i = tid; i < rows; i += NT) I_loc[i] = i < kl ? skl[i] : skr[i - kl];
     cplx<T> *B12 = P + C.B12, *B21 = P + C.B21;
-    for (int e = tid; e < kl * kr; e += NT) {
-      int a = e % kl, b = e / kl;
-      B12[a + (long)b * kl] = S[skl[a] + (long)skr[b] * ldS];
-    }
-    for (int e = tid; e < kr * kl; e += NT) {
-      int a = e % kr, b = e / kr;
-      B21[a + (long)b * kr] = S[skr[a] + (long)skl[b] * ldS];
-    }
+    // B12 = S(sk_l, sk_r), B21 = S(sk_r, sk_l): skeleton indices, then the
+    // entries, then the stores, eight elements per lane at a time
+    auto gather = [&](cplx<T> *Bd, const int *ra, const int *cb, int na, int nb) {
+      for (int e0 = tid; e0 < na * nb; e0 += NT * 8) {
+        int ia[8], ib[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + NT * u;
+          const bool ok = e < na * nb;
+          ia[u] = ok ? ra[e % na] : 0;
+          ib[u] = ok ? cb[e / na] : 0;
+        }
+        cplx<T> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = e0 + NT * u < na * nb ? S[ia[u] + (long)ib[u] * ldS] : czero<T>();
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e0 + NT * u < na * nb) Bd[e0 + NT * u] = v[u];
+      }
+    };
+    gather(B12, skl, skr, kl, kr);
+    gather(B21, skr, skl, kr, kl);
     __syncthreads();
     if (it.cl != 0) {
       const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
-      for (int e = tid; e < rows * s; e += NT) {
-        int i = e % rows, j = e / rows;
-        Oloc[i + (long)j * rcap] = i < kl ? Oml[i + (long)j * kl] : Omr[(i - kl) + (long)j * kr];
+      for (int e0 = tid; e0 < rows * s; e0 += NT * 8) {
+        cplx<T> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + NT * u, i = e % rows, j = e / rows;
+          v[u] = e >= rows * s ? czero<T>()
+                 : i < kl      ? Oml[i + (long)j * kl]
+                               : Omr[(i - kl) + (long)j * kr];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + NT * u;
+          if (e < rows * s) Oloc[e % rows + (long)(e / rows) * rcap] = v[u];
+        }
       }
       // S_loc = [Sr_l - B12 Om_r ; Sr_r - B21 Om_l]
       wg_gemm<T, NT, false, true>(kl, s, kr, B12, kl, Omr, kr, Srl, kl, Sloc, rcap, As, Bs);
