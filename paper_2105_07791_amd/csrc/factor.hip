@@ -18,9 +18,9 @@
 // level by level, and estimate together; only those whose estimate
 // (eq. 2.7) misses the tolerance grow k <- k + r and go round again.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
-#include <array>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -249,6 +249,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     // ---- bottom-up compression, one launch per cluster-tree level and size
     // class (clusters of at most 64 rows in small workgroups; the larger
     // ones in large workgroups, split by whether they fit the register path)
+    // all levels' work lists go up in one upload
+    std::vector<HssItem> all_items;
+    std::vector<std::array<long, 4>> launches;   // level, size class, offset, count
     for (int lev = maxlev; lev >= 0; --lev) {
       std::vector<HssItem> items[3];
       for (size_t a = 0; a < active.size(); ++a) {
@@ -269,15 +272,21 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       }
       for (int sz = 0; sz < 3; ++sz) {
         if (items[sz].empty()) continue;
-        HssItem *d_items = sg.put(items[sz]);
-        double cflops = 0;
-        for (const auto &it : items[sz])
-          cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
-        hipEvent_t pc = prof_begin(st);
-        launch_compress_level<T>((int)items[sz].size(), d_items, d_inst, d_cls, d_pool, d_ipool,
-                                 d_rank, base, Y, Om, d_scr, id_tol, sz, st);
-        prof_end("compress_level", st, pc, cflops);
+        launches.push_back({lev, sz, (long)all_items.size(), (long)items[sz].size()});
+        all_items.insert(all_items.end(), items[sz].begin(), items[sz].end());
       }
+    }
+    HssItem *d_all = all_items.empty() ? nullptr : sg.put(all_items);
+    for (const auto &l : launches) {
+      double cflops = 0;
+      for (long e = l[2]; e < l[2] + l[3]; ++e) {
+        const auto &it = all_items[e];
+        cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
+      }
+      hipEvent_t pc = prof_begin(st);
+      launch_compress_level<T>((int)l[3], d_all + l[2], d_inst, d_cls, d_pool, d_ipool, d_rank,
+                               base, Y, Om, d_scr, id_tol, (int)l[1], st);
+      prof_end("compress_level", st, pc, cflops);
     }
 
     // ---- error estimate with r fresh probes (eq. 2.7), kXC columns per job
@@ -454,8 +463,11 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   int maxne = 0;
   for (const auto &j : big) maxne = std::max(maxne, j.ne);
   cplx<T> *W = maxne > 1536 ? ar.get<cplx<T>>(wsz) : nullptr;
+  // every panel step's job list goes up in one upload
+  std::vector<PanelJob<T>> all_pj;
+  std::vector<std::array<int, 6>> step_cfg;   // offset, count, max m, cols, panel rows, nb
   for (int k = 0; k < steps; ++k) {
-    std::vector<PanelJob<T>> pj;
+    const int off = (int)all_pj.size();
     int mm = 0, mc = 0, mp = 0, mnb = 0;
     for (size_t a = 0; a < big.size(); ++a) {
       const auto &j = big[a];
@@ -474,14 +486,17 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       q.Y = Y + yo[a];
       q.W = W ? W + wo[a] : nullptr;
       q.node = j.node;
-      pj.push_back(q);
+      all_pj.push_back(q);
       mm = std::max(mm, j.ne);
       mc = std::max(mc, j.ncols - p0);
       mp = std::max(mp, j.ne - p0);
       mnb = std::max(mnb, q.nb);
     }
-    launch_panel_step<T>((int)pj.size(), sg.put(pj), mm, mc, mp, mnb, err, st);
+    step_cfg.push_back({off, (int)all_pj.size() - off, mm, mc, mp, mnb});
   }
+  PanelJob<T> *d_pj = all_pj.empty() ? nullptr : sg.put(all_pj);
+  for (const auto &c : step_cfg)
+    launch_panel_step<T>(c[1], d_pj + c[0], c[2], c[3], c[4], c[5], err, st);
   // non-pivot rows: F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols)
   std::vector<GemmJob<T>> gj;
   int gm = 0, gn = 0;
