@@ -35,7 +35,7 @@ class _OperatorBase:
     """Calls shared by single-problem and batch operators (handle, n, device)."""
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._LIB is not None:
+        if getattr(self, "handle", None) and getattr(_lib, "_LIB", None) is not None:
             lib().hssx_op_destroy(self.handle)
             self.handle = None
 
@@ -183,7 +183,7 @@ class Factor:
         return self
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._LIB is not None:
+        if getattr(self, "handle", None) and getattr(_lib, "_LIB", None) is not None:
             lib().hssx_fact_destroy(self.handle)
             self.handle = None
 

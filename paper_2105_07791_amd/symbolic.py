@@ -47,7 +47,7 @@ class Analysis:
         self.handle = h
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._LIB is not None:
+        if getattr(self, "handle", None) and getattr(_lib, "_LIB", None) is not None:
             lib().hssx_fact_destroy(self.handle)
             self.handle = None
 
