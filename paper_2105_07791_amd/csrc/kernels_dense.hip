@@ -292,18 +292,19 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(const PanelJob<T> *__re
   }
 }
 
-// Register-resident panel factorization: 512 threads, thread tid owns panel
-// rows tid + 512 q (q < RQ) across all NBW columns; pivot search by
+// Register-resident panel factorization: NT threads (512, or 256 when no
+// panel of the launch has more rows), thread tid owns panel rows tid + NT q
+// (q < RQ) across all NBW columns; pivot search by
 // wavefront shuffles, the pivot row broadcast and row exchanges through LDS.
 // Same results as panel_kernel (cabs1 pivots, lowest row on ties).
 constexpr int kPT = 512;
-template <typename T, int NBW, int RQ>
-__global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__restrict__ jobs,
+template <typename T, int NBW, int RQ, int NT = kPT>
+__global__ __launch_bounds__(NT) void panel_reg_kernel(const PanelJob<T> *__restrict__ jobs,
                                                         int *__restrict__ err_node) {
   // wavefront maxima and exchanged rows, double-buffered by step parity so
   // that a step needs two barriers
-  __shared__ T sv[2][kPT / 64];
-  __shared__ int si[2][kPT / 64];
+  __shared__ T sv[2][NT / 64];
+  __shared__ int si[2][NT / 64];
   __shared__ cplx<T> prowb[2][NBW], trowb[2][NBW];
   __shared__ cplx<T> LU[NBW][NBW + 1];
   const PanelJob<T> jb = jobs[blockIdx.x];
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
   cplx<T> w[RQ][NBW];
 #pragma unroll
   for (int q = 0; q < RQ; ++q) {
-    const int i = tid + kPT * q;
+    const int i = tid + NT * q;
 #pragma unroll
     for (int c = 0; c < NBW; ++c)
       w[q][c] = (i < rows && c < nb) ? jb.F[(jb.p0 + i) + (long)(jb.p0 + c) * ld] : czero<T>();
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     int bi = 0x7fffffff;
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
-      const int i = tid + kPT * q;
+      const int i = tid + NT * q;
       cplx<T> wt = czero<T>();
 #pragma unroll
       for (int c = 0; c < NBW; ++c)
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     best = sv[par][0];
     bi = si[par][0];
 #pragma unroll
-    for (int k = 1; k < kPT / 64; ++k)
+    for (int k = 1; k < NT / 64; ++k)
       if (sv[par][k] > best || (sv[par][k] == best && si[par][k] < bi)) {
         best = sv[par][k];
         bi = si[par][k];
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     // exchange rows t and pv; the pivot row ends in prow
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
-      const int i = tid + kPT * q;
+      const int i = tid + NT * q;
       if (i == pv) {
 #pragma unroll
         for (int c = 0; c < NBW; ++c) prow[c] = w[q][c];
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
-      const int i = tid + kPT * q;
+      const int i = tid + NT * q;
       if (i == t) {
 #pragma unroll
         for (int c = 0; c < NBW; ++c) w[q][c] = prow[c];
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(kPT) void panel_reg_kernel(const PanelJob<T> *__res
     const cplx<T> inv = zero ? czero<T>() : cinv(prow[t]);
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
-      const int i = tid + kPT * q;
+      const int i = tid + NT * q;
       if (i > t && i < rows) {
         cplx<T> l = czero<T>();
 #pragma unroll
@@ -877,7 +878,10 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
                        int max_prows, int max_nb, int *err_node, hipStream_t st) {
   if (count <= 0) return;
   constexpr int NBW = sizeof(T) == sizeof(float) ? 32 : 16;
-  if (max_nb <= NBW && max_prows <= kPT)
+  if (max_nb <= NBW && max_prows <= kPT / 2)
+    hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 1, kPT / 2>), dim3(count), dim3(kPT / 2), 0, st,
+                       jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= kPT)
     hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 1>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
   else if (max_nb <= NBW && max_prows <= 2 * kPT)
     hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 2>), dim3(count), dim3(kPT), 0, st, jobs, err_node);
