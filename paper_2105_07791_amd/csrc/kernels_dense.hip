@@ -292,8 +292,8 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(const PanelJob<T> *__re
   }
 }
 
-// Register-resident panel factorization: NT threads (512, or 256 when no
-// panel of the launch has more rows), thread tid owns panel rows tid + NT q
+// Register-resident panel factorization: NT threads (512, or 256 / 128 when
+// no panel of the launch has more rows), thread tid owns panel rows tid + NT q
 // (q < RQ) across all NBW columns; pivot search by
 // wavefront shuffles, the pivot row broadcast and row exchanges through LDS.
 // Same results as panel_kernel (cabs1 pivots, lowest row on ties).
@@ -878,7 +878,10 @@ void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_co
                        int max_prows, int max_nb, int *err_node, hipStream_t st) {
   if (count <= 0) return;
   constexpr int NBW = sizeof(T) == sizeof(float) ? 32 : 16;
-  if (max_nb <= NBW && max_prows <= kPT / 2)
+  if (max_nb <= NBW && max_prows <= kPT / 4)
+    hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 1, kPT / 4>), dim3(count), dim3(kPT / 4), 0, st,
+                       jobs, err_node);
+  else if (max_nb <= NBW && max_prows <= kPT / 2)
     hipLaunchKernelGGL((panel_reg_kernel<T, NBW, 1, kPT / 2>), dim3(count), dim3(kPT / 2), 0, st,
                        jobs, err_node);
   else if (max_nb <= NBW && max_prows <= kPT)
