@@ -1003,11 +1003,12 @@ __global__ __launch_bounds__(kMT) void mv_up_kernel(int lev, const MatvecJob<T> 
   const int k = rank[I.cl_off + c], nc = jb.nc;
   cplx<T> *W = scratch + jb.woff;
   cplx<T> *xh = W + cc.XH;
-  if (!jb.X && (cc.start + cc.size <= jb.c0 || cc.start >= jb.c0 + nc)) {
-    // identity columns outside this cluster: its up-sweep vector is zero
-    for (int e = threadIdx.x; e < k * nc; e += kMT) xh[e] = czero<T>();
-    return;
-  }
+  // identity columns outside a cluster make its up-sweep vector zero; it is
+  // not stored, its readers (the parent here, mv_couple_kernel) test for it
+  auto outside = [&](const HssCluster &h) {
+    return !jb.X && (h.start + h.size <= jb.c0 || h.start >= jb.c0 + nc);
+  };
+  if (outside(cc)) return;
   const cplx<T> *U = pool + I.pool + cc.U;
   auto put = [&](int a, int j, cplx<T> v) { xh[a + (long)j * k] = v; };
   if (cc.left < 0) {
@@ -1021,10 +1022,13 @@ __global__ __launch_bounds__(kMT) void mv_up_kernel(int lev, const MatvecJob<T> 
     mv_block<T, true>(k, rows, nc, aload, xin, put, As, Xs);
   } else {
     const int kl = rank[I.cl_off + cc.left], kr = rank[I.cl_off + cc.right], rows = kl + kr;
-    const cplx<T> *xl = W + cls[I.cl_off + cc.left].XH, *xr = W + cls[I.cl_off + cc.right].XH;
+    const HssCluster L = cls[I.cl_off + cc.left], R = cls[I.cl_off + cc.right];
+    const bool lz = outside(L), rz = outside(R);
+    const cplx<T> *xl = W + L.XH, *xr = W + R.XH;
     auto aload = [&](int a, int i) { return U[i + (long)a * rows]; };
     auto xin = [&](int i, int j) {
-      return i < kl ? xl[i + (long)j * kl] : xr[(i - kl) + (long)j * kr];
+      if (i < kl) return lz ? czero<T>() : xl[i + (long)j * kl];
+      return rz ? czero<T>() : xr[(i - kl) + (long)j * kr];
     };
     mv_block<T, true>(k, rows, nc, aload, xin, put, As, Xs);
   }
