@@ -510,35 +510,59 @@ __global__ __launch_bounds__(kTT) void panel_tall_kernel(const PanelJob<T> *__re
     }
     lds_barrier();
     const cplx<T> inv = zero ? czero<T>() : cinv(prow[t]);
+    // two rows per batch: both rows' loads are in flight before either is
+    // updated and stored
+    static_assert(RQ % 2 == 0, "rows are updated in pairs");
 #pragma unroll 1
-    for (int q = 0; q < RQ; ++q) {
-      const int i = tid + kTT * q;
-      if (i >= rows) break;
-      if (i < t) continue;
-      if (i == t) {
-        // row t takes the pivot row (the U row stays unscaled)
+    for (int q = 0; q < RQ; q += 2) {
+      const int ia = tid + kTT * q, ib = ia + kTT;
+      if (ia >= rows) break;
+      // row t takes the pivot row (the U row stays unscaled)
+      if (ia == t || ib == t) {
+        const int it = ia == t ? ia : ib;
 #pragma unroll
         for (int c = 0; c < NBW; ++c)
-          if (c < nb) W[i + (long)c * rows] = prow[c];
-        continue;
+          if (c < nb) W[it + (long)c * rows] = prow[c];
       }
       // row pv takes the displaced row t; every row below t is updated
-      const bool sw = i == pv;
-      cplx<T> r[NBW];
-#pragma unroll
-      for (int c = 0; c < NBW; ++c)
-        r[c] = sw ? trow[c] : ((c >= t && c < nb) ? W[i + (long)c * rows] : czero<T>());
-      cplx<T> l = czero<T>();
-#pragma unroll
-      for (int c = 0; c < NBW; ++c)
-        if (c == t) l = r[c] * inv;
-#pragma unroll
-      for (int c = 0; c < NBW; ++c)
-        if (c > t && c < nb) cfms(r[c], l, prow[c]);
+      const bool ua = ia > t, ub = ib > t && ib < rows;
+      const bool swa = ia == pv, swb = ib == pv;
+      cplx<T> ra[NBW], rb[NBW];
 #pragma unroll
       for (int c = 0; c < NBW; ++c) {
-        if (c == t) W[i + (long)c * rows] = l;
-        else if ((c > t || sw) && c < nb) W[i + (long)c * rows] = r[c];
+        ra[c] = !ua ? czero<T>()
+                : swa ? trow[c]
+                : (c >= t && c < nb) ? W[ia + (long)c * rows] : czero<T>();
+        rb[c] = !ub ? czero<T>()
+                : swb ? trow[c]
+                : (c >= t && c < nb) ? W[ib + (long)c * rows] : czero<T>();
+      }
+      cplx<T> la = czero<T>(), lb = czero<T>();
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        if (c == t) {
+          la = ra[c] * inv;
+          lb = rb[c] * inv;
+        }
+#pragma unroll
+      for (int c = 0; c < NBW; ++c)
+        if (c > t && c < nb) {
+          cfms(ra[c], la, prow[c]);
+          cfms(rb[c], lb, prow[c]);
+        }
+      if (ua) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) {
+          if (c == t) W[ia + (long)c * rows] = la;
+          else if ((c > t || swa) && c < nb) W[ia + (long)c * rows] = ra[c];
+        }
+      }
+      if (ub) {
+#pragma unroll
+        for (int c = 0; c < NBW; ++c) {
+          if (c == t) W[ib + (long)c * rows] = lb;
+          else if ((c > t || swb) && c < nb) W[ib + (long)c * rows] = rb[c];
+        }
       }
     }
   }
