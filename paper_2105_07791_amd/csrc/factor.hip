@@ -31,6 +31,31 @@ namespace hssx {
 
 namespace {
 
+// A second stream per device and host thread (default priority) for launches
+// that may overlap the factor's own stream, with the events that fork work
+// onto it and join it back.  Thread-local, so concurrent factorizations on
+// different host threads never share one.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+SideStream &side_stream() {
+  thread_local std::map<int, SideStream> per_device;
+  int dev = 0;
+  HSSX_HIP(hipGetDevice(&dev));
+  SideStream &x = per_device[dev];
+  if (!x.s) {
+    HSSX_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    HSSX_HIP(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+    HSSX_HIP(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+  }
+  return x;
+}
+
+}  // namespace
+
+namespace {
+
 template <typename T> struct CompressTask {
   int node = 0, kind = 0;
   int m = 0;
@@ -277,16 +302,36 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
       }
     }
     HssItem *d_all = all_items.empty() ? nullptr : sg.put(all_items);
-    for (const auto &l : launches) {
-      double cflops = 0;
-      for (long e = l[2]; e < l[2] + l[3]; ++e) {
-        const auto &it = all_items[e];
-        cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
+    // the small-cluster launch of a level is independent of its large-cluster
+    // launches (different clusters, same inputs): when a level has both, the
+    // small one runs on a side stream, forked from and joined back into st
+    SideStream &side = side_stream();
+    for (size_t a = 0; a < launches.size();) {
+      size_t b = a;
+      while (b < launches.size() && launches[b][0] == launches[a][0]) ++b;
+      const bool fork = b - a > 1 && launches[a][1] == 0;
+      if (fork) {
+        HSSX_HIP(hipEventRecord(side.fork, st));
+        HSSX_HIP(hipStreamWaitEvent(side.s, side.fork, 0));
       }
-      hipEvent_t pc = prof_begin(st);
-      launch_compress_level<T>((int)l[3], d_all + l[2], d_inst, d_cls, d_pool, d_ipool, d_rank,
-                               base, Y, Om, d_scr, id_tol, (int)l[1], st);
-      prof_end("compress_level", st, pc, cflops);
+      for (size_t e = a; e < b; ++e) {
+        const auto &l = launches[e];
+        hipStream_t ls = fork && l[1] == 0 ? side.s : st;
+        double cflops = 0;
+        for (long q = l[2]; q < l[2] + l[3]; ++q) {
+          const auto &it = all_items[q];
+          cflops += compress_flops(cls[inst[it.inst].cl_off + it.cl], inst[it.inst]);
+        }
+        hipEvent_t pc = prof_begin(ls);
+        launch_compress_level<T>((int)l[3], d_all + l[2], d_inst, d_cls, d_pool, d_ipool, d_rank,
+                                 base, Y, Om, d_scr, id_tol, (int)l[1], ls);
+        prof_end("compress_level", ls, pc, cflops);
+      }
+      if (fork) {
+        HSSX_HIP(hipEventRecord(side.join, side.s));
+        HSSX_HIP(hipStreamWaitEvent(st, side.join, 0));
+      }
+      a = b;
     }
 
     // ---- error estimate with r fresh probes (eq. 2.7), kXC columns per job
