@@ -478,16 +478,32 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       (j.ne < kSmall && j.m <= 128 ? small : big).push_back(j);
     }
   }
+  // the few-pivot fronts are independent of the blocked elimination of the
+  // large fronts until the product over the non-pivot rows: with large
+  // fronts present they run on the side stream (forked after their job lists
+  // are uploaded on st, joined before that product)
+  const bool overlap = !big.empty() && (!in_lds.empty() || !small.empty());
+  int *queue = nullptr;
+  ElimJob<T> *d_order = nullptr, *d_small = nullptr;
   if (!in_lds.empty()) {
     // longest first: GJ work of the pivot rows, about ne^2 ncols
     std::vector<ElimJob<T>> order = in_lds;
     std::stable_sort(order.begin(), order.end(), [](const ElimJob<T> &a, const ElimJob<T> &b) {
       return (long)a.ne * a.ne * a.ncols > (long)b.ne * b.ne * b.ncols;
     });
-    int *queue = sg.put(std::vector<int>{0});
-    launch_eliminate<T>((int)order.size(), sg.put(order), err, st, lds, queue);
+    queue = sg.put(std::vector<int>{0});
+    d_order = sg.put(order);
   }
-  if (!small.empty()) launch_eliminate<T>((int)small.size(), sg.put(small), err, st);
+  if (!small.empty()) d_small = sg.put(small);
+  SideStream *side = overlap ? &side_stream() : nullptr;
+  hipStream_t fs = st;
+  if (overlap) {
+    HSSX_HIP(hipEventRecord(side->fork, st));
+    HSSX_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    fs = side->s;
+  }
+  if (d_order) launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);
+  if (d_small) launch_eliminate<T>((int)small.size(), d_small, err, fs);
   if (big.empty() && rows_done.empty()) return;
   // scratch per job: pivots, G, Y, W
   long ysz = 0, wsz = 0;
@@ -542,6 +558,10 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   PanelJob<T> *d_pj = all_pj.empty() ? nullptr : sg.put(all_pj);
   for (const auto &c : step_cfg)
     launch_panel_step<T>(c[1], d_pj + c[0], c[2], c[3], c[4], c[5], err, st);
+  if (overlap) {
+    HSSX_HIP(hipEventRecord(side->join, side->s));
+    HSSX_HIP(hipStreamWaitEvent(st, side->join, 0));
+  }
   // non-pivot rows: F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols)
   std::vector<GemmJob<T>> gj;
   int gm = 0, gn = 0;
