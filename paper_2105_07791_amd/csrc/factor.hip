@@ -449,8 +449,39 @@ template <typename T> double elim_flops(const std::vector<ElimJob<T>> &jobs) {
 // product per front, F(ne:m, ne:) -= F(ne:m, 0:ne) F(0:ne, ne:), which gives
 // S = A_bb - A_bi A_ii^-1 A_ib and L = -A_bi A_ii^-1 (eqs. 3.2-3.5) with
 // every entry accumulated once instead of once per panel.
+// After the pivot rows of a front are eliminated: the non-pivot rows,
+// F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols), and R = -(A_ii^-1
+// A_ib), the negated block F(0:ne, ne:m), as batched job lists
+template <typename T> struct ProductListsT {
+  std::vector<GemmJob<T>> gj;
+  std::vector<AxpbyJob<T>> neg;
+  int gm = 0, gn = 0, nm = 0, nn = 0;
+};
+template <typename T>
+ProductListsT<T> product_lists_of(const std::vector<ElimJob<T>> &js) {
+  ProductListsT<T> p;
+  for (const auto &j : js) {
+    if (j.m == j.ne || j.ne == 0) continue;
+    const cplx<T> *Abi = j.ptr + j.ne, *Bx = j.ptr + (long)j.ne * j.ld;
+    cplx<T> *C = j.ptr + j.ne + (long)j.ne * j.ld;
+    p.gj.push_back(GemmJob<T>{Abi, Bx, C, j.ld, j.ld, j.ld, j.m - j.ne, j.ncols - j.ne, j.ne});
+    p.gm = std::max(p.gm, j.m - j.ne);
+    p.gn = std::max(p.gn, j.ncols - j.ne);
+  }
+  for (const auto &j : js) {
+    if (!j.negate_r || j.m == j.ne) continue;
+    cplx<T> *R = j.ptr + (long)j.ne * j.ld;
+    p.neg.push_back(AxpbyJob<T>{R, R, nullptr, j.ld, j.ld, 0, j.ne, j.m - j.ne, (T)-2, (T)0});
+    p.nm = std::max(p.nm, j.ne);
+    p.nn = std::max(p.nn, j.m - j.ne);
+  }
+  return p;
+}
+
 template <typename T>
 void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, Arena &ar) {
+  using ProductLists = ProductListsT<T>;
+  auto product_lists = [](const std::vector<ElimJob<T>> &js) { return product_lists_of<T>(js); };
   // panel width: the register-resident panel holds 32 complex64 or 16
   // complex128 columns per row
   constexpr int NB = sizeof(T) == sizeof(float) ? 32 : 16, kSmall = 64;
@@ -495,6 +526,11 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     d_order = sg.put(order);
   }
   if (!small.empty()) d_small = sg.put(small);
+  // products over the non-pivot rows and the negation of R for the fronts
+  // eliminated in LDS, queued on the same stream right after them
+  const ProductLists pr_done = product_lists(rows_done);
+  GemmJob<T> *d_gd = pr_done.gj.empty() ? nullptr : sg.put(pr_done.gj);
+  AxpbyJob<T> *d_nd = pr_done.neg.empty() ? nullptr : sg.put(pr_done.neg);
   SideStream *side = overlap ? &side_stream() : nullptr;
   hipStream_t fs = st;
   if (overlap) {
@@ -504,7 +540,9 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   }
   if (d_order) launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);
   if (d_small) launch_eliminate<T>((int)small.size(), d_small, err, fs);
-  if (big.empty() && rows_done.empty()) return;
+  if (d_gd) launch_gemm_sub<T>((int)pr_done.gj.size(), d_gd, pr_done.gm, pr_done.gn, fs);
+  if (d_nd) launch_axpby<T>((int)pr_done.neg.size(), d_nd, pr_done.nm, pr_done.nn, fs);
+  if (big.empty()) return;   // no fork without large fronts
   // scratch per job: pivots, G, Y, W
   long ysz = 0, wsz = 0;
   std::vector<long> yo, wo;
@@ -558,34 +596,16 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   PanelJob<T> *d_pj = all_pj.empty() ? nullptr : sg.put(all_pj);
   for (const auto &c : step_cfg)
     launch_panel_step<T>(c[1], d_pj + c[0], c[2], c[3], c[4], c[5], err, st);
+  // non-pivot rows and R of the large fronts
+  const ProductLists pr_big = product_lists(big);
+  if (!pr_big.gj.empty())
+    launch_gemm_sub<T>((int)pr_big.gj.size(), sg.put(pr_big.gj), pr_big.gm, pr_big.gn, st);
+  if (!pr_big.neg.empty())
+    launch_axpby<T>((int)pr_big.neg.size(), sg.put(pr_big.neg), pr_big.nm, pr_big.nn, st);
   if (overlap) {
     HSSX_HIP(hipEventRecord(side->join, side->s));
     HSSX_HIP(hipStreamWaitEvent(st, side->join, 0));
   }
-  // non-pivot rows: F(ne:m, ne:ncols) -= F(ne:m, 0:ne) F(0:ne, ne:ncols)
-  std::vector<GemmJob<T>> gj;
-  int gm = 0, gn = 0;
-  big.insert(big.end(), rows_done.begin(), rows_done.end());
-  for (const auto &j : big) {
-    if (j.m == j.ne || j.ne == 0) continue;
-    const cplx<T> *Abi = j.ptr + j.ne, *Bx = j.ptr + (long)j.ne * j.ld;
-    cplx<T> *C = j.ptr + j.ne + (long)j.ne * j.ld;
-    gj.push_back(GemmJob<T>{Abi, Bx, C, j.ld, j.ld, j.ld, j.m - j.ne, j.ncols - j.ne, j.ne});
-    gm = std::max(gm, j.m - j.ne);
-    gn = std::max(gn, j.ncols - j.ne);
-  }
-  if (!gj.empty()) launch_gemm_sub<T>((int)gj.size(), sg.put(gj), gm, gn, st);
-  // R = -(A_ii^-1 A_ib): negate the block F(0:ne, ne:m)
-  std::vector<AxpbyJob<T>> neg;
-  int nm = 0, nn = 0;
-  for (const auto &j : big) {
-    if (!j.negate_r || j.m == j.ne) continue;
-    cplx<T> *R = j.ptr + (long)j.ne * j.ld;
-    neg.push_back(AxpbyJob<T>{R, R, nullptr, j.ld, j.ld, 0, j.ne, j.m - j.ne, (T)-2, (T)0});
-    nm = std::max(nm, j.ne);
-    nn = std::max(nn, j.m - j.ne);
-  }
-  if (!neg.empty()) launch_axpby<T>((int)neg.size(), sg.put(neg), nm, nn, st);
   // the panel scratch is released on return (stream-ordered reuse)
   ar.release(mk0);
 }
