@@ -852,7 +852,10 @@ void factor_numeric(hssx_fact_ &P, hipStream_t st) {
     if (P.dtype == HSSX_C128) factor_impl<double>(P, st, *sg, *ar);
     else factor_impl<float>(P, st, *sg, *ar);
   } catch (...) {
-    (void)hipStreamSynchronize(st);
+    // an error between a fork onto the side stream and its join leaves work
+    // there that st does not wait for: drain the device before the arena and
+    // the staging areas are handed on
+    (void)hipDeviceSynchronize();
     return_arena(dev, std::move(ar));
     return_staging(dev, std::move(sg));
     throw;
