@@ -90,6 +90,11 @@ typedef struct {
                        operand split into a bf16 head and tail (three
                        products, about 16 significant bits); 0 = fp32
                        vector arithmetic (default) */
+  int strict_tol;   /* nonzero: hssx_factor / hssx_refactor fail with
+                       HSSX_ERANKCAP when any compression stops with its
+                       error estimate above tol; 0 (default): such
+                       compressions are accepted and counted in
+                       hssx_factor_stats.n_above_tol */
 } hssx_factor_opts;
 
 typedef struct {
@@ -117,13 +122,22 @@ typedef struct {
   int k_max;            /* largest rank among compressed blocks (Sec. 4.2) */
   int max_rounds_used;  /* most rank-growth rounds of any compression */
   double max_estimate;  /* largest accepted relative error estimate (eq. 2.7) */
-  double factor_bytes;  /* bytes the apply reads (LU blocks, pivots, R) */
-  double factor_flops;  /* nominal flops of the numeric factorization */
+  double factor_bytes;  /* bytes the apply reads: dense blocks (A_ii^-1, L, R)
+                           of dense-class nodes; telescoping inverses and
+                           Gauss-transform generators of HSS-class nodes */
+  double factor_flops;  /* nominal flops of the numeric factorization
+                           (products, eliminations, compressions) */
   double ms_symbolic;   /* host symbolic analysis (trees, orders) */
   double ms_numeric;    /* numeric factorization (device, hipEvents) */
   double ms_setup;      /* front descriptors, their upload and the front
                            pool allocation (host) */
   int rounds_total;     /* rank-growth rounds summed over all compressions */
+  int n_above_tol;      /* compressions accepted with an estimate above tol
+                           (round or capacity limit, or the complex64
+                           rounding-noise floor) */
+  double exact_factor_bytes;  /* the same counts for the exact multifrontal */
+  double exact_factor_flops;  /* factorization of this tree (dense fronts,
+                                 Gauss-Jordan), for comparison */
 } hssx_factor_stats;
 
 /* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for
@@ -301,6 +315,33 @@ hssx_status hssx_get_factor_stats(hssx_fact P, hssx_factor_stats *s);
  * (expanded from HSS when compressed), |B| x |B| column-major complex128 into
  * host memory.  For tests.  Synchronises. */
 hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld);
+
+/* The HSS arithmetic the factorization runs on its compressed Schur
+ * complements (Sec. 2.2, Sec. 3.3), applied to one complex symmetric HSS
+ * matrix H given by the caller in generator form:
+ *   op 0: Y = H X, the telescoping product (eqs. 2.5-2.6);
+ *   op 1: Y = H^-1 X, the telescoping inverse (per level D^-1, the
+ *         reduced blocks (U^T D^-1 U)^-1, and a dense inverse at the root)
+ *         and its two-sweep solve;
+ *   op 2: vals[e] = H(i, j), entry access through the full bases;
+ *   op 3: vals[e] = H^-1(i, j), the same on the inverse's HSS form;
+ * for (i, j) = (ij[2e], ij[2e+1]).  tree: host int32[ncl*5] (start, size,
+ * left, right, level) per cluster in level order, root 0 = [0, m), each
+ * internal cluster split into two consecutive children; rank: host
+ * int32[ncl], rank[0] = 0.  gens: host float64 (re, im) pairs packed per
+ * cluster c = 0, 1, ...: for c > 0 the basis U (rows x rank[c], rows = size
+ * at a leaf, rank[left] + rank[right] otherwise), then D (size x size) at a
+ * leaf, or B12 (rank[left] x rank[right]) and B21 (rank[right] x rank[left])
+ * at an internal cluster; all column-major.  X, Y: device complex128
+ * m x nrhs (ld m) for op 0/1; ij: host int32[2 nij], vals: host float64
+ * [2 nij] for op 2/3.  dtype: arithmetic precision (C64 rounds the
+ * generators and vectors).  ESINGULAR when a block of the inverse is
+ * singular.  Synchronises stream. */
+hssx_status hssx_hss_eval(int device, hssx_dtype dtype, int m, int ncl,
+                          const int32_t *tree, const int32_t *rank,
+                          const double *gens, int op, int nrhs,
+                          const void *x_dev, void *y_dev, long nij,
+                          const int32_t *ij, double *vals, void *stream);
 
 /* Measurement support.  hssx_prof_enable(1) clears the records and starts
  * bracketing the main kernels with HIP events on their launch stream;

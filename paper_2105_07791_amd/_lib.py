@@ -21,7 +21,7 @@ class FactorOpts(C.Structure):
     _fields_ = [("beta", C.c_int), ("h_sw", C.c_int), ("k0", C.c_int), ("r", C.c_int),
                 ("max_rounds", C.c_int), ("dtype", C.c_int), ("seed", C.c_uint32),
                 ("id_rel_tol", C.c_double), ("apply_graph", C.c_int), ("autotune", C.c_int),
-                ("sample_bf16", C.c_int)]
+                ("sample_bf16", C.c_int), ("strict_tol", C.c_int)]
 
 
 class GmresOpts(C.Structure):
@@ -39,7 +39,9 @@ class FactorStats(C.Structure):
                 ("max_rounds_used", C.c_int), ("max_estimate", C.c_double),
                 ("factor_bytes", C.c_double), ("factor_flops", C.c_double),
                 ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
-                ("ms_setup", C.c_double), ("rounds_total", C.c_int)]
+                ("ms_setup", C.c_double), ("rounds_total", C.c_int),
+                ("n_above_tol", C.c_int), ("exact_factor_bytes", C.c_double),
+                ("exact_factor_flops", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -72,6 +74,7 @@ SIGNATURES = {
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),
     "hssx_get_schur": (_i, [_vp, _i, _dp, _l]),
+    "hssx_hss_eval": (_i, [_i, _i, _i, _i, _ip, _ip, _dp, _i, _i, _vp, _vp, _l, _ip, _dp, _vp]),
     "hssx_prof_enable": (_i, [_i]),
     "hssx_prof_query": (_i, [C.c_char_p, _dp, C.POINTER(_l), _dp]),
     "hssx_fact_destroy": (None, [_vp]),

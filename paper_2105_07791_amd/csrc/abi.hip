@@ -45,6 +45,152 @@ struct DeviceScope {
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Subtree roots of a child's cluster tree: [P0 | P1] split at the root when
+// both parts exist (Fig. 4), else the whole tree is the one present part.
+void child_roots(const NDNode &c, int &ii, int &bb, int &split) {
+  const int nb = (int)c.B.size();
+  split = 0;
+  ii = bb = -1;
+  if (c.ct.count() == 0) return;
+  if (c.p0 > 0 && c.p0 < nb) {
+    split = 1;
+    ii = c.ct.left[0];
+    bb = c.ct.right[0];
+  } else if (c.p0 == nb) {
+    ii = 0;
+  } else {
+    bb = 0;
+  }
+}
+
+// Index maps and coupling lists of the HSS-class nodes (eq. 3.4 layout):
+// where each position of sigma's front sits in its children's boundaries,
+// and the entries of A that couple the two children, split by the blocks
+// they fall in (A~_ii both ways, A~_ib as sparse columns, A~_bb).
+void build_hss_sym(hssx_fact_ &P, const hssx_op_ &A) {
+  const Symbolic &sym = P.sym;
+  const int nn = (int)sym.nodes.size();
+  P.hsym.clear();
+  std::vector<int> pool;
+  auto put = [&](const std::vector<int> &v) {
+    const long o = (long)pool.size();
+    pool.insert(pool.end(), v.begin(), v.end());
+    pool.push_back(0);   // no empty arrays
+    return o;
+  };
+  std::vector<int> own(A.n, -1), cpos(A.n, -1), spos(A.n, -1);
+  auto csr_index = [&](int r, int c) {
+    const int *b = A.h_col.data() + A.h_rowptr[r], *e = A.h_col.data() + A.h_rowptr[r + 1];
+    const int *q = std::lower_bound(b, e, c);
+    HSSX_CHECK(q != e && *q == c, HSSX_EINVAL, "unsymmetric sparsity pattern");
+    return (int)(q - A.h_col.data());
+  };
+  for (int k = 0; k < nn; ++k) {
+    if (P.hss_idx[k] < 0) continue;
+    const NDNode &nd = sym.nodes[k], &mu = sym.nodes[nd.lo], &nu = sym.nodes[nd.hi];
+    HssSym h;
+    h.node = k;
+    h.mu = nd.lo;
+    h.nu = nd.hi;
+    h.pmu = mu.p0;
+    h.pnu = nu.p0;
+    h.ni = (int)nd.I.size();
+    h.nb = (int)nd.B.size();
+    h.mmu = (int)mu.B.size();
+    h.mnu = (int)nu.B.size();
+    child_roots(mu, h.ii_mu, h.bb_mu, h.split_mu);
+    child_roots(nu, h.ii_nu, h.bb_nu, h.split_nu);
+    HSSX_CHECK(h.ni == h.pmu + h.pnu, HSSX_EINVAL, "interior is not [P0(mu); P0(nu)]");
+    for (int i = 0; i < h.pmu; ++i)
+      HSSX_CHECK(nd.I[i] == mu.B[i], HSSX_EINVAL, "interior order differs from P0(mu)");
+    for (int i = 0; i < h.pnu; ++i)
+      HSSX_CHECK(nd.I[h.pmu + i] == nu.B[i], HSSX_EINVAL, "interior order differs from P0(nu)");
+    for (int i = 0; i < h.mmu; ++i) { own[mu.B[i]] = 0; cpos[mu.B[i]] = i; }
+    for (int i = 0; i < h.mnu; ++i) { own[nu.B[i]] = 1; cpos[nu.B[i]] = i; }
+    for (int b = 0; b < h.nb; ++b) spos[nd.B[b]] = b;
+    std::vector<int> bchild(h.nb), bcp(h.nb), gid(h.nb), smu(h.nb, -1), snu(h.nb, -1);
+    std::vector<int> p1mu(std::max(0, h.mmu - h.pmu)), p1nu(std::max(0, h.mnu - h.pnu));
+    for (int b = 0; b < h.nb; ++b) {
+      const int v = nd.B[b];
+      HSSX_CHECK(own[v] >= 0 && cpos[v] >= (own[v] ? h.pnu : h.pmu), HSSX_EINVAL,
+                 "boundary position outside the children's P1 parts");
+      bchild[b] = own[v];
+      bcp[b] = cpos[v];
+      gid[b] = v;
+      if (own[v] == 0) {
+        smu[b] = cpos[v] - h.pmu;
+        p1mu[cpos[v] - h.pmu] = b;
+      } else {
+        snu[b] = cpos[v] - h.pnu;
+        p1nu[cpos[v] - h.pnu] = b;
+      }
+    }
+    // couplings of the two children through A
+    std::vector<std::vector<std::pair<int, int>>> imu(h.pmu), inu(h.pnu), bb(h.nb);
+    std::vector<std::array<int, 3>> ib;   // I row, B position, value index
+    for (int i = 0; i < h.mmu; ++i) {
+      const int v = mu.B[i];
+      for (int e = A.h_rowptr[v]; e < A.h_rowptr[v + 1]; ++e) {
+        const int u = A.h_col[e];
+        if (u < 0 || u >= A.n || own[u] != 1) continue;
+        const int j = cpos[u], euv = csr_index(u, v);
+        const bool vi = i < h.pmu, ui = j < h.pnu;
+        if (vi && ui) {
+          imu[i].push_back({j, e});
+          inu[j].push_back({i, euv});
+        } else if (vi) {
+          ib.push_back({i, spos[u], e});
+        } else if (ui) {
+          ib.push_back({h.pmu + j, spos[v], euv});
+        } else {
+          bb[spos[v]].push_back({spos[u], e});
+          bb[spos[u]].push_back({spos[v], euv});
+        }
+      }
+    }
+    auto csr = [&](std::vector<std::vector<std::pair<int, int>>> &rows, long &rp, long &cp,
+                   long &vi) {
+      std::vector<int> r{0}, c, w;
+      for (auto &row : rows) {
+        std::sort(row.begin(), row.end());
+        for (auto &x : row) { c.push_back(x.first); w.push_back(x.second); }
+        r.push_back((int)c.size());
+      }
+      rp = put(r);
+      cp = put(c);
+      vi = put(w);
+    };
+    csr(imu, h.imu_rp, h.imu_cp, h.imu_vi);
+    csr(inu, h.inu_rp, h.inu_cp, h.inu_vi);
+    csr(bb, h.bb_rp, h.bb_cp, h.bb_vi);
+    std::sort(ib.begin(), ib.end(), [](const std::array<int, 3> &a, const std::array<int, 3> &b) {
+      return a[1] != b[1] ? a[1] < b[1] : a[0] < b[0];
+    });
+    std::vector<int> ri, ci, vv, yr, yc, yv;
+    for (const auto &x : ib) {
+      if (yr.empty() || yr.back() != x[1]) {
+        yr.push_back(x[1]);
+        yc.push_back((int)yc.size());
+        yv.push_back(-1);
+      }
+      ri.push_back(x[0]);
+      ci.push_back((int)yc.size() - 1);
+      vv.push_back(x[2]);
+    }
+    h.nib = (int)ri.size();
+    h.ncr = (int)yr.size();
+    h.ib_ri = put(ri); h.ib_ci = put(ci); h.ib_vi = put(vv);
+    h.yb_ri = put(yr); h.yb_ci = put(yc); h.yb_vi = put(yv);
+    h.bchild = put(bchild); h.bcpos = put(bcp); h.gid = put(gid);
+    h.smu = put(smu); h.snu = put(snu); h.p1mu = put(p1mu); h.p1nu = put(p1nu);
+    for (int v : mu.B) own[v] = -1;
+    for (int v : nu.B) own[v] = -1;
+    P.hsym.push_back(h);
+  }
+  if (pool.empty()) pool.push_back(0);
+  upload(P.hsym_pool, pool);
+}
+
 }  // namespace
 
 hssx_fact_::~hssx_fact_() {
@@ -332,7 +478,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(tol > 0 && tol < 1, HSSX_EINVAL, "tol must lie in (0, 1)");
     HSSX_CHECK(leaf_size >= 1, HSSX_EINVAL, "leaf_size must be >= 1");
     *P_out = nullptr;
-    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0};
+    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0, 0};
     if (opts) o = *opts;
     HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
                HSSX_EINVAL, "invalid factor options");
@@ -387,6 +533,12 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     for (int k = 0; k < nn; ++k) P->arith[k] = o.h_sw >= 0 && sym.nodes[k].height > o.h_sw;
     for (int k = 0; k < nn; ++k) P->comp[k] = sym.nodes[k].parent >= 0 && P->arith[sym.nodes[k].parent];
     P->node_rank.assign(nn, 0);
+    // HSS-class nodes: HSS arithmetic and not a root (a root factors its
+    // dense A_ii); they keep no dense front
+    P->hss_idx.assign(nn, -1);
+    int n_hss = 0;
+    for (int k = 0; k < nn; ++k)
+      if (P->arith[k] && sym.nodes[k].parent >= 0 && !sym.nodes[k].leafnode()) P->hss_idx[k] = n_hss++;
 
     // descriptors (sizes and offsets, one pass over the nodes)
     std::vector<FrontDesc> dsc(nn);
@@ -394,7 +546,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     // their own (offsets roff)
     const bool split_roots = o.dtype == HSSX_C64;
     long foff = 0, roff = 0, boff = 0, soff = 0;
-    double fbytes = 0, flops = 0;
+    double fbytes = 0, flops = 0;   // of the exact multifrontal factorization
     const size_t esz_pool = o.dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
     for (int k = 0; k < nn; ++k) {
       const NDNode &nd = sym.nodes[k];
@@ -404,8 +556,17 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
       d.f = d.ni + d.nb;
       const bool in64 = split_roots && nd.parent < 0;
       long &off = in64 ? roff : foff;
-      d.foff = off;
-      off += (long)d.f * (d.f + d.ni);
+      if (P->hss_idx[k] < 0) {
+        d.foff = off;
+        off += (long)d.f * (d.f + d.ni);
+      } else if (P->hss_idx[nd.parent] < 0) {
+        // HSS-class child of a dense parent: only its Schur block S (ld f),
+        // the expansion the parent's front assembly reads
+        d.foff = off - d.ni - (long)d.ni * d.f;
+        off += (long)d.f * d.nb;
+      } else {
+        d.foff = 0;
+      }
       d.ioff = nd.offset;
       d.bpos_off = (int)boff;
       boff += d.nb;
@@ -483,8 +644,14 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     upload(P->src_gid, sg);
     upload(P->src_code, scode);
     upload(P->perm, sym.perm);
+    build_hss_sym(*P, *A);
     P->depth_nodes.assign(sym.max_depth + 1, {});
-    for (int k = 0; k < nn; ++k) P->depth_nodes[sym.nodes[k].depth].push_back(k);
+    P->dense_nodes.assign(sym.max_depth + 1, {});
+    P->hss_nodes.assign(sym.max_depth + 1, {});
+    for (int k = 0; k < nn; ++k) {
+      P->depth_nodes[sym.nodes[k].depth].push_back(k);
+      (P->hss_idx[k] < 0 ? P->dense_nodes : P->hss_nodes)[sym.nodes[k].depth].push_back(k);
+    }
     P->depth_dev.resize(sym.max_depth + 1);
     P->depth_max_ni.assign(sym.max_depth + 1, 0);
     P->depth_max_nb.assign(sym.max_depth + 1, 0);
@@ -493,8 +660,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->up_fbytes.assign(D1, 0); P->up_velems.assign(D1, 0);
     P->down_fbytes.assign(D1, 0); P->down_velems.assign(D1, 0); P->asm_bytes.assign(D1, 0);
     for (int d = 0; d <= sym.max_depth; ++d) {
-      upload(P->depth_dev[d], P->depth_nodes[d]);
-      for (int k : P->depth_nodes[d]) {
+      upload(P->depth_dev[d], P->dense_nodes[d]);
+      for (int k : P->dense_nodes[d]) {
         const FrontDesc &q = dsc[k];
         const size_t esz = split_roots && sym.nodes[k].parent < 0 ? sizeof(c128) : esz_pool;
         P->depth_max_ni[d] = std::max(P->depth_max_ni[d], q.ni);
@@ -524,6 +691,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     P->stats.n_hss_nodes = nh;
     P->stats.factor_bytes = fbytes;
     P->stats.factor_flops = flops;
+    P->stats.exact_factor_bytes = fbytes;
+    P->stats.exact_factor_flops = flops;
     factor_numeric(*P, st);
     *P_out = P.release();
   });
@@ -681,6 +850,16 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
     if (d.nb == 0) return;   // the root: no Schur complement
     DeviceScope ds(P->A->device);
     HSSX_HIP(hipDeviceSynchronize());
+    std::vector<c128> e;
+    if (expand_schur(*P, node, e)) {   // compressed: expansion of its generators
+      for (int j = 0; j < d.nb; ++j)
+        for (int i = 0; i < d.nb; ++i) {
+          S_host[2 * (i + (long)j * ld)] = e[i + (size_t)j * d.nb].re;
+          S_host[2 * (i + (long)j * ld) + 1] = e[i + (size_t)j * d.nb].im;
+        }
+      return;
+    }
+    HSSX_CHECK(P->hss_idx.empty() || P->hss_idx[node] < 0, HSSX_EINVAL, "node keeps no Schur complement");
     const size_t esz = P->dtype == HSSX_C128 ? sizeof(c128) : sizeof(c64);
     std::vector<char> buf((size_t)d.f * (d.f + d.ni) * esz);
     HSSX_HIP(hipMemcpy(buf.data(), (char *)P->front.p + d.foff * esz, buf.size(),
@@ -701,6 +880,21 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
         S_host[2 * (i + (long)j * ld)] = re;
         S_host[2 * (i + (long)j * ld) + 1] = im;
       }
+  });
+}
+
+hssx_status hssx_hss_eval(int device, hssx_dtype dtype, int m, int ncl, const int32_t *tree,
+                          const int32_t *rank, const double *gens, int op, int nrhs,
+                          const void *x_dev, void *y_dev, long nij, const int32_t *ij,
+                          double *vals, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(m >= 1 && ncl >= 1 && tree && rank && gens && op >= 0 && op <= 3, HSSX_EINVAL,
+               "invalid argument");
+    HSSX_CHECK(op >= 2 || (nrhs >= 1 && x_dev && y_dev), HSSX_EINVAL, "vectors");
+    HSSX_CHECK(op < 2 || (nij >= 0 && (nij == 0 || (ij && vals))), HSSX_EINVAL, "entry lists");
+    HSSX_CHECK(dtype == HSSX_C128 || dtype == HSSX_C64, HSSX_EINVAL, "dtype");
+    DeviceScope ds(device);
+    hss_eval(dtype, m, ncl, tree, rank, gens, op, nrhs, x_dev, y_dev, nij, ij, vals, S(stream));
   });
 }
 

@@ -5,9 +5,54 @@
 #include <memory>
 
 #include "common.h"
+#include "hss_arith.h"
 #include "kernels.h"
 #include "prof.h"
 #include "symbolic.h"
+
+namespace hssx {
+
+// Index maps of one HSS-class node sigma (children mu, nu), built once per
+// analysis; the int arrays live in one device pool at the listed offsets.
+// Positions: sigma's interior I = [P0(mu); P0(nu)] (pmu + pnu), sigma's
+// boundary B in its cluster-tree order (nb), a child's boundary in its own
+// cluster-tree order (P0 first).
+struct HssSym {
+  int node = -1, mu = -1, nu = -1;
+  int pmu = 0, pnu = 0, ni = 0, nb = 0, mmu = 0, mnu = 0;
+  int ii_mu = -1, bb_mu = -1, ii_nu = -1, bb_nu = -1;   // subtree roots in the children's trees
+  int split_mu = 0, split_nu = 0;                       // child's tree splits [P0 | P1] at its root
+  long bchild = 0, bcpos = 0, gid = 0;                  // per B position: child, child position, DOF
+  long p1mu = 0, p1nu = 0;                              // child's P1 row -> B position
+  long smu = 0, snu = 0;                                // B position -> child's P1 row or -1
+  long bb_rp = 0, bb_cp = 0, bb_vi = 0;                 // couplings of the children inside B
+  long inu_rp = 0, inu_cp = 0, inu_vi = 0;              // A~(nu,mu): rows P0(nu), columns P0(mu)
+  long imu_rp = 0, imu_cp = 0, imu_vi = 0;              // A~(mu,nu)
+  long ib_ri = 0, ib_ci = 0, ib_vi = 0;                 // A_ib couplings across the children (COO)
+  long yb_ri = 0, yb_ci = 0, yb_vi = 0;                 // unit entries of those columns in Y_B
+  int nib = 0, ncr = 0;                                 // COO entries, coupling columns
+};
+
+// Factor data of the HSS arithmetic for one precision.
+template <typename T> struct HssNodeData {
+  HssMat<T> S;          // S(sigma) in generator form (when its parent uses HSS arithmetic)
+  bool has_S = false;
+  HssMat<T> St;         // inner Schur complement S~ (Alg. 3.3)
+  HssInv<T> Hmu, Hs;    // telescoping inverses of S_ii^mu and S~
+  cplx<T> *W = nullptr, *YB = nullptr;   // R = -W Y_B^T, L = -Y_B W^T (eq. 3.7)
+  int r = 0;
+};
+
+// Apply program of the HSS-class nodes for one right-hand-side count: per
+// depth the up-step (block solve of Alg. 3.3 and the L update) and the
+// down-step (R update); scratch in its own arena.
+template <typename T> struct HssApplyPlan {
+  std::vector<Plan<T>> up, down;
+  std::unique_ptr<Arena> mem;
+  double fbytes = 0;
+};
+
+}  // namespace hssx
 
 struct hssx_op_ {
   int device = 0;
@@ -48,13 +93,24 @@ struct hssx_fact_ {
   hssx_factor_opts opts{};
   hssx::Symbolic sym;
   std::vector<int> arith, comp; // per node: HSS arithmetic, compressed S
+  // HSS-class nodes (HSS arithmetic, not the root): their maps, and the
+  // factor data of both precisions (only the factor's is filled)
+  std::vector<int> hss_idx;                 // node -> index into hsym or -1
+  std::vector<hssx::HssSym> hsym;
+  hssx::DevBuf hsym_pool;
+  std::vector<hssx::HssNodeData<float>> h32;
+  std::vector<hssx::HssNodeData<double>> h64;
+  hssx::Arena store;                        // device storage of the HSS factor data
+  std::map<int, hssx::HssApplyPlan<float>> plans32;
+  std::map<int, hssx::HssApplyPlan<double>> plans64;
   std::vector<hssx::FrontDesc> h_desc;
   hssx::DevBuf desc, bpos, src_gid, src_code, perm, front;
   // complex64 factors keep the roots (top separators) in complex128: their
   // fronts live in front64, at the roots' foff
   hssx::DevBuf front64;
-  // per depth (index = depth): nodes, and the largest |I|, |B|, front size
-  std::vector<std::vector<int>> depth_nodes;
+  // per depth (index = depth): nodes, and the largest |I|, |B|, front size;
+  // depth_dev lists the nodes with dense fronts, hss_nodes the others
+  std::vector<std::vector<int>> depth_nodes, dense_nodes, hss_nodes;
   std::vector<hssx::DevBuf> depth_dev;
   std::vector<int> depth_max_ni, depth_max_nb, depth_max_f;
   // per depth: factor bytes and vector elements (per rhs) the apply moves
@@ -82,6 +138,11 @@ void factor_numeric(hssx_fact_ &P, hipStream_t st);
 void destroy_graphs(hssx_fact_ &P);
 void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
            hipStream_t st);
+bool expand_schur(hssx_fact_ &P, int node, std::vector<c128> &out);
+// hssx_hss_eval's work (one caller-given HSS matrix)
+void hss_eval(hssx_dtype dtype, int m, int ncl, const int32_t *tree, const int32_t *rank,
+              const double *gens, int op, int nrhs, const void *x_dev, void *y_dev, long nij,
+              const int32_t *ij, double *vals, hipStream_t st);
 void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long ldb, c128 *x,
            long ldx, const hssx_gmres_opts &o, hssx_gmres_stats *stats, hipStream_t st);
 

@@ -175,6 +175,9 @@ struct HssInstance {
   long ooff;            // offset of Omega (real pool)
   int ldY;
   long woff;            // scratch offset (two rows_cap x s blocks per cluster)
+  int pre;              // 1: D and B blocks are written into the pool before
+                        // each level's launch (operators not formed densely)
+  int eop;              // entry operator of such an instance (-1: dense S)
 };
 struct HssItem {
   int inst, cl;         // instance, cluster id within it

@@ -447,7 +447,8 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
     cplx<T> *D = P + C.D;
     // D = S(I, I) and Om_loc = Om(I, :) (the real sketch as complex), copied
     // in batches of loads ahead of their stores; then S_loc = Y(I, :) - D Om_loc
-    for (int e0 = tid; e0 < rows * rows; e0 += NT * 8) {
+    // (an instance whose operator is not formed has D in the pool already)
+    for (int e0 = I.pre ? rows * rows : tid; e0 < rows * rows; e0 += NT * 8) {
       cplx<T> v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -503,8 +504,10 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           if (e0 + NT * u < na * nb) Bd[e0 + NT * u] = v[u];
       }
     };
-    gather(B12, skl, skr, kl, kr);
-    gather(B21, skr, skl, kr, kl);
+    if (!I.pre) {
+      gather(B12, skl, skr, kl, kr);
+      gather(B21, skr, skl, kr, kl);
+    }
     __syncthreads();
     if (it.cl != 0) {
       const cplx<T> *Srl = P + L.Sr, *Srr = P + R.Sr, *Oml = P + L.Om, *Omr = P + R.Om;
