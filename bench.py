@@ -58,11 +58,14 @@ PEAKS = {  # MI355X published peaks
     "alu_f64": (78.6, "TFLOP/s"),
 }
 KERNELS = ["front_eliminate", "front_assemble", "compress_level", "hss_matvec", "sample",
-           "apply_up", "apply_down", "apply_graph", "spmv"]
+           "apply_up", "apply_down", "apply_graph", "spmv",
+           # HSS-class nodes: structured sampling, entry extraction, entry-access
+           # preparation, telescoping inverses, Gauss transforms, their apply
+           "sample_struct", "hss_entries", "hss_prep", "hss_inverse", "hss_gauss", "apply_hss"]
 BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "apply_graph", "spmv"}
 # categories timed around one kernel per launch (the roofline needs a single
-# kernel); front_eliminate, hss_matvec, apply_up/down (staging + product)
-# and apply_graph time launch sequences
+# kernel); front_eliminate, hss_matvec, apply_up/down (staging + product),
+# apply_graph and the HSS-arithmetic categories time launch sequences
 SINGLE_KERNELS = {"front_assemble", "compress_level", "sample", "spmv"}
 
 
@@ -110,6 +113,7 @@ def cpu_baseline_child(workload):
     except OSError:
         pass
     print(json.dumps({"seconds": t1 - t0, "true_res": res, "threads": threads, "cpu": cpu,
+                      "nproc": os.cpu_count(),
                       "n": int(A.shape[0]), "N": getattr(pr, "N", getattr(pr, "Nc", 0))}))
 
 
@@ -130,15 +134,17 @@ def run_cpu_baseline(workload):
                 "sample": f"{CPU_SAMPLE[workload]} (N={d['N']}, n={d['n']}, same "
                           f"family, not the full {workload}): exact nested-dissection "
                           f"factorization (no compression) + solve, float64, "
-                          f"{d['threads']} thread(s) on {d['cpu']} (true residual "
-                          f"{d['true_res']:.1e})",
+                          f"{d['threads']} thread(s) on {d['cpu']} ({d.get('nproc')} host "
+                          f"CPUs visible; true residual {d['true_res']:.1e})",
+                "host_nproc": d.get("nproc"),
                 "full_size_estimate_s": d["seconds"] * (n_full / d["n"]) ** 1.5,
                 "estimate_rule": "sample seconds x (n_full / n_sample)^1.5 (nested-dissection "
                                  "cost in 2D)"}
     return {"value": d["seconds"], "unit": "s", "cores": d["threads"], "kind": "oracle",
             "sample": f"full {workload}: exact nested-dissection factorization (no compression) "
                       f"+ solve of all right-hand sides, float64, {d['threads']} thread(s) on "
-                      f"{d['cpu']} (true residual {d['true_res']:.1e})"}
+                      f"{d['cpu']} ({d.get('nproc')} host CPUs visible; true residual "
+                      f"{d['true_res']:.1e})", "host_nproc": d.get("nproc")}
 
 
 def batch_cpu_child(workload, budget_s=15.0):
@@ -379,47 +385,97 @@ def main():
     b = A.load(torch.tensor(pr.f, device=dev))
     torch.cuda.synchronize()
     L = _lib.lib()
-
     tol_mixed = args.tol if args.tol is not None else pr.tol
 
-    # analyze once, factor many: the first call of a form builds its factor
-    # (symbolic analysis, descriptors, numeric factorization); later calls
-    # recompute the numeric factorization from the operator (hssx_refactor)
+    # Forms.  The analysis (symbolic + descriptors + first numeric factor) of
+    # each form happens once, untimed; a timed step recomputes the numeric
+    # factorization from the operator (hssx_refactor) and solves all
+    # right-hand sides.  "hss_c64" is the timed metric (the mixed-precision,
+    # batched form of the method); the others are timed the same way for
+    # comparison: the same HSS factor in complex128 (precision alone), the
+    # exact multifrontal factorization of the same tree on the same GPU
+    # (h_sw < 0: no compression) in both precisions, and the plain FP64 form
+    # (complex128 HSS factor, left GMRES, right-hand sides one at a time).
+    FORMS = {
+        "hss_c64": dict(dtype="c64", h_sw=pr.h_sw, tol=tol_mixed, flexible=True),
+        "hss_c128": dict(dtype="c128", h_sw=pr.h_sw, tol=pr.tol, flexible=True),
+        "exact_c64": dict(dtype="c64", h_sw=-1, tol=pr.tol, flexible=True),
+        "exact_c128": dict(dtype="c128", h_sw=-1, tol=pr.tol, flexible=True),
+        "plain_fp64": dict(dtype="c128", h_sw=pr.h_sw, tol=pr.tol, flexible=False, single=True),
+    }
     factors, analysis = {}, {}
 
-    def step(dtype, flexible, tol_hss=tol_mixed, key="mixed"):
+    def step(key):
+        f = FORMS[key]
         P = factors.get(key)
         if P is None:
-            P = hssx.Factor(A, tol=tol_hss, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
-                            dtype=dtype, seed=1)
+            P = hssx.Factor(A, tol=f["tol"], leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=f["h_sw"],
+                            dtype=f["dtype"], seed=1)
             factors[key] = P
             fs = P.stats()
             analysis[key] = {"symbolic_ms": fs["ms_symbolic"], "setup_ms": fs["ms_setup"],
                              "first_numeric_ms": fs["ms_numeric"]}
+            torch.cuda.synchronize()
+        s0 = torch.cuda.current_stream()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(s0)
+        P.refactor(A)
+        e1.record(s0)
+        if f.get("single"):
+            xs, st = [], []
+            for rr in range(b.shape[1]):
+                xr, sr = hssx.gmres_solve(A, P, b[:, rr].contiguous(), m=pr.gmres_m,
+                                          tol=pr.gmres_tol, flexible=False)
+                xs.append(xr)
+                st += sr
+            x = torch.stack(xs, dim=1)
         else:
-            P.refactor(A)
-        x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol, flexible=flexible)
-        return P, x, st
+            x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol,
+                                     flexible=f["flexible"])
+        e2.record(s0)
+        e2.synchronize()
+        return P, x, st, e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+
+    def summarize(key, runs):
+        P, x, st, _, _ = runs[-1]
+        tot = sorted(r[3] + r[4] for r in runs)
+        fs = P.stats()
+        res = (torch.linalg.vector_norm(A.matvec(x) - b, dim=0)
+               / torch.linalg.vector_norm(b, dim=0)).max().item()
+        f = FORMS[key]
+        return {"seconds": tot[len(tot) // 2], "steps": len(runs),
+                "factor_s": sorted(r[3] for r in runs)[len(runs) // 2],
+                "solve_s": sorted(r[4] for r in runs)[len(runs) // 2],
+                "factor_dtype": f["dtype"], "h_sw": f["h_sw"], "hss_tol": f["tol"],
+                "gmres": ("left GMRES(%d), one rhs at a time" % pr.gmres_m if f.get("single")
+                          else "%s GMRES(%d), all rhs batched"
+                          % ("flexible" if f["flexible"] else "left", pr.gmres_m)),
+                "iters_max": max(v["iters"] for v in st), "true_res_max": res,
+                "factor_bytes": fs["factor_bytes"], "factor_flops": fs["factor_flops"],
+                "exact_factor_bytes": fs["exact_factor_bytes"],
+                "exact_factor_flops": fs["exact_factor_flops"], "k_max": fs["k_max"],
+                "max_estimate": fs["max_estimate"], "n_above_tol": fs["n_above_tol"],
+                "hss_nodes": fs["n_hss_nodes"], "compressions": fs["n_compressed"]}, x
 
     print(f"[bench] {args.workload}: n={pr.n} nrhs={pr.nrhs} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
     for w in range(args.warmup):
-        step("c64", True)
+        step("hss_c64")
         print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    _lib.check(L.hssx_prof_enable(1))
-    t0 = time.perf_counter()
-    results = []
+    runs = []
     for k in range(args.steps):
-        ts = time.perf_counter()
-        P, x, st = step("c64", True)
-        torch.cuda.synchronize()
-        results.append((P.stats(), st, time.perf_counter() - ts))
-        print(f"[bench] step {k} {results[-1][2]:.3f}s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = (t1 - t0) / args.steps
+        runs.append(step("hss_c64"))
+        print(f"[bench] step {k} {runs[-1][3] + runs[-1][4]:.4f}s", file=sys.stderr, flush=True)
+    main, x = summarize("hss_c64", runs)
+    sec = main["seconds"]
 
+    # per-kernel HIP-event profile in separate steps (not in the timed ones)
+    nprof = 2
+    _lib.check(L.hssx_prof_enable(1))
+    for _ in range(nprof):
+        step("hss_c64")
+    torch.cuda.synchronize()
     kern = {}
     for name in KERNELS:
         ms, n, work = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
@@ -428,14 +484,7 @@ def main():
         kern[name] = (ms.value, n.value, work.value)
     _lib.check(L.hssx_prof_enable(0))
 
-    # verification of the last step against the true residual
-    r = A.matvec(x) - b
-    true_res = (torch.linalg.vector_norm(r, dim=0) / torch.linalg.vector_norm(b, dim=0)).max().item()
-    fstats, gst, _ = results[-1]
-    iters = [s["iters"] for s in gst]
-
-    # dominant kernel (largest event time per step among single-kernel
-    # categories) and its roofline
+    # dominant single kernel (largest event time per step) and its roofline
     dom = max(SINGLE_KERNELS, key=lambda k: kern[k][0])
     ms, nl, work = kern[dom]
     avg_s = ms / 1e3 / max(nl, 1)
@@ -447,13 +496,21 @@ def main():
         bound, (peak, unit) = "alu", PEAKS["alu_f32"]
         achieved = per_launch / avg_s / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
+            "frac": achieved / peak, "traffic": None, "launches_per_step": nl / nprof,
             "avg_launch_us": avg_s * 1e6}
-    kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in kern.items()}
-    # achieved rate of each category over the timed steps: GB/s for the
-    # byte-counted ones, TFLOP/s for the flop-counted ones (0: no count)
-    kernel_rate = {k: round(v[2] / (v[0] / 1e3) / (1e9 if k in BYTE_KERNELS else 1e12), 3)
-                   if v[0] > 0 and v[2] > 0 else 0.0 for k, v in kern.items()}
+    # per-stage table: time per step, work per step, achieved rate and its
+    # fraction of the stage's bound (HBM for byte-counted stages, FP32 vector
+    # peak for flop-counted ones; 0 where no work is counted)
+    stages = {}
+    for k, (kms, kn, kw) in kern.items():
+        if kn == 0:
+            continue
+        byte = k in BYTE_KERNELS
+        rate = kw / (kms / 1e3) / (1e9 if byte else 1e12) if kms > 0 and kw > 0 else 0.0
+        pk = PEAKS["hbm"][0] if byte else PEAKS["alu_f32"][0]
+        stages[k] = {"ms_per_step": round(kms / nprof, 3), "launches_per_step": kn / nprof,
+                     "work_per_step": kw / nprof, "rate": round(rate, 3),
+                     "unit": "GB/s" if byte else "TFLOP/s", "frac_of_peak": rate / pk}
     # HBM traffic per launch from the committed counter measurement, valid only
     # while the measured kernel's source is unchanged
     try:
@@ -466,55 +523,22 @@ def main():
     except (OSError, KeyError, ValueError):
         pass
 
-    alt = None
-    if args.alt_tol and args.alt_tol != tol_mixed:
-        step("c64", True, tol_hss=args.alt_tol, key="alt")       # analysis, untimed
+    forms = {"hss_c64": main}
+    others = [] if args.no_plain else ["hss_c128", "exact_c64", "exact_c128", "plain_fp64"]
+    for key in others:
+        step(key)                                            # analysis, untimed
+        rr = [step(key) for _ in range(1 if FORMS[key].get("single") else 2)]
+        forms[key], xk = summarize(key, rr)
+        forms[key]["rel_diff_vs_hss_c64"] = (torch.linalg.vector_norm(x - xk, dim=0)
+                                             / torch.linalg.vector_norm(xk, dim=0)).max().item()
+        print(f"[bench] {key}: {forms[key]['seconds']:.4f}s", file=sys.stderr, flush=True)
+        del factors[key]
         torch.cuda.synchronize()
-        ta0 = time.perf_counter()
-        Pa, xa, sa = step("c64", True, tol_hss=args.alt_tol, key="alt")
-        torch.cuda.synchronize()
-        ta1 = time.perf_counter()
-        ra = (torch.linalg.vector_norm(A.matvec(xa) - b, dim=0)
-              / torch.linalg.vector_norm(b, dim=0)).max().item()
-        alt = {"hss_tol": args.alt_tol, "seconds": ta1 - ta0,
-               "gmres_iters_max": max(v["iters"] for v in sa), "true_res_max": ra,
-               "k_max": Pa.stats()["k_max"]}
-        print(f"[bench] c64 form at tol {args.alt_tol}: {ta1 - ta0:.3f}s", file=sys.stderr,
-              flush=True)
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-
-    plain = None
-    if not args.no_plain:
-        Pp = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=pr.h_sw,
-                         dtype="c128", seed=1)                      # analysis, untimed
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        Pp.refactor(A)
-        torch.cuda.synchronize()
-        tp1 = time.perf_counter()
-        pit = []
-        xs = []
-        for rr in range(pr.nrhs):
-            xr, sr = hssx.gmres_solve(A, Pp, b[:, rr].contiguous(), m=pr.gmres_m,
-                                      tol=pr.gmres_tol, flexible=False)
-            pit.append(sr[0]["iters"])
-            xs.append(xr)
-        torch.cuda.synchronize()
-        tp2 = time.perf_counter()
-        xp = torch.stack(xs, dim=1)
-        rp = (torch.linalg.vector_norm(A.matvec(xp) - b, dim=0)
-              / torch.linalg.vector_norm(b, dim=0)).max().item()
-        dx = (torch.linalg.vector_norm(x - xp, dim=0)
-              / torch.linalg.vector_norm(xp, dim=0)).max().item()
-        plain = {"seconds": tp2 - tp0, "factor_s": tp1 - tp0, "solve_s": tp2 - tp1,
-                 "iters_max": max(pit), "true_res_max": rp, "factor_dtype": "c128",
-                 "gmres": "left GMRES(50), one rhs at a time",
-                 "mixed_vs_plain_rel_diff_max": dx}
-        print(f"[bench] plain fp64 form {tp2 - tp0:.3f}s", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -533,19 +557,20 @@ def main():
                    "nrhs": pr.nrhs, "factor_dtype": "c64", "hss_tol": tol_mixed,
                    "nd_leaf_dofs": pr.leaf_dofs, "hss_leaf": pr.beta, "h_sw": pr.h_sw,
                    "krylov": f"flexible GMRES({pr.gmres_m}) to {pr.gmres_tol}, all rhs batched"},
-        "gmres_iters_max": max(iters), "gmres_iters_mean": sum(iters) / len(iters),
-        "true_res_max": true_res, "factor_ms": fstats["ms_numeric"],
-        "analyze": dict(analysis.get("mixed", {}), note="symbolic analysis and front "
+        "timing": "median of the timed steps' HIP-event time (refactor + solve) on the "
+                  "solve stream; the per-kernel profile comes from separate steps",
+        "gmres_iters_max": main["iters_max"], "true_res_max": main["true_res_max"],
+        "factor_ms": main["factor_s"] * 1e3, "solve_ms": main["solve_s"] * 1e3,
+        "analyze": dict(analysis.get("hss_c64", {}), note="symbolic analysis and front "
                         "descriptors, once per pattern, outside the timed steps"),
-        "k_max": fstats["k_max"], "factor_bytes": fstats["factor_bytes"],
-        "compressions": fstats["n_compressed"], "max_rank_rounds": fstats["max_rounds_used"],
-        "rounds_total": fstats["rounds_total"],
-        "max_estimate": fstats["max_estimate"], "hss_nodes": fstats["n_hss_nodes"],
-        "kernel_ms_per_step": kernel_ms,
-        "kernel_rate": kernel_rate,
-        "kernel_rate_units": {k: ("GB/s" if k in BYTE_KERNELS else "TFLOP/s") for k in kern},
-        "plain_fp64": plain,
-        "mixed_alt_tol": alt,
+        "k_max": main["k_max"], "factor_bytes": main["factor_bytes"],
+        "factor_flops": main["factor_flops"],
+        "exact_factor_bytes": main["exact_factor_bytes"],
+        "exact_factor_flops": main["exact_factor_flops"],
+        "max_estimate": main["max_estimate"], "n_above_tol": main["n_above_tol"],
+        "hss_nodes": main["hss_nodes"], "compressions": main["compressions"],
+        "forms": forms,
+        "stages": stages,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

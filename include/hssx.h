@@ -258,7 +258,8 @@ hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev,
 
 /* Restarted GMRES on A x = b (eq. 1.2) with preconditioner P, all nrhs
  * right-hand sides advanced together; x0 = 0.  trans = 1 solves A^T x = b
- * with P^-T (adjoint solves).  Each (right-hand side, problem) pair is its
+ * with P^-T; trans = 2 solves the adjoint system A^H x = b, as
+ * conj(A^-T conj(b)) with P^-T, the conjugations done in the library.  Each (right-hand side, problem) pair is its
  * own system with its own Krylov basis and stopping test; for a batch of np
  * problems, system r * np + p is part p of column r.  stats: host array of
  * nrhs * np entries in that order (may be NULL).  Host-blocking: reads
@@ -277,6 +278,14 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs,
 hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev,
                                const void *x_dev, double *grad_dev,
                                void *stream);
+
+/* The same contraction with the adjoint state mu = A^-H dJ/dx (as returned
+ * by hssx_gmres_solve with trans = 2): grad_s[l] += -Re sum_rhs
+ * mu^H (dA/ds_l) x.  For J real, dJ/db = mu.  Same arguments and errors as
+ * hssx_dAds_contract. */
+hssx_status hssx_dAds_contract_adjoint(hssx_op A, int nrhs, const void *mu_dev,
+                                       const void *x_dev, double *grad_dev,
+                                       void *stream);
 
 /* Symbolic analysis only (box nested dissection, elimination tree, cluster
  * trees; Sec. 3.1 Def. 3.1, Fig. 3, Fig. 4) for an N x N grid with dofs

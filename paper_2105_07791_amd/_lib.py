@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhssx.so")
 
 HSSX_OK, HSSX_ENOCONV = 0, 1
+HSSX_EINVAL, HSSX_ENOMEM, HSSX_ESINGULAR, HSSX_ERANKCAP, HSSX_EHIP = -1, -2, -3, -4, -5
 HSSX_C128, HSSX_C64 = 0, 1
 
 STATUS_NAMES = {0: "HSSX_OK", 1: "HSSX_ENOCONV", -1: "HSSX_EINVAL", -2: "HSSX_ENOMEM",
@@ -66,6 +67,7 @@ SIGNATURES = {
     "hssx_gmres_solve": (_i, [_vp, _vp, _i, _i, _vp, _l, _vp, _l, C.POINTER(GmresOpts),
                               C.POINTER(GmresStats), _vp]),
     "hssx_dAds_contract": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "hssx_dAds_contract_adjoint": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "hssx_analyze": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
     "hssx_analyze_dg": (_i, [_i, _i, _i, C.POINTER(_vp)]),
     "hssx_refactor": (_i, [_vp, _vp, _vp]),

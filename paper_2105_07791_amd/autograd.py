@@ -4,11 +4,13 @@ Forward: factor A(s) (Algorithm 3.4) and run preconditioned GMRES.
 Backward (adjoint): for a real loss L with torch's complex gradient
 g = dL/dRe(x) + i dL/dIm(x), dL = Re(g^H dx) and dx = -A^-1 (dA) x, so
 
-    lambda  = A^-T conj(g)                    (GMRES on A^T with P^-T)
-    dL/ds_l = -Re( lambda^T (dA/ds_l) x )     (hssx_dAds_contract)
-    dL/db   = conj(lambda)
+    mu      = A^-H g                          (GMRES, trans = 2: conj(A^-T conj(g))
+                                               with P^-T, conjugations in the library)
+    dL/ds_l = -Re( mu^H (dA/ds_l) x )         (hssx_dAds_contract_adjoint)
+    dL/db   = mu
 
-All three steps run in libhssx.so; this module only marshals tensors.
+All three steps run in libhssx.so; this module only marshals tensors.  A
+forward or adjoint solve that stops at its iteration limit raises.
 A batch of uneven problems (N and omega given as lists) is one
 block-diagonal operator: s, b and x are the parts' vectors stacked.
 
@@ -37,6 +39,14 @@ def _operator(s, N, omega):
 __all__ = ["WaveSolve", "solve"]
 
 
+def _require_converged(stats, which):
+    """A solve that stopped at maxit leaves x (or the gradient) wrong: fail."""
+    bad = [i for i, s in enumerate(stats) if not s["converged"]]
+    if bad:
+        raise RuntimeError(f"{which} GMRES did not converge for systems {bad[:8]}: "
+                           f"{stats[bad[0]]}")
+
+
 class WaveSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, s, b, N, omega, opts):
@@ -56,6 +66,7 @@ class WaveSolve(torch.autograd.Function):
         else:
             P.refactor(A)
         x, st = gmres_solve(A, P, b.detach(), **gm)
+        _require_converged(st, "forward")
         ctx.A, ctx.P, ctx.gm, ctx.stats = A, P, gm, st
         ctx.save_for_backward(x)
         return x
@@ -64,9 +75,11 @@ class WaveSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         A, P, gm = ctx.A, ctx.P, ctx.gm
-        lam, _ = gmres_solve(A, P, gx.conj_physical(), trans=True, **gm)
-        gs = A.dAds_contract(lam, x) if ctx.needs_input_grad[0] else None
-        gb = lam.conj_physical() if ctx.needs_input_grad[1] else None
+        # adjoint state mu = A^-H dJ/dx (conjugations inside the library)
+        mu, st = gmres_solve(A, P, gx, trans="adjoint", **gm)
+        _require_converged(st, "adjoint")
+        gs = A.dAds_contract(mu, x, adjoint=True) if ctx.needs_input_grad[0] else None
+        gb = mu if ctx.needs_input_grad[1] else None
         return gs, gb, None, None, None
 
 

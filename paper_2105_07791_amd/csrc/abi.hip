@@ -198,6 +198,24 @@ hssx_fact_::~hssx_fact_() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
+namespace {
+hssx_status dads(hssx_op A, int nrhs, const void *lambda_dev, const void *x_dev, double *grad_dev,
+                 int conj_lam, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
+    HSSX_CHECK(A->dofs == 1 && A->mesh == kMeshCG, HSSX_EINVAL,
+               "the slowness gradient is defined for P1 Helmholtz operators");
+    DeviceScope ds(A->device);
+    for (size_t q = 0; q < A->part_N.size(); ++q) {
+      const int o = A->part_off[q];
+      launch_dads(A->part_N[q], A->part_omega[q], A->s.as<double>() + o, nrhs,
+                  (const c128 *)lambda_dev + o, (const c128 *)x_dev + o, A->n, grad_dev + o,
+                  conj_lam, S(stream));
+    }
+  });
+}
+}  // namespace
+
 extern "C" {
 
 const char *hssx_last_error(void) { return g_err.c_str(); }
@@ -733,8 +751,9 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const 
     hssx_gmres_opts o{50, 1e-8, 1000, 0};
     if (opts) o = *opts;
     HSSX_CHECK(o.m >= 1 && o.m <= 500 && o.tol > 0 && o.maxit >= 1, HSSX_EINVAL, "gmres options");
+    HSSX_CHECK(trans >= 0 && trans <= 2, HSSX_EINVAL, "trans must be 0, 1 or 2");
     DeviceScope ds(A->device);
-    gmres(*A, P, trans ? 1 : 0, nrhs, (const c128 *)b_dev, ldb, (c128 *)x_dev, ldx, o, stats,
+    gmres(*A, P, trans, nrhs, (const c128 *)b_dev, ldb, (c128 *)x_dev, ldx, o, stats,
           S(stream));
   });
   if (st == HSSX_OK && stats) {
@@ -747,19 +766,15 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const 
 
 hssx_status hssx_dAds_contract(hssx_op A, int nrhs, const void *lambda_dev, const void *x_dev,
                                double *grad_dev, void *stream) {
-  return guarded([&] {
-    HSSX_CHECK(A && lambda_dev && x_dev && grad_dev && nrhs >= 1, HSSX_EINVAL, "invalid argument");
-    HSSX_CHECK(A->dofs == 1 && A->mesh == kMeshCG, HSSX_EINVAL,
-               "the slowness gradient is defined for P1 Helmholtz operators");
-    DeviceScope ds(A->device);
-    for (size_t q = 0; q < A->part_N.size(); ++q) {
-      const int o = A->part_off[q];
-      launch_dads(A->part_N[q], A->part_omega[q], A->s.as<double>() + o, nrhs,
-                  (const c128 *)lambda_dev + o, (const c128 *)x_dev + o, A->n, grad_dev + o,
-                  S(stream));
-    }
-  });
+  return dads(A, nrhs, lambda_dev, x_dev, grad_dev, 0, stream);
 }
+
+hssx_status hssx_dAds_contract_adjoint(hssx_op A, int nrhs, const void *mu_dev, const void *x_dev,
+                                       double *grad_dev, void *stream) {
+  return dads(A, nrhs, mu_dev, x_dev, grad_dev, 1, stream);
+}
+
+
 
 hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_out) {
   return guarded([&] {

@@ -1154,19 +1154,25 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
           if (!r) continue;
           z.copy.push_back(CopyJob<T>{nullptr, XI[a], 0, h.ni, h.ni, r, 3, (T)1});
           z.copy.push_back(CopyJob<T>{nullptr, L.nd->YB, 0, h.nb, h.nb, r, 3, (T)1});
+          // S_ib of a child = (full P0 basis) B12 (full P1 basis)^T: X_I takes
+          // the first product, Y_B the P1 basis at sigma's boundary positions
           if (L.kmu) {
-            c.copy.push_back(CopyJob<T>{L.emu.UB[h.ii_mu], XI[a], h.pmu, h.ni, h.pmu, L.kmu, 0, (T)1});
-            g.gtt.push_back(GatherJob<cplx<T>, cplx<T>>{L.emu.Uf[h.bb_mu], L.nd->YB, h.mmu - h.pmu,
-                                                        h.nb, ip + h.smu, nullptr, h.nb, L.kmu, 0,
-                                                        1.0});
+            const int m1 = h.mmu - h.pmu;
+            cplx<T> *Ub = scratch((size_t)m1 * L.kmu);
+            c.copy.push_back(CopyJob<T>{L.emu.UB[h.ii_mu], XI[a], L.kmu, h.ni, h.pmu, L.kmu, 1, (T)1});
+            c.copy.push_back(CopyJob<T>{L.emu.Uf[h.bb_mu], Ub, L.kmu, m1, m1, L.kmu, 1, (T)1});
+            g.gtt.push_back(GatherJob<cplx<T>, cplx<T>>{Ub, L.nd->YB, m1, h.nb, ip + h.smu, nullptr,
+                                                        h.nb, L.kmu, 0, 1.0});
           }
           if (L.knu) {
+            const int m1 = h.mnu - h.pnu;
+            cplx<T> *Ub = scratch((size_t)m1 * L.knu);
             c.copy.push_back(CopyJob<T>{L.enu.UB[h.ii_nu], XI[a] + h.pmu + (long)L.kmu * h.ni,
-                                        h.pnu, h.ni, h.pnu, L.knu, 0, (T)1});
-            g.gtt.push_back(GatherJob<cplx<T>, cplx<T>>{L.enu.Uf[h.bb_nu],
-                                                        L.nd->YB + (long)L.kmu * h.nb,
-                                                        h.mnu - h.pnu, h.nb, ip + h.snu, nullptr,
-                                                        h.nb, L.knu, 0, 1.0});
+                                        L.knu, h.ni, h.pnu, L.knu, 1, (T)1});
+            c.copy.push_back(CopyJob<T>{L.enu.Uf[h.bb_nu], Ub, L.knu, m1, m1, L.knu, 1, (T)1});
+            g.gtt.push_back(GatherJob<cplx<T>, cplx<T>>{Ub, L.nd->YB + (long)L.kmu * h.nb, m1,
+                                                        h.nb, ip + h.snu, nullptr, h.nb, L.knu, 0,
+                                                        1.0});
           }
           if (h.ncr) {
             f.fill.push_back(FillJob<T>{ip + h.ib_ri, ip + h.ib_ci, ip + h.ib_vi, h.nib, h.ni,

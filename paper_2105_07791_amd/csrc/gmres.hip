@@ -217,7 +217,16 @@ void gmres(hssx_op_ &A, hssx_fact_ *P, int trans, int nrhs, const c128 *b, long 
   std::unique_ptr<Arena> ar = acquire_arena(dev);
   std::unique_ptr<Staging> stg = acquire_staging(dev, st);
   try {
-    gmres_impl(A, P, trans, nrhs, b, ldb, x, ldx, o, stats, st, *ar, *stg);
+    if (trans == 2) {
+      // adjoint system A^H x = b as conj(A^-T conj(b)): the transposed
+      // solve with the transposed preconditioner on conjugated data
+      c128 *bc = ar->get<c128>((size_t)A.n * nrhs);
+      launch_conj(A.n, nrhs, b, ldb, bc, A.n, st);
+      gmres_impl(A, P, 1, nrhs, bc, A.n, x, ldx, o, stats, st, *ar, *stg);
+      launch_conj(A.n, nrhs, x, ldx, x, ldx, st);
+    } else {
+      gmres_impl(A, P, trans, nrhs, b, ldb, x, ldx, o, stats, st, *ar, *stg);
+    }
   } catch (...) {
     (void)hipStreamSynchronize(st);
     return_arena(dev, std::move(ar));

@@ -25,6 +25,7 @@
 // launches: each builder appends stages (one launch each) to a program.
 #pragma once
 
+#include <cstring>
 #include <deque>
 #include <functional>
 #include <vector>
@@ -138,90 +139,86 @@ template <typename T> inline long stage_elems(const Stage<T> &s) {
   }
 }
 
-// run a program now: job arrays go up through the staging area
+// host image of a program's job arrays (one upload): per stage the offset
+// of its jobs and of its tile list
+template <typename T> struct ProgBlob {
+  std::vector<char> h;
+  std::vector<size_t> jobs, tiles;
+  std::vector<int> ntiles;
+  std::vector<long> me;
+  size_t put(const void *src, size_t bytes) {
+    const size_t off = (h.size() + 255) / 256 * 256;
+    h.resize(off + std::max<size_t>(bytes, 1));
+    if (bytes) std::memcpy(h.data() + off, src, bytes);
+    return off;
+  }
+  template <typename V> size_t putv(const V &v) { return put(v.data(), v.size() * sizeof(v[0])); }
+  template <typename Q> void build(const Q &stages) {
+    for (const Stage<T> &s : stages) {
+      size_t j = 0, t = 0;
+      int nt = 0;
+      switch (s.kind) {
+        case kGemm: {
+          std::vector<BgTile> tl = gemm_tiles(s.gemm);
+          j = putv(s.gemm);
+          t = putv(tl);
+          nt = (int)tl.size();
+          break;
+        }
+        case kCopy: j = putv(s.copy); break;
+        case kSpmm: j = putv(s.sp); break;
+        case kGtt: j = putv(s.gtt); break;
+        case kGwt: j = putv(s.gwt); break;
+        case kGtw: j = putv(s.gtw); break;
+        case kGrt: j = putv(s.grt); break;
+        case kFill: j = putv(s.fill); break;
+        default: j = putv(s.sym); break;
+      }
+      jobs.push_back(j);
+      tiles.push_back(t);
+      ntiles.push_back(nt);
+      me.push_back(stage_elems(s));
+    }
+  }
+  template <typename Q>
+  void launch(const Q &stages, const char *base, const c128 *val, hipStream_t st) const {
+    size_t i = 0;
+    for (const Stage<T> &s : stages) {
+      const size_t q = i++;
+      if (s.size() == 0 || (s.kind == kGemm && ntiles[q] == 0)) continue;
+      launch_stage(s, base + jobs[q], (const BgTile *)(base + tiles[q]), ntiles[q], me[q], val, st);
+    }
+  }
+};
+
+// run a program now: all its job arrays go up through the staging area in
+// one copy
 template <typename T>
 inline void run_prog(const Prog<T> &p, Staging &sg, const c128 *val, hipStream_t st) {
-  for (const auto &s : p.st) {
-    if (s.size() == 0) continue;
-    const void *jobs = nullptr;
-    const BgTile *tiles = nullptr;
-    int nt = 0;
-    switch (s.kind) {
-      case kGemm: {
-        std::vector<BgTile> t = gemm_tiles(s.gemm);
-        if (t.empty()) continue;
-        jobs = sg.put(s.gemm);
-        tiles = sg.put(t);
-        nt = (int)t.size();
-        break;
-      }
-      case kCopy: jobs = sg.put(s.copy); break;
-      case kSpmm: jobs = sg.put(s.sp); break;
-      case kGtt: jobs = sg.put(s.gtt); break;
-      case kGwt: jobs = sg.put(s.gwt); break;
-      case kGtw: jobs = sg.put(s.gtw); break;
-      case kGrt: jobs = sg.put(s.grt); break;
-      case kFill: jobs = sg.put(s.fill); break;
-      default: jobs = sg.put(s.sym); break;
-    }
-    launch_stage(s, jobs, tiles, nt, stage_elems(s), val, st);
-  }
+  if (p.st.empty()) return;
+  ProgBlob<T> b;
+  b.build(p.st);
+  const char *d = sg.put(b.h);
+  b.launch(p.st, d, val, st);
 }
 
 // A program kept on the device for replay (the apply runs the same launches
 // for every vector block of a given width).
 template <typename T> struct Plan {
-  struct Rec {
-    size_t jobs = 0, tiles = 0;
-    int ntiles = 0;
-    long me = 0;
-  };
   std::vector<Stage<T>> st;   // job lists (host copies; sizes and kinds)
-  std::vector<Rec> rec;
+  ProgBlob<T> b;
   DevBuf blob;
   void build(Prog<T> &&p) {
     st.assign(std::make_move_iterator(p.st.begin()), std::make_move_iterator(p.st.end()));
-    rec.assign(st.size(), Rec{});
-    std::vector<char> h;
-    auto put = [&](const void *src, size_t bytes) {
-      size_t off = (h.size() + 255) / 256 * 256;
-      h.resize(off + std::max<size_t>(bytes, 1));
-      if (bytes) std::memcpy(h.data() + off, src, bytes);
-      return off;
-    };
-    for (size_t i = 0; i < st.size(); ++i) {
-      const Stage<T> &s = st[i];
-      Rec &r = rec[i];
-      r.me = stage_elems(s);
-      switch (s.kind) {
-        case kGemm: {
-          std::vector<BgTile> t = gemm_tiles(s.gemm);
-          r.jobs = put(s.gemm.data(), s.gemm.size() * sizeof(BgJob<T>));
-          r.tiles = put(t.data(), t.size() * sizeof(BgTile));
-          r.ntiles = (int)t.size();
-          break;
-        }
-        case kCopy: r.jobs = put(s.copy.data(), s.copy.size() * sizeof(s.copy[0])); break;
-        case kSpmm: r.jobs = put(s.sp.data(), s.sp.size() * sizeof(s.sp[0])); break;
-        case kGtt: r.jobs = put(s.gtt.data(), s.gtt.size() * sizeof(s.gtt[0])); break;
-        case kGwt: r.jobs = put(s.gwt.data(), s.gwt.size() * sizeof(s.gwt[0])); break;
-        case kGtw: r.jobs = put(s.gtw.data(), s.gtw.size() * sizeof(s.gtw[0])); break;
-        case kGrt: r.jobs = put(s.grt.data(), s.grt.size() * sizeof(s.grt[0])); break;
-        case kFill: r.jobs = put(s.fill.data(), s.fill.size() * sizeof(s.fill[0])); break;
-        default: r.jobs = put(s.sym.data(), s.sym.size() * sizeof(s.sym[0])); break;
-      }
-    }
-    blob.alloc(std::max<size_t>(h.size(), 256));
-    if (!h.empty()) HSSX_HIP(hipMemcpy(blob.p, h.data(), h.size(), hipMemcpyHostToDevice));
+    b = ProgBlob<T>{};
+    b.build(st);
+    blob.alloc(std::max<size_t>(b.h.size(), 256));
+    if (!b.h.empty()) HSSX_HIP(hipMemcpy(blob.p, b.h.data(), b.h.size(), hipMemcpyHostToDevice));
+    b.h.clear();
+    b.h.shrink_to_fit();
   }
   void launch(const c128 *val, hipStream_t s) const {
-    const char *b = static_cast<const char *>(blob.p);
-    for (size_t i = 0; i < st.size(); ++i) {
-      if (st[i].size() == 0) continue;
-      if (st[i].kind == kGemm && rec[i].ntiles == 0) continue;
-      launch_stage(st[i], b + rec[i].jobs, (const BgTile *)(b + rec[i].tiles), rec[i].ntiles,
-                   rec[i].me, val, s);
-    }
+    b.launch(st, static_cast<const char *>(blob.p), val, s);
   }
   bool empty() const { return st.empty(); }
 };
@@ -722,11 +719,12 @@ void gym_inverse_blocks(Prog<T> &p, std::vector<HssInv<T> *> &hs, const Alloc<T>
 }
 
 // ---------------------------------------------------------------- entries
-// Full bases Uf and coupling products UB of a generator set, and the
-// per-cluster entry descriptors (positions relative to the subtree).
+// Transposed full bases Uf^T and coupling products (Uf B)^T of a generator
+// set, and the per-cluster entry descriptors (positions relative to the
+// subtree).
 template <typename T> struct EntPrep {
   const Gen<T> *g = nullptr;
-  std::vector<cplx<T> *> Uf, UB;
+  std::vector<cplx<T> *> Uf, UB;   // k_c x size_c and k_sibling x size_c
   std::vector<EntCl<T>> cl;
   std::vector<int> leaf_of;
 };
@@ -736,6 +734,7 @@ void entry_prep(Prog<T> &p, std::vector<EntPrep<T>> &ep, const Alloc<T> &scratch
   int maxL = -1;
   std::vector<std::vector<std::vector<int>>> lev(ep.size());
   std::vector<std::vector<int>> par(ep.size());
+  Stage<T> &cp = p.add(kCopy);
   for (size_t a = 0; a < ep.size(); ++a) {
     const Gen<T> &g = *ep[a].g;
     lev[a] = sub_levels(*g.ct, g.root);
@@ -746,11 +745,12 @@ void entry_prep(Prog<T> &p, std::vector<EntPrep<T>> &ep, const Alloc<T> &scratch
     for (const auto &l : lev[a])
       for (int c : l) {
         if (c == g.root) continue;
-        if (g.ct->leaf(c)) ep[a].Uf[c] = const_cast<cplx<T> *>(g.U[c]);
-        else ep[a].Uf[c] = scratch((size_t)std::max(1, g.ct->size[c] * g.k[c]));
-        const int pp = par[a][c];
+        const int pp = par[a][c], sz = g.ct->size[c];
         const int sib = g.ct->left[pp] == c ? g.ct->right[pp] : g.ct->left[pp];
-        ep[a].UB[c] = scratch((size_t)std::max(1, g.ct->size[c] * g.k[sib]));
+        ep[a].Uf[c] = scratch((size_t)std::max(1, sz * g.k[c]));
+        ep[a].UB[c] = scratch((size_t)std::max(1, sz * g.k[sib]));
+        if (g.ct->leaf(c) && g.k[c])
+          cp.copy.push_back(CopyJob<T>{g.U[c], ep[a].Uf[c], g.ldU[c], g.k[c], g.k[c], sz, 1, (T)1});
       }
     maxL = std::max(maxL, (int)lev[a].size() - 1);
   }
@@ -761,11 +761,12 @@ void entry_prep(Prog<T> &p, std::vector<EntPrep<T>> &ep, const Alloc<T> &scratch
       if (L >= (int)lev[a].size()) continue;
       for (int c : lev[a][L]) {
         if (g.ct->leaf(c)) continue;
-        const int l = g.ct->left[c], r = g.ct->right[c], sl = g.ct->size[l], sz = g.ct->size[c];
-        p.gemm_job(s, ep[a].Uf[l], std::max(1, sl), 0, g.U[c], g.ldU[c], 0, ep[a].Uf[c],
-                   std::max(1, sz), sl, g.k[c], g.k[l], (T)1, 0);
-        p.gemm_job(s, ep[a].Uf[r], std::max(1, g.ct->size[r]), 0, g.U[c] + g.k[l], g.ldU[c], 0,
-                   ep[a].Uf[c] + sl, std::max(1, sz), g.ct->size[r], g.k[c], g.k[r], (T)1, 0);
+        const int l = g.ct->left[c], r = g.ct->right[c], sl = g.ct->size[l];
+        const int kc = g.k[c], kl = g.k[l], kr = g.k[r];
+        p.gemm_job(s, g.U[c], g.ldU[c], 1, ep[a].Uf[l], std::max(1, kl), 0, ep[a].Uf[c],
+                   std::max(1, kc), kc, sl, kl, (T)1, 0);
+        p.gemm_job(s, g.U[c] + kl, g.ldU[c], 1, ep[a].Uf[r], std::max(1, kr), 0,
+                   ep[a].Uf[c] + (long)sl * kc, std::max(1, kc), kc, g.ct->size[r], kr, (T)1, 0);
       }
     }
   }
@@ -777,10 +778,10 @@ void entry_prep(Prog<T> &p, std::vector<EntPrep<T>> &ep, const Alloc<T> &scratch
         if (g.ct->leaf(c)) continue;
         const int lc = g.ct->left[c], rc = g.ct->right[c];
         const int kl = g.k[lc], kr = g.k[rc], sl = g.ct->size[lc], sr = g.ct->size[rc];
-        p.gemm_job(s, ep[a].Uf[lc], std::max(1, sl), 0, g.B12[c], g.ldB12[c], 0, ep[a].UB[lc],
-                   std::max(1, sl), sl, kr, kl, (T)1, 0);
-        p.gemm_job(s, ep[a].Uf[rc], std::max(1, sr), 0, g.B21[c], g.ldB21[c], 0, ep[a].UB[rc],
-                   std::max(1, sr), sr, kl, kr, (T)1, 0);
+        p.gemm_job(s, g.B12[c], g.ldB12[c], 1, ep[a].Uf[lc], std::max(1, kl), 0, ep[a].UB[lc],
+                   std::max(1, kr), kr, sl, kl, (T)1, 0);
+        p.gemm_job(s, g.B21[c], g.ldB21[c], 1, ep[a].Uf[rc], std::max(1, kr), 0, ep[a].UB[rc],
+                   std::max(1, kl), kl, sr, kr, (T)1, 0);
       }
   }
   // descriptors (ids of the full tree; only the subtree's entries are used)

@@ -90,12 +90,13 @@ void launch_symmetrize(int count, const SymJob<T> *jobs, long max_elems, hipStre
 
 // ---------------------------------------------------------------- entries
 // One cluster of a nested-basis symmetric HSS matrix prepared for entry
-// access: Uf is the cluster's full basis (size x k, ld size, the product of
-// the transfer matrices down to the leaves, eq. 2.3), UB = Uf times the
-// coupling block towards the sibling (size x k_sibling, ld size), D the
-// diagonal block of a leaf.  Then for positions i, j in different leaves,
-// with a, b the children of their lowest common ancestor containing i, j:
-//   H(i, j) = UB_a(i, :) . Uf_b(j, :).
+// access: Uf is the transpose of the cluster's full basis (k x size, ld k;
+// the basis is the product of the transfer matrices down to the leaves,
+// eq. 2.3), UB the transpose of that basis times the coupling block towards
+// the sibling (k_sibling x size, ld k_sibling), D the diagonal block of a
+// leaf.  Then for positions i, j in different leaves, with a, b the children
+// of their lowest common ancestor containing i, j:
+//   H(i, j) = UB_a(:, i) . Uf_b(:, j)   (contiguous columns).
 template <typename T> struct EntCl {
   int start, size, left, right, parent, level, k, ldD;
   const cplx<T> *D, *Uf, *UB;
@@ -120,8 +121,8 @@ __device__ __forceinline__ cplx<T> hss_entry(const EntView<T> &V, int i, int j) 
   }
   const EntCl<T> &ca = C[a], &cb = C[b];
   cplx<T> v = czero<T>();
-  const cplx<T> *u = ca.UB + (i - ca.start), *w = cb.Uf + (j - cb.start);
-  for (int t = 0; t < cb.k; ++t) cfma(v, u[(long)t * ca.size], w[(long)t * cb.size]);
+  const cplx<T> *u = ca.UB + (long)(i - ca.start) * cb.k, *w = cb.Uf + (long)(j - cb.start) * cb.k;
+  for (int t = 0; t < cb.k; ++t) cfma(v, u[t], w[t]);
   return v;
 }
 

@@ -23,8 +23,10 @@ void launch_load(int n, int nrhs, const int *rowptr, const int *col, const doubl
 // row_max: longest row (7 scalar stencil, 14 for 2 x 2 blocks, 24 for P2 triangles)
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
                  const c128 *x, long ldx, c128 *y, long ldy, int row_max, hipStream_t st);
+// grad[l] += -Re sum_rhs lam^T (dA/ds_l) x, with conj(lam) in place of lam
+// when conj_lam is set
 void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
-                 const c128 *x, long ld, double *grad, hipStream_t st);
+                 const c128 *x, long ld, double *grad, int conj_lam, hipStream_t st);
 
 // ------------------------------------------------------------ dense fronts
 // One elimination-tree node's augmented dense front
@@ -275,5 +277,7 @@ void launch_givens(int nseg, int j, int m, c128 *H, const c128 *hcol, const doub
 void launch_hsolve(int nseg, int m, const c128 *H, const c128 *g, const int *cnt, c128 *y,
                    hipStream_t st);
 void launch_fill(long n, c128 v, c128 *x, hipStream_t st);
+// y = conj(x), n x nrhs (x may equal y)
+void launch_conj(long n, int nrhs, const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st);
 
 }  // namespace hssx

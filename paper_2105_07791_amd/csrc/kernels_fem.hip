@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *_
 // sum_{T ni l,a,b} int l_l l_a l_b and Gedge_l likewise on boundary edges.
 __global__ void dads_kernel(int N, double omega, const double *__restrict__ s, int nrhs,
                             const c128 *__restrict__ lam, const c128 *__restrict__ x, long ld,
-                            double *__restrict__ grad) {
+                            double *__restrict__ grad, int conj_lam) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   int n = N * N;
   if (l >= n) return;
@@ -314,7 +314,8 @@ __global__ void dads_kernel(int N, double omega, const double *__restrict__ s, i
           for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
               double c = 2.0 * area * tri3(ll, a, b);
-              cfma(accT, mk(c, 0.0), lr[T.v[a]] * xr[T.v[b]]);
+              const c128 la = conj_lam ? conj(lr[T.v[a]]) : lr[T.v[a]];
+              cfma(accT, mk(c, 0.0), la * xr[T.v[b]]);
             }
         }
       }
@@ -336,7 +337,8 @@ __global__ void dads_kernel(int N, double omega, const double *__restrict__ s, i
         for (int a = 0; a < 2; ++a)
           for (int b = 0; b < 2; ++b) {
             double c = (ll == a && a == b) ? 0.25 : 1.0 / 12.0;
-            cfma(accE, mk(h * c, 0.0), lr[vv[a]] * xr[vv[b]]);
+            const c128 la = conj_lam ? conj(lr[vv[a]]) : lr[vv[a]];
+            cfma(accE, mk(h * c, 0.0), la * xr[vv[b]]);
           }
       }
     }
@@ -392,10 +394,10 @@ void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 
 }
 
 void launch_dads(int N, double omega, const double *s, int nrhs, const c128 *lam,
-                 const c128 *x, long ld, double *grad, hipStream_t st) {
+                 const c128 *x, long ld, double *grad, int conj_lam, hipStream_t st) {
   int n = N * N;
   hipLaunchKernelGGL(dads_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, N, omega, s, nrhs,
-                     lam, x, ld, grad);
+                     lam, x, ld, grad, conj_lam);
   HSSX_HIP(hipGetLastError());
 }
 

@@ -176,6 +176,13 @@ __global__ void fill_kernel(long n, c128 v, c128 *__restrict__ x) {
   if (t < n) x[t] = v;
 }
 
+__global__ void conj_kernel(long n, int nrhs, const c128 *x, long ldx, c128 *y, long ldy) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const long i = t % n, r = t / n;
+  y[i + r * ldy] = conj(x[i + r * ldx]);
+}
+
 }  // namespace
 
 void launch_mdot(int n, int nrhs, const Segs &g, int cnt, const c128 *V, long stride,
@@ -248,6 +255,13 @@ void launch_hsolve(int nseg, int m, const c128 *H, const c128 *g, const int *cnt
 void launch_fill(long n, c128 v, c128 *x, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, v, x);
+  HSSX_HIP(hipGetLastError());
+}
+
+void launch_conj(long n, int nrhs, const c128 *x, long ldx, c128 *y, long ldy, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(conj_kernel, dim3(ceil_div(n * nrhs, 256)), dim3(256), 0, st, n, nrhs, x, ldx,
+                     y, ldy);
   HSSX_HIP(hipGetLastError());
 }
 

@@ -67,15 +67,16 @@ class _OperatorBase:
                                  None, _stream()))
         return rp, col, val.view(np.complex128)
 
-    def dAds_contract(self, lam, x, grad=None, stream=None):
-        """grad += -Re sum_rhs lam^T (dA/ds) x."""
+    def dAds_contract(self, lam, x, grad=None, adjoint=False, stream=None):
+        """grad += -Re sum_rhs lam^T (dA/ds) x, or with adjoint=True
+        -Re sum_rhs lam^H (dA/ds) x (lam the adjoint state A^-H dJ/dx)."""
         lt, n, nrhs = _col_major(lam, torch.complex128)
         xt, _, _ = _col_major(x, torch.complex128)
         if grad is None:
             grad = torch.zeros(n, dtype=torch.float64, device=lt.device)
-        check(lib().hssx_dAds_contract(self.handle, nrhs, C.c_void_p(lt.data_ptr()),
-                                       C.c_void_p(xt.data_ptr()), C.c_void_p(grad.data_ptr()),
-                                       _stream(stream)))
+        fn = lib().hssx_dAds_contract_adjoint if adjoint else lib().hssx_dAds_contract
+        check(fn(self.handle, nrhs, C.c_void_p(lt.data_ptr()), C.c_void_p(xt.data_ptr()),
+                 C.c_void_p(grad.data_ptr()), _stream(stream)))
         return grad
 
 
@@ -216,12 +217,14 @@ class Factor:
 
 def gmres_solve(A, P, b, m=50, tol=1e-8, maxit=1000, flexible=False, trans=False, stream=None):
     """Preconditioned restarted GMRES; returns (x, list of per-system stats).
-    A system is one right-hand side of one problem: entry r * A.parts + p."""
+    A system is one right-hand side of one problem: entry r * A.parts + p.
+    trans: False (A x = b), True (A^T x = b) or "adjoint" (A^H x = b)."""
     bt, n, nrhs = _col_major(b, torch.complex128)
     x = torch.empty((nrhs, n), dtype=torch.complex128, device=b.device)
     opts = _lib.GmresOpts(m, tol, maxit, int(flexible))
     stats = (_lib.GmresStats * (nrhs * A.parts))()
-    code = lib().hssx_gmres_solve(A.handle, P.handle if P is not None else None, int(trans), nrhs,
+    tr = 2 if trans == "adjoint" else int(bool(trans))
+    code = lib().hssx_gmres_solve(A.handle, P.handle if P is not None else None, tr, nrhs,
                                   C.c_void_p(bt.data_ptr()), n, C.c_void_p(x.data_ptr()), n,
                                   C.byref(opts), stats, _stream(stream))
     check(code)

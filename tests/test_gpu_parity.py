@@ -158,3 +158,22 @@ def test_errors_are_reported():
         hx.Factor(A, tol=0.0)
     with pytest.raises(HssxError):
         hx.Factor(A, tol=1e-6, leaf_size=0)
+
+
+def test_compression_stopped_above_tol_is_reported():
+    """A compression that stops at its round limit above tol is counted in the
+    factor statistics, and fails the factorization in strict mode."""
+    _dev()
+    hx = _hssx()
+    from paper_2105_07791_amd._lib import HSSX_ERANKCAP, HssxError
+    N, om = 33, 8.0
+    A = hx.Operator(N, om, np.ones(N * N))
+    kw = dict(tol=1e-12, leaf_size=32, beta=16, h_sw=1, k0=2, r=2, max_rounds=1)
+    P = hx.Factor(A, **kw)
+    st = P.stats()
+    assert st["n_above_tol"] > 0 and st["max_estimate"] > 1e-12
+    with pytest.raises(HssxError) as e:
+        hx.Factor(A, strict_tol=True, **kw)
+    assert e.value.code == HSSX_ERANKCAP
+    P2 = hx.Factor(A, tol=1e-6, leaf_size=32, beta=16, h_sw=1, strict_tol=True)
+    assert P2.stats()["n_above_tol"] == 0
