@@ -256,6 +256,21 @@ hssx_status hssx_refactor(hssx_fact P, hssx_op A, void *stream);
 hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev,
                        long ldx, void *y_dev, long ldy, void *stream);
 
+/* hssx_apply for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid allocation): the same y = P^-1 x or P^-T x, with every device buffer it
+ * needs (the elimination-order workspace, the HSS-class nodes' scratch and
+ * their job arrays) taken from a 64 MiB array in the library's device image,
+ * one per GPU, held until the process ends.  No hipMalloc, hipFree or
+ * allocating library call; the dense nodes use the default tile shapes (no
+ * autotuning) and no graph is captured.  HSSX_EINVAL when the workspace for
+ * this factor and nrhs exceeds 64 MiB (about 2 n nrhs 16 bytes plus the HSS
+ * nodes' share).  Every call on one GPU uses that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (other streams, other host
+ * threads) race.  Synchronises stream before returning. */
+hssx_status hssx_apply_noalloc(hssx_fact P, int trans, int nrhs,
+                               const void *x_dev, long ldx, void *y_dev,
+                               long ldy, void *stream);
+
 /* Restarted GMRES on A x = b (eq. 1.2) with preconditioner P, all nrhs
  * right-hand sides advanced together; x0 = 0.  trans = 1 solves A^T x = b
  * with P^-T; trans = 2 solves the adjoint system A^H x = b, as

@@ -64,6 +64,7 @@ SIGNATURES = {
     "hssx_get_csr": (_i, [_vp, _ip, _ip, _dp, C.POINTER(_l), _vp]),
     "hssx_factor": (_i, [_vp, _d, _i, C.POINTER(FactorOpts), _vp, C.POINTER(_vp)]),
     "hssx_apply": (_i, [_vp, _i, _i, _vp, _l, _vp, _l, _vp]),
+    "hssx_apply_noalloc": (_i, [_vp, _i, _i, _vp, _l, _vp, _l, _vp]),
     "hssx_gmres_solve": (_i, [_vp, _vp, _i, _i, _vp, _l, _vp, _l, C.POINTER(GmresOpts),
                               C.POINTER(GmresStats), _vp]),
     "hssx_dAds_contract": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),

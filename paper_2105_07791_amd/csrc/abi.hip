@@ -510,6 +510,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     hipStream_t st = S(stream);
     auto P = std::make_unique<hssx_fact_>();
     P->A = A;
+    P->device = A->device;
     P->pattern = A->pattern_key();
     P->dtype = o.dtype;
     P->tol = tol;
@@ -741,6 +742,20 @@ hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev, long
   });
 }
 
+hssx_status hssx_apply_noalloc(hssx_fact P, int trans, int nrhs, const void *x_dev, long ldx,
+                               void *y_dev, long ldy, void *stream) {
+  return guarded([&] {
+    HSSX_CHECK(P && P->A && x_dev && y_dev && nrhs >= 1 && ldx >= P->A->n && ldy >= P->A->n,
+               HSSX_EINVAL, "invalid argument");
+    HSSX_CHECK(P->desc.p != nullptr, HSSX_EINVAL, "handle holds no factorization");
+    DeviceScope ds(P->device);
+    size_t bytes = 0;
+    char *ws = noalloc_workspace(&bytes);
+    apply_workspace(*P, trans ? 1 : 0, nrhs, (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy,
+                    S(stream), ws, bytes);
+  });
+}
+
 hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const void *b_dev,
                              long ldb, void *x_dev, long ldx, const hssx_gmres_opts *opts,
                              hssx_gmres_stats *stats, void *stream) {
@@ -926,11 +941,14 @@ hssx_status hssx_prof_query(const char *kernel, double *ms, long *launches, doub
 
 void hssx_fact_destroy(hssx_fact P) {
   if (P) {
+    // the factor's own device id: the operator it refers to may already be
+    // destroyed
     int prev = 0;
-    const bool dev = P->A && hipGetDevice(&prev) == hipSuccess;
-    if (dev) (void)hipSetDevice(P->A->device);
+    const int d = P->device;
+    const bool dev = hipGetDevice(&prev) == hipSuccess;
+    if (dev && prev != d) (void)hipSetDevice(d);
     delete P;
-    if (dev) (void)hipSetDevice(prev);
+    if (dev && prev != d) (void)hipSetDevice(prev);
   }
 }
 void hssx_op_destroy(hssx_op A) { delete A; }

@@ -86,6 +86,7 @@ struct hssx_op_ {
 
 struct hssx_fact_ {
   hssx_op_ *A = nullptr;      // operator the factor was built from (not owned)
+  int device = 0;             // device of its buffers (A may be gone at destroy)
   std::vector<long> pattern;  // its pattern key (checked by hssx_refactor)
   hssx_dtype dtype = HSSX_C128;
   double tol = 0;
@@ -139,6 +140,13 @@ void destroy_graphs(hssx_fact_ &P);
 void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
            hipStream_t st);
 bool expand_schur(hssx_fact_ &P, int node, std::vector<c128> &out);
+// the allocation-free apply's workspace on the current device (its address,
+// looked up once per device, and its size)
+char *noalloc_workspace(size_t *bytes);
+// Algorithm 3.1 with every device buffer taken from the caller's workspace
+// (no device allocation); synchronises st before returning
+void apply_workspace(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
+                     long ldy, hipStream_t st, char *ws, size_t ws_bytes);
 // hssx_hss_eval's work (one caller-given HSS matrix)
 void hss_eval(hssx_dtype dtype, int m, int ncl, const int32_t *tree, const int32_t *rank,
               const double *gens, int op, int nrhs, const void *x_dev, void *y_dev, long nij,

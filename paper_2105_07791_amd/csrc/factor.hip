@@ -26,6 +26,8 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -503,7 +505,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
 
     HssInstance *d_inst = sg.put(inst);
     HssCluster *d_cls = sg.put(cls);
-    cplx<T> *d_pool = ar.get<cplx<T>>(pool);
+    // generator pools live in the factor's storage: an accepted instance's
+    // generators stay where the compression wrote them
+    cplx<T> *d_pool = store.get<cplx<T>>(pool);
     int *d_ipool = ar.get<int>(ipool);
     int *d_rank = ar.get<int>(cls.size());
     long scratch_sz = 0;
@@ -706,9 +710,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     for (int a : acc_ids) {
       auto &t = tasks[active[a]];
       if (!t.out) continue;
-      cplx<T> *dst = store.get<cplx<T>>(lay[a].pool);
-      HSSX_HIP(hipMemcpyAsync(dst, d_pool + inst[a].pool, lay[a].pool * sizeof(cplx<T>),
-                              hipMemcpyDeviceToDevice, st));
+      cplx<T> *dst = d_pool + inst[a].pool;
       HssMat<T> &H = *t.out;
       H.m = t.m;
       H.ct = t.ct;
@@ -753,12 +755,32 @@ template <typename T> struct HssLocal {
   Gen<T> gmu, gnu, gii_mu, gbb_mu, gii_nu, gbb_nu, xg;
   EntPrep<T> emu, enu, ex;
   EntView<T> vmu{}, vnu{}, vx{};
-  cplx<T> *YC = nullptr;   // Y_B C
+  cplx<T> *YC = nullptr;   // Y_B C (nb x r)
+  cplx<T> *YCt = nullptr, *YBt = nullptr;   // (Y_B C)^T and Y_B^T (r x nb)
   int kmu = 0, knu = 0;    // columns of Y_B from mu's and nu's S_ib
 };
 
-template <typename T> EntView<T> upload_view(const EntPrep<T> &e, Staging &sg) {
-  return EntView<T>{sg.put(e.cl), sg.put(e.leaf_of)};
+// entry descriptors of many matrices in one upload
+template <typename T>
+std::vector<EntView<T>> upload_views(const std::vector<const EntPrep<T> *> &ep, Staging &sg) {
+  std::vector<char> h;
+  std::vector<size_t> oc, ol;
+  auto put = [&](const void *src, size_t bytes) {
+    const size_t off = (h.size() + 63) / 64 * 64;
+    h.resize(off + std::max<size_t>(bytes, 1));
+    if (bytes) std::memcpy(h.data() + off, src, bytes);
+    return off;
+  };
+  for (const auto *e : ep) {
+    oc.push_back(put(e->cl.data(), e->cl.size() * sizeof(EntCl<T>)));
+    ol.push_back(put(e->leaf_of.data(), e->leaf_of.size() * sizeof(int)));
+  }
+  std::vector<EntView<T>> v(ep.size());
+  if (ep.empty()) return v;
+  const char *d = sg.put(h);
+  for (size_t i = 0; i < ep.size(); ++i)
+    v[i] = EntView<T>{(const EntCl<T> *)(d + oc[i]), (const int *)(d + ol[i])};
+  return v;
 }
 
 // Algorithm 3.3 (with the index reading of Alg. 3.2 for the B21 block):
@@ -994,11 +1016,17 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         run_prog(p, sg, val, st);
         prof_end("hss_prep", st, pp, p.flops);
         flops += p.flops;
+        std::vector<const EntPrep<T> *> eps;
         for (size_t a = 0; a < loc.size(); ++a) {
           loc[a].emu = std::move(ev[2 * a]);
           loc[a].enu = std::move(ev[2 * a + 1]);
-          loc[a].vmu = upload_view(loc[a].emu, sg);
-          loc[a].vnu = upload_view(loc[a].enu, sg);
+          eps.push_back(&loc[a].emu);
+          eps.push_back(&loc[a].enu);
+        }
+        const std::vector<EntView<T>> vs = upload_views(eps, sg);
+        for (size_t a = 0; a < loc.size(); ++a) {
+          loc[a].vmu = vs[2 * a];
+          loc[a].vnu = vs[2 * a + 1];
         }
       }
       // (b) telescoping inverse of S_ii^mu (Alg. 3.3, first block)
@@ -1034,10 +1062,13 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         run_prog(p, sg, val, st);
         prof_end("hss_prep", st, pp, p.flops);
         flops += p.flops;
+        std::vector<const EntPrep<T> *> eps;
         for (size_t i = 0; i < who.size(); ++i) {
           who[i]->ex = std::move(ev[i]);
-          who[i]->vx = upload_view(who[i]->ex, sg);
+          eps.push_back(&who[i]->ex);
         }
+        const std::vector<EntView<T>> vs = upload_views(eps, sg);
+        for (size_t i = 0; i < who.size(); ++i) who[i]->vx = vs[i];
       }
       // (c) inner Schur complement S~ = S_ii^nu - A~(nu,mu) (S_ii^mu)^-1 A~(mu,nu),
       // compressed by Algorithm A.1 from products and entries
@@ -1190,6 +1221,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
           it.push_back(A33Item<T>{L.hs, L.nd, XI[a], L.hs->ni, L.nd->W, L.hs->ni, r});
           Cm[a] = scratch((size_t)r * r);
           L.YC = scratch((size_t)L.hs->nb * r);
+          L.YCt = scratch((size_t)L.hs->nb * r);
         }
         alg33(p, it, ip, scratch);
         Stage<T> &s1 = p.add(kGemm);
@@ -1199,12 +1231,18 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
           if (!r) continue;
           p.gemm_job(s1, XI[a], ni, 1, L.nd->W, ni, 0, Cm[a], r, r, r, ni, (T)1, 0);
         }
+        // (Y_B C)^T = C^T Y_B^T and Y_B^T (r x nb): contiguous rows for the
+        // low-rank term of single entries
         Stage<T> &s2 = p.add(kGemm);
+        Stage<T> &s3 = p.add(kCopy);
         for (size_t a = 0; a < loc.size(); ++a) {
           HssLocal<T> &L = loc[a];
           const int r = L.nd->r, nb = L.hs->nb;
-          if (!r) continue;
+          if (!r || !nb) continue;
+          L.YBt = scratch((size_t)r * nb);
           p.gemm_job(s2, L.nd->YB, nb, 0, Cm[a], r, 0, L.YC, nb, nb, r, r, (T)1, 0);
+          p.gemm_job(s2, Cm[a], r, 1, L.nd->YB, nb, 1, L.YCt, r, r, nb, r, (T)1, 0);
+          s3.copy.push_back(CopyJob<T>{L.nd->YB, L.YBt, nb, r, r, nb, 1, (T)1});
         }
         hipEvent_t pp = prof_begin(st);
         run_prog(p, sg, val, st);
@@ -1223,9 +1261,8 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         op.bchild = ip + h.bchild;
         op.bcpos = ip + h.bcpos;
         op.gid = ip + h.gid;
-        op.YC = L.YC;
-        op.YB = L.nd->YB;
-        op.ldy = h.nb;
+        op.YC = L.YCt;
+        op.YB = L.YBt;
         op.r = L.nd->r;
         CompressTask<T> t;
         t.node = L.node;
@@ -1581,17 +1618,15 @@ void tune_apply(hssx_fact_ &P, int nrhs, hipStream_t st) {
 // The approximate A_ii, L and R are symmetric and transposed (L = R^T), so
 // the transposed apply runs the same programs.
 template <typename T>
-void build_hss_plan(hssx_fact_ &P, int nrhs, c128 *w, HssApplyPlan<T> &pl) {
+void build_hss_progs(hssx_fact_ &P, int nrhs, c128 *w, const Alloc<T> &al,
+                     std::vector<Prog<T>> &ups, std::vector<Prog<T>> &downs, double &fbytes) {
   auto &HD = hdata<T>(P);
   const int n = P.A->n, D = P.sym.max_depth;
   const int *ip = P.hsym_pool.as<int>();
   const int *bpos = P.bpos.as<int>();
-  pl.mem = std::make_unique<Arena>();
-  Arena &mem = *pl.mem;
-  Alloc<T> al = [&](size_t k) { return mem.get<cplx<T>>(k); };
-  pl.up.resize(D + 1);
-  pl.down.resize(D + 1);
-  pl.fbytes = 0;
+  ups.assign(D + 1, Prog<T>{});
+  downs.assign(D + 1, Prog<T>{});
+  fbytes = 0;
   for (int d = 0; d <= D; ++d) {
     const auto &hn = P.hss_nodes[d];
     if (hn.empty()) continue;
@@ -1607,7 +1642,7 @@ void build_hss_plan(hssx_fact_ &P, int nrhs, c128 *w, HssApplyPlan<T> &pl) {
       const HssNodeData<T> &nd = HD[k];
       const FrontDesc &fd = P.h_desc[k];
       const int r = nd.r;
-      pl.fbytes += nd.Hmu.bytes() + nd.Hs.bytes() + (double)(h.ni + h.nb) * r * sizeof(cplx<T>);
+      fbytes += nd.Hmu.bytes() + nd.Hs.bytes() + (double)(h.ni + h.nb) * r * sizeof(cplx<T>);
       cplx<T> *t = al((size_t)h.ni * nrhs);
       z[a] = al((size_t)h.ni * nrhs);
       g0.gwt.push_back(GatherJob<c128, cplx<T>>{w + fd.ioff, t, n, h.ni, nullptr, nullptr, h.ni,
@@ -1655,8 +1690,24 @@ void build_hss_plan(hssx_fact_ &P, int nrhs, c128 *w, HssApplyPlan<T> &pl) {
       s2.gtw.push_back(GatherJob<cplx<T>, c128>{q[a], w + fd.ioff, h.ni, n, nullptr, nullptr,
                                                  h.ni, nrhs, 1, 1.0});
     }
-    pl.up[d].build(std::move(up));
-    pl.down[d].build(std::move(dn));
+    ups[d] = std::move(up);
+    downs[d] = std::move(dn);
+  }
+}
+
+template <typename T>
+void build_hss_plan(hssx_fact_ &P, int nrhs, c128 *w, HssApplyPlan<T> &pl) {
+  pl.mem = std::make_unique<Arena>();
+  Arena &mem = *pl.mem;
+  Alloc<T> al = [&](size_t k) { return mem.get<cplx<T>>(k); };
+  std::vector<Prog<T>> ups, downs;
+  build_hss_progs<T>(P, nrhs, w, al, ups, downs, pl.fbytes);
+  const int D = P.sym.max_depth;
+  pl.up.resize(D + 1);
+  pl.down.resize(D + 1);
+  for (int d = 0; d <= D; ++d) {
+    pl.up[d].build(std::move(ups[d]));
+    pl.down[d].build(std::move(downs[d]));
   }
 }
 
@@ -1687,9 +1738,11 @@ void hss_step(hssx_fact_ &P, int d, bool up, int nrhs, hipStream_t st) {
 
 // Algorithm 3.1 on vectors in elimination order: up-sweep with the fused
 // block solve depth by depth from the leaves, then the down-sweep
-void sweeps(hssx_fact_ &P, int trans, int nrhs, c128 *w, c128 *tb, hipStream_t st) {
+using HssLauncher = std::function<void(int, bool)>;
+
+void sweeps(hssx_fact_ &P, int trans, int nrhs, c128 *w, c128 *tb, hipStream_t st,
+            const std::vector<int> &cu, const std::vector<int> &cd, const HssLauncher &hss) {
   const int D = P.sym.max_depth;
-  const auto &cu = P.cfg_up.at(nrhs), &cd = P.cfg_down.at(nrhs);
   const bool prof = prof_on() && !P.capturing;
   for (int d = D; d >= 0; --d) {
     if (!P.dense_nodes[d].empty()) {
@@ -1699,7 +1752,7 @@ void sweeps(hssx_fact_ &P, int trans, int nrhs, c128 *w, c128 *tb, hipStream_t s
     }
     if (!P.hss_nodes[d].empty()) {
       hipEvent_t ph = prof ? prof_begin(st) : nullptr;
-      hss_step(P, d, true, nrhs, st);
+      hss(d, true);
       if (prof) prof_end("apply_hss", st, ph, 0.0);
     }
   }
@@ -1712,7 +1765,7 @@ void sweeps(hssx_fact_ &P, int trans, int nrhs, c128 *w, c128 *tb, hipStream_t s
     }
     if (!P.hss_nodes[d].empty()) {
       hipEvent_t ph = prof ? prof_begin(st) : nullptr;
-      hss_step(P, d, false, nrhs, st);
+      hss(d, false);
       if (prof) prof_end("apply_hss", st, ph, 0.0);
     }
   }
@@ -1757,7 +1810,8 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
       hipGraph_t graph = nullptr;
       P.capturing = true;
       try {
-        sweeps(P, trans, nrhs, w, tb, P.cap_stream);
+        sweeps(P, trans, nrhs, w, tb, P.cap_stream, P.cfg_up.at(nrhs), P.cfg_down.at(nrhs),
+               [&](int d, bool up) { hss_step(P, d, up, nrhs, P.cap_stream); });
       } catch (...) {
         P.capturing = false;
         (void)hipStreamEndCapture(P.cap_stream, &graph);
@@ -1779,7 +1833,8 @@ void apply(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
                (P.up_velems[d] + P.down_velems[d]) * nrhs * sizeof(c128);
     prof_end("apply_graph", st, pg, bytes);
   } else {
-    sweeps(P, trans, nrhs, w, tb, st);
+    sweeps(P, trans, nrhs, w, tb, st, P.cfg_up.at(nrhs), P.cfg_down.at(nrhs),
+           [&](int d, bool up) { hss_step(P, d, up, nrhs, st); });
   }
   launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);
 }
@@ -1826,6 +1881,68 @@ template <typename T> bool expand_t(hssx_fact_ &P, int node, std::vector<c128> &
 // kept none)
 bool expand_schur(hssx_fact_ &P, int node, std::vector<c128> &out) {
   return P.dtype == HSSX_C64 ? expand_t<float>(P, node, out) : expand_t<double>(P, node, out);
+}
+
+namespace {
+
+template <typename T>
+void apply_ws_t(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y, long ldy,
+                hipStream_t st, char *ws, size_t ws_bytes) {
+  const int n = P.A->n, D = P.sym.max_depth;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = (off + 255) / 256 * 256;
+    HSSX_CHECK(o + bytes <= ws_bytes, HSSX_EINVAL,
+               "apply workspace exceeds the allocation-free entry point's maximum (" +
+                   std::to_string(ws_bytes >> 20) + " MiB)");
+    off = o + bytes;
+    return ws + o;
+  };
+  c128 *w = reinterpret_cast<c128 *>(take((size_t)n * nrhs * sizeof(c128)));
+  c128 *tb = reinterpret_cast<c128 *>(take((size_t)n * nrhs * sizeof(c128)));
+  // programs of the HSS-class nodes: scratch and job arrays in the workspace
+  std::vector<Prog<T>> ups, downs;
+  double fb = 0;
+  Alloc<T> al = [&](size_t k) {
+    return reinterpret_cast<cplx<T> *>(take(std::max<size_t>(k, 1) * sizeof(cplx<T>)));
+  };
+  if (!P.hsym.empty()) build_hss_progs<T>(P, nrhs, w, al, ups, downs, fb);
+  std::vector<ProgBlob<T>> bu(D + 1), bd(D + 1);
+  std::vector<char> h;
+  std::vector<size_t> ou(D + 1, 0), od(D + 1, 0);
+  auto append = [&](const std::vector<char> &v) {
+    const size_t o = (h.size() + 255) / 256 * 256;
+    h.resize(o + std::max<size_t>(v.size(), 1));
+    if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size());
+    return o;
+  };
+  for (int d = 0; d <= D && !P.hsym.empty(); ++d) {
+    bu[d].build(ups[d].st);
+    bd[d].build(downs[d].st);
+    ou[d] = append(bu[d].h);
+    od[d] = append(bd[d].h);
+  }
+  char *jobs = h.empty() ? nullptr : take(h.size());
+  if (jobs) HSSX_HIP(hipMemcpyAsync(jobs, h.data(), h.size(), hipMemcpyHostToDevice, st));
+  // default tile shapes (the autotuner would allocate its trial vectors)
+  const std::vector<int> cfg(D + 1, 2);
+  const c128 *val = P.A->val.as<c128>();
+  launch_permute(n, nrhs, P.perm.as<int>(), x, ldx, w, n, 0, st);
+  sweeps(P, trans, nrhs, w, tb, st, cfg, cfg, [&](int d, bool up) {
+    if (up) bu[d].launch(ups[d].st, jobs + ou[d], val, st);
+    else bd[d].launch(downs[d].st, jobs + od[d], val, st);
+  });
+  launch_permute(n, nrhs, P.perm.as<int>(), w, n, y, ldy, 1, st);
+  // the job image is host memory of this call
+  HSSX_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void apply_workspace(hssx_fact_ &P, int trans, int nrhs, const c128 *x, long ldx, c128 *y,
+                     long ldy, hipStream_t st, char *ws, size_t ws_bytes) {
+  if (P.dtype == HSSX_C64) apply_ws_t<float>(P, trans, nrhs, x, ldx, y, ldy, st, ws, ws_bytes);
+  else apply_ws_t<double>(P, trans, nrhs, x, ldx, y, ldy, st, ws, ws_bytes);
 }
 
 }  // namespace hssx

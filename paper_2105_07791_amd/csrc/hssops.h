@@ -136,8 +136,8 @@ template <typename T> struct EntryOp {
   int kind;
   EntView<T> H0, H1;              // kind 0: mu's and nu's S; kind 1: X and nu's S
   const int *bchild, *bcpos, *gid;
-  const cplx<T> *YC, *YB;         // kind 0: Y_B C and Y_B (nb x r, ld ldy)
-  int ldy, r;
+  const cplx<T> *YC, *YB;         // kind 0: (Y_B C)^T and Y_B^T (r x nb, ld r)
+  int r;
   const int *rp, *cp, *vi;        // kind 1: A~(nu,mu) rows
 };
 

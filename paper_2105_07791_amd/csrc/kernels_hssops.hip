@@ -176,8 +176,8 @@ __device__ cplx<T> op_entry(const EntryOp<T> &op, int i, int j, const int *__res
         if (col[lo] == gj) v = ccast<T>(val[lo]);
       }
     }
-    for (int t = 0; t < op.r; ++t)
-      cfms(v, op.YC[i + (long)t * op.ldy], op.YB[j + (long)t * op.ldy]);
+    const cplx<T> *yc = op.YC + (long)i * op.r, *yb = op.YB + (long)j * op.r;
+    for (int t = 0; t < op.r; ++t) cfms(v, yc[t], yb[t]);
   } else {
     v = hss_entry(op.H1, i, j);
     for (int e = op.rp[i]; e < op.rp[i + 1]; ++e) {

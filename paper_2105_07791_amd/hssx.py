@@ -196,6 +196,15 @@ class Factor:
                                C.c_void_p(y.data_ptr()), n, _stream(stream)))
         return y.t() if x.dim() == 2 else y[0]
 
+    def apply_noalloc(self, x, trans=False, stream=None):
+        """apply() through hssx_apply_noalloc (no device allocation in the
+        library; y is allocated here by torch)."""
+        xt, n, nrhs = _col_major(x, torch.complex128)
+        y = torch.empty((nrhs, n), dtype=torch.complex128, device=x.device)
+        check(lib().hssx_apply_noalloc(self.handle, int(trans), nrhs, C.c_void_p(xt.data_ptr()),
+                                       n, C.c_void_p(y.data_ptr()), n, _stream(stream)))
+        return y.t() if x.dim() == 2 else y[0]
+
     def stats(self):
         s = _lib.FactorStats()
         check(lib().hssx_get_factor_stats(self.handle, C.byref(s)))
