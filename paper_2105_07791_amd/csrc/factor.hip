@@ -364,12 +364,17 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
   const int k0 = o.k0, r = o.r;
   const c128 *val = A.val.as<c128>();
   long osz = 0, ysz = 0;
+  // sample columns one compression kernel holds
+  constexpr int kMaxCols = 1024;
   for (auto &t : tasks) {
-    t.k = std::max(1, std::min(std::max(k0, t.k_init), t.m));
+    // the initial rank guess stays below the capacity (s + r probes fit)
+    t.k = std::max(1, std::min(std::min(std::max(k0, t.k_init), t.m), kMaxCols - 2 * r));
     t.s = t.k + r;
-    // room for every round up to k >= m (s = k + r samples + r probes)
+    // room for every round up to k >= m (s = k + r samples + r probes), at
+    // most the kernel's capacity: a compression that reaches it stops there
+    // (counted above tol when its estimate misses)
     t.cap = std::min(t.k + r * (o.max_rounds + 1), t.m + 3 * r);
-    t.cap = std::max(t.cap, t.s + r);
+    t.cap = std::min(kMaxCols, std::max(t.cap, t.s + r));
     t.ooff = osz;
     t.yoff = ysz;
     osz += (long)t.m * t.cap;

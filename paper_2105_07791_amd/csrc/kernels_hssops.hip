@@ -191,9 +191,11 @@ __device__ cplx<T> op_entry(const EntryOp<T> &op, int i, int j, const int *__res
   return v;
 }
 
-// One (instance, cluster) per workgroup: a leaf's diagonal block D = S(I, I),
-// or an internal cluster's B12 = S(sk_l, sk_r), B21 = S(sk_r, sk_l), written
-// where the compression kernel reads them.
+// kEntSplit workgroups per (instance, cluster): a leaf's diagonal block
+// D = S(I, I), or an internal cluster's B12 = S(sk_l, sk_r) with
+// B21 = B12^T (the operators are symmetric), written where the compression
+// kernel reads them.
+constexpr int kEntSplit = 8;
 template <typename T>
 __global__ __launch_bounds__(kBT) void entries_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
@@ -205,10 +207,11 @@ __global__ __launch_bounds__(kBT) void entries_kernel(
   const EntryOp<T> &op = ops[I.eop];
   const HssCluster C = cls[I.cl_off + it.cl];
   cplx<T> *P = pool + I.pool;
+  const int t0 = blockIdx.y * kBT + threadIdx.x, stride = kEntSplit * kBT;
   if (C.left < 0) {
     const int rows = C.size;
     cplx<T> *D = P + C.D;
-    for (int e = threadIdx.x; e < rows * rows; e += kBT)
+    for (int e = t0; e < rows * rows; e += stride)
       D[e] = op_entry(op, C.start + e % rows, C.start + e / rows, rowptr, col, val);
     return;
   }
@@ -216,13 +219,11 @@ __global__ __launch_bounds__(kBT) void entries_kernel(
   const int kl = rank[I.cl_off + C.left], kr = rank[I.cl_off + C.right];
   const int *skl = ipool + I.ipool + L.sk, *skr = ipool + I.ipool + R.sk;
   cplx<T> *B12 = P + C.B12, *B21 = P + C.B21;
-  for (int e = threadIdx.x; e < kl * kr; e += kBT) {
+  for (int e = t0; e < kl * kr; e += stride) {
     const int a = e % kl, b = e / kl;
-    B12[e] = op_entry(op, skl[a], skr[b], rowptr, col, val);
-  }
-  for (int e = threadIdx.x; e < kl * kr; e += kBT) {
-    const int a = e % kr, b = e / kr;
-    B21[e] = op_entry(op, skr[a], skl[b], rowptr, col, val);
+    const cplx<T> v = op_entry(op, skl[a], skr[b], rowptr, col, val);
+    B12[e] = v;
+    B21[b + (long)a * kr] = v;
   }
 }
 
@@ -293,8 +294,8 @@ void launch_entries(int count, const HssItem *items, const HssInstance *inst,
                     const EntryOp<T> *ops, const int *rowptr, const int *col, const c128 *val,
                     hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(entries_kernel<T>, dim3(count), dim3(kBT), 0, st, items, inst, cl, pool,
-                     ipool, rank, ops, rowptr, col, val);
+  hipLaunchKernelGGL(entries_kernel<T>, dim3(count, kEntSplit), dim3(kBT), 0, st, items, inst, cl,
+                     pool, ipool, rank, ops, rowptr, col, val);
   HSSX_HIP(hipGetLastError());
 }
 

@@ -172,6 +172,8 @@ BATCHES = {
     # reduced batches for parity tests
     "helmholtz_p1_batch8": dict(count=8, lo=9, hi=65, seed=8, kh=0.3, receivers=8),
     "helmholtz_p1_batch32": dict(count=32, lo=65, hi=129, seed=9, kh=0.2, receivers=8),
+    # the 256-problem batch's size range and resolution on 16 problems
+    "helmholtz_p1_batch16": dict(count=16, lo=65, hi=513, seed=0, kh=0.25, receivers=8),
 }
 
 
