@@ -221,17 +221,23 @@ hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col,
 
 /* Approximate factorization P = LDR (Algorithm 3.4): box nested dissection
  * with leaf boxes of at most leaf_size DOFs (Sec. 4: ND until the leaf boxes
- * are small), dense elimination below the switching height, Schur
- * complements compressed to HSS by adaptive randomized sampling (Algorithm
- * A.1, relative tolerance tol, eq. 2.7), and the HSS-class interior blocks
- * handled by the 2x2 block inverse of Algorithms 3.2/3.3.  With dtype
- * HSSX_C64 every front is stored and eliminated in complex64 except the
- * roots (top separators), which stay complex128.  The rank of a compression
- * grows by r per round until its estimate meets tol; it also stops, and the
- * estimate is reported in max_estimate, at max_rounds, at the sample or
- * local-block capacity (2 (k + r) > 1024 rows), and, for complex64 fronts,
- * when the estimate is within 10 tol and a round no longer halves it (the
- * rounding-noise floor of single precision).  A batch operator gets one
+ * are small); dense fronts (Gauss-Jordan) up to the switching height h_sw
+ * and at the roots; above it HSS arithmetic (Sec. 3.3-3.5): the children's
+ * Schur complements stay in generator form, the interior block is inverted
+ * by Algorithm 3.3 with telescoping HSS inverses of S_ii^mu and of the inner
+ * Schur complement S~, the Gauss transforms are kept as low-rank generators
+ * (eq. 3.7), and S(sigma) and S~ are compressed by adaptive randomized
+ * sampling (Algorithm A.1, relative tolerance tol, eq. 2.7) from structured
+ * products and entries without being formed.  With dtype HSSX_C64 every
+ * factor is stored and computed in complex64 except the roots (top
+ * separators), which stay complex128.  The rank of a compression grows by r
+ * per round until its estimate meets tol; it also stops at max_rounds and
+ * at the sample or local-block capacity (1024 columns; 2 (k + r) > 1024
+ * rows), and, in complex64, when the estimate is within 10 tol and a round
+ * no longer halves it (the rounding-noise floor of single precision) or
+ * when a round keeps more than 0.7 of the previous estimate.  Compressions
+ * that stop above tol are counted in n_above_tol (HSSX_ERANKCAP with
+ * opts->strict_tol); max_estimate reports the largest accepted estimate.  A batch operator gets one
  * tree per problem, all processed depth by depth in the same launches.
  * Host-blocking: synchronises stream after every batch of compressions to
  * read the error estimates.  opts may be NULL (defaults). */

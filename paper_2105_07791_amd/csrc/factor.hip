@@ -348,6 +348,9 @@ inline double compress_flops(const HssCluster &c, const HssInstance &I) {
 constexpr int kMaxLocalRows = 1024;
 // acceptance slack of a stalled complex64 estimate, relative to tol
 constexpr double kStallSlack = 10.0;
+// a complex64 round that keeps more than this fraction of the previous
+// estimate makes no progress
+constexpr double kNoProgress = 0.7;
 
 struct CompressAcc {
   double flops = 0;
@@ -657,9 +660,14 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
                     t.s + 2 * r > t.cap || 2 * (t.k + r) > kMaxLocalRows;
       // complex64 operators carry rounding noise of relative size ~ eps_fp32
       // sqrt(m): once the estimate sits within kStallSlack of tol and another
-      // r columns no longer halve it, the rank is chasing that noise
-      if (sizeof(T) == sizeof(float) && t.rounds >= 2 && t.est <= kStallSlack * tol &&
-          t.est > 0.5 * t.est_prev)
+      // r columns no longer halve it, the rank is chasing that noise.  Far
+      // above tol the same holds when a round improves the estimate by less
+      // than kNoProgress: the operator's entries and products then disagree
+      // at that level (rounding of a telescoping inverse of ill-conditioned
+      // blocks), and more rank cannot remove it
+      if (sizeof(T) == sizeof(float) && t.rounds >= 2 &&
+          ((t.est <= kStallSlack * tol && t.est > 0.5 * t.est_prev) ||
+           t.est > kNoProgress * t.est_prev))
         accept = true;
       if (!accept) {
         t.k += r;
