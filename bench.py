@@ -349,7 +349,11 @@ def main():
                     help="also run one 256 MiB device-to-device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--alt-tol", type=float, default=1e-4,
-                    help="also time the complex64 form at this HSS tolerance (0: skip)")
+                    help="(unused; kept for command compatibility)")
+    ap.add_argument("--switch-study", action="store_true",
+                    help="instead of the benchmark: time the complex64 HSS form with the "
+                         "switching height h_sw = 2..6 and with the size rule at 2, 4 and "
+                         "8 beta, reporting GMRES iterations, ranks, bytes and time")
     args = ap.parse_args()
     from synth import BATCHES
     if args.cpu_baseline_child:
@@ -410,7 +414,7 @@ def main():
         P = factors.get(key)
         if P is None:
             P = hssx.Factor(A, tol=f["tol"], leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=f["h_sw"],
-                            dtype=f["dtype"], seed=1)
+                            dtype=f["dtype"], seed=1, switch_size=f.get("switch_size", 0))
             factors[key] = P
             fs = P.stats()
             analysis[key] = {"symbolic_ms": fs["ms_symbolic"], "setup_ms": fs["ms_setup"],
@@ -456,6 +460,34 @@ def main():
                 "exact_factor_flops": fs["exact_factor_flops"], "k_max": fs["k_max"],
                 "max_estimate": fs["max_estimate"], "n_above_tol": fs["n_above_tol"],
                 "hss_nodes": fs["n_hss_nodes"], "compressions": fs["n_compressed"]}, x
+
+    if args.switch_study:
+        # the switching level (Alg. 3.4): by height above the leaves, and by
+        # separator size (the paper's 3D rule switches at four times beta)
+        study = []
+        for rule, val in [("h_sw", v) for v in (2, 3, 4, 5, 6)] + \
+                         [("size", m * pr.beta) for m in (2, 4, 8)]:
+            key = f"{rule}={val}"
+            FORMS[key] = dict(dtype="c64", h_sw=val if rule == "h_sw" else pr.h_sw,
+                              tol=tol_mixed, flexible=True,
+                              switch_size=val if rule == "size" else 0)
+            step(key)
+            rr = [step(key) for _ in range(2)]
+            sm, _ = summarize(key, rr)
+            study.append({"rule": rule, "value": val, "seconds": sm["seconds"],
+                          "factor_s": sm["factor_s"], "solve_s": sm["solve_s"],
+                          "iters_max": sm["iters_max"], "k_max": sm["k_max"],
+                          "hss_nodes": sm["hss_nodes"], "factor_bytes": sm["factor_bytes"],
+                          "factor_flops": sm["factor_flops"], "max_estimate": sm["max_estimate"],
+                          "n_above_tol": sm["n_above_tol"], "true_res_max": sm["true_res_max"]})
+            print(f"[bench] {key}: {sm['seconds']:.4f}s iters {sm['iters_max']}", file=sys.stderr,
+                  flush=True)
+            del factors[key]
+            torch.cuda.synchronize()
+        print(json.dumps({"switch_study": study, "workload": args.workload, "n": pr.n,
+                          "nrhs": pr.nrhs, "hss_tol": tol_mixed, "beta": pr.beta,
+                          "timing": "median of 2 HIP-event timed steps (refactor + solve)"}))
+        return 0
 
     print(f"[bench] {args.workload}: n={pr.n} nrhs={pr.nrhs} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)

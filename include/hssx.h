@@ -56,6 +56,19 @@ typedef enum { HSSX_C128 = 0, HSSX_C64 = 1 } hssx_dtype;
 
 typedef struct hssx_op_ *hssx_op;      /* assembled operator A */
 typedef struct hssx_fact_ *hssx_fact;  /* approximate factorization P */
+typedef struct hssx_ctx_ *hssx_ctx;    /* caller-allocator context */
+
+/* Device allocator of a context: alloc returns bytes of device memory on the
+ * context's device (NULL: out of memory), usable by work queued on stream
+ * (the hipStream_t of the library call, as void*; NULL outside a call);
+ * free gives back a pointer alloc returned, with its size.  user is passed
+ * through.  The callbacks may be called from any library call made on a
+ * handle of the context, on that call's thread. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *stream, void *user);
+  void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+  void *user;
+} hssx_allocator;
 
 /* Problem description (Sec. 4.2), with a first-order absorbing condition on
  * all four sides of the unit square. */
@@ -90,6 +103,10 @@ typedef struct {
                        operand split into a bf16 head and tail (three
                        products, about 16 significant bits); 0 = fp32
                        vector arithmetic (default) */
+  int switch_size;  /* > 0: switching by size instead of height: a node uses
+                       HSS arithmetic when its interior |I| holds at least
+                       switch_size DOFs or a child does (the paper's 3D rule
+                       switches at four times beta); 0: the h_sw rule */
   int strict_tol;   /* nonzero: hssx_factor / hssx_refactor fail with
                        HSSX_ERANKCAP when any compression stops with its
                        error estimate above tol; 0 (default): such
@@ -139,6 +156,29 @@ typedef struct {
   double exact_factor_flops;  /* factorization of this tree (dense fronts,
                                  Gauss-Jordan), for comparison */
 } hssx_factor_stats;
+
+/* Contexts (the boundary's allocator injection; eq. 1.1 / eq. 3.1 calls made
+ * with caller-owned device memory).  hssx_create makes a context on device
+ * with a copy of *alloc.  hssx_bind(ctx) binds it to the calling thread
+ * (NULL unbinds): operators and factors created by that thread while it is
+ * bound (hssx_assemble*, hssx_op_batch, hssx_factor; also hssx_hss_eval)
+ * belong to the context, and every device buffer the library takes for
+ * them, in that call and in every later call on them (factor storage,
+ * scratch arenas, staging areas, GMRES bases, apply workspaces and
+ * programs), comes from its allocator and goes back through it when the
+ * handle or the context is destroyed.  hssx_destroy synchronises the device,
+ * frees the context's cached scratch and staging areas through the
+ * allocator and deletes it: destroy the context's handles first.  Memory
+ * HIP itself takes for graph instantiation and pinned host staging are not
+ * device buffers of the library and do not pass through the allocator.
+ * hssx_ctx_stats reports the bytes currently taken from the allocator and
+ * the counts of alloc and free calls. */
+hssx_status hssx_create(int device, const hssx_allocator *alloc,
+                        hssx_ctx *ctx_out);
+hssx_status hssx_bind(hssx_ctx ctx);
+hssx_status hssx_ctx_stats(hssx_ctx ctx, long *live_bytes, long *allocs,
+                           long *frees);
+void hssx_destroy(hssx_ctx ctx);
 
 /* Build A (CSR, natural numbering, 7-point P1 stencil, sorted columns) for
  * the slowness field s (device, float64[N*N], caller-owned, read during the

@@ -14,6 +14,14 @@ STATUS_NAMES = {0: "HSSX_OK", 1: "HSSX_ENOCONV", -1: "HSSX_EINVAL", -2: "HSSX_EN
                 -3: "HSSX_ESINGULAR", -4: "HSSX_ERANKCAP", -5: "HSSX_EHIP"}
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 class ProblemDesc(C.Structure):
     _fields_ = [("N", C.c_int), ("omega", C.c_double)]
 
@@ -22,7 +30,7 @@ class FactorOpts(C.Structure):
     _fields_ = [("beta", C.c_int), ("h_sw", C.c_int), ("k0", C.c_int), ("r", C.c_int),
                 ("max_rounds", C.c_int), ("dtype", C.c_int), ("seed", C.c_uint32),
                 ("id_rel_tol", C.c_double), ("apply_graph", C.c_int), ("autotune", C.c_int),
-                ("sample_bf16", C.c_int), ("strict_tol", C.c_int)]
+                ("sample_bf16", C.c_int), ("switch_size", C.c_int), ("strict_tol", C.c_int)]
 
 
 class GmresOpts(C.Structure):
@@ -78,6 +86,10 @@ SIGNATURES = {
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),
     "hssx_get_schur": (_i, [_vp, _i, _dp, _l]),
     "hssx_hss_eval": (_i, [_i, _i, _i, _i, _ip, _ip, _dp, _i, _i, _vp, _vp, _l, _ip, _dp, _vp]),
+    "hssx_create": (_i, [_i, _vp, C.POINTER(_vp)]),
+    "hssx_bind": (_i, [_vp]),
+    "hssx_ctx_stats": (_i, [_vp, C.POINTER(_l), C.POINTER(_l), C.POINTER(_l)]),
+    "hssx_destroy": (None, [_vp]),
     "hssx_prof_enable": (_i, [_i]),
     "hssx_prof_query": (_i, [C.c_char_p, _dp, C.POINTER(_l), _dp]),
     "hssx_fact_destroy": (None, [_vp]),

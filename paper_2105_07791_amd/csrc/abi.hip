@@ -45,6 +45,10 @@ struct DeviceScope {
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// the context bound to the calling thread (hssx_bind): handles created
+// while it is bound allocate through its allocator
+thread_local hssx_ctx_ *g_bound = nullptr;
+
 // Subtree roots of a child's cluster tree: [P0 | P1] split at the root when
 // both parts exist (Fig. 4), else the whole tree is the one present part.
 void child_roots(const NDNode &c, int &ii, int &bb, int &split) {
@@ -206,6 +210,7 @@ hssx_status dads(hssx_op A, int nrhs, const void *lambda_dev, const void *x_dev,
     HSSX_CHECK(A->dofs == 1 && A->mesh == kMeshCG, HSSX_EINVAL,
                "the slowness gradient is defined for P1 Helmholtz operators");
     DeviceScope ds(A->device);
+    AllocScope as_(A->ctx, stream);
     for (size_t q = 0; q < A->part_N.size(); ++q) {
       const int o = A->part_off[q];
       launch_dads(A->part_N[q], A->part_omega[q], A->s.as<double>() + o, nrhs,
@@ -229,8 +234,10 @@ hssx_status hssx_assemble(int device, const hssx_problem_desc *desc, const doubl
     HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
     *A_out = nullptr;
     DeviceScope ds(device);
+    AllocScope as_(g_bound, stream);
     auto A = std::make_unique<hssx_op_>();
     A->device = device;
+    A->ctx = g_bound;
     A->N = desc->N;
     A->omega = desc->omega;
     const int N = desc->N, n = N * N;
@@ -276,9 +283,11 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc, con
     HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
     *A_out = nullptr;
     DeviceScope ds(device);
+    AllocScope as_(g_bound, stream);
     hipStream_t st = S(stream);
     auto A = std::make_unique<hssx_op_>();
     A->device = device;
+    A->ctx = g_bound;
     A->N = desc->N;
     A->omega = desc->omega;
     A->dofs = 2;
@@ -332,9 +341,11 @@ hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const do
     HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
     *A_out = nullptr;
     DeviceScope ds(device);
+    AllocScope as_(g_bound, stream);
     hipStream_t st = S(stream);
     auto A = std::make_unique<hssx_op_>();
     A->device = device;
+    A->ctx = g_bound;
     A->N = desc->N;
     A->omega = desc->omega;
     A->dofs = 6;
@@ -400,9 +411,11 @@ hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op
     }
     HSSX_CHECK(n < (1L << 31) && nnz < (1L << 31), HSSX_EINVAL, "batch too large for 32-bit indices");
     DeviceScope ds(parts[0]->device);
+    AllocScope as_(g_bound, stream);
     hipStream_t st = S(stream);
     auto A = std::make_unique<hssx_op_>();
     A->device = parts[0]->device;
+    A->ctx = g_bound;
     A->n = (int)n;
     A->nnz = nnz;
     A->h_rowptr.reserve(n + 1);
@@ -458,6 +471,7 @@ hssx_status hssx_load(hssx_op A, int nrhs, const double *f_dev, long ldf, void *
     HSSX_CHECK(A && f_dev && b_dev && nrhs >= 1 && ldf >= A->n && ldb >= A->n, HSSX_EINVAL,
                "invalid argument");
     DeviceScope ds(A->device);
+    AllocScope as_(A->ctx, stream);
     launch_load(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->mval.as<double>(), f_dev, ldf,
                 (c128 *)b_dev, ldb, S(stream));
   });
@@ -471,6 +485,7 @@ hssx_status hssx_matvec(hssx_op A, int trans, int nrhs, const void *x_dev, long 
     HSSX_CHECK(x_dev != y_dev, HSSX_EINVAL, "matvec output may not alias its input");
     (void)trans;   // A^T = A
     DeviceScope ds(A->device);
+    AllocScope as_(A->ctx, stream);
     launch_spmv(A->n, nrhs, A->rowptr.as<int>(), A->col.as<int>(), A->val.as<c128>(),
                 (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, A->row_max, S(stream));
   });
@@ -481,6 +496,7 @@ hssx_status hssx_get_csr(hssx_op A, int32_t *rowptr, int32_t *col, double *val, 
   return guarded([&] {
     HSSX_CHECK(A, HSSX_EINVAL, "null operator");
     DeviceScope ds(A->device);
+    AllocScope as_(A->ctx, stream);
     HSSX_HIP(hipStreamSynchronize(S(stream)));
     if (nnz_out) *nnz_out = A->nnz;
     if (rowptr) std::memcpy(rowptr, A->h_rowptr.data(), (A->n + 1) * sizeof(int));
@@ -496,7 +512,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(tol > 0 && tol < 1, HSSX_EINVAL, "tol must lie in (0, 1)");
     HSSX_CHECK(leaf_size >= 1, HSSX_EINVAL, "leaf_size must be >= 1");
     *P_out = nullptr;
-    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0, 0};
+    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0, 0, 0};
     if (opts) o = *opts;
     HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
                HSSX_EINVAL, "invalid factor options");
@@ -507,9 +523,11 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(!o.sample_bf16 || o.dtype == HSSX_C64, HSSX_EINVAL,
                "bf16 sampling needs a complex64 factor");
     DeviceScope ds(A->device);
+    AllocScope as_(g_bound, stream);
     hipStream_t st = S(stream);
     auto P = std::make_unique<hssx_fact_>();
     P->A = A;
+    P->ctx = g_bound;
     P->device = A->device;
     P->pattern = A->pattern_key();
     P->dtype = o.dtype;
@@ -549,7 +567,19 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     auto ts = std::chrono::steady_clock::now();
     P->arith.assign(nn, 0);
     P->comp.assign(nn, 0);
-    for (int k = 0; k < nn; ++k) P->arith[k] = o.h_sw >= 0 && sym.nodes[k].height > o.h_sw;
+    HSSX_CHECK(o.switch_size >= 0, HSSX_EINVAL, "switch_size must be >= 0");
+    if (o.switch_size > 0) {
+      // size rule: a separator of at least switch_size DOFs, or a child with
+      // HSS arithmetic (post-order: children first), keeps the classes
+      // monotone up the tree
+      for (int k = 0; k < nn; ++k) {
+        const NDNode &nd = sym.nodes[k];
+        if (nd.leafnode() || o.h_sw < 0) continue;
+        P->arith[k] = (int)nd.I.size() >= o.switch_size || P->arith[nd.lo] || P->arith[nd.hi];
+      }
+    } else {
+      for (int k = 0; k < nn; ++k) P->arith[k] = o.h_sw >= 0 && sym.nodes[k].height > o.h_sw;
+    }
     for (int k = 0; k < nn; ++k) P->comp[k] = sym.nodes[k].parent >= 0 && P->arith[sym.nodes[k].parent];
     P->node_rank.assign(nn, 0);
     // HSS-class nodes: HSS arithmetic and not a root (a root factors its
@@ -724,6 +754,7 @@ hssx_status hssx_refactor(hssx_fact P, hssx_op A, void *stream) {
     HSSX_CHECK(A->pattern_key() == P->pattern, HSSX_EINVAL,
                "refactor needs an operator with the factor's pattern (same grids and kind)");
     DeviceScope ds(A->device);
+    AllocScope as_(P->ctx, stream);
     P->A = A;
     P->stats.ms_symbolic = 0;
     P->stats.ms_setup = 0;
@@ -738,6 +769,7 @@ hssx_status hssx_apply(hssx_fact P, int trans, int nrhs, const void *x_dev, long
     HSSX_CHECK(P && x_dev && y_dev && nrhs >= 1 && ldx >= P->A->n && ldy >= P->A->n, HSSX_EINVAL,
                "invalid argument");
     DeviceScope ds(P->A->device);
+    AllocScope as_(P->ctx, stream);
     hssx::apply(*P, trans ? 1 : 0, nrhs, (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy, S(stream));
   });
 }
@@ -749,6 +781,7 @@ hssx_status hssx_apply_noalloc(hssx_fact P, int trans, int nrhs, const void *x_d
                HSSX_EINVAL, "invalid argument");
     HSSX_CHECK(P->desc.p != nullptr, HSSX_EINVAL, "handle holds no factorization");
     DeviceScope ds(P->device);
+    AllocScope as_(P->ctx, stream);
     size_t bytes = 0;
     char *ws = noalloc_workspace(&bytes);
     apply_workspace(*P, trans ? 1 : 0, nrhs, (const c128 *)x_dev, ldx, (c128 *)y_dev, ldy,
@@ -768,6 +801,7 @@ hssx_status hssx_gmres_solve(hssx_op A, hssx_fact P, int trans, int nrhs, const 
     HSSX_CHECK(o.m >= 1 && o.m <= 500 && o.tol > 0 && o.maxit >= 1, HSSX_EINVAL, "gmres options");
     HSSX_CHECK(trans >= 0 && trans <= 2, HSSX_EINVAL, "trans must be 0, 1 or 2");
     DeviceScope ds(A->device);
+    AllocScope as_(P ? P->ctx : A->ctx, stream);
     gmres(*A, P, trans, nrhs, (const c128 *)b_dev, ldb, (c128 *)x_dev, ldx, o, stats,
           S(stream));
   });
@@ -879,6 +913,7 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld) {
     HSSX_CHECK(ld >= d.nb, HSSX_EINVAL, "ld < |B|");
     if (d.nb == 0) return;   // the root: no Schur complement
     DeviceScope ds(P->A->device);
+    AllocScope as_(P->ctx, nullptr);
     HSSX_HIP(hipDeviceSynchronize());
     std::vector<c128> e;
     if (expand_schur(*P, node, e)) {   // compressed: expansion of its generators
@@ -924,8 +959,53 @@ hssx_status hssx_hss_eval(int device, hssx_dtype dtype, int m, int ncl, const in
     HSSX_CHECK(op < 2 || (nij >= 0 && (nij == 0 || (ij && vals))), HSSX_EINVAL, "entry lists");
     HSSX_CHECK(dtype == HSSX_C128 || dtype == HSSX_C64, HSSX_EINVAL, "dtype");
     DeviceScope ds(device);
+    AllocScope as_(g_bound, stream);
     hss_eval(dtype, m, ncl, tree, rank, gens, op, nrhs, x_dev, y_dev, nij, ij, vals, S(stream));
   });
+}
+
+hssx_status hssx_create(int device, const hssx_allocator *alloc, hssx_ctx *ctx_out) {
+  return guarded([&] {
+    HSSX_CHECK(ctx_out && alloc && alloc->alloc && alloc->free, HSSX_EINVAL, "invalid argument");
+    int count = 0;
+    HSSX_HIP(hipGetDeviceCount(&count));
+    HSSX_CHECK(device >= 0 && device < count, HSSX_EINVAL, "no such device");
+    auto c = std::make_unique<hssx_ctx_>();
+    c->device = device;
+    c->a = *alloc;
+    *ctx_out = c.release();
+  });
+}
+
+hssx_status hssx_bind(hssx_ctx ctx) {
+  g_bound = ctx;
+  return HSSX_OK;
+}
+
+hssx_status hssx_ctx_stats(hssx_ctx ctx, long *live_bytes, long *allocs, long *frees) {
+  return guarded([&] {
+    HSSX_CHECK(ctx, HSSX_EINVAL, "null context");
+    if (live_bytes) *live_bytes = ctx->live_bytes;
+    if (allocs) *allocs = ctx->allocs;
+    if (frees) *frees = ctx->frees;
+  });
+}
+
+void hssx_destroy(hssx_ctx ctx) {
+  if (!ctx) return;
+  if (g_bound == ctx) g_bound = nullptr;
+  int prev = 0;
+  const int d = ctx->device;
+  const bool dev = hipGetDevice(&prev) == hipSuccess;
+  if (dev && prev != d) (void)hipSetDevice(d);
+  (void)hipDeviceSynchronize();
+  {
+    AllocScope as_(ctx, nullptr);
+    ctx->arenas.clear();
+    ctx->stagings.clear();
+  }
+  delete ctx;
+  if (dev && prev != d) (void)hipSetDevice(prev);
 }
 
 hssx_status hssx_prof_enable(int on) {

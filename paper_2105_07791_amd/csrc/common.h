@@ -161,33 +161,59 @@ template <typename T> __device__ __forceinline__ void wave_argmax(T &v, int &idx
 }
 
 // ---------------------------------------------------------------- memory
+}  // namespace hssx
+struct hssx_ctx_;
+namespace hssx {
+
+// Device memory of the library: taken from the allocator of the allocation
+// scope's context when one is active on the calling thread (AllocScope),
+// else from hipMalloc.  *owner receives the context that must free it.
+void *dev_alloc(size_t bytes, hssx_ctx_ **owner);
+void dev_free(void *p, size_t bytes, hssx_ctx_ *owner);
+
+// The context (and stream) whose allocator serves this thread's device
+// allocations while the scope lives; scopes nest.
+struct AllocScope {
+  hssx_ctx_ *prev;
+  void *prev_stream;
+  AllocScope(hssx_ctx_ *ctx, void *stream);
+  ~AllocScope();
+  AllocScope(const AllocScope &) = delete;
+  AllocScope &operator=(const AllocScope &) = delete;
+};
+hssx_ctx_ *alloc_scope();
+
 // Device buffer owned by the library (RAII, not copyable).
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  hssx_ctx_ *owner = nullptr;   // context whose allocator it came from
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), owner(o.owner) {
+    o.p = nullptr; o.bytes = 0; o.owner = nullptr;
+  }
   DevBuf &operator=(DevBuf &&o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; owner = o.owner;
+      o.p = nullptr; o.bytes = 0; o.owner = nullptr;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw Error(HSSX_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-    }
+    p = dev_alloc(b, &owner);
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, bytes, owner);
     p = nullptr;
     bytes = 0;
+    owner = nullptr;
   }
   template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };

@@ -1,8 +1,10 @@
 // Handles behind the C ABI and the host drivers that sequence the kernels.
 #pragma once
 
+#include <atomic>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "common.h"
 #include "hss_arith.h"
@@ -54,8 +56,21 @@ template <typename T> struct HssApplyPlan {
 
 }  // namespace hssx
 
+// A context: the device allocator the caller hands in (hssx_create), and
+// the scratch arenas and staging areas of the calls made on its handles,
+// all freed through that allocator by hssx_destroy.
+struct hssx_ctx_ {
+  int device = 0;
+  hssx_allocator a{};
+  std::atomic<long> live_bytes{0}, allocs{0}, frees{0};
+  std::mutex mu;
+  std::vector<std::unique_ptr<hssx::Arena>> arenas;
+  std::vector<std::unique_ptr<hssx::Staging>> stagings;
+};
+
 struct hssx_op_ {
   int device = 0;
+  hssx_ctx_ *ctx = nullptr;   // context it was created under (or null)
   int N = 0;          // grid side (0 for a batch of problems)
   double omega = 0;
   int n = 0;
@@ -86,6 +101,7 @@ struct hssx_op_ {
 
 struct hssx_fact_ {
   hssx_op_ *A = nullptr;      // operator the factor was built from (not owned)
+  hssx_ctx_ *ctx = nullptr;   // context it was created under (or null)
   int device = 0;             // device of its buffers (A may be gone at destroy)
   std::vector<long> pattern;  // its pattern key (checked by hssx_refactor)
   hssx_dtype dtype = HSSX_C128;

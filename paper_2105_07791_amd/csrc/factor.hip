@@ -1440,7 +1440,16 @@ std::map<int, std::vector<std::unique_ptr<Arena>>> g_arenas;
 std::map<int, std::vector<std::unique_ptr<Staging>>> g_stagings;
 }  // namespace
 
+// Calls under a context take their arena and staging area from the
+// context's own pools (freed through its allocator by hssx_destroy)
 std::unique_ptr<Arena> acquire_arena(int device) {
+  if (hssx_ctx_ *c = alloc_scope()) {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->arenas.empty()) return std::make_unique<Arena>();
+    auto a = std::move(c->arenas.back());
+    c->arenas.pop_back();
+    return a;
+  }
   std::lock_guard<std::mutex> g(g_pool_mu);
   auto &v = g_arenas[device];
   if (v.empty()) return std::make_unique<Arena>();
@@ -1451,13 +1460,24 @@ std::unique_ptr<Arena> acquire_arena(int device) {
 
 void return_arena(int device, std::unique_ptr<Arena> a) {
   a->release(Arena::Mark{0, 0});
+  if (hssx_ctx_ *c = alloc_scope()) {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->arenas.push_back(std::move(a));
+    return;
+  }
   std::lock_guard<std::mutex> g(g_pool_mu);
   g_arenas[device].push_back(std::move(a));
 }
 
 std::unique_ptr<Staging> acquire_staging(int device, hipStream_t st) {
   std::unique_ptr<Staging> s;
-  {
+  if (hssx_ctx_ *c = alloc_scope()) {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->stagings.empty()) {
+      s = std::move(c->stagings.back());
+      c->stagings.pop_back();
+    }
+  } else {
     std::lock_guard<std::mutex> g(g_pool_mu);
     auto &v = g_stagings[device];
     if (!v.empty()) {
@@ -1472,6 +1492,11 @@ std::unique_ptr<Staging> acquire_staging(int device, hipStream_t st) {
 
 void return_staging(int device, std::unique_ptr<Staging> s) {
   s->recycle();
+  if (hssx_ctx_ *c = alloc_scope()) {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->stagings.push_back(std::move(s));
+    return;
+  }
   std::lock_guard<std::mutex> g(g_pool_mu);
   g_stagings[device].push_back(std::move(s));
 }

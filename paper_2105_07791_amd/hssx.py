@@ -164,13 +164,13 @@ class Factor:
 
     def __init__(self, A, tol=1e-6, leaf_size=32, beta=16, h_sw=4, k0=32, r=16,
                  max_rounds=32, dtype="c128", seed=0, id_rel_tol=0.0, apply_graph=True,
-                 autotune=True, sample_bf16=False, strict_tol=False, stream=None):
+                 autotune=True, sample_bf16=False, strict_tol=False, switch_size=0, stream=None):
         self.A = A
         opts = _lib.FactorOpts(beta, h_sw, k0, r, max_rounds,
                                _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64,
                                seed, id_rel_tol, int(apply_graph), int(autotune),
                                int(sample_bf16),  # 0, 1 (bf16) or 2 (split bf16)
-                               int(strict_tol))
+                               int(switch_size), int(strict_tol))
         h = C.c_void_p()
         check(lib().hssx_factor(A.handle, float(tol), int(leaf_size), C.byref(opts),
                                 _stream(stream), C.byref(h)))
@@ -266,6 +266,58 @@ def hss_eval(tree, rank, gens, op, X=None, ij=None, dtype="c128", device=0, stre
     check(lib().hssx_hss_eval(*args, 0, None, None, ijc.shape[0], ijc.ctypes.data_as(_lib._ip),
                               vals.view(np.float64).ctypes.data_as(_lib._dp), _stream(stream)))
     return vals
+
+
+class Context:
+    """A library context whose device memory comes from torch's caching
+    allocator (hssx_create with an allocator that calls
+    torch.cuda.caching_allocator_alloc / _delete).  Use as a context
+    manager: handles created inside belong to it; destroy them before the
+    context.  alloc_calls / free_calls / live count what passed through."""
+
+    def __init__(self, device=0):
+        self.device = device
+        self.alloc_calls = self.free_calls = 0
+        self.alloc_bytes = self.free_bytes = 0
+
+        def _alloc(nbytes, stream, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                       int(stream or 0))
+            except RuntimeError:
+                return None
+            self.alloc_calls += 1
+            self.alloc_bytes += int(nbytes)
+            return p
+
+        def _free(ptr, nbytes, stream, user):
+            torch.cuda.caching_allocator_delete(ptr)
+            self.free_calls += 1
+            self.free_bytes += int(nbytes)
+
+        self._fns = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))   # kept alive
+        self._spec = _lib.Allocator(self._fns[0], self._fns[1], None)
+        h = C.c_void_p()
+        check(lib().hssx_create(device, C.byref(self._spec), C.byref(h)))
+        self.handle = h
+
+    def __enter__(self):
+        check(lib().hssx_bind(self.handle))
+        return self
+
+    def __exit__(self, *exc):
+        check(lib().hssx_bind(None))
+        return False
+
+    def stats(self):
+        live, a, f = C.c_long(), C.c_long(), C.c_long()
+        check(lib().hssx_ctx_stats(self.handle, C.byref(live), C.byref(a), C.byref(f)))
+        return {"live_bytes": live.value, "allocs": a.value, "frees": f.value}
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().hssx_destroy(self.handle)
+            self.handle = None
 
 
 def assemble(N, omega, slowness, device=0):
