@@ -61,12 +61,14 @@ KERNELS = ["front_eliminate", "front_assemble", "compress_level", "hss_matvec", 
            "apply_up", "apply_down", "apply_graph", "spmv",
            # HSS-class nodes: structured sampling, entry extraction, entry-access
            # preparation, telescoping inverses, Gauss transforms, their apply
-           "sample_struct", "hss_entries", "hss_prep", "hss_inverse", "hss_gauss", "apply_hss"]
+           "sample_struct", "hss_entries", "hss_prep", "hss_inverse", "hss_gauss", "apply_hss",
+           # every batched small product of the HSS arithmetic, whichever stage runs it
+           "bgemm"]
 BYTE_KERNELS = {"front_assemble", "apply_up", "apply_down", "apply_graph", "spmv"}
 # categories timed around one kernel per launch (the roofline needs a single
 # kernel); front_eliminate, hss_matvec, apply_up/down (staging + product),
 # apply_graph and the HSS-arithmetic categories time launch sequences
-SINGLE_KERNELS = {"front_assemble", "compress_level", "sample", "spmv"}
+SINGLE_KERNELS = {"front_assemble", "compress_level", "sample", "spmv", "bgemm"}
 
 
 #: workloads too large for the oracle within the time budget are sampled on

@@ -532,27 +532,36 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     std::vector<std::array<long, 4>> launches;   // level, size class, offset, count
     std::vector<std::array<long, 2>> ent_of;     // per level: offset, count of entry items
     for (int lev = maxlev; lev >= 0; --lev) {
-      std::vector<HssItem> items[3];
+      std::vector<HssItem> items[7];
       const long e0 = (long)ent_items.size();
       for (size_t a = 0; a < active.size(); ++a) {
         for (int c = inst[a].lev_off[std::min(lev, inst[a].nlev)];
              c < inst[a].lev_off[std::min(lev + 1, inst[a].nlev)]; ++c) {
-          const int rc = cls[inst[a].cl_off + c].rows_cap;
-          const bool reg = rc <= kRegRows && inst[a].s <= kRegCols;
-          items[rc <= 64 ? 0 : reg ? 1 : 2].push_back(HssItem{(int)a, c});
+          const int rc = cls[inst[a].cl_off + c].rows_cap, sc = inst[a].s;
+          int v;
+          if (rc <= 64) v = sc <= 64 ? kCls256S64 : sc <= 128 ? kCls256S128 : kCls256;
+          else if (rc <= kRegRows && sc <= kRegCols)
+            v = rc > 128 ? kCls1024 : sc <= 64 ? kCls1024R128S64 : sc <= 128 ? kCls1024R128S128
+                                                                             : kCls1024;
+          else v = kClsGlobal;
+          items[v].push_back(HssItem{(int)a, c});
           if (inst[a].pre) ent_items.push_back(HssItem{(int)a, c});
         }
       }
       ent_of.push_back({e0, (long)ent_items.size() - e0});
-      // the one-barrier 1024-thread variant holds one workgroup per CU: used
-      // when the level's large clusters all fit it and do not outnumber the
+      // the one-barrier 1024-thread variants hold one workgroup per CU: used
+      // when the level's large clusters all fit them and do not outnumber the
       // CUs (otherwise occupancy, or running with the global-memory ones in
       // one launch, matters more)
-      if (items[1].size() > 256 || !items[2].empty()) {
-        items[2].insert(items[2].end(), items[1].begin(), items[1].end());
-        items[1].clear();
-      }
-      for (int sz = 0; sz < 3; ++sz) {
+      const int big[3] = {kCls1024, kCls1024R128S64, kCls1024R128S128};
+      size_t nbig = 0;
+      for (int v : big) nbig += items[v].size();
+      if (nbig > 256 || !items[kClsGlobal].empty())
+        for (int v : big) {
+          items[kClsGlobal].insert(items[kClsGlobal].end(), items[v].begin(), items[v].end());
+          items[v].clear();
+        }
+      for (int sz = 0; sz < 7; ++sz) {
         if (items[sz].empty()) continue;
         launches.push_back({lev, sz, (long)all_items.size(), (long)items[sz].size()});
         all_items.insert(all_items.end(), items[sz].begin(), items[sz].end());
@@ -574,14 +583,19 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
                           d_eops, A.rowptr.as<int>(), A.col.as<int>(), val, st);
         prof_end("hss_entries", st, pe, 0.0);
       }
-      const bool fork = b - a > 1 && launches[a][1] == 0;
+      // the 256-thread launches run on the side stream when the level also
+      // has 1024-thread ones
+      auto small = [](long v) { return v == kCls256 || v == kCls256S64 || v == kCls256S128; };
+      bool any_small = false, any_big = false;
+      for (size_t e = a; e < b; ++e) (small(launches[e][1]) ? any_small : any_big) = true;
+      const bool fork = any_small && any_big;
       if (fork) {
         HSSX_HIP(hipEventRecord(side.fork, st));
         HSSX_HIP(hipStreamWaitEvent(side.s, side.fork, 0));
       }
       for (size_t e = a; e < b; ++e) {
         const auto &l = launches[e];
-        hipStream_t ls = fork && l[1] == 0 ? side.s : st;
+        hipStream_t ls = fork && small(l[1]) ? side.s : st;
         double cflops = 0;
         for (long q = l[2]; q < l[2] + l[3]; ++q) {
           const auto &it = all_items[q];

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "hssops.h"
+#include "prof.h"
 #include "symbolic.h"
 
 namespace hssx {
@@ -113,7 +114,16 @@ inline void launch_stage(const Stage<T> &s, const void *jobs, const BgTile *tile
                          long me, const c128 *val, hipStream_t st) {
   const int n = (int)s.size();
   switch (s.kind) {
-    case kGemm: launch_bgemm<T>(ntiles, tiles, (const BgJob<T> *)jobs, st); break;
+    case kGemm: {
+      hipEvent_t pe = prof_begin(st);
+      launch_bgemm<T>(ntiles, tiles, (const BgJob<T> *)jobs, st);
+      if (pe) {
+        double fl = 0;
+        for (const BgJob<T> &g : s.gemm) fl += 8.0 * g.M * g.N * g.K;
+        prof_end("bgemm", st, pe, fl);
+      }
+      break;
+    }
     case kCopy: launch_copy<T>(n, (const CopyJob<T> *)jobs, me, st); break;
     case kSpmm: launch_spmm<T>(n, (const SpJob<T> *)jobs, val, me, st); break;
     case kGtt: launch_gather<cplx<T>, cplx<T>>(n, (const GatherJob<cplx<T>, cplx<T>> *)jobs, me, st); break;

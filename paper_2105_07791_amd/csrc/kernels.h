@@ -184,10 +184,16 @@ struct HssInstance {
 struct HssItem {
   int inst, cl;         // instance, cluster id within it
 };
-// size_class 0: every item's cluster has at most 64 rows (256-thread
-// workgroups); 1: larger clusters that fit the 1024-thread register path
-// (at most kRegRows rows, s <= kRegCols; complex64); 2: any other cluster
+// Size classes of one compression launch (every item of the launch fits its
+// class): clusters of at most 64 rows in 256-thread workgroups (s <= 64,
+// s <= 128, any s); larger clusters that fit the 1024-thread register path
+// (at most kRegRows rows, s <= kRegCols; complex64), with tiles for at most
+// 128 rows and s <= 64 or s <= 128; any other cluster (global-memory QR).
 constexpr int kRegRows = 256, kRegCols = 192;
+enum : int {
+  kCls256 = 0, kCls1024 = 1, kClsGlobal = 2, kCls256S64 = 3, kCls256S128 = 4,
+  kCls1024R128S64 = 5, kCls1024R128S128 = 6
+};
 template <typename T>
 void launch_compress_level(int count, const HssItem *items, const HssInstance *inst,
                            const HssCluster *cl, cplx<T> *pool, int *ipool, int *rank,

@@ -268,7 +268,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, int nrhs, const int *_
                                                    const c128 *__restrict__ val,
                                                    const c128 *__restrict__ x, long ldx,
                                                    c128 *__restrict__ y, long ldy) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // workgroups go round-robin to the 8 XCDs: give each XCD one contiguous
+  // eighth of the rows, so the neighbouring rows a row's columns reach are
+  // mostly read through the same XCD's L2 (the grid is a multiple of 8)
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  int i = blk * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int p0 = rowptr[i], cnt = rowptr[i + 1] - p0;
   int cj[W];
@@ -379,15 +384,16 @@ void launch_load(int n, int nrhs, const int *rowptr, const int *col, const doubl
 
 void launch_spmv(int n, int nrhs, const int *rowptr, const int *col, const c128 *val,
                  const c128 *x, long ldx, c128 *y, long ldy, int row_max, hipStream_t st) {
+  const dim3 grid(8 * ceil_div(ceil_div(n, 256), 8));
   if (row_max <= 7)
-    hipLaunchKernelGGL(spmv_kernel<7>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs, rowptr,
-                       col, val, x, ldx, y, ldy);
+    hipLaunchKernelGGL(spmv_kernel<7>, grid, dim3(256), 0, st, n, nrhs, rowptr, col, val, x, ldx,
+                       y, ldy);
   else if (row_max <= 14)
-    hipLaunchKernelGGL(spmv_kernel<14>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs,
-                       rowptr, col, val, x, ldx, y, ldy);
+    hipLaunchKernelGGL(spmv_kernel<14>, grid, dim3(256), 0, st, n, nrhs, rowptr, col, val, x, ldx,
+                       y, ldy);
   else if (row_max <= 24)
-    hipLaunchKernelGGL(spmv_kernel<24>, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nrhs,
-                       rowptr, col, val, x, ldx, y, ldy);
+    hipLaunchKernelGGL(spmv_kernel<24>, grid, dim3(256), 0, st, n, nrhs, rowptr, col, val, x, ldx,
+                       y, ldy);
   else
     throw Error(HSSX_EINVAL, "rows longer than 24 entries");
   HSSX_HIP(hipGetLastError());

@@ -38,6 +38,11 @@ constexpr int kPasses = 1;       // projections per pivot step
 // than 64 rows, 256 below.  The register-resident pivoted QR (complex64)
 // uses RT lanes per row, NT / RT row slots, RPT rows per slot and RSEG
 // columns per lane: rows <= NT / RT * RPT, sample columns <= RT * RSEG.
+// register tiles of the pivoted Gram-Schmidt: RT lanes per row, RPT rows
+// per lane group, RSEG column segments of RT entries each (capacity
+// NT / RT * RPT rows by RT * RSEG columns); the defaults are the largest
+// tiles, smaller ones are chosen per launch so that a step's instruction
+// stream follows the block's size
 template <int NT> struct CCfg;
 template <> struct CCfg<1024> { static constexpr int RT = 16, RPT = 4, RSEG = 12; };
 template <> struct CCfg<256> { static constexpr int RT = 8, RPT = 2, RSEG = 24; };
@@ -345,13 +350,23 @@ __device__ void wg_gemm(int M, int N, int K, const cplx<T> *__restrict__ A, long
 // index b, original row), R11(b, a) = R(b, perm[a]).  kG lanes per column
 // hold its kXU-strided entries in registers; back substitution over a, the
 // new entry broadcast to the column's lanes by a shuffle.  rk <= kG * kXU.
-constexpr int kG = 32, kXU = 6;
-template <typename T, int NT>
-__device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *__restrict__ Rm,
-                              long ldr, cplx<T> *__restrict__ U) {
+// When R11 fits the LDS area Rs (kRsCap entries) it is staged there first,
+// Rs[b + a * rk] = R11(b, a), so the back substitution reads no global
+// memory.  Every thread of the workgroup calls it.
+constexpr int kG = 32, kXU = 6, kRsCap = 2 * 16 * 128;
+template <typename T, int NT, bool STAGED>
+__device__ void interp_coeffs_t(int rows, int rk, const int *perm,
+                                const cplx<T> *__restrict__ Rm, long ldr,
+                                cplx<T> *__restrict__ U, const cplx<T> *Rs) {
   const int tid = threadIdx.x, sub = tid % kG, col = tid / kG;
   const int base = (tid % 64) & ~(kG - 1);
   const int nc = rows - rk;
+  constexpr bool staged = STAGED;
+  // R11(b, a); rows b >= rk (lanes past the rank) read as zero
+  auto r11 = [&](int b, int a, long pa) -> cplx<T> {
+    if constexpr (STAGED) return b < rk ? Rs[b + a * rk] : czero<T>();
+    else return Rm[b + pa];
+  };
   for (int c0 = 0; c0 < nc; c0 += NT / kG) {
     const int ci = c0 + col;
     const bool act = ci < nc;
@@ -367,14 +382,14 @@ __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *
       for (int la = kG - 1; la >= 0; --la) {
         const int a = u * kG + la;
         if (a >= rk) continue;
-        const long pa = (long)perm[a] * ldr;
-        cplx<T> v = x[u] * cinv(Rm[a + pa]);
+        const long pa = staged ? 0 : (long)perm[a] * ldr;
+        cplx<T> v = x[u] * cinv(r11(a, a, pa));
         v.re = __shfl(v.re, base + la);
         v.im = __shfl(v.im, base + la);
         if (sub == la) x[u] = v;
 #pragma unroll
-        for (int w = 0; w < u; ++w) cfms(x[w], Rm[sub + kG * w + pa], v);
-        if (sub < la) cfms(x[u], Rm[sub + kG * u + pa], v);
+        for (int w = 0; w < u; ++w) cfms(x[w], r11(sub + kG * w, a, pa), v);
+        if (sub < la) cfms(x[u], r11(sub + kG * u, a, pa), v);
       }
     }
     if (act) {
@@ -388,12 +403,24 @@ __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *
   }
 }
 
+template <typename T, int NT>
+__device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *__restrict__ Rm,
+                              long ldr, cplx<T> *__restrict__ U, cplx<T> *Rs) {
+  if (rk * rk <= kRsCap) {
+    for (int e = threadIdx.x; e < rk * rk; e += NT) Rs[e] = Rm[e % rk + (long)perm[e / rk] * ldr];
+    __syncthreads();
+    interp_coeffs_t<T, NT, true>(rows, rk, perm, Rm, ldr, U, Rs);
+  } else {
+    interp_coeffs_t<T, NT, false>(rows, rk, perm, Rm, ldr, U, Rs);
+  }
+}
+
 // ONEB: the register path takes one barrier per pivot (each wavefront's best
 // row staged in LDS: in the product staging area for 256 threads, in a
 // buffer of its own for 1024); else two (pivot row broadcast after the
 // maxima).  The 1024-thread one-barrier variant is launched only for
 // clusters that fit the register path, since its buffer costs occupancy.
-template <typename T, int NT, bool ONEB>
+template <typename T, int NT, bool ONEB, int RPT = CCfg<NT>::RPT, int RSEG = CCfg<NT>::RSEG>
 __global__ __launch_bounds__(NT) void compress_level_kernel(
     const HssItem *__restrict__ items, const HssInstance *__restrict__ insts,
     const HssCluster *__restrict__ cls, cplx<T> *__restrict__ pool, int *__restrict__ ipool,
@@ -406,19 +433,23 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   __shared__ int si[NT / 64];
   __shared__ unsigned char sel[kMaxRows];
   __shared__ int s_rank;
-  constexpr int kRT = CCfg<NT>::RT, kRS = NT / kRT, kRPT = CCfg<NT>::RPT, kRSEG = CCfg<NT>::RSEG;
+  constexpr int kRT = CCfg<NT>::RT, kRS = NT / kRT, kRPT = RPT, kRSEG = RSEG;
   // register path: pivot rows (two-barrier steps, 1024 threads) or each
   // wavefront's best row (one-barrier steps, 256 threads; held in the
   // product staging area As, idle during the ID), and the wavefront maxima,
   // double-buffered by step parity
   __shared__ cplx<T> qb[2][kRT * kRSEG];
   constexpr int kOwnCand = (ONEB && NT != 256 && sizeof(T) == sizeof(float)) ? kRT * kRSEG : 1;
-  static_assert(NT != 1024 || (kRS * kRPT == kRegRows && kRT * kRSEG == kRegCols),
-                "host size classes must match the register-path capacity");
+  static_assert(NT != 1024 || (kRS * kRPT <= kRegRows && kRT * kRSEG <= kRegCols),
+                "host size classes must not exceed the register-path capacity");
   __shared__ cplx<T> own_cand[2][NT / 64][kOwnCand];
   __shared__ T sv2[2][NT / 64];
   __shared__ int si2[2][NT / 64];
-  __shared__ cplx<T> As[16][128], Bs[16][128];
+  // product staging areas, contiguous so that the interpolation step can
+  // hold R11 in both
+  __shared__ cplx<T> ABs[2][16][128];
+  auto &As = ABs[0];
+  auto &Bs = ABs[1];
   const HssItem it = items[blockIdx.x];
   const HssInstance I = insts[it.inst];
   const int cg = I.cl_off + it.cl;
@@ -582,10 +613,14 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         int bi = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
+          if (kRS * r >= rows) continue;
           const int row = slot + kRS * r;
           T nrm = 0;
 #pragma unroll
-          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
+          for (int c = 0; c < kRSEG; ++c) {
+            if (kRT * c >= s) continue;
+            nrm += abs2(w[r][c]);
+          }
           nrm = group_sum<kRT>(nrm);
           if (row < rows && !pk[r] && (nrm > best || (nrm == best && row < bi))) {
             best = nrm;
@@ -600,6 +635,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             if (r == ro) {
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
+                if (kRT * c >= s) continue;
                 const int j = sub + kRT * c;
                 if (j < s) cand[par][wv][j] = w[r][c];
               }
@@ -634,6 +670,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         }
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
+          if (kRS * r >= rows) continue;
           const int row = slot + kRS * r;
           const bool act = row < rows && !pk[r];
           cplx<T> rr = czero<T>();
@@ -641,6 +678,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             cplx<T> d = czero<T>();
 #pragma unroll
             for (int c = 0; c < kRSEG; ++c) {
+              if (kRT * c >= s) continue;
               const int j = sub + kRT * c;
               if (j < s) cfma(d, conj(qr[j]), w[r][c]);
             }
@@ -650,6 +688,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
               const cplx<T> dq = inv * d;
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
+                if (kRT * c >= s) continue;
                 const int j = sub + kRT * c;
                 if (j < s) cfms(w[r][c], dq, qr[j]);
               }
@@ -681,10 +720,14 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         int bi = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
+          if (kRS * r >= rows) continue;
           const int row = slot + kRS * r;
           T nrm = 0;
 #pragma unroll
-          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
+          for (int c = 0; c < kRSEG; ++c) {
+            if (kRT * c >= s) continue;
+            nrm += abs2(w[r][c]);
+          }
           nrm = group_sum<kRT>(nrm);
           if (row < rows && !sel[row] && (nrm > best || (nrm == best && row < bi))) {
             best = nrm;
@@ -703,6 +746,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             if (r == ro) {
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
+                if (kRT * c >= s) continue;
                 const int j = sub + kRT * c;
                 if (j < s) q[j] = inv * w[r][c];
               }
@@ -718,6 +762,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
         lds_barrier();
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
+          if (kRS * r >= rows) continue;
           const int row = slot + kRS * r;
           const bool act = row < rows && !sel[row];
           cplx<T> rr = czero<T>();
@@ -725,6 +770,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             cplx<T> d = czero<T>();
 #pragma unroll
             for (int c = 0; c < kRSEG; ++c) {
+              if (kRT * c >= s) continue;
               const int j = sub + kRT * c;
               if (j < s) cfma(d, conj(q[j]), w[r][c]);
             }
@@ -733,6 +779,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             if (act) {
 #pragma unroll
               for (int c = 0; c < kRSEG; ++c) {
+                if (kRT * c >= s) continue;
                 const int j = sub + kRT * c;
                 if (j < s) cfms(w[r][c], d, q[j]);
               }
@@ -885,7 +932,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
   __syncthreads();
   for (int a = tid; a < rk; a += NT) U[perm[a] + (long)a * rows] = mk((T)1, (T)0);
   if (rk <= kG * kXU) {
-    interp_coeffs<T, NT>(rows, rk, perm, Rm, C.k_cap, U);
+    interp_coeffs<T, NT>(rows, rk, perm, Rm, C.k_cap, U, &ABs[0][0][0]);
   } else {
     for (int c2 = tid; c2 < rows - rk; c2 += NT) {
       int row = perm[rk + c2];
@@ -1214,15 +1261,25 @@ void launch_compress_level(int count, const HssItem *items, const HssInstance *i
                            cplx<T> *scratch, double id_tol, int size_class, hipStream_t st) {
   if (count <= 0) return;
   constexpr bool kF32 = sizeof(T) == sizeof(float);
-  if (size_class == 0)
-    hipLaunchKernelGGL((compress_level_kernel<T, 256, kF32>), dim3(count), dim3(256), 0, st, items,
-                       inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
-  else if (size_class == 1 && kF32)
-    hipLaunchKernelGGL((compress_level_kernel<T, 1024, kF32>), dim3(count), dim3(1024), 0, st,
-                       items, inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
-  else
-    hipLaunchKernelGGL((compress_level_kernel<T, 1024, false>), dim3(count), dim3(1024), 0, st,
-                       items, inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol);
+  // the register path exists for complex64 only: complex128 takes the
+  // general kernels for every class
+  if (!kF32) size_class = size_class == kCls256S64 || size_class == kCls256S128 ? kCls256
+                          : size_class == kCls1024R128S64 || size_class == kCls1024R128S128
+                              ? kCls1024
+                              : size_class;
+#define HSSX_CL(NT, ONEB, ...)                                                              \
+  hipLaunchKernelGGL((compress_level_kernel<T, NT, ONEB, ##__VA_ARGS__>), dim3(count), dim3(NT), \
+                     0, st, items, inst, cl, pool, ipool, rank, front, Y, Om, scratch, id_tol)
+  switch (size_class) {
+    case kCls256: HSSX_CL(256, kF32); break;
+    case kCls1024: if (kF32) HSSX_CL(1024, kF32); else HSSX_CL(1024, false); break;
+    case kCls256S64: if constexpr (kF32) HSSX_CL(256, true, 2, 8); break;
+    case kCls256S128: if constexpr (kF32) HSSX_CL(256, true, 2, 16); break;
+    case kCls1024R128S64: if constexpr (kF32) HSSX_CL(1024, true, 2, 4); break;
+    case kCls1024R128S128: if constexpr (kF32) HSSX_CL(1024, true, 2, 8); break;
+    default: HSSX_CL(1024, false); break;
+  }
+#undef HSSX_CL
   HSSX_HIP(hipGetLastError());
 }
 

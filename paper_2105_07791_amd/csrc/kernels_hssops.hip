@@ -10,49 +10,75 @@ constexpr int kBT = 256;   // threads per workgroup
 
 // 32 x 32 output tile per workgroup, K in steps of 16 staged in LDS; thread
 // (tx, ty) = (tid % 16, tid / 16) owns rows tx, tx + 16 and columns ty, ty + 16.
+// The next step's global loads are issued before the current step's
+// products (two LDS buffers, one barrier per step), so their latency
+// overlaps the arithmetic.
 template <typename T>
 __global__ __launch_bounds__(kBT) void bgemm_kernel(const BgTile *__restrict__ tiles,
                                                     const BgJob<T> *__restrict__ jobs) {
-  __shared__ cplx<T> As[16][33], Bs[16][33];
+  __shared__ cplx<T> As[2][16][33], Bs[2][16][33];
   const BgTile tl = tiles[blockIdx.x];
   const BgJob<T> jb = jobs[tl.job];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int i0 = tl.tm * 32, j0 = tl.tn * 32;
+  // per-thread staging coordinates (k index within the step, row / column)
+  int ak[2], ai[2], bk[2], bj[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + kBT * u;
+    if (jb.ta) { ak[u] = e & 15; ai[u] = e >> 4; } else { ai[u] = e & 31; ak[u] = e >> 5; }
+    if (jb.tb) { bj[u] = e & 31; bk[u] = e >> 5; } else { bk[u] = e & 15; bj[u] = e >> 4; }
+  }
+  cplx<T> ra[2], rb[2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int gi = i0 + ai[u], gk = k0 + ak[u];
+      ra[u] = czero<T>();
+      if (gi < jb.M && gk < jb.K)
+        ra[u] = jb.ta ? jb.A[gk + (long)gi * jb.lda] : jb.A[gi + (long)gk * jb.lda];
+      const int gj = j0 + bj[u], gk2 = k0 + bk[u];
+      rb[u] = czero<T>();
+      if (gj < jb.N && gk2 < jb.K)
+        rb[u] = jb.tb ? jb.B[gj + (long)gk2 * jb.ldb] : jb.B[gk2 + (long)gj * jb.ldb];
+    }
+  };
   cplx<T> acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = czero<T>();
+  // the accumulated-into block is read up front, its latency hidden too
+  cplx<T> c0[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
+      c0[a][b] = (jb.beta && gi < jb.M && gj < jb.N) ? jb.C[gi + (long)gj * jb.ldc] : czero<T>();
+    }
+  fetch(0);
+  int buf = 0;
   for (int k0 = 0; k0 < jb.K; k0 += 16) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int e = tid + kBT * u;
-      int i, kk;
-      if (jb.ta) { kk = e & 15; i = e >> 4; } else { i = e & 31; kk = e >> 5; }
-      const int gi = i0 + i, gk = k0 + kk;
-      cplx<T> v = czero<T>();
-      if (gi < jb.M && gk < jb.K)
-        v = jb.ta ? jb.A[gk + (long)gi * jb.lda] : jb.A[gi + (long)gk * jb.lda];
-      As[kk][i] = v;
-      int j;
-      if (jb.tb) { j = e & 31; kk = e >> 5; } else { kk = e & 15; j = e >> 4; }
-      const int gj = j0 + j, gk2 = k0 + kk;
-      cplx<T> w = czero<T>();
-      if (gj < jb.N && gk2 < jb.K)
-        w = jb.tb ? jb.B[gj + (long)gk2 * jb.ldb] : jb.B[gk2 + (long)gj * jb.ldb];
-      Bs[kk][j] = w;
+      As[buf][ak[u]][ai[u]] = ra[u];
+      Bs[buf][bk[u]][bj[u]] = rb[u];
     }
+    // after this barrier every thread is done with the other buffer's
+    // products of the previous step, so the next step may overwrite it
     __syncthreads();
+    if (k0 + 16 < jb.K) fetch(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      const cplx<T> a0 = As[kk][tx], a1 = As[kk][tx + 16];
-      const cplx<T> b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+      const cplx<T> a0 = As[buf][kk][tx], a1 = As[buf][kk][tx + 16];
+      const cplx<T> b0 = Bs[buf][kk][ty], b1 = Bs[buf][kk][ty + 16];
       cfma(acc[0][0], a0, b0);
       cfma(acc[0][1], a0, b1);
       cfma(acc[1][0], a1, b0);
       cfma(acc[1][1], a1, b1);
     }
-    __syncthreads();
+    buf ^= 1;
   }
   const cplx<T> al = mk(jb.ar, jb.ai);
 #pragma unroll
@@ -61,9 +87,7 @@ __global__ __launch_bounds__(kBT) void bgemm_kernel(const BgTile *__restrict__ t
     for (int b = 0; b < 2; ++b) {
       const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
       if (gi < jb.M && gj < jb.N) {
-        cplx<T> *c = jb.C + gi + (long)gj * jb.ldc;
-        const cplx<T> v = al * acc[a][b];
-        *c = jb.beta ? *c + v : v;
+        jb.C[gi + (long)gj * jb.ldc] = c0[a][b] + al * acc[a][b];
       }
     }
 }

@@ -30,6 +30,11 @@ void prof_enable(bool on) {
 
 hipEvent_t prof_begin(hipStream_t st) {
   if (!g_on) return nullptr;
+  // launches recorded into a graph are not timed one by one (an event
+  // captured into a graph has no elapsed time of its own)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return nullptr;
   hipEvent_t e;
   HSSX_HIP(hipEventCreate(&e));
   HSSX_HIP(hipEventRecord(e, st));
