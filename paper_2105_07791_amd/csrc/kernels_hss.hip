@@ -415,6 +415,23 @@ __device__ void interp_coeffs(int rows, int rk, const int *perm, const cplx<T> *
   }
 }
 
+// perm[t..rows) = the rows i < rows with sel[i] == 0, ascending (rows <= NT):
+// per-wavefront ballots and counts, one exclusive offset per wavefront.
+// Every thread calls it; wcnt holds NT / 64 ints of LDS.
+template <int NT>
+__device__ void append_unselected(int rows, int t, const unsigned char *sel, int *perm,
+                                  int *wcnt) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool un = tid < rows && !sel[tid];
+  const unsigned long long m = __ballot(un);
+  if (lane == 0) wcnt[wv] = __popcll(m);
+  __syncthreads();
+  int off = t;
+  for (int k = 0; k < wv; ++k) off += wcnt[k];
+  if (un) perm[off + __popcll(m & ((1ull << lane) - 1))] = tid;
+  __syncthreads();
+}
+
 // ONEB: the register path takes one barrier per pivot (each wavefront's best
 // row staged in LDS: in the product staging area for 256 threads, in a
 // buffer of its own for 1024); else two (pivot row broadcast after the
@@ -637,7 +654,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
               for (int c = 0; c < kRSEG; ++c) {
                 if (kRT * c >= s) continue;
                 const int j = sub + kRT * c;
-                if (j < s) cand[par][wv][j] = w[r][c];
+                cand[par][wv][j] = w[r][c];   // zero past s
               }
             }
         }
@@ -680,18 +697,19 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
             for (int c = 0; c < kRSEG; ++c) {
               if (kRT * c >= s) continue;
               const int j = sub + kRT * c;
-              if (j < s) cfma(d, conj(qr[j]), w[r][c]);
+              cfma(d, conj(qr[j]), w[r][c]);
             }
             d.re = inv * group_sum<kRT>(d.re);
             d.im = inv * group_sum<kRT>(d.im);
-            if (act) {
-              const cplx<T> dq = inv * d;
+            // no lane or row guards: entries past s are zero in w and in
+            // the candidate rows, rows past the block stay zero, and a
+            // picked row (projected onto itself) is never read again
+            const cplx<T> dq = inv * d;
 #pragma unroll
-              for (int c = 0; c < kRSEG; ++c) {
-                if (kRT * c >= s) continue;
-                const int j = sub + kRT * c;
-                if (j < s) cfms(w[r][c], dq, qr[j]);
-              }
+            for (int c = 0; c < kRSEG; ++c) {
+              if (kRT * c >= s) continue;
+              const int j = sub + kRT * c;
+              cfms(w[r][c], dq, qr[j]);
             }
             rr = rr + d;
           }
@@ -700,14 +718,11 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       }
       __syncthreads();
       // the unselected rows follow the pivots in ascending order
-      if (tid == 0) {
-        for (int i = 0; i < rows; ++i) sel[i] = 0;
-        for (int a = 0; a < t; ++a) sel[perm[a]] = 1;
-        int pos = t;
-        for (int i = 0; i < rows; ++i)
-          if (!sel[i]) perm[pos++] = i;
-      }
+      for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
+      for (int a = tid; a < t; a += NT) sel[perm[a]] = 1;
+      __syncthreads();
+      append_unselected<NT>(rows, t, sel, perm, si);
       } else {
       for (int i = tid; i < rows; i += NT) sel[i] = 0;
       __syncthreads();
@@ -791,12 +806,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
       }
       __syncthreads();
       // the unselected rows follow the pivots in ascending order
-      if (tid == 0) {
-        int pos = t;
-        for (int i = 0; i < rows; ++i)
-          if (!sel[i]) perm[pos++] = i;
-      }
-      __syncthreads();
+      append_unselected<NT>(rows, t, sel, perm, si);
       }
       reg_done = true;
     }
