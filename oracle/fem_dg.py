@@ -1,31 +1,42 @@
-"""Symmetric interior-penalty DG discretization of the Helmholtz problem with
-P2 elements (oracle; test infrastructure only).
+"""Symmetric interior-penalty DG discretizations of the Helmholtz problem
+with P1 or P2 elements (oracle; test infrastructure only).
 
-The paper's IPDG runs (Sec. 4.1-4.2) use interior-penalty discontinuous
-Galerkin on a regular triangular mesh.  This module writes out the symmetric
-variant for
+The paper's IPDG runs (Sec. 4.1-4.2 and the scaling study of Sec. 4.6) use
+interior-penalty discontinuous Galerkin on a regular triangular mesh.  This
+module writes out the symmetric variant for
 
-    -lap u - k(x)^2 u = f  on [0,1]^2,   d_n u - i k u = 0 on the boundary,
+    -lap u - k(x)^2 u = f  on [0,1]^2,   k = omega s(x),
 
-k = omega s(x), as the complex-symmetric bilinear form (no conjugation)
+as the complex-symmetric bilinear form (no conjugation)
 
     a(u, v) = sum_T int_T (grad u . grad v - k^2 u v)
             + sum_{interior F} ( - int_F {grad u . n}[v] - int_F {grad v . n}[u]
                                  + tau_F int_F [u][v] )
-            - i sum_{boundary F} int_F k u v ,
+            + boundary terms,
 
 with [w] = w+ - w-, {w} = (w+ + w-)/2, n the unit normal from + to -, and
-tau_F = 10 p^2 / |F| (p = 2, |F| the face length).  k^2 is the P1 interpolant
-of the nodal omega^2 s^2 inside each triangle, k on a boundary face the P1
-interpolant of omega s.
+tau_F = 10 p^2 / |F| (p the polynomial degree, |F| the face length).  The
+boundary terms are either the first-order absorbing condition
+d_n u - i k u = 0,
+
+            - i sum_{boundary F} int_F k u v ,
+
+or the homogeneous Dirichlet condition u = 0 of Sec. 4.1-4.2 and 4.6, imposed
+as in the interior with the outside value zero (n the outward normal):
+
+            sum_{boundary F} ( - int_F (grad u . n) v - int_F (grad v . n) u
+                               + tau_F int_F u v ).
+
+k^2 is the P1 interpolant of the nodal omega^2 s^2 inside each triangle, k on
+a boundary face the P1 interpolant of omega s.
 
 Mesh: Nc x Nc cells of side h = 1/Nc; cell (i, j) holds the lower triangle
 t = 0 with vertices (i,j), (i+1,j), (i+1,j+1) and the upper triangle t = 1
 with (i,j), (i+1,j+1), (i,j+1) (grid vertices, counter-clockwise).  Element
-id e = 2 (j Nc + i) + t.  Each element carries the six nodal P2 Lagrange
-functions: the three vertices in that order, then the midpoints of edges
-(v0,v1), (v1,v2), (v2,v0).  DOF id = 6 e + a.  Faces: f = 0 is (v0,v1),
-f = 1 is (v1,v2), f = 2 is (v2,v0).
+id e = 2 (j Nc + i) + t.  Each element carries the nodal Lagrange functions
+of degree p: the three vertices in that order, then (p = 2) the midpoints of
+edges (v0,v1), (v1,v2), (v2,v0).  DOF id = nb e + a with nb = 3 (P1) or 6
+(P2).  Faces: f = 0 is (v0,v1), f = 1 is (v1,v2), f = 2 is (v2,v0).
 
 Quadrature: collapsed (Duffy) 4 x 4 Gauss-Legendre on triangles (exact to
 degree 6), 4-point Gauss-Legendre on faces (degree 7).
@@ -33,11 +44,17 @@ degree 6), 4-point Gauss-Legendre on faces (degree 7).
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["P", "PENALTY", "elements", "dof_coords", "faces", "basis", "assemble_dg_parts",
-           "assemble_dg", "mass_matrix_dg", "dg_nnz"]
+__all__ = ["P", "PENALTY", "nbasis", "elements", "dof_coords", "faces", "basis",
+           "assemble_dg_parts", "assemble_dg", "mass_matrix_dg", "dg_nnz"]
 
-P = 2
+P = 2            # default polynomial degree
 PENALTY = 10.0
+
+
+def nbasis(deg):
+    """Nodal functions per triangle: 3 (P1) or 6 (P2)."""
+    assert deg in (1, 2)
+    return (deg + 1) * (deg + 2) // 2
 
 _T4, _W4 = np.polynomial.legendre.leggauss(4)
 _T4 = (_T4 + 1.0) / 2.0
@@ -57,17 +74,19 @@ def elements(Nc):
     return xy, vid
 
 
-def _local_nodes(V):
-    """P2 node coordinates of elements with vertices V (..., 3, 2)."""
+def _local_nodes(V, deg=P):
+    """Node coordinates of elements with vertices V (..., 3, 2)."""
+    if deg == 1:
+        return V
     mid = np.stack([(V[..., 0, :] + V[..., 1, :]) / 2, (V[..., 1, :] + V[..., 2, :]) / 2,
                     (V[..., 2, :] + V[..., 0, :]) / 2], axis=-2)
     return np.concatenate([V, mid], axis=-2)
 
 
-def dof_coords(Nc):
-    """(12 Nc^2, 2) coordinates of the DOF nodes."""
+def dof_coords(Nc, deg=P):
+    """(2 Nc^2 nb, 2) coordinates of the DOF nodes."""
     V, _ = elements(Nc)
-    return _local_nodes(V).reshape(-1, 2)
+    return _local_nodes(V, deg).reshape(-1, 2)
 
 
 def _bary(V, p):
@@ -93,9 +112,14 @@ def _bary(V, p):
 _EDGES = ((0, 1), (1, 2), (2, 0))
 
 
-def basis(V, p):
-    """P2 values (E, Q, 6) and gradients (E, Q, 6, 2) at points p (E, Q, 2)."""
+def basis(V, p, deg=P):
+    """Values (E, Q, nb) and gradients (E, Q, nb, 2) at points p (E, Q, 2) of
+    the degree-deg nodal functions: the barycentric coordinates for P1; for
+    P2 lam_a (2 lam_a - 1) at the vertices and 4 lam_a lam_b at the edge
+    midpoints."""
     lam, g, _ = _bary(V, p)
+    if deg == 1:
+        return lam.copy(), np.broadcast_to(g[:, None, :, :], lam.shape + (2,)).copy()
     phi = np.empty(lam.shape[:2] + (6,))
     dphi = np.empty(lam.shape[:2] + (6, 2))
     for a in range(3):
@@ -167,24 +191,27 @@ def _face_points(V, f):
     return pts, _W4[None, :] * L[:, None], nrm, L
 
 
-def assemble_dg_parts(Nc, omega, s_vertex):
+def assemble_dg_parts(Nc, omega, s_vertex, deg=P, bc="absorbing"):
     """Unordered DOF pairs (rows <= cols) with the values of A and of the
     plain DG mass matrix; each pair accumulates its contributions in a fixed
-    order, so mirroring yields a bitwise symmetric matrix."""
+    order, so mirroring yields a bitwise symmetric matrix.  deg: 1 or 2;
+    bc: "absorbing" or "dirichlet"."""
+    assert bc in ("absorbing", "dirichlet")
+    nb = nbasis(deg)
     s = np.asarray(s_vertex, dtype=np.float64)
     V, vid = elements(Nc)
     ne = V.shape[0]
     rows, cols, vals, mvals = [], [], [], []
-    ia, ib = np.triu_indices(6)
+    ia, ib = np.triu_indices(nb)
 
     # volume terms
     pts, w, lam = _tri_quad(V)
-    phi, dphi = basis(V, pts)
+    phi, dphi = basis(V, pts, deg)
     k2 = omega * omega * (lam[None, :, :] * (s[vid] ** 2)[:, None, :]).sum(axis=2)
     Kl = np.einsum("eq,eqad,eqbd->eab", w, dphi, dphi)
     Ml = np.einsum("eq,eqa,eqb->eab", w * k2, phi, phi)
     M1 = np.einsum("eq,eqa,eqb->eab", w, phi, phi)
-    dof = 6 * np.arange(ne)[:, None] + np.arange(6)[None, :]
+    dof = nb * np.arange(ne)[:, None] + np.arange(nb)[None, :]
     rows.append(dof[:, ia].ravel())
     cols.append(dof[:, ib].ravel())
     vals.append((Kl - Ml)[:, ia, ib].ravel().astype(np.complex128))
@@ -194,9 +221,9 @@ def assemble_dg_parts(Nc, omega, s_vertex):
     inner, bnd = faces(Nc)
     ep, fp, em, _ = inner.T
     fpts, fw, nrm, L = _face_points(V[ep], fp)
-    tau = PENALTY * P * P / L
-    php, dpp = basis(V[ep], fpts)
-    phm, dpm = basis(V[em], fpts)
+    tau = PENALTY * deg * deg / L
+    php, dpp = basis(V[ep], fpts, deg)
+    phm, dpm = basis(V[em], fpts, deg)
     dnp = np.einsum("eqad,ed->eqa", dpp, nrm)
     dnm = np.einsum("eqad,ed->eqa", dpm, nrm)
     # block (row side, column side): sides + (sign +1) and - (sign -1)
@@ -208,8 +235,8 @@ def assemble_dg_parts(Nc, omega, s_vertex):
                + (sr * sc) * tau[:, None, None] * np.einsum("eq,eqa,eqb->eab", fw, pr, pc))
         er = ep if rs == 0 else em
         ec = ep if cs == 0 else em
-        R = 6 * er[:, None, None] + np.arange(6)[None, :, None]
-        Cc = 6 * ec[:, None, None] + np.arange(6)[None, None, :]
+        R = nb * er[:, None, None] + np.arange(nb)[None, :, None]
+        Cc = nb * ec[:, None, None] + np.arange(nb)[None, None, :]
         R = np.broadcast_to(R, blk.shape)
         Cc = np.broadcast_to(Cc, blk.shape)
         keep = R <= Cc
@@ -218,22 +245,29 @@ def assemble_dg_parts(Nc, omega, s_vertex):
         vals.append(blk[keep].astype(np.complex128))
         mvals.append(np.zeros(int(keep.sum())))
 
-    # absorbing boundary faces
+    # boundary faces: absorbing, or Dirichlet with the outside value zero
     eb, fb = bnd.T
-    bpts, bw, _, _ = _face_points(V[eb], fb)
-    lam_b, _, _ = _bary(V[eb], bpts)
-    kb = omega * (lam_b * s[vid[eb]][:, None, :]).sum(axis=2)
-    phb, _ = basis(V[eb], bpts)
-    Gl = np.einsum("eq,eqa,eqb->eab", bw * kb, phb, phb)
-    dofb = 6 * eb[:, None] + np.arange(6)[None, :]
+    bpts, bw, bn, bL = _face_points(V[eb], fb)
+    phb, dphb = basis(V[eb], bpts, deg)
+    if bc == "absorbing":
+        lam_b, _, _ = _bary(V[eb], bpts)
+        kb = omega * (lam_b * s[vid[eb]][:, None, :]).sum(axis=2)
+        Gl = -1j * np.einsum("eq,eqa,eqb->eab", bw * kb, phb, phb)
+    else:
+        dnb = np.einsum("eqad,ed->eqa", dphb, bn)
+        taub = PENALTY * deg * deg / bL
+        Gl = (-np.einsum("eq,eqb,eqa->eab", bw, dnb, phb)
+              - np.einsum("eq,eqa,eqb->eab", bw, dnb, phb)
+              + taub[:, None, None] * np.einsum("eq,eqa,eqb->eab", bw, phb, phb))
+    dofb = nb * eb[:, None] + np.arange(nb)[None, :]
     rows.append(dofb[:, ia].ravel())
     cols.append(dofb[:, ib].ravel())
-    vals.append((-1j * Gl[:, ia, ib]).ravel())
+    vals.append(Gl[:, ia, ib].ravel().astype(np.complex128))
     mvals.append(np.zeros(ia.size * eb.size))
 
     r = np.concatenate(rows)
     c = np.concatenate(cols)
-    n = 6 * ne
+    n = nb * ne
     uniq, inv = np.unique(r * n + c, return_inverse=True)
     acc = np.zeros(uniq.size, dtype=np.complex128)
     np.add.at(acc, inv, np.concatenate(vals))
@@ -250,27 +284,29 @@ def _mirror(n, rows, cols, v):
     return sp.csr_matrix((Vv, (R, C)), shape=(n, n))
 
 
-def assemble_dg(Nc, omega, s_vertex=None):
-    """A (complex128 CSR, sorted columns) on DOFs 6 e + a.  Structural zeros
+def assemble_dg(Nc, omega, s_vertex=None, deg=P, bc="absorbing"):
+    """A (complex128 CSR, sorted columns) on DOFs nb e + a.  Structural zeros
     of the element-face block pattern are kept as explicit entries.
     s_vertex: nodal slowness on the (Nc+1)^2 vertex grid (default 1)."""
     if s_vertex is None:
         s_vertex = np.ones((Nc + 1) ** 2)
-    rows, cols, v, _ = assemble_dg_parts(Nc, omega, s_vertex)
-    A = _mirror(12 * Nc * Nc, rows, cols, v)
+    rows, cols, v, _ = assemble_dg_parts(Nc, omega, s_vertex, deg, bc)
+    A = _mirror(2 * Nc * Nc * nbasis(deg), rows, cols, v)
     A.sort_indices()
     return A
 
 
-def mass_matrix_dg(Nc):
-    """Block-diagonal P2 mass matrix (the load b = M f of nodal samples)."""
-    rows, cols, _, m = assemble_dg_parts(Nc, 0.0, np.ones((Nc + 1) ** 2))
-    M = _mirror(12 * Nc * Nc, rows, cols, m)
+def mass_matrix_dg(Nc, deg=P):
+    """Block-diagonal mass matrix of the nodal basis (the load b = M f of
+    nodal samples)."""
+    rows, cols, _, m = assemble_dg_parts(Nc, 0.0, np.ones((Nc + 1) ** 2), deg)
+    M = _mirror(2 * Nc * Nc * nbasis(deg), rows, cols, m)
     M.eliminate_zeros()
     return M
 
 
-def dg_nnz(Nc):
-    """Entries of the element-face block pattern: 36 per element self block
+def dg_nnz(Nc, deg=P):
+    """Entries of the element-face block pattern: nb^2 per element self block
     and per face-neighbour block."""
-    return 36 * (2 * Nc * Nc + 2 * (3 * Nc * Nc - 2 * Nc))
+    nb = nbasis(deg)
+    return nb * nb * (2 * Nc * Nc + 2 * (3 * Nc * Nc - 2 * Nc))

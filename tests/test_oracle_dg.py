@@ -121,3 +121,88 @@ def test_variable_slowness_scales():
     A1 = fem_dg.assemble_dg(Nc, 3.0, np.full((Nc + 1) ** 2, c))
     A2 = fem_dg.assemble_dg(Nc, 3.0 * c)
     assert abs(A1 - A2).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P1, Dirichlet
+# The scaling study of Sec. 4.6 runs IPDG with p = 1 and u = 0 on the whole
+# boundary (Sec. 4.1-4.2); the pins below fix the P1 basis and the boundary
+# terms by closed forms and by the second-order convergence of a
+# manufactured solution.
+
+def _ind1(Nc, e):
+    return np.repeat(np.eye(2 * Nc * Nc)[e], 3)
+
+
+@pytest.mark.parametrize("Nc", [1, 2, 5])
+def test_p1_dirichlet_pattern_and_symmetry(Nc):
+    rng = np.random.default_rng(Nc)
+    A = fem_dg.assemble_dg(Nc, 7.0, 0.5 + rng.random((Nc + 1) ** 2), deg=1, bc="dirichlet")
+    assert A.shape == (6 * Nc * Nc, 6 * Nc * Nc)
+    assert A.nnz == fem_dg.dg_nnz(Nc, 1)
+    assert (A != A.T).nnz == 0
+    assert abs(A.imag).max() == 0.0          # real operator: no absorbing term
+
+
+def test_p1_dirichlet_linear_energies():
+    """Continuous linear u, v have no interior jumps; by hand on the unit
+    square with tau = 10 / h on the boundary faces:
+    a(x, y) = 0 (volume) + 0 (consistency) + tau int_boundary x y = 10 Nc;
+    a(x, x) = 1 - 2 int_{x=1} 1 + tau (1 + 1/3 + 1/3) = -1 + 50 Nc / 3."""
+    Nc = 4
+    A = fem_dg.assemble_dg(Nc, 0.0, deg=1, bc="dirichlet")
+    xy = fem_dg.dof_coords(Nc, 1)
+    x, y = xy[:, 0], xy[:, 1]
+    assert (x @ (A @ y)).real == pytest.approx(10.0 * Nc, rel=1e-12)
+    assert (x @ (A @ x)).real == pytest.approx(-1.0 + 50.0 * Nc / 3.0, rel=1e-12)
+
+
+def test_p1_dirichlet_penalty_on_indicators():
+    """Piecewise constants: every face of an element, interior or on the
+    Dirichlet boundary, adds tau |F| = 10 p^2 = 10, so a(1_e, 1_e) = 30 for
+    every e; face neighbours couple with -10 (omega = 0)."""
+    Nc = 4
+    A = fem_dg.assemble_dg(Nc, 0.0, deg=1, bc="dirichlet")
+    for e in (0, 2 * (1 * Nc + 1), 2 * (2 * Nc) + 1, 2 * Nc * Nc - 1):
+        assert _ind1(Nc, e) @ (A @ _ind1(Nc, e)) == pytest.approx(30.0, rel=1e-13)
+    e = 2 * (1 * Nc + 1)
+    assert _ind1(Nc, e) @ (A @ _ind1(Nc, e + 1)) == pytest.approx(-10.0, rel=1e-13)
+    assert abs(_ind1(Nc, e) @ (A @ _ind1(Nc, e + 2))) < 1e-13
+
+
+def test_p1_dirichlet_consistency_signs():
+    """a(x, 1_e): zero inside; zero for a triangle with its face on x = 0
+    (the boundary consistency term +h cancels the interior faces' -h); and
+    -h + (h - h) + tau h = 10 for a triangle with its face on x = 1."""
+    Nc = 4
+    A = fem_dg.assemble_dg(Nc, 0.0, deg=1, bc="dirichlet")
+    x = fem_dg.dof_coords(Nc, 1)[:, 0]
+    assert abs(_ind1(Nc, 2 * (1 * Nc + 1)) @ (A @ x)) < 1e-13
+    assert abs(_ind1(Nc, 2 * (2 * Nc) + 1) @ (A @ x)) < 1e-13
+    east = 2 * (2 * Nc + Nc - 1)
+    assert (_ind1(Nc, east) @ (A @ x)).real == pytest.approx(10.0, rel=1e-12)
+
+
+def _p1_manufactured_error(Nc, kappa):
+    """Nodal RMS error for u = sin(pi x) sin(pi y) (zero on the boundary),
+    f = (2 pi^2 - kappa^2) u, b_i = int f phi_i by the 16-point rule."""
+    A = fem_dg.assemble_dg(Nc, kappa, deg=1, bc="dirichlet")
+    V, _ = fem_dg.elements(Nc)
+    pts, w, _ = fem_dg._tri_quad(V)
+    phi, _ = fem_dg.basis(V, pts, 1)
+    f = (2 * np.pi ** 2 - kappa ** 2) * np.sin(np.pi * pts[..., 0]) * np.sin(np.pi * pts[..., 1])
+    b = np.einsum("eq,eqa->ea", w * f, phi).ravel() + 0j
+    uh = spla.spsolve(A.tocsc(), b)
+    xy = fem_dg.dof_coords(Nc, 1)
+    u = np.sin(np.pi * xy[:, 0]) * np.sin(np.pi * xy[:, 1])
+    return np.sqrt(np.mean(np.abs(uh - u) ** 2))
+
+
+@pytest.mark.parametrize("kappa,grids", [(0.0, (8, 16, 32, 64)), (10.0, (16, 32, 64, 128))])
+def test_p1_dirichlet_second_order(kappa, grids):
+    """Every refinement gains at least second order less a margin; the mean
+    rate over the range is second order (the Helmholtz error mixes the
+    pollution term into single steps, so only the mean is held from above)."""
+    errs = np.array([_p1_manufactured_error(Nc, kappa) for Nc in grids])
+    rates = np.log2(errs[:-1] / errs[1:])
+    mean = np.log2(errs[0] / errs[-1]) / (len(grids) - 1)
+    assert np.all(rates > 1.8) and 1.85 < mean < 2.3, (errs, rates, mean)
