@@ -336,6 +336,68 @@ def run_batch(args):
     return 0
 
 
+def run_paper_table(args):
+    """The scaling study of Sec. 4.6 on this GPU: IPDG-P1 with u = 0 on the
+    boundary and f = 1, the paper's solver settings (HSS tolerance 1e-6,
+    beta = 30, ND leaves below 10 elements, HSS from 4 levels above the
+    leaves, left-preconditioned GMRES(10) to 1e-9, at most 30 iterations),
+    complex128 factors.  Per grid: the factorization (median of 3 numeric
+    refactorizations, HIP events), one application of P^-1 (median of 5),
+    the factor's bytes (the paper's "memory"), GMRES iterations and k_max;
+    the exact multifrontal factorization of the same tree beside it."""
+    import torch
+    from paper_2105_07791_amd import hssx
+    from synth import IPDG_INV_H, make_ipdg
+
+    dev = torch.device("cuda:0")
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b_.record()
+            b_.synchronize()
+            out.append(a.elapsed_time(b_) / 1e3)
+        return sorted(out)[len(out) // 2]
+
+    for fam in args.paper_table.split(","):
+        for inv_h in IPDG_INV_H:
+            if inv_h > args.max_inv_h:
+                continue
+            pr = make_ipdg(fam, inv_h)
+            A = hssx.DGOperator(pr.Nc, pr.omega, pr.slowness, p=1, bc="dirichlet")
+            b = A.load(torch.tensor(pr.f, device=dev))
+            row = {"paper_table": fam, "inv_h": inv_h, "n": pr.n, "kappa": pr.omega}
+            for key, h_sw in (("hss", pr.h_sw), ("exact", -1)):
+                P = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=h_sw,
+                                dtype=pr.factor_dtype, seed=1)
+                fs = P.stats()
+                t_fac = timed(lambda: P.refactor(A), 3)
+                t_app = timed(lambda: P.apply(b), 5)
+                x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol,
+                                         maxit=pr.gmres_maxit)
+                res = ((A.matvec(x) - b).abs().pow(2).sum().sqrt()
+                       / b.abs().pow(2).sum().sqrt()).item()
+                fs = P.stats()
+                row[key] = {"factor_s": t_fac, "apply_s": t_app, "memory_bytes": fs["factor_bytes"],
+                            "iters": st[0]["iters"], "converged": st[0]["converged"],
+                            "prec_res": st[0]["prec_res"], "true_res": res, "k_max": fs["k_max"],
+                            "hss_nodes": fs["n_hss_nodes"], "depth": fs["depth"],
+                            "max_estimate": fs["max_estimate"], "n_above_tol": fs["n_above_tol"],
+                            "factor_flops": fs["factor_flops"],
+                            "analysis_ms": fs["ms_symbolic"] + fs["ms_setup"]}
+                del P
+                torch.cuda.synchronize()
+            print(json.dumps(row), flush=True)
+            print(f"[bench] {fam} 1/h={inv_h}: hss {row['hss']['factor_s']:.4f}s "
+                  f"apply {row['hss']['apply_s'] * 1e3:.2f}ms iters {row['hss']['iters']} "
+                  f"k_max {row['hss']['k_max']}", file=sys.stderr, flush=True)
+            del A
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +414,12 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--alt-tol", type=float, default=1e-4,
                     help="(unused; kept for command compatibility)")
+    ap.add_argument("--paper-table", default=None, metavar="FAMILIES",
+                    help="the IPDG-P1 Dirichlet scaling sweep of Sec. 4.6 (Tables 2-3) for "
+                    "a comma-separated list of families (poisson, helmholtz_k10, "
+                    "helmholtz_kh025, helmholtz_kh05) over 1/h = 22 ... --max-inv-h; "
+                    "one JSON line per grid, then exits")
+    ap.add_argument("--max-inv-h", type=int, default=512)
     ap.add_argument("--switch-study", action="store_true",
                     help="instead of the benchmark: time the complex64 HSS form with the "
                          "switching height h_sw = 2..6 and with the size rule at 2, 4 and "
@@ -370,6 +438,8 @@ def main():
         return 2
     if args.workload in BATCHES:
         return run_batch(args)
+    if args.paper_table:
+        return run_paper_table(args)
 
     import ctypes
     import torch

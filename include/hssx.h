@@ -77,6 +77,16 @@ typedef struct {
   double omega;   /* angular frequency; wavenumber k(x) = omega * s(x) */
 } hssx_problem_desc;
 
+/* Interior-penalty DG problem (Sec. 4.1-4.2, 4.6): N x N cells of the unit
+ * square, polynomial degree p (1 or 2), boundary condition bc. */
+enum { HSSX_BC_ABSORBING = 0, HSSX_BC_DIRICHLET = 1 };
+typedef struct {
+  int N;          /* cells per side, N >= 1 */
+  int p;          /* polynomial degree: 1 or 2 */
+  int bc;         /* HSSX_BC_ABSORBING (d_n u - i k u = 0) or HSSX_BC_DIRICHLET (u = 0) */
+  double omega;   /* angular frequency; wavenumber k(x) = omega * s(x); 0 = Poisson */
+} hssx_ipdg_desc;
+
 /* Factorization options (Sec. 4 parameter choices; Algorithm 3.4, A.1). */
 typedef struct {
   int beta;         /* HSS leaf size in DOFs (eq. 2.1); default 16 */
@@ -224,6 +234,20 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc,
 hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc,
                              const double *s_dev, void *stream, hssx_op *A_out);
 
+/* The symmetric interior-penalty DG operator of hssx_assemble_dg for either
+ * polynomial degree and either boundary condition (the IPDG runs of Sec.
+ * 4.1-4.2 and the p = 1 scaling study of Sec. 4.6 with u = 0 on the whole
+ * boundary).  P1: DOF 3 e + a over the vertex functions (barycentric
+ * coordinates), 3 x 3 blocks, tau_F = 10 / |F|; P2 as in hssx_assemble_dg.
+ * Dirichlet faces add -int (grad u.n) v - int (grad v.n) u + tau_F int u v
+ * with the outward normal (the interior face terms with zero outside); the
+ * operator is then real (imaginary parts exactly zero) for real omega s.
+ * hssx_load with f = 1 gives the load of the constant source f = 1.  s_dev,
+ * ownership, uses and errors as for hssx_assemble_dg; EINVAL also for p or bc
+ * out of range, and N above 5400 (P1) or 2700 (P2). */
+hssx_status hssx_assemble_ipdg(int device, const hssx_ipdg_desc *desc,
+                               const double *s_dev, void *stream, hssx_op *A_out);
+
 /* Batch of independent problems as one block-diagonal operator (the
  * batching form: fronts of one tree depth, across all problems, are
  * eliminated and compressed in the same launches, and GMRES advances every
@@ -362,6 +386,10 @@ hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_
  * adjacency across faces, cluster coordinates at the triangle centroids.
  * leaf_size and beta count DOFs (>= 6).  Host-only, as hssx_analyze. */
 hssx_status hssx_analyze_dg(int Nc, int leaf_size, int beta, hssx_fact *P_out);
+
+/* hssx_analyze_dg for either degree: units of 3 (p = 1) or 6 (p = 2) DOFs;
+ * leaf_size and beta count DOFs (>= the unit).  Host-only. */
+hssx_status hssx_analyze_ipdg(int Nc, int p, int leaf_size, int beta, hssx_fact *P_out);
 
 /* Elimination permutation (host int32[n]): perm[k] = node id eliminated at
  * position k (concatenation of I(sigma) over the post-order). */

@@ -26,6 +26,13 @@ class ProblemDesc(C.Structure):
     _fields_ = [("N", C.c_int), ("omega", C.c_double)]
 
 
+class IpdgDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("p", C.c_int), ("bc", C.c_int), ("omega", C.c_double)]
+
+
+BC_ABSORBING, BC_DIRICHLET = 0, 1
+
+
 class FactorOpts(C.Structure):
     _fields_ = [("beta", C.c_int), ("h_sw", C.c_int), ("k0", C.c_int), ("r", C.c_int),
                 ("max_rounds", C.c_int), ("dtype", C.c_int), ("seed", C.c_uint32),
@@ -79,8 +86,10 @@ SIGNATURES = {
     "hssx_dAds_contract_adjoint": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "hssx_analyze": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
     "hssx_analyze_dg": (_i, [_i, _i, _i, C.POINTER(_vp)]),
+    "hssx_analyze_ipdg": (_i, [_i, _i, _i, _i, C.POINTER(_vp)]),
     "hssx_refactor": (_i, [_vp, _vp, _vp]),
     "hssx_assemble_dg": (_i, [_i, C.POINTER(ProblemDesc), _vp, _vp, C.POINTER(_vp)]),
+    "hssx_assemble_ipdg": (_i, [_i, C.POINTER(IpdgDesc), _vp, _vp, C.POINTER(_vp)]),
     "hssx_get_perm": (_i, [_vp, _ip, _l]),
     "hssx_get_tree": (_i, [_vp, _i64p, _ip, _ip, _ip, _ip, _ip, _ip, _ip]),
     "hssx_get_factor_stats": (_i, [_vp, C.POINTER(FactorStats)]),

@@ -332,13 +332,20 @@ hssx_status hssx_assemble_elastic(int device, const hssx_problem_desc *desc, con
   });
 }
 
-hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const double *s_dev,
-                             void *stream, hssx_op *A_out) {
+namespace {
+
+// the SIPG operators of hssx_assemble_dg and hssx_assemble_ipdg
+hssx_status assemble_sipg(int device, int Nc, int deg, int bc, double omega, const double *s_dev,
+                          void *stream, hssx_op *A_out) {
   return guarded([&] {
-    HSSX_CHECK(desc && A_out && s_dev, HSSX_EINVAL, "null argument");
-    // 32-bit CSR offsets: nnz < 288 Nc^2 must stay below 2^31
-    HSSX_CHECK(desc->N >= 1 && desc->N <= 2700, HSSX_EINVAL, "cell count out of range");
-    HSSX_CHECK(std::isfinite(desc->omega) && desc->omega >= 0, HSSX_EINVAL, "omega");
+    HSSX_CHECK(A_out && s_dev, HSSX_EINVAL, "null argument");
+    HSSX_CHECK(deg == 1 || deg == 2, HSSX_EINVAL, "polynomial degree must be 1 or 2");
+    HSSX_CHECK(bc == HSSX_BC_ABSORBING || bc == HSSX_BC_DIRICHLET, HSSX_EINVAL,
+               "boundary condition");
+    const int nb = deg == 1 ? 3 : 6;
+    // 32-bit CSR offsets: nnz < 8 nb^2 Nc^2 must stay below 2^31
+    HSSX_CHECK(Nc >= 1 && Nc <= (deg == 1 ? 5400 : 2700), HSSX_EINVAL, "cell count out of range");
+    HSSX_CHECK(std::isfinite(omega) && omega >= 0, HSSX_EINVAL, "omega");
     *A_out = nullptr;
     DeviceScope ds(device);
     AllocScope as_(g_bound, stream);
@@ -346,17 +353,17 @@ hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const do
     auto A = std::make_unique<hssx_op_>();
     A->device = device;
     A->ctx = g_bound;
-    A->N = desc->N;
-    A->omega = desc->omega;
-    A->dofs = 6;
+    A->N = Nc;
+    A->omega = omega;
+    A->dofs = nb;
     A->mesh = kMeshDG;
-    A->row_max = 24;
-    const int Nc = desc->N, ne = 2 * Nc * Nc, n = 6 * ne, nv = (Nc + 1) * (Nc + 1);
+    A->row_max = 4 * nb;
+    const int ne = 2 * Nc * Nc, n = nb * ne, nv = (Nc + 1) * (Nc + 1);
     A->n = n;
-    // 6 x 6 blocks of each triangle with itself and its face neighbours,
+    // nb x nb blocks of each triangle with itself and its face neighbours,
     // neighbour elements in increasing id (columns sorted)
     A->h_rowptr.resize(n + 1);
-    A->h_col.reserve((size_t)24 * n);
+    A->h_col.reserve((size_t)4 * nb * n);
     A->h_rowptr[0] = 0;
     for (int e = 0; e < ne; ++e) {
       const int c = e >> 1, t = e & 1, i = c % Nc, j = c / Nc;
@@ -371,10 +378,10 @@ hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const do
         if (i > 0) el[k++] = 2 * (j * Nc + i - 1);
       }
       std::sort(el, el + k);
-      for (int a = 0; a < 6; ++a) {
+      for (int a = 0; a < nb; ++a) {
         for (int q = 0; q < k; ++q)
-          for (int b = 0; b < 6; ++b) A->h_col.push_back(6 * el[q] + b);
-        A->h_rowptr[6 * e + a + 1] = (int)A->h_col.size();
+          for (int b = 0; b < nb; ++b) A->h_col.push_back(nb * el[q] + b);
+        A->h_rowptr[nb * e + a + 1] = (int)A->h_col.size();
       }
     }
     A->nnz = (long)A->h_col.size();
@@ -384,15 +391,30 @@ hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const do
     A->mval.alloc(A->nnz * sizeof(double));
     A->s.alloc((size_t)nv * sizeof(double));
     HSSX_HIP(hipMemcpyAsync(A->s.p, s_dev, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_assemble_dg(Nc, desc->omega, A->s.as<double>(), A->rowptr.as<int>(), A->col.as<int>(),
-                       A->val.as<c128>(), A->mval.as<double>(), st);
+    launch_assemble_dg(Nc, deg, bc == HSSX_BC_DIRICHLET, omega, A->s.as<double>(),
+                       A->rowptr.as<int>(), A->col.as<int>(), A->val.as<c128>(),
+                       A->mval.as<double>(), st);
     A->part_N = {Nc};
-    A->part_omega = {desc->omega};
+    A->part_omega = {omega};
     A->part_off = {0, n};
     upload(A->part_off_dev, A->part_off);
     HSSX_HIP(hipStreamSynchronize(st));
     *A_out = A.release();
   });
+}
+
+}  // namespace
+
+hssx_status hssx_assemble_dg(int device, const hssx_problem_desc *desc, const double *s_dev,
+                             void *stream, hssx_op *A_out) {
+  if (!desc) return guarded([] { throw Error(HSSX_EINVAL, "null argument"); });
+  return assemble_sipg(device, desc->N, 2, HSSX_BC_ABSORBING, desc->omega, s_dev, stream, A_out);
+}
+
+hssx_status hssx_assemble_ipdg(int device, const hssx_ipdg_desc *desc, const double *s_dev,
+                               void *stream, hssx_op *A_out) {
+  if (!desc) return guarded([] { throw Error(HSSX_EINVAL, "null argument"); });
+  return assemble_sipg(device, desc->N, desc->p, desc->bc, desc->omega, s_dev, stream, A_out);
 }
 
 hssx_status hssx_op_batch(int count, const hssx_op *parts, void *stream, hssx_op *A_out) {
@@ -840,18 +862,24 @@ hssx_status hssx_analyze(int N, int dofs, int leaf_size, int beta, hssx_fact *P_
   });
 }
 
-hssx_status hssx_analyze_dg(int Nc, int leaf_size, int beta, hssx_fact *P_out) {
+hssx_status hssx_analyze_ipdg(int Nc, int p, int leaf_size, int beta, hssx_fact *P_out) {
   return guarded([&] {
-    HSSX_CHECK(P_out && Nc >= 1 && Nc <= 2700 && leaf_size >= 6 && beta >= 6, HSSX_EINVAL,
-               "invalid argument");
+    const int nb = p == 1 ? 3 : 6;
+    HSSX_CHECK(P_out && (p == 1 || p == 2) && Nc >= 1 && Nc <= (p == 1 ? 5400 : 2700) &&
+                   leaf_size >= nb && beta >= nb,
+               HSSX_EINVAL, "invalid argument");
     *P_out = nullptr;
     auto P = std::make_unique<hssx_fact_>();
     P->leaf = leaf_size;
     P->opts.beta = beta;
     P->sym = build_symbolic(Nc, leaf_size, beta, std::min(16, (int)std::thread::hardware_concurrency()),
-                            6, kMeshDG);
+                            nb, kMeshDG);
     *P_out = P.release();
   });
+}
+
+hssx_status hssx_analyze_dg(int Nc, int leaf_size, int beta, hssx_fact *P_out) {
+  return hssx_analyze_ipdg(Nc, 2, leaf_size, beta, P_out);
 }
 
 hssx_status hssx_get_perm(hssx_fact P, int32_t *perm_host, long n) {

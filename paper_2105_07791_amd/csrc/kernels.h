@@ -14,10 +14,12 @@ void launch_assemble(int N, double omega, const double *s, const int *rowptr, co
 void launch_assemble_elastic(int N, double omega, const double *lam, const double *mu,
                              const double *rho, const int *rowptr, const int *col, c128 *val,
                              double *mval, hipStream_t st);
-// SIPG-P2 Helmholtz operator on Nc x Nc x 2 triangles (DOF 6 e + a; pattern:
-// 6 x 6 blocks of each triangle with itself and its face neighbours)
-void launch_assemble_dg(int Nc, double omega, const double *s_vertex, const int *rowptr,
-                        const int *col, c128 *val, double *mval, hipStream_t st);
+// SIPG Helmholtz operator of degree deg (1 or 2) on Nc x Nc x 2 triangles
+// (DOF nb e + a, nb = 3 or 6; pattern: nb x nb blocks of each triangle with
+// itself and its face neighbours); dirichlet: 0 absorbing boundary, 1 u = 0
+void launch_assemble_dg(int Nc, int deg, int dirichlet, double omega, const double *s_vertex,
+                        const int *rowptr, const int *col, c128 *val, double *mval,
+                        hipStream_t st);
 void launch_load(int n, int nrhs, const int *rowptr, const int *col, const double *mval,
                  const double *f, long ldf, c128 *b, long ldb, hipStream_t st);
 // row_max: longest row (7 scalar stencil, 14 for 2 x 2 blocks, 24 for P2 triangles)

@@ -1,16 +1,21 @@
-// Symmetric interior-penalty DG assembly with P2 elements for the Helmholtz
-// operator (the IPDG discretization of Sec. 4.1-4.2) on the structured mesh:
+// Symmetric interior-penalty DG assembly with P1 or P2 elements for the
+// Helmholtz operator (the IPDG discretization of Sec. 4.1-4.2 and 4.6) on the
+// structured mesh:
 //
 //   a(u,v) = sum_T int_T grad u . grad v - k^2 u v
 //          + sum_{interior F} -int {grad u . n}[v] - int {grad v . n}[u]
 //                              + tau_F int [u][v]
-//          - i sum_{boundary F} int k u v,          tau_F = 10 p^2 / |F|,
+//          + boundary terms,                          tau_F = 10 p^2 / |F|,
 //
+// the boundary terms being either the absorbing -i int_F k u v or the
+// homogeneous Dirichlet condition, imposed like an interior face with zero
+// outside: -int_F (grad u . n) v - int_F (grad v . n) u + tau_F int_F u v.
 // k^2 = omega^2 (P1 interpolant of the vertex values s^2), k on boundary faces
 // = omega (P1 interpolant of s).  Cells (i, j) of side h = 1/Nc hold the lower
 // triangle (i,j),(i+1,j),(i+1,j+1) (element 2 c) and the upper triangle
-// (i,j),(i+1,j+1),(i,j+1) (element 2 c + 1), c = j Nc + i; DOF 6 e + a with
-// the nodal P2 basis (vertices, then midpoints of (v0,v1), (v1,v2), (v2,v0)).
+// (i,j),(i+1,j+1),(i,j+1) (element 2 c + 1), c = j Nc + i; DOF NB e + a with
+// the nodal basis of degree p (NB = 3: the vertices; NB = 6: the vertices,
+// then the midpoints of (v0,v1), (v1,v2), (v2,v0)).
 //
 // Each thread builds one CSR row.  Entry (r, c) is evaluated for the ordered
 // pair (min, max) with the same quadrature and summation order from either
@@ -23,7 +28,7 @@ namespace hssx {
 
 namespace {
 
-constexpr double kPenalty = 10.0 * 2 * 2;   // 10 p^2, p = 2
+constexpr double kPenaltyBase = 10.0;   // tau_F |F| = 10 p^2
 
 // Gauss-Legendre on [0, 1]: nodes and weights of the 4-point rule
 __device__ __forceinline__ void gl4(int q, double &t, double &w) {
@@ -67,12 +72,17 @@ __device__ void bary(const Elem &E, double px, double py, double lam[3], double 
   }
 }
 
-// P2 function a of element E at (px, py): value and gradient
-__device__ void p2(const Elem &E, int a, double px, double py, double &phi, double &gx,
-                   double &gy) {
+// nodal function a (of NB per element) of E at (px, py): value and gradient
+template <int NB>
+__device__ void shape(const Elem &E, int a, double px, double py, double &phi, double &gx,
+                      double &gy) {
   double lam[3], g[3][2];
   bary(E, px, py, lam, g);
-  if (a < 3) {
+  if (NB == 3) {
+    phi = lam[a];
+    gx = g[a][0];
+    gy = g[a][1];
+  } else if (a < 3) {
     phi = lam[a] * (2.0 * lam[a] - 1.0);
     gx = (4.0 * lam[a] - 1.0) * g[a][0];
     gy = (4.0 * lam[a] - 1.0) * g[a][1];
@@ -111,9 +121,12 @@ __device__ void face_geom(const Elem &E, int f, double &sx, double &sy, double &
 }
 
 // same-element entry (a, b) of element e: volume terms, the same-side terms
-// of its interior faces and its absorbing faces
-__device__ void dg_self(int Nc, double omega, const double *s, int e, int a, int b, double &re,
-                        double &im, double &m1) {
+// of its interior faces and its boundary faces (absorbing, or Dirichlet when
+// dir is set)
+template <int NB>
+__device__ void dg_self(int Nc, double omega, const double *s, int dir, int e, int a, int b,
+                        double &re, double &im, double &m1) {
+  constexpr double kPenalty = kPenaltyBase * (NB == 3 ? 1 : 4);
   const Elem E = make_elem(Nc, e);
   const double area2 = fabs(E.det);
   double k = 0, m = 0, mm = 0;
@@ -129,8 +142,8 @@ __device__ void dg_self(int Nc, double omega, const double *s, int e, int a, int
       const double s2 = l0 * s[E.vid[0]] * s[E.vid[0]] + xi * s[E.vid[1]] * s[E.vid[1]] +
                         eta * s[E.vid[2]] * s[E.vid[2]];
       double pa, gax, gay, pb, gbx, gby;
-      p2(E, a, px, py, pa, gax, gay);
-      p2(E, b, px, py, pb, gbx, gby);
+      shape<NB>(E, a, px, py, pa, gax, gay);
+      shape<NB>(E, b, px, py, pb, gbx, gby);
       k += w * (gax * gbx + gay * gby);
       m += w * omega * omega * s2 * pa * pb;
       mm += w * pa * pb;
@@ -147,11 +160,13 @@ __device__ void dg_self(int Nc, double omega, const double *s, int e, int a, int
       w *= L;
       const double px = sx + t * dx, py = sy + t * dy;
       double pa, gax, gay, pb, gbx, gby;
-      p2(E, a, px, py, pa, gax, gay);
-      p2(E, b, px, py, pb, gbx, gby);
+      shape<NB>(E, a, px, py, pa, gax, gay);
+      shape<NB>(E, b, px, py, pb, gbx, gby);
       if (en >= 0) {
         fre += w * (-0.5 * (gbx * nx + gby * ny) * pa - 0.5 * (gax * nx + gay * ny) * pb +
                     tau * pa * pb);
+      } else if (dir) {
+        fre += w * (-(gbx * nx + gby * ny) * pa - (gax * nx + gay * ny) * pb + tau * pa * pb);
       } else {
         const int v0 = E.vid[f], v1 = E.vid[(f + 1) % 3];
         const double kb = omega * ((1.0 - t) * s[v0] + t * s[v1]);
@@ -165,7 +180,9 @@ __device__ void dg_self(int Nc, double omega, const double *s, int e, int a, int
 }
 
 // cross entry between DOF a of element e1 and DOF b of face neighbour e2 > e1
+template <int NB>
 __device__ double dg_cross(int Nc, int e1, int a, int e2, int b) {
+  constexpr double kPenalty = kPenaltyBase * (NB == 3 ? 1 : 4);
   const Elem E1 = make_elem(Nc, e1), E2 = make_elem(Nc, e2);
   int f = 0;
   while (f < 3 && face_nbr(Nc, e1, f) != e2) ++f;
@@ -179,8 +196,8 @@ __device__ double dg_cross(int Nc, int e1, int a, int e2, int b) {
     w *= L;
     const double px = sx + t * dx, py = sy + t * dy;
     double pa, gax, gay, pb, gbx, gby;
-    p2(E1, a, px, py, pa, gax, gay);
-    p2(E2, b, px, py, pb, gbx, gby);
+    shape<NB>(E1, a, px, py, pa, gax, gay);
+    shape<NB>(E2, b, px, py, pb, gbx, gby);
     // row side +, column side -: signs s_r = 1, s_c = -1
     acc += w * (-0.5 * (gbx * nx + gby * ny) * pa + 0.5 * (gax * nx + gay * ny) * pb -
                 tau * pa * pb);
@@ -188,21 +205,22 @@ __device__ double dg_cross(int Nc, int e1, int a, int e2, int b) {
   return acc;
 }
 
-__global__ void assemble_dg_kernel(int Nc, double omega, const double *__restrict__ s,
+template <int NB>
+__global__ void assemble_dg_kernel(int Nc, double omega, const double *__restrict__ s, int dir,
                                    const int *__restrict__ rowptr, const int *__restrict__ col,
                                    c128 *__restrict__ val, double *__restrict__ mval) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= 12 * Nc * Nc) return;
+  if (r >= 2 * NB * Nc * Nc) return;
   for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
     const int lo = min(r, col[p]), hi = max(r, col[p]);
-    const int e1 = lo / 6, a = lo % 6, e2 = hi / 6, b = hi % 6;
+    const int e1 = lo / NB, a = lo % NB, e2 = hi / NB, b = hi % NB;
     if (e1 == e2) {
       double re, im, m1;
-      dg_self(Nc, omega, s, e1, a, b, re, im, m1);
+      dg_self<NB>(Nc, omega, s, dir, e1, a, b, re, im, m1);
       val[p] = mk(re, im);
       mval[p] = m1;
     } else {
-      val[p] = mk(dg_cross(Nc, e1, a, e2, b), 0.0);
+      val[p] = mk(dg_cross<NB>(Nc, e1, a, e2, b), 0.0);
       mval[p] = 0.0;
     }
   }
@@ -210,11 +228,16 @@ __global__ void assemble_dg_kernel(int Nc, double omega, const double *__restric
 
 }  // namespace
 
-void launch_assemble_dg(int Nc, double omega, const double *s, const int *rowptr, const int *col,
-                        c128 *val, double *mval, hipStream_t st) {
-  const int n = 12 * Nc * Nc;
-  hipLaunchKernelGGL(assemble_dg_kernel, dim3(ceil_div(n, 128)), dim3(128), 0, st, Nc, omega, s,
-                     rowptr, col, val, mval);
+void launch_assemble_dg(int Nc, int deg, int dirichlet, double omega, const double *s,
+                        const int *rowptr, const int *col, c128 *val, double *mval,
+                        hipStream_t st) {
+  const int nb = deg == 1 ? 3 : 6, n = 2 * nb * Nc * Nc;
+  if (deg == 1)
+    hipLaunchKernelGGL(assemble_dg_kernel<3>, dim3(ceil_div(n, 128)), dim3(128), 0, st, Nc, omega,
+                       s, dirichlet, rowptr, col, val, mval);
+  else
+    hipLaunchKernelGGL(assemble_dg_kernel<6>, dim3(ceil_div(n, 128)), dim3(128), 0, st, Nc, omega,
+                       s, dirichlet, rowptr, col, val, mval);
   HSSX_HIP(hipGetLastError());
 }
 

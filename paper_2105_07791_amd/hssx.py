@@ -119,20 +119,27 @@ class ElasticOperator(_OperatorBase):
 
 
 class DGOperator(_OperatorBase):
-    """SIPG-P2 Helmholtz operator on Nc x Nc x 2 triangles (DOF 6 e + a);
-    slowness given at the (Nc+1)^2 mesh vertices."""
+    """SIPG Helmholtz operator on Nc x Nc x 2 triangles with P2 (default) or
+    P1 elements (DOF nb e + a, nb = 6 or 3) and an absorbing (default) or
+    homogeneous Dirichlet boundary; slowness given at the (Nc+1)^2 mesh
+    vertices (None: 1)."""
     parts = 1
 
-    def __init__(self, Nc, omega, slowness, device=0, stream=None):
+    def __init__(self, Nc, omega, slowness=None, p=2, bc="absorbing", device=0, stream=None):
+        if slowness is None:
+            slowness = torch.ones((Nc + 1) ** 2, dtype=torch.float64)
         s = torch.as_tensor(slowness, dtype=torch.float64, device=f"cuda:{device}").contiguous()
         assert s.numel() == (Nc + 1) ** 2
-        self.N, self.omega, self.n, self.device = Nc, float(omega), 12 * Nc * Nc, device
+        nb = 3 if p == 1 else 6
+        self.N, self.omega, self.n, self.device = Nc, float(omega), 2 * nb * Nc * Nc, device
+        self.p, self.bc = p, bc
         self.slowness = s
         self.part_off = [0, self.n]
         h = C.c_void_p()
-        desc = _lib.ProblemDesc(Nc, float(omega))
-        check(lib().hssx_assemble_dg(device, C.byref(desc), C.c_void_p(s.data_ptr()),
-                                     _stream(stream), C.byref(h)))
+        code = {"absorbing": _lib.BC_ABSORBING, "dirichlet": _lib.BC_DIRICHLET}[bc]
+        desc = _lib.IpdgDesc(Nc, p, code, float(omega))
+        check(lib().hssx_assemble_ipdg(device, C.byref(desc), C.c_void_p(s.data_ptr()),
+                                       _stream(stream), C.byref(h)))
         self.handle = h
 
 

@@ -34,13 +34,15 @@ def read_tree(handle):
 class Analysis:
     """Symbolic analysis of an N x N grid with `dofs` unknowns per node
     (hssx_analyze), or with dg=True of the N x N x 2 triangle mesh of the
-    SIPG-P2 operator (hssx_analyze_dg)."""
+    SIPG operator of degree p (hssx_analyze_ipdg; 6 DOFs per triangle for
+    p = 2, 3 for p = 1)."""
 
-    def __init__(self, N, leaf_size=32, beta=16, dofs=1, dg=False):
+    def __init__(self, N, leaf_size=32, beta=16, dofs=1, dg=False, p=2):
         h = C.c_void_p()
         if dg:
-            self.N, self.n, self.dofs = N, 12 * N * N, 6
-            check(lib().hssx_analyze_dg(int(N), int(leaf_size), int(beta), C.byref(h)))
+            nb = 3 if p == 1 else 6
+            self.N, self.n, self.dofs = N, 2 * nb * N * N, nb
+            check(lib().hssx_analyze_ipdg(int(N), int(p), int(leaf_size), int(beta), C.byref(h)))
         else:
             self.N, self.n, self.dofs = N, N * N * dofs, dofs
             check(lib().hssx_analyze(int(N), int(dofs), int(leaf_size), int(beta), C.byref(h)))

@@ -20,6 +20,7 @@ __all__ = [
     "random_field", "speed_field", "make_problem", "CONFIGS", "make_batch", "BATCHES",
     "receiver_nodes", "batch_grid_sizes", "ElasticProblem", "lame_fields",
     "make_elastic", "ELASTIC", "DGProblem", "dg_node_coords", "make_dg", "DG",
+    "IpdgProblem", "make_ipdg", "IPDG_FAMILIES", "IPDG_INV_H",
 ]
 
 
@@ -349,3 +350,60 @@ def make_dg(name, device=None, **overrides):
     for q, (cx, cy) in enumerate(centers):
         f[:, q] = np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * 0.02 * 0.02))
     return DGProblem(name=name, Nc=Nc, omega=omega, slowness=s, f=f, **cfg)
+
+
+# ---------------------------------------------------------------- IPDG-P1
+@dataclass
+class IpdgProblem:
+    """The scaling workload of Sec. 4.6: IPDG with P1 elements on Nc x Nc x 2
+    triangles of the unit square (n = 6 Nc^2 = 6 / h^2 DOFs), u = 0 on the
+    whole boundary, constant source f = 1, constant wavenumber kappa = omega
+    (s = 1); omega = 0 is the Poisson problem.  Solver settings of Sec. 4:
+    HSS tolerance 1e-6, block size beta = 10 (p+1)(p+2)/2 = 30 DOFs, ND
+    leaves of fewer than 10 elements, HSS arithmetic from 4 levels above the
+    leaves, GMRES restarted every 10 iterations, tolerance 1e-9, at most 30
+    iterations."""
+    name: str
+    Nc: int
+    omega: float
+    slowness: np.ndarray          # ((Nc+1)^2,) ones
+    f: np.ndarray                 # (6 Nc^2, 1) ones: the source f = 1 at the DOF nodes
+    p: int = 1
+    bc: str = "dirichlet"
+    leaf_dofs: int = 30
+    beta: int = 30
+    tol: float = 1e-6
+    h_sw: int = 4
+    gmres_m: int = 10
+    gmres_tol: float = 1e-9
+    gmres_maxit: int = 30
+    factor_dtype: str = "c128"
+
+    @property
+    def n(self):
+        return 6 * self.Nc * self.Nc
+
+    @property
+    def nrhs(self):
+        return self.f.shape[1]
+
+
+#: wavenumber of each family as a function of the cells per side Nc = 1/h:
+#: Poisson, Helmholtz kappa = 10 (Table 2), and kappa h = 1/4, 1/2 (Table 3)
+IPDG_FAMILIES = {
+    "poisson": lambda Nc: 0.0,
+    "helmholtz_k10": lambda Nc: 10.0,
+    "helmholtz_kh025": lambda Nc: Nc / 4.0,
+    "helmholtz_kh05": lambda Nc: Nc / 2.0,
+}
+#: the mesh widths 1/h of Tables 2-3
+IPDG_INV_H = (22, 32, 45, 64, 90, 128, 181, 256, 362, 512)
+
+
+def make_ipdg(family, Nc, **overrides):
+    """The IPDG-P1 Dirichlet workload of `family` on Nc = 1/h cells per side."""
+    omega = float(IPDG_FAMILIES[family](Nc))
+    cfg = dict(name=f"ipdg_p1_{family}_{Nc}", Nc=Nc, omega=omega,
+               slowness=np.ones((Nc + 1) ** 2), f=np.ones((6 * Nc * Nc, 1)))
+    cfg.update(overrides)
+    return IpdgProblem(**cfg)

@@ -55,12 +55,14 @@ def test_symbolic_bit_exact(N, leaf, beta, dofs):
         assert np.array_equal(cl, ref), k
 
 
-@pytest.mark.parametrize("Nc,leaf,beta", [(1, 12, 6), (3, 12, 12), (8, 60, 60), (11, 36, 24),
-                                          (32, 60, 60), (45, 60, 30)])
-def test_symbolic_dg_bit_exact(Nc, leaf, beta):
+@pytest.mark.parametrize("Nc,leaf,beta,p", [(1, 12, 6, 2), (3, 12, 12, 2), (8, 60, 60, 2),
+                                            (11, 36, 24, 2), (32, 60, 60, 2), (45, 60, 30, 2),
+                                            (2, 6, 3, 1), (9, 30, 30, 1), (22, 30, 30, 1),
+                                            (45, 30, 30, 1)])
+def test_symbolic_dg_bit_exact(Nc, leaf, beta, p):
     from paper_2105_07791_amd.symbolic import Analysis
-    an = Analysis(Nc, leaf, beta, dg=True)
-    t = nd.build_nd_dg(Nc, leaf, beta)
+    an = Analysis(Nc, leaf, beta, dg=True, p=p)
+    t = nd.build_nd_dg(Nc, leaf, beta, dofs=3 if p == 1 else 6)
     assert np.array_equal(an.perm(), t.perm)
     tr = an.tree()
     assert tr["info"].shape[0] == len(t.boxes)
@@ -88,3 +90,5 @@ def test_invalid_arguments_rejected():
     assert L.hssx_analyze(9, 3, 32, 16, ctypes.byref(h)) == -1
     assert L.hssx_analyze_dg(0, 60, 60, ctypes.byref(h)) == -1
     assert L.hssx_analyze_dg(8, 5, 60, ctypes.byref(h)) == -1
+    assert L.hssx_analyze_ipdg(8, 3, 30, 30, ctypes.byref(h)) == -1
+    assert L.hssx_analyze_ipdg(8, 1, 2, 30, ctypes.byref(h)) == -1
