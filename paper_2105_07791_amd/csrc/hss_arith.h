@@ -90,11 +90,11 @@ template <typename T> struct Prog {
   }
 };
 
-template <typename T> inline std::vector<BgTile> gemm_tiles(const std::vector<BgJob<T>> &jobs) {
-  std::vector<BgTile> t;
+template <typename T> inline std::vector<BgTask<T>> gemm_tasks(const std::vector<BgJob<T>> &jobs) {
+  std::vector<BgTask<T>> t;
   for (size_t j = 0; j < jobs.size(); ++j)
     for (int a = 0; a < (jobs[j].M + 31) / 32; ++a)
-      for (int b = 0; b < (jobs[j].N + 31) / 32; ++b) t.push_back(BgTile{(int)j, a, b});
+      for (int b = 0; b < (jobs[j].N + 31) / 32; ++b) t.push_back(BgTask<T>{jobs[j], a, b});
   return t;
 }
 
@@ -110,13 +110,13 @@ template <typename V> inline long max_elems(const V &v) {
 
 // one stage from device job arrays
 template <typename T>
-inline void launch_stage(const Stage<T> &s, const void *jobs, const BgTile *tiles, int ntiles,
-                         long me, const c128 *val, hipStream_t st) {
+inline void launch_stage(const Stage<T> &s, const void *jobs, int ntiles, long me,
+                         const c128 *val, hipStream_t st) {
   const int n = (int)s.size();
   switch (s.kind) {
     case kGemm: {
       hipEvent_t pe = prof_begin(st);
-      launch_bgemm<T>(ntiles, tiles, (const BgJob<T> *)jobs, st);
+      launch_bgemm<T>(ntiles, (const BgTask<T> *)jobs, st);
       if (pe) {
         double fl = 0;
         for (const BgJob<T> &g : s.gemm) fl += 8.0 * g.M * g.N * g.K;
@@ -153,7 +153,7 @@ template <typename T> inline long stage_elems(const Stage<T> &s) {
 // of its jobs and of its tile list
 template <typename T> struct ProgBlob {
   std::vector<char> h;
-  std::vector<size_t> jobs, tiles;
+  std::vector<size_t> jobs;
   std::vector<int> ntiles;
   std::vector<long> me;
   size_t put(const void *src, size_t bytes) {
@@ -165,13 +165,12 @@ template <typename T> struct ProgBlob {
   template <typename V> size_t putv(const V &v) { return put(v.data(), v.size() * sizeof(v[0])); }
   template <typename Q> void build(const Q &stages) {
     for (const Stage<T> &s : stages) {
-      size_t j = 0, t = 0;
+      size_t j = 0;
       int nt = 0;
       switch (s.kind) {
         case kGemm: {
-          std::vector<BgTile> tl = gemm_tiles(s.gemm);
-          j = putv(s.gemm);
-          t = putv(tl);
+          std::vector<BgTask<T>> tl = gemm_tasks(s.gemm);
+          j = putv(tl);
           nt = (int)tl.size();
           break;
         }
@@ -185,7 +184,6 @@ template <typename T> struct ProgBlob {
         default: j = putv(s.sym); break;
       }
       jobs.push_back(j);
-      tiles.push_back(t);
       ntiles.push_back(nt);
       me.push_back(stage_elems(s));
     }
@@ -196,7 +194,7 @@ template <typename T> struct ProgBlob {
     for (const Stage<T> &s : stages) {
       const size_t q = i++;
       if (s.size() == 0 || (s.kind == kGemm && ntiles[q] == 0)) continue;
-      launch_stage(s, base + jobs[q], (const BgTile *)(base + tiles[q]), ntiles[q], me[q], val, st);
+      launch_stage(s, base + jobs[q], ntiles[q], me[q], val, st);
     }
   }
 };

@@ -20,12 +20,14 @@ template <typename T> struct BgJob {
   int ta, tb, beta;
   T ar, ai;   // alpha
 };
-// one 32 x 32 output tile of one job
-struct BgTile {
-  int job, tm, tn;
+// one 32 x 32 output tile of one job, with a copy of the job so that a
+// workgroup reads its whole description in one load
+template <typename T> struct BgTask {
+  BgJob<T> jb;
+  int tm, tn;
 };
 template <typename T>
-void launch_bgemm(int ntiles, const BgTile *tiles, const BgJob<T> *jobs, hipStream_t st);
+void launch_bgemm(int ntiles, const BgTask<T> *tasks, hipStream_t st);
 
 // Block copies: mode 0 dst = s src, 1 dst = s src^T, 2 dst = I, 3 dst = 0,
 // 4 dst += s src (m x n block of dst; src m x n, or n x m for mode 1).

@@ -128,10 +128,30 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
       Fs[p + j * m] = j == p ? mk((T)1, (T)0) : b * inv;
     }
     __syncthreads();
-    const int w = nc - p - 1;
-    for (int e = tid; e < m * w; e += kThreads) {
-      const int i = e % m, j = p + 1 + e / m;
-      if (i != p) cfms(Fs[i + j * m], Fs[i + p * m], Fs[p + j * m]);
+    // rank-1 update in register tiles of 4 rows (strided by rs, so that
+    // neighbouring threads touch neighbouring rows) by 4 columns: the pivot
+    // column's and the pivot row's entries are read once per tile, not once
+    // per element
+    const int w = nc - p - 1, rs = (m + 3) >> 2, tj = (w + 3) >> 2;
+    for (int e = tid; e < rs * tj; e += kThreads) {
+      const int i0 = e % rs, j0 = p + 1 + ((e / rs) << 2);
+      cplx<T> a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r * rs;
+        a[r] = (i < m && i != p) ? Fs[i + p * m] : czero<T>();
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = j0 + c < nc ? Fs[p + (j0 + c) * m] : czero<T>();
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (j0 + c >= nc) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r * rs;
+          if (i < m && i != p) cfms(Fs[i + (j0 + c) * m], a[r], b[c]);
+        }
+      }
     }
     __syncthreads();
   }

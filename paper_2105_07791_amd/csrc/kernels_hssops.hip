@@ -14,11 +14,10 @@ constexpr int kBT = 256;   // threads per workgroup
 // products (two LDS buffers, one barrier per step), so their latency
 // overlaps the arithmetic.
 template <typename T>
-__global__ __launch_bounds__(kBT) void bgemm_kernel(const BgTile *__restrict__ tiles,
-                                                    const BgJob<T> *__restrict__ jobs) {
+__global__ __launch_bounds__(kBT) void bgemm_kernel(const BgTask<T> *__restrict__ tasks) {
   __shared__ cplx<T> As[2][16][33], Bs[2][16][33];
-  const BgTile tl = tiles[blockIdx.x];
-  const BgJob<T> jb = jobs[tl.job];
+  const BgTask<T> tl = tasks[blockIdx.x];
+  const BgJob<T> &jb = tl.jb;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int i0 = tl.tm * 32, j0 = tl.tn * 32;
   // per-thread staging coordinates (k index within the step, row / column)
@@ -265,9 +264,9 @@ inline int grid_for(long elems) {
 }  // namespace
 
 template <typename T>
-void launch_bgemm(int ntiles, const BgTile *tiles, const BgJob<T> *jobs, hipStream_t st) {
+void launch_bgemm(int ntiles, const BgTask<T> *tasks, hipStream_t st) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(bgemm_kernel<T>, dim3(ntiles), dim3(kBT), 0, st, tiles, jobs);
+  hipLaunchKernelGGL(bgemm_kernel<T>, dim3(ntiles), dim3(kBT), 0, st, tasks);
   HSSX_HIP(hipGetLastError());
 }
 
@@ -333,7 +332,7 @@ void launch_entries_list(EntView<T> view, const int *ij, int n, cplx<T> *out, hi
 
 #define HSSX_OPS_INST(T)                                                                       \
   template void launch_entries_list<T>(EntView<T>, const int *, int, cplx<T> *, hipStream_t);  \
-  template void launch_bgemm<T>(int, const BgTile *, const BgJob<T> *, hipStream_t);           \
+  template void launch_bgemm<T>(int, const BgTask<T> *, hipStream_t);                          \
   template void launch_copy<T>(int, const CopyJob<T> *, long, hipStream_t);                    \
   template void launch_spmm<T>(int, const SpJob<T> *, const c128 *, long, hipStream_t);        \
   template void launch_fill_coo<T>(int, const FillJob<T> *, const c128 *, int, hipStream_t);   \
