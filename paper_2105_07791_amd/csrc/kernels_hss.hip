@@ -634,10 +634,7 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           const int row = slot + kRS * r;
           T nrm = 0;
 #pragma unroll
-          for (int c = 0; c < kRSEG; ++c) {
-            if (kRT * c >= s) continue;
-            nrm += abs2(w[r][c]);
-          }
+          for (int c = 0; c < kRSEG; ++c) nrm += abs2(w[r][c]);
           nrm = group_sum<kRT>(nrm);
           if (row < rows && !pk[r] && (nrm > best || (nrm == best && row < bi))) {
             best = nrm;
@@ -651,22 +648,26 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           for (int r = 0; r < kRPT; ++r)
             if (r == ro) {
 #pragma unroll
-              for (int c = 0; c < kRSEG; ++c) {
-                if (kRT * c >= s) continue;
-                const int j = sub + kRT * c;
-                cand[par][wv][j] = w[r][c];   // zero past s
-              }
+              for (int c = 0; c < kRSEG; ++c) cand[par][wv][sub + kRT * c] = w[r][c];
             }
         }
         if ((tid & 63) == 0) { sv2[par][wv] = best; si2[par][wv] = bi; }
         lds_barrier();
-        T v = sv2[par][0];
-        int vi = si2[par][0], ww = 0;
+        // all wavefront maxima loaded before the first comparison
+        T vv[NT / 64];
+        int iv[NT / 64];
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) {
+          vv[k] = sv2[par][k];
+          iv[k] = si2[par][k];
+        }
+        T v = vv[0];
+        int vi = iv[0], ww = 0;
 #pragma unroll
         for (int k = 1; k < NT / 64; ++k)
-          if (sv2[par][k] > v || (sv2[par][k] == v && si2[par][k] < vi)) {
-            v = sv2[par][k];
-            vi = si2[par][k];
+          if (vv[k] > v || (vv[k] == v && iv[k] < vi)) {
+            v = vv[k];
+            vi = iv[k];
             ww = k;
           }
         const T pn = sqrt(v);
@@ -685,6 +686,10 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           perm[t] = vi;
           Rm[t + (long)vi * C.k_cap] = mk(pn, (T)0);
         }
+        // this lane's entries of the pivot row, loaded once per step
+        cplx<T> qv[kRSEG];
+#pragma unroll
+        for (int c = 0; c < kRSEG; ++c) qv[c] = qr[sub + kRT * c];
 #pragma unroll
         for (int r = 0; r < kRPT; ++r) {
           if (kRS * r >= rows) continue;
@@ -694,23 +699,15 @@ __global__ __launch_bounds__(NT) void compress_level_kernel(
           for (int pass = 0; pass < kPasses; ++pass) {
             cplx<T> d = czero<T>();
 #pragma unroll
-            for (int c = 0; c < kRSEG; ++c) {
-              if (kRT * c >= s) continue;
-              const int j = sub + kRT * c;
-              cfma(d, conj(qr[j]), w[r][c]);
-            }
+            for (int c = 0; c < kRSEG; ++c) cfma(d, conj(qv[c]), w[r][c]);
             d.re = inv * group_sum<kRT>(d.re);
             d.im = inv * group_sum<kRT>(d.im);
-            // no lane or row guards: entries past s are zero in w and in
-            // the candidate rows, rows past the block stay zero, and a
-            // picked row (projected onto itself) is never read again
+            // no lane guards: entries past s are zero in w and in the
+            // candidate rows, rows past the block stay zero, and a picked
+            // row (projected onto itself) is never read again
             const cplx<T> dq = inv * d;
 #pragma unroll
-            for (int c = 0; c < kRSEG; ++c) {
-              if (kRT * c >= s) continue;
-              const int j = sub + kRT * c;
-              cfms(w[r][c], dq, qr[j]);
-            }
+            for (int c = 0; c < kRSEG; ++c) cfms(w[r][c], dq, qv[c]);
             rr = rr + d;
           }
           if (act && sub == 0) Rm[t + (long)row * C.k_cap] = rr;
