@@ -296,10 +296,48 @@ class Staging {
     for (auto &c : chunks_)
       if (c.host) (void)hipHostFree(c.host);
   }
-  template <typename T> T *put(const std::vector<T> &v) {
+  // v uploaded; kernels may write to the device copy (a counter, a queue)
+  template <typename T> T *put(const std::vector<T> &v) { return place(v, false); }
+  // v uploaded for reading only: when the same bytes already sit at this
+  // position on both sides from an upload known to have landed (synced()),
+  // the copy is skipped (repeated factorizations of one pattern stage
+  // identical job arrays at identical positions)
+  template <typename T> T *put_const(const std::vector<T> &v) { return place(v, true); }
+  // the stream has been synchronised: every copy issued so far has landed
+  // and its bytes can be trusted by later put_const calls at that position
+  void synced() {
+    for (auto &c : chunks_)
+      for (auto &g : c.state)
+        if (g == kPending) g = kClean;
+  }
+  // start again at the first position (after a synchronisation, once no
+  // pointer returned before is used again); uploads not followed by
+  // synced() are forgotten
+  void recycle() {
+    for (auto &c : chunks_)
+      for (auto &g : c.state)
+        if (g == kPending) g = kUnknown;
+    cur_ = 0;
+    off_ = 0;
+  }
+  void set_stream(hipStream_t st) { st_ = st; }
+  hipStream_t stream() const { return st_; }
+
+ private:
+  static constexpr size_t kGran = 256;
+  // per granule: device bytes unknown (or writable by kernels), uploaded
+  // since the last recycle, or equal to the host bytes
+  enum : unsigned char { kUnknown = 0, kPending = 1, kClean = 2 };
+  struct Chunk {
+    void *host = nullptr;
+    std::unique_ptr<DevBuf> dev;
+    size_t cap = 0;
+    std::vector<unsigned char> state;
+  };
+  template <typename T> T *place(const std::vector<T> &v, bool read_only) {
     size_t bytes = v.size() * sizeof(T);
-    size_t need = ((bytes + 255) / 256) * 256;
-    if (need == 0) need = 256;
+    size_t need = ((bytes + kGran - 1) / kGran) * kGran;
+    if (need == 0) need = kGran;
     while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].cap) {
       ++cur_;
       off_ = 0;
@@ -310,32 +348,27 @@ class Staging {
       HSSX_HIP(hipHostMalloc(&c.host, c.cap, hipHostMallocDefault));
       c.dev = std::make_unique<DevBuf>();
       c.dev->alloc(c.cap);
+      c.state.assign(c.cap / kGran, kUnknown);
       chunks_.push_back(std::move(c));
       off_ = 0;
     }
     Chunk &c = chunks_[cur_];
     char *h = static_cast<char *>(c.host) + off_;
     char *d = static_cast<char *>(c.dev->p) + off_;
+    const size_t g0 = off_ / kGran, g1 = (off_ + need) / kGran;
     if (bytes) {
-      std::memcpy(h, v.data(), bytes);
-      HSSX_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st_));
+      bool same = read_only;
+      for (size_t g = g0; same && g < g1; ++g) same = c.state[g] == kClean;
+      same = same && std::memcmp(h, v.data(), bytes) == 0;
+      if (!same) {
+        std::memcpy(h, v.data(), bytes);
+        HSSX_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st_));
+        for (size_t g = g0; g < g1; ++g) c.state[g] = read_only ? kPending : kUnknown;
+      }
     }
     off_ += need;
     return reinterpret_cast<T *>(d);
   }
-  void recycle() {
-    cur_ = 0;
-    off_ = 0;
-  }
-  void set_stream(hipStream_t st) { st_ = st; }
-  hipStream_t stream() const { return st_; }
-
- private:
-  struct Chunk {
-    void *host = nullptr;
-    std::unique_ptr<DevBuf> dev;
-    size_t cap = 0;
-  };
   hipStream_t st_;
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, off_ = 0;

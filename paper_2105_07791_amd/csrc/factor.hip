@@ -151,14 +151,14 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       return (long)a.ne * a.ne * a.ncols > (long)b.ne * b.ne * b.ncols;
     });
     queue = sg.put(std::vector<int>{0});
-    d_order = sg.put(order);
+    d_order = sg.put_const(order);
   }
-  if (!small.empty()) d_small = sg.put(small);
+  if (!small.empty()) d_small = sg.put_const(small);
   // products over the non-pivot rows and the negation of R for the fronts
   // eliminated in LDS, queued on the same stream right after them
   const ProductLists pr_done = product_lists(rows_done);
-  GemmJob<T> *d_gd = pr_done.gj.empty() ? nullptr : sg.put(pr_done.gj);
-  AxpbyJob<T> *d_nd = pr_done.neg.empty() ? nullptr : sg.put(pr_done.neg);
+  GemmJob<T> *d_gd = pr_done.gj.empty() ? nullptr : sg.put_const(pr_done.gj);
+  AxpbyJob<T> *d_nd = pr_done.neg.empty() ? nullptr : sg.put_const(pr_done.neg);
   SideStream *side = overlap ? &side_stream() : nullptr;
   hipStream_t fs = st;
   if (overlap) {
@@ -221,15 +221,15 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     }
     step_cfg.push_back({off, (int)all_pj.size() - off, mm, mc, mp, mnb});
   }
-  PanelJob<T> *d_pj = all_pj.empty() ? nullptr : sg.put(all_pj);
+  PanelJob<T> *d_pj = all_pj.empty() ? nullptr : sg.put_const(all_pj);
   for (const auto &c : step_cfg)
     launch_panel_step<T>(c[1], d_pj + c[0], c[2], c[3], c[4], c[5], err, st);
   // non-pivot rows and R of the large fronts
   const ProductLists pr_big = product_lists(big);
   if (!pr_big.gj.empty())
-    launch_gemm_sub<T>((int)pr_big.gj.size(), sg.put(pr_big.gj), pr_big.gm, pr_big.gn, st);
+    launch_gemm_sub<T>((int)pr_big.gj.size(), sg.put_const(pr_big.gj), pr_big.gm, pr_big.gn, st);
   if (!pr_big.neg.empty())
-    launch_axpby<T>((int)pr_big.neg.size(), sg.put(pr_big.neg), pr_big.nm, pr_big.nn, st);
+    launch_axpby<T>((int)pr_big.neg.size(), sg.put_const(pr_big.neg), pr_big.nm, pr_big.nn, st);
   if (overlap) {
     HSSX_HIP(hipEventRecord(side->join, side->s));
     HSSX_HIP(hipStreamWaitEvent(st, side->join, 0));
@@ -393,7 +393,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
   double *Om = ar.get<double>(osz);
   cplx<T> *Y = ar.get<cplx<T>>(ysz);
   double *d_err = ar.get<double>(2 * tasks.size());
-  const EntryOp<T> *d_eops = eops.empty() ? nullptr : sg.put(eops);
+  const EntryOp<T> *d_eops = eops.empty() ? nullptr : sg.put_const(eops);
   Alloc<T> scratch = [&](size_t n) { return ar.get<cplx<T>>(n); };
 
   auto gen_and_sample = [&](const std::vector<int> &ids, bool probe) {
@@ -419,10 +419,10 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
                                   Y + t.yoff + (long)c0 * t.m, t.m, nc});
       }
     }
-    GaussJob *dg = sg.put(gj);
+    GaussJob *dg = sg.put_const(gj);
     launch_gaussian((int)gj.size(), dg, o.seed, gm, gc, st);
     if (!sj.empty()) {
-      SampleJob<T> *ds = sg.put(sj);
+      SampleJob<T> *ds = sg.put_const(sj);
       double sflops = 0;
       for (const auto &q : sj) sflops += 4.0 * q.m * (double)q.m * q.nc;
       acc.flops += sflops;
@@ -511,8 +511,8 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
     for (size_t a = 0; a < active.size(); ++a)
       inst[a].soff = tasks[active[a]].S ? tasks[active[a]].S - base : 0;
 
-    HssInstance *d_inst = sg.put(inst);
-    HssCluster *d_cls = sg.put(cls);
+    HssInstance *d_inst = sg.put_const(inst);
+    HssCluster *d_cls = sg.put_const(cls);
     // generator pools live in the factor's storage: an accepted instance's
     // generators stay where the compression wrote them
     cplx<T> *d_pool = store.get<cplx<T>>(pool);
@@ -567,8 +567,8 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
         all_items.insert(all_items.end(), items[sz].begin(), items[sz].end());
       }
     }
-    HssItem *d_all = all_items.empty() ? nullptr : sg.put(all_items);
-    HssItem *d_ent = ent_items.empty() ? nullptr : sg.put(ent_items);
+    HssItem *d_all = all_items.empty() ? nullptr : sg.put_const(all_items);
+    HssItem *d_ent = ent_items.empty() ? nullptr : sg.put_const(ent_items);
     // the small-cluster launch of a level is independent of its large-cluster
     // launches (different clusters, same inputs): when a level has both, the
     // small one runs on a side stream, forked from and joined back into st
@@ -638,7 +638,7 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
         mj.push_back(j);
       }
     }
-    MatvecJob<T> *d_mj = sg.put(mj);
+    MatvecJob<T> *d_mj = sg.put_const(mj);
     cplx<T> *d_xh = ar.get<cplx<T>>(xh_total);
     HSSX_HIP(hipMemsetAsync(d_err, 0, 2 * tasks.size() * sizeof(double), st));
     hipEvent_t pm = prof_begin(st);
@@ -725,9 +725,9 @@ void compress_batch(std::vector<CompressTask<T>> &tasks, const hssx_factor_opts 
         ej.push_back(j);
       }
     }
-    if (!sj.empty()) launch_symmetrize<T>((int)sj.size(), sg.put(sj), sym_max, st);
+    if (!sj.empty()) launch_symmetrize<T>((int)sj.size(), sg.put_const(sj), sym_max, st);
     if (!ej.empty()) {
-      MatvecJob<T> *d_ej = sg.put(ej);
+      MatvecJob<T> *d_ej = sg.put_const(ej);
       cplx<T> *d_xh2 = ar.get<cplx<T>>(xh2_total);
       hipEvent_t pm2 = prof_begin(st);
       launch_hss_matvec<T>((int)ej.size(), d_ej, d_inst, d_cls, d_pool, d_rank, d_xh2,
@@ -804,7 +804,7 @@ std::vector<EntView<T>> upload_views(const std::vector<const EntPrep<T> *> &ep, 
   }
   std::vector<EntView<T>> v(ep.size());
   if (ep.empty()) return v;
-  const char *d = sg.put(h);
+  const char *d = sg.put_const(h);
   for (size_t i = 0; i < ep.size(); ++i)
     v[i] = EntView<T>{(const EntCl<T> *)(d + oc[i]), (const int *)(d + ol[i])};
   return v;
@@ -925,7 +925,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   const double id_tol =
       P.opts.id_rel_tol > 0 ? P.opts.id_rel_tol : std::max(1e-2 * P.tol, 4.0 * eps);
   int *err = ar.get<int>(1);
-  int *d_err = sg.put(std::vector<int>{-1});
+  int *d_err = sg.put_const(std::vector<int>{-1});
   HSSX_HIP(hipMemcpyAsync(err, d_err, sizeof(int), hipMemcpyDeviceToDevice, st));
   // storage of this factorization's HSS data (the previous one's is dropped:
   // every use of it was queued on this stream before)
@@ -981,7 +981,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
       flops += ef;
       prof_end("front_eliminate", st, pe, ef);
       HSSX_HIP(hipStreamSynchronize(st));
-      sg.recycle();
+      sg.synced();
       ar.release(depth_mark);
       continue;
     }
@@ -1407,10 +1407,11 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         ++ncomp;
       }
     }
-    // everything launched for this depth is complete before its scratch
-    // and the staged descriptors are released
+    // everything launched for this depth is complete before its scratch is
+    // released; the staged descriptors stay (positions keep advancing within
+    // a factorization, so a repeated one finds its arrays where it left them)
     HSSX_HIP(hipStreamSynchronize(st));
-    sg.recycle();
+    sg.synced();
     ar.release(depth_mark);
   }
   int bad = -1;

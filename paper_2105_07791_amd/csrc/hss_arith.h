@@ -206,7 +206,7 @@ inline void run_prog(const Prog<T> &p, Staging &sg, const c128 *val, hipStream_t
   if (p.st.empty()) return;
   ProgBlob<T> b;
   b.build(p.st);
-  const char *d = sg.put(b.h);
+  const char *d = sg.put_const(b.h);
   b.launch(p.st, d, val, st);
 }
 
