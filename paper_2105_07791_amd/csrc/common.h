@@ -147,7 +147,23 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
   if (G >= 16) v += dpp<kDppMirror>(v);
   return v;
 }
-// argmax (ties: smaller index) over the whole wavefront, result in every lane
+// one lane's value, read into a scalar register (every lane gets it)
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int lane_value(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// argmax (ties: smaller index) over the whole wavefront, result in every
+// lane: DPP butterflies within each row of 16 lanes, then the four rows'
+// results compared through scalar reads of one lane per row (no LDS round
+// trip).  Every lane of the wavefront must be active.
 template <typename T> __device__ __forceinline__ void wave_argmax(T &v, int &idx) {
   auto step = [&](T ov, int oi) {
     if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
@@ -156,8 +172,16 @@ template <typename T> __device__ __forceinline__ void wave_argmax(T &v, int &idx
   step(dpp<kDppXor2>(v), dpp<kDppXor2>(idx));
   step(dpp<kDppHalfMirror>(v), dpp<kDppHalfMirror>(idx));
   step(dpp<kDppMirror>(v), dpp<kDppMirror>(idx));
-  step(__shfl_xor(v, 16), __shfl_xor(idx, 16));
-  step(__shfl_xor(v, 32), __shfl_xor(idx, 32));
+  T bv = lane_value(v, 0);
+  int bi = lane_value(idx, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const T ov = lane_value(v, 16 * r);
+    const int oi = lane_value(idx, 16 * r);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  v = bv;
+  idx = bi;
 }
 
 // ---------------------------------------------------------------- memory
