@@ -362,18 +362,19 @@ def run_paper_table(args):
             out.append(a.elapsed_time(b_) / 1e3)
         return sorted(out)[len(out) // 2]
 
+    extra = [int(v) for v in args.extra_inv_h.split(",") if v]
     for fam in args.paper_table.split(","):
-        for inv_h in IPDG_INV_H:
-            if inv_h > args.max_inv_h:
-                continue
+        for inv_h in [h for h in IPDG_INV_H if h <= args.max_inv_h] + extra:
             pr = make_ipdg(fam, inv_h)
             A = hssx.DGOperator(pr.Nc, pr.omega, pr.slowness, p=1, bc="dirichlet")
             b = A.load(torch.tensor(pr.f, device=dev))
             row = {"paper_table": fam, "inv_h": inv_h, "n": pr.n, "kappa": pr.omega}
             for key, h_sw in (("hss", pr.h_sw), ("exact", -1)):
+                print(f"[bench] {fam} 1/h={inv_h} {key}: factor", file=sys.stderr, flush=True)
                 P = hssx.Factor(A, tol=pr.tol, leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=h_sw,
                                 dtype=pr.factor_dtype, seed=1)
                 fs = P.stats()
+                print(f"[bench] {fam} 1/h={inv_h} {key}: timed steps", file=sys.stderr, flush=True)
                 t_fac = timed(lambda: P.refactor(A), 3)
                 t_app = timed(lambda: P.apply(b), 5)
                 x, st = hssx.gmres_solve(A, P, b, m=pr.gmres_m, tol=pr.gmres_tol,
@@ -420,6 +421,9 @@ def main():
                     "helmholtz_kh025, helmholtz_kh05) over 1/h = 22 ... --max-inv-h; "
                     "one JSON line per grid, then exits")
     ap.add_argument("--max-inv-h", type=int, default=512)
+    ap.add_argument("--extra-inv-h", default="",
+                    help="comma-separated grids beyond the tables' for --paper-table "
+                    "(e.g. 724,1024,1448: 3.1M, 6.3M, 12.6M DOFs)")
     ap.add_argument("--switch-study", action="store_true",
                     help="instead of the benchmark: time the complex64 HSS form with the "
                          "switching height h_sw = 2..6 and with the size rule at 2, 4 and "
