@@ -92,3 +92,11 @@ def test_invalid_arguments_rejected():
     assert L.hssx_analyze_dg(8, 5, 60, ctypes.byref(h)) == -1
     assert L.hssx_analyze_ipdg(8, 3, 30, 30, ctypes.byref(h)) == -1
     assert L.hssx_analyze_ipdg(8, 1, 2, 30, ctypes.byref(h)) == -1
+    # IPDG assembly arguments are checked before any device call
+    bad = [_lib.IpdgDesc(8, 3, _lib.BC_DIRICHLET, 1.0), _lib.IpdgDesc(8, 1, 7, 1.0),
+           _lib.IpdgDesc(0, 1, _lib.BC_DIRICHLET, 1.0), _lib.IpdgDesc(5401, 1, _lib.BC_DIRICHLET, 1.0),
+           _lib.IpdgDesc(8, 1, _lib.BC_DIRICHLET, -1.0)]
+    for d in bad:
+        assert L.hssx_assemble_ipdg(0, ctypes.byref(d), ctypes.c_void_p(8), None,
+                                    ctypes.byref(h)) == -1
+    assert L.hssx_assemble_ipdg(0, None, ctypes.c_void_p(8), None, ctypes.byref(h)) == -1

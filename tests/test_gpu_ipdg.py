@@ -117,3 +117,26 @@ def test_largest_grid_of_the_table():
     assert stats[0]["converged"] and stats[0]["iters"] <= pr.gmres_maxit, stats
     r = (A.matvec(x) - b).abs().pow(2).sum().sqrt() / b.abs().pow(2).sum().sqrt()
     assert r.item() <= 1e-8
+
+
+@pytest.mark.parametrize("p,bc,Nc,omega", [(1, "absorbing", 5, 6.0), (2, "dirichlet", 4, 3.0),
+                                         (2, "dirichlet", 1, 0.0)])
+def test_other_degree_and_boundary_combinations(p, bc, Nc, omega):
+    """The remaining (degree, boundary) pairs of hssx_assemble_ipdg: assembly
+    to rounding against the oracle, and the exact factor (no compression)
+    solving to rounding."""
+    dev = _dev()
+    from paper_2105_07791_amd import hssx
+    s = 0.5 + np.random.default_rng(Nc).random((Nc + 1) ** 2)
+    A = hssx.DGOperator(Nc, omega, s, p=p, bc=bc)
+    Ao = fem_dg.assemble_dg(Nc, omega, s, deg=p, bc=bc)
+    rp, col, val = A.csr()
+    assert np.array_equal(rp, Ao.indptr) and np.array_equal(col, Ao.indices)
+    assert np.abs(val - Ao.data).max() <= 1e-13 * np.abs(Ao.data).max()
+    nb = 3 if p == 1 else 6
+    P = hssx.Factor(A, tol=1e-6, leaf_size=10 * nb, beta=10 * nb, h_sw=-1)
+    b = A.load(torch.ones((A.n, 1), dtype=torch.float64, device=dev))
+    x, st = hssx.gmres_solve(A, P, b, m=10, tol=1e-9, maxit=30)
+    xe = spla.splu(Ao.tocsc()).solve(b.cpu().numpy())
+    assert st[0]["converged"] and st[0]["iters"] == 1
+    assert np.linalg.norm(x.cpu().numpy() - xe) <= 1e-10 * np.linalg.norm(xe)
