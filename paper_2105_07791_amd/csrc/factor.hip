@@ -980,8 +980,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
       const double ef = elim_flops(rj);
       flops += ef;
       prof_end("front_eliminate", st, pe, ef);
-      HSSX_HIP(hipStreamSynchronize(st));
-      sg.synced();
+      // stream order makes the depth's scratch reusable by the next one
       ar.release(depth_mark);
       continue;
     }
@@ -1407,15 +1406,16 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         ++ncomp;
       }
     }
-    // everything launched for this depth is complete before its scratch is
-    // released; the staged descriptors stay (positions keep advancing within
-    // a factorization, so a repeated one finds its arrays where it left them)
-    HSSX_HIP(hipStreamSynchronize(st));
-    sg.synced();
+    // the next depth's launches follow this depth's on the same stream (the
+    // side stream of the compressions is joined back), so its scratch is
+    // reused without waiting; the staged descriptors stay (positions keep
+    // advancing within a factorization, so a repeated one finds its arrays
+    // where it left them)
     ar.release(depth_mark);
   }
   int bad = -1;
   HSSX_HIP(hipStreamSynchronize(st));
+  sg.synced();
   HSSX_HIP(hipMemcpy(&bad, err, sizeof(int), hipMemcpyDeviceToHost));
   HSSX_CHECK(bad < 0, HSSX_ESINGULAR, "zero pivot in a dense block of tree node " + std::to_string(bad));
   // bytes the apply reads: dense blocks of the dense-class nodes, telescoping
