@@ -473,11 +473,14 @@ def main():
     # right-hand sides.  "hss_c64" is the timed metric (the mixed-precision,
     # batched form of the method); the others are timed the same way for
     # comparison: the same HSS factor in complex128 (precision alone), the
+    # complex64 factor with complex128 telescoping inverses ("hss_c64_wide"), the
     # exact multifrontal factorization of the same tree on the same GPU
     # (h_sw < 0: no compression) in both precisions, and the plain FP64 form
     # (complex128 HSS factor, left GMRES, right-hand sides one at a time).
     FORMS = {
         "hss_c64": dict(dtype="c64", h_sw=pr.h_sw, tol=tol_mixed, flexible=True),
+        "hss_c64_wide": dict(dtype="c64", h_sw=pr.h_sw, tol=tol_mixed, flexible=True,
+                             wide_inverse=True),
         "hss_c128": dict(dtype="c128", h_sw=pr.h_sw, tol=pr.tol, flexible=True),
         "exact_c64": dict(dtype="c64", h_sw=-1, tol=pr.tol, flexible=True),
         "exact_c128": dict(dtype="c128", h_sw=-1, tol=pr.tol, flexible=True),
@@ -490,7 +493,8 @@ def main():
         P = factors.get(key)
         if P is None:
             P = hssx.Factor(A, tol=f["tol"], leaf_size=pr.leaf_dofs, beta=pr.beta, h_sw=f["h_sw"],
-                            dtype=f["dtype"], seed=1, switch_size=f.get("switch_size", 0))
+                            dtype=f["dtype"], seed=1, switch_size=f.get("switch_size", 0),
+                            wide_inverse=f.get("wide_inverse", False))
             factors[key] = P
             fs = P.stats()
             analysis[key] = {"symbolic_ms": fs["ms_symbolic"], "setup_ms": fs["ms_setup"],
@@ -632,10 +636,11 @@ def main():
         pass
 
     forms = {"hss_c64": main}
-    others = [] if args.no_plain else ["hss_c128", "exact_c64", "exact_c128", "plain_fp64"]
+    others = [] if args.no_plain else ["hss_c64_wide", "hss_c128", "exact_c64", "exact_c128",
+                                       "plain_fp64"]
     for key in others:
         step(key)                                            # analysis, untimed
-        rr = [step(key) for _ in range(1 if FORMS[key].get("single") else 2)]
+        rr = [step(key) for _ in range(1 if FORMS[key].get("single") else 3)]
         forms[key], xk = summarize(key, rr)
         forms[key]["rel_diff_vs_hss_c64"] = (torch.linalg.vector_norm(x - xk, dim=0)
                                              / torch.linalg.vector_norm(xk, dim=0)).max().item()

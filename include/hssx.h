@@ -122,6 +122,13 @@ typedef struct {
                        error estimate above tol; 0 (default): such
                        compressions are accepted and counted in
                        hssx_factor_stats.n_above_tol */
+  int wide_inverse; /* complex64 factors only, nonzero: the telescoping
+                       inverses of the HSS blocks (Sec. 3.3) are computed in
+                       complex128 from widened generators and stored in
+                       complex64.  Lowers the disagreement between entries
+                       and products of Schur complements whose interior
+                       blocks are ill-conditioned (indefinite elastic
+                       operators); 0 (default): complex64 throughout */
 } hssx_factor_opts;
 
 typedef struct {
@@ -423,6 +430,8 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld);
  *         and its two-sweep solve;
  *   op 2: vals[e] = H(i, j), entry access through the full bases;
  *   op 3: vals[e] = H^-1(i, j), the same on the inverse's HSS form;
+ *   op 4, op 5: op 1 and op 3 with the telescoping inverse computed in
+ *         complex128 and stored in dtype (hssx_factor_opts.wide_inverse);
  * for (i, j) = (ij[2e], ij[2e+1]).  tree: host int32[ncl*5] (start, size,
  * left, right, level) per cluster in level order, root 0 = [0, m), each
  * internal cluster split into two consecutive children; rank: host
@@ -431,8 +440,8 @@ hssx_status hssx_get_schur(hssx_fact P, int node, double *S_host, long ld);
  * at a leaf, rank[left] + rank[right] otherwise), then D (size x size) at a
  * leaf, or B12 (rank[left] x rank[right]) and B21 (rank[right] x rank[left])
  * at an internal cluster; all column-major.  X, Y: device complex128
- * m x nrhs (ld m) for op 0/1; ij: host int32[2 nij], vals: host float64
- * [2 nij] for op 2/3.  dtype: arithmetic precision (C64 rounds the
+ * m x nrhs (ld m) for op 0/1/4; ij: host int32[2 nij], vals: host float64
+ * [2 nij] for op 2/3/5.  dtype: arithmetic precision (C64 rounds the
  * generators and vectors).  ESINGULAR when a block of the inverse is
  * singular.  Synchronises stream. */
 hssx_status hssx_hss_eval(int device, hssx_dtype dtype, int m, int ncl,

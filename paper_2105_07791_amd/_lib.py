@@ -37,7 +37,8 @@ class FactorOpts(C.Structure):
     _fields_ = [("beta", C.c_int), ("h_sw", C.c_int), ("k0", C.c_int), ("r", C.c_int),
                 ("max_rounds", C.c_int), ("dtype", C.c_int), ("seed", C.c_uint32),
                 ("id_rel_tol", C.c_double), ("apply_graph", C.c_int), ("autotune", C.c_int),
-                ("sample_bf16", C.c_int), ("switch_size", C.c_int), ("strict_tol", C.c_int)]
+                ("sample_bf16", C.c_int), ("switch_size", C.c_int), ("strict_tol", C.c_int),
+                ("wide_inverse", C.c_int)]
 
 
 class GmresOpts(C.Structure):

@@ -534,7 +534,7 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
     HSSX_CHECK(tol > 0 && tol < 1, HSSX_EINVAL, "tol must lie in (0, 1)");
     HSSX_CHECK(leaf_size >= 1, HSSX_EINVAL, "leaf_size must be >= 1");
     *P_out = nullptr;
-    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0, 0, 0};
+    hssx_factor_opts o{16, 4, 32, 16, 32, HSSX_C128, 0u, 0.0, 1, 1, 0, 0, 0, 0};
     if (opts) o = *opts;
     HSSX_CHECK(o.beta >= 1 && o.k0 >= 1 && o.r >= 1 && o.r <= 64 && o.max_rounds >= 1,
                HSSX_EINVAL, "invalid factor options");
@@ -544,6 +544,8 @@ hssx_status hssx_factor(hssx_op A, double tol, int leaf_size, const hssx_factor_
                "leaf and HSS leaf sizes must hold one grid node's unknowns");
     HSSX_CHECK(!o.sample_bf16 || o.dtype == HSSX_C64, HSSX_EINVAL,
                "bf16 sampling needs a complex64 factor");
+    HSSX_CHECK(!o.wide_inverse || o.dtype == HSSX_C64, HSSX_EINVAL,
+               "wide_inverse applies to complex64 factors");
     DeviceScope ds(A->device);
     AllocScope as_(g_bound, stream);
     hipStream_t st = S(stream);
@@ -981,10 +983,11 @@ hssx_status hssx_hss_eval(int device, hssx_dtype dtype, int m, int ncl, const in
                           const void *x_dev, void *y_dev, long nij, const int32_t *ij,
                           double *vals, void *stream) {
   return guarded([&] {
-    HSSX_CHECK(m >= 1 && ncl >= 1 && tree && rank && gens && op >= 0 && op <= 3, HSSX_EINVAL,
+    HSSX_CHECK(m >= 1 && ncl >= 1 && tree && rank && gens && op >= 0 && op <= 5, HSSX_EINVAL,
                "invalid argument");
-    HSSX_CHECK(op >= 2 || (nrhs >= 1 && x_dev && y_dev), HSSX_EINVAL, "vectors");
-    HSSX_CHECK(op < 2 || (nij >= 0 && (nij == 0 || (ij && vals))), HSSX_EINVAL, "entry lists");
+    const int base = op == 4 ? 1 : op == 5 ? 3 : op;
+    HSSX_CHECK(base >= 2 || (nrhs >= 1 && x_dev && y_dev), HSSX_EINVAL, "vectors");
+    HSSX_CHECK(base < 2 || (nij >= 0 && (nij == 0 || (ij && vals))), HSSX_EINVAL, "entry lists");
     HSSX_CHECK(dtype == HSSX_C128 || dtype == HSSX_C64, HSSX_EINVAL, "dtype");
     DeviceScope ds(device);
     AllocScope as_(g_bound, stream);

@@ -385,8 +385,12 @@ class Staging {
       for (size_t g = g0; same && g < g1; ++g) same = c.state[g] == kClean;
       same = same && std::memcmp(h, v.data(), bytes) == 0;
       if (!same) {
+        // whole granules go up (the tail of the last one zeroed): a granule
+        // marked clean then equals its host image in every byte, also where a
+        // later placement at a shifted offset reaches past this one's end
         std::memcpy(h, v.data(), bytes);
-        HSSX_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st_));
+        std::memset(h + bytes, 0, need - bytes);
+        HSSX_HIP(hipMemcpyAsync(d, h, need, hipMemcpyHostToDevice, st_));
         for (size_t g = g0; g < g1; ++g) c.state[g] = read_only ? kPending : kUnknown;
       }
     }

@@ -935,6 +935,20 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
   HD.resize(sym.nodes.size());
   Alloc<T> keep = [&](size_t n) { return P.store.get<cplx<T>>(n); };
   Alloc<T> scratch = [&](size_t n) { return ar.get<cplx<T>>(n); };
+  // telescoping inverses of the HSS-class nodes; with wide_inverse a
+  // complex64 factor computes them in complex128 (gym_factor_wide) and keeps
+  // them in complex64
+  auto gym_inverse = [&](std::vector<HssInv<T>> &out, const std::vector<const Gen<T> *> &in,
+                         const std::vector<int> &nid, double &gf) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (P.opts.wide_inverse) {
+        Alloc<double> wide = [&](size_t n) { return ar.get<c128>(n); };
+        gym_factor_wide(out, in, nid, keep, wide, err, sg, ar, val, st, &gf);
+        return;
+      }
+    }
+    gym_factor(out, in, nid, keep, scratch, err, sg, ar, val, st, &gf);
+  };
   CompressAcc cacc;
   double flops = 0;
   int kmax = 0, rounds_max = 0, ncomp = 0, rounds_sum = 0;
@@ -1069,7 +1083,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         std::vector<HssInv<T>> out;
         hipEvent_t pg = prof_begin(st);
         double gf = 0;
-        gym_factor(out, in, nid, keep, scratch, err, sg, ar, val, st, &gf);
+        gym_inverse(out, in, nid, gf);
         prof_end("hss_inverse", st, pg, gf);
         flops += gf;
         for (size_t i = 0; i < who.size(); ++i) who[i]->nd->Hmu = std::move(out[i]);
@@ -1183,7 +1197,7 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
         std::vector<HssInv<T>> out;
         hipEvent_t pg = prof_begin(st);
         double gf = 0;
-        gym_factor(out, in, nid, keep, scratch, err, sg, ar, val, st, &gf);
+        gym_inverse(out, in, nid, gf);
         prof_end("hss_inverse", st, pg, gf);
         flops += gf;
         for (size_t i = 0; i < who.size(); ++i) who[i]->nd->Hs = std::move(out[i]);

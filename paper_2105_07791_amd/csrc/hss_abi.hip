@@ -14,6 +14,9 @@ template <typename T>
 void hss_eval_t(int m, int ncl, const int32_t *tree, const int32_t *rank, const double *gens, int op,
               int nrhs, const c128 *X, c128 *Y, long nij, const int32_t *ij, double *vals,
               hipStream_t st) {
+  // ops 4 and 5: ops 1 and 3 with the inverse computed in complex128
+  const bool wide = op == 4 || op == 5;
+  if (wide) op = op == 4 ? 1 : 3;
   HssMat<T> H;
   H.m = m;
   ClusterTree &ct = H.ct;
@@ -87,8 +90,18 @@ void hss_eval_t(int m, int ncl, const int32_t *tree, const int32_t *rank, const 
       int *d0 = sg->put(std::vector<int>{-1});
       HSSX_HIP(hipMemcpyAsync(err, d0, sizeof(int), hipMemcpyDeviceToDevice, st));
       double fl = 0;
-      gym_factor(inv, std::vector<const Gen<T> *>{&gen}, std::vector<int>{0}, al, al, err, *sg,
-                 *ar, nullptr, st, &fl);
+      bool done_wide = false;
+      if constexpr (sizeof(T) == sizeof(float)) {
+        if (wide) {
+          Alloc<double> wal = [&](size_t n) { return ar->get<c128>(n); };
+          gym_factor_wide(inv, std::vector<const Gen<T> *>{&gen}, std::vector<int>{0}, al, wal,
+                          err, *sg, *ar, nullptr, st, &fl);
+          done_wide = true;
+        }
+      }
+      if (!done_wide)
+        gym_factor(inv, std::vector<const Gen<T> *>{&gen}, std::vector<int>{0}, al, al, err, *sg,
+                   *ar, nullptr, st, &fl);
       int bad = -1;
       HSSX_HIP(hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, st));
       HSSX_HIP(hipStreamSynchronize(st));

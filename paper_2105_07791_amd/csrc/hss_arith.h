@@ -687,6 +687,98 @@ void gym_solve(Prog<T> &p, const std::vector<SolveItem<T>> &items, const Alloc<T
   }
 }
 
+// Telescoping inverses of complex64 generators computed in complex128 and
+// stored in complex64.  On indefinite Schur complements the leaf blocks D
+// and the reduced blocks U^T D^-1 U can be nearly singular; in single
+// precision their inverses, and G = D^-1 - E Z^T formed from them, then carry
+// errors far above the rounding level, which the compressions built on these
+// inverses cannot get below.  The generators are widened once, the levels run
+// as in gym_factor<double> (scratch from wide), and E, G are rounded once.
+inline void gym_factor_wide(std::vector<HssInv<float>> &out,
+                            const std::vector<const Gen<float> *> &in, const std::vector<int> &node,
+                            const Alloc<float> &store, const Alloc<double> &wide, int *err,
+                            Staging &sg, Arena &ar, const c128 *val, hipStream_t st,
+                            double *flops) {
+  const size_t n = in.size();
+  std::vector<Gen<double>> gd(n);
+  Prog<float> up;
+  Stage<float> &sw = up.add(kGtw);
+  auto widen = [&](const cplx<float> *src, int ld, int rows, int cols) -> const c128 * {
+    if (!src || rows <= 0 || cols <= 0) return nullptr;
+    c128 *d = wide((size_t)rows * cols);
+    sw.gtw.push_back(GatherJob<cplx<float>, c128>{src, d, ld, rows, nullptr, nullptr, rows, cols, 0,
+                                                  1.0});
+    return d;
+  };
+  for (size_t i = 0; i < n; ++i) {
+    const Gen<float> &g = *in[i];
+    Gen<double> &h = gd[i];
+    h.ct = g.ct;
+    h.root = g.root;
+    h.k = g.k;
+    const int nc = g.ct->count();
+    h.U.assign(nc, nullptr); h.D.assign(nc, nullptr); h.B12.assign(nc, nullptr);
+    h.B21.assign(nc, nullptr);
+    h.ldU.assign(nc, 1); h.ldD.assign(nc, 1); h.ldB12.assign(nc, 1); h.ldB21.assign(nc, 1);
+    for (const auto &l : sub_levels(*g.ct, g.root))
+      for (int c : l) {
+        const int rows = g.rowsU(c), k = c == g.root ? 0 : g.k[c];
+        if (k) {
+          h.U[c] = widen(g.U[c], g.ldU[c], rows, k);
+          h.ldU[c] = std::max(1, rows);
+        }
+        if (g.ct->leaf(c)) {
+          const int sz = g.ct->size[c];
+          h.D[c] = widen(g.D[c], g.ldD[c], sz, sz);
+          h.ldD[c] = std::max(1, sz);
+        } else {
+          const int kl = g.k[g.ct->left[c]], kr = g.k[g.ct->right[c]];
+          h.B12[c] = widen(g.B12[c], g.ldB12[c], kl, kr);
+          h.B21[c] = widen(g.B21[c], g.ldB21[c], kr, kl);
+          h.ldB12[c] = std::max(1, kl);
+          h.ldB21[c] = std::max(1, kr);
+        }
+      }
+  }
+  run_prog(up, sg, val, st);
+  std::vector<const Gen<double> *> gp;
+  for (auto &h : gd) gp.push_back(&h);
+  std::vector<HssInv<double>> od;
+  gym_factor<double>(od, gp, node, wide, wide, err, sg, ar, val, st, flops);
+  // the same structure in complex64 storage
+  out.assign(n, HssInv<float>{});
+  Prog<float> down;
+  Stage<float> &sn = down.add(kGwt);
+  for (size_t i = 0; i < n; ++i) {
+    const HssInv<double> &w = od[i];
+    HssInv<float> &h = out[i];
+    h.ct = w.ct;
+    h.root = w.root;
+    h.base = w.base;
+    h.lev = w.lev;
+    h.k = w.k;
+    h.mc = w.mc;
+    h.par = w.par;
+    const int nc = w.ct->count();
+    h.E.assign(nc, nullptr);
+    h.G.assign(nc, nullptr);
+    h.W.assign(nc, nullptr);
+    for (const auto &l : w.lev)
+      for (int c : l) {
+        const int m = w.mc[c], k = w.k[c];
+        h.E[c] = store(std::max<size_t>(1, (size_t)m * k));
+        h.G[c] = store(std::max<size_t>(1, (size_t)m * m));
+        if (m && k)
+          sn.gwt.push_back(GatherJob<c128, cplx<float>>{w.E[c], h.E[c], m, m, nullptr, nullptr, m,
+                                                        k, 0, 1.0});
+        if (m)
+          sn.gwt.push_back(GatherJob<c128, cplx<float>>{w.G[c], h.G[c], m, m, nullptr, nullptr, m,
+                                                        m, 0, 1.0});
+      }
+  }
+  run_prog(down, sg, val, st);
+}
+
 // W_c = G_c + E_c W_p(c, c) E_c^T top-down (W_root = G_root): H^-1 in HSS
 // form with bases E (inverse_view)
 template <typename T>

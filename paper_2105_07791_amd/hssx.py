@@ -171,13 +171,14 @@ class Factor:
 
     def __init__(self, A, tol=1e-6, leaf_size=32, beta=16, h_sw=4, k0=32, r=16,
                  max_rounds=32, dtype="c128", seed=0, id_rel_tol=0.0, apply_graph=True,
-                 autotune=True, sample_bf16=False, strict_tol=False, switch_size=0, stream=None):
+                 autotune=True, sample_bf16=False, strict_tol=False, switch_size=0,
+                 wide_inverse=False, stream=None):
         self.A = A
         opts = _lib.FactorOpts(beta, h_sw, k0, r, max_rounds,
                                _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64,
                                seed, id_rel_tol, int(apply_graph), int(autotune),
                                int(sample_bf16),  # 0, 1 (bf16) or 2 (split bf16)
-                               int(switch_size), int(strict_tol))
+                               int(switch_size), int(strict_tol), int(wide_inverse))
         h = C.c_void_p()
         check(lib().hssx_factor(A.handle, float(tol), int(leaf_size), C.byref(opts),
                                 _stream(stream), C.byref(h)))
@@ -254,7 +255,8 @@ def hss_eval(tree, rank, gens, op, X=None, ij=None, dtype="c128", device=0, stre
     rows (start, size, left, right, level); rank int32 (ncl,); gens complex128
     packed as in include/hssx.h.  op 0: H X, 1: H^-1 X (X a complex128 device
     tensor (m,) or (m, nrhs)); op 2: H(i, j), 3: H^-1(i, j) for the rows of ij
-    (int (n, 2)), returned as a complex128 numpy array."""
+    (int (n, 2)), returned as a complex128 numpy array; ops 4 and 5: ops 1 and 3
+    with the inverse computed in complex128."""
     tree = np.ascontiguousarray(tree, dtype=np.int32)
     rank = np.ascontiguousarray(rank, dtype=np.int32)
     g = np.ascontiguousarray(np.asarray(gens, dtype=np.complex128)).view(np.float64)
@@ -262,7 +264,7 @@ def hss_eval(tree, rank, gens, op, X=None, ij=None, dtype="c128", device=0, stre
     dt = _lib.HSSX_C128 if dtype == "c128" else _lib.HSSX_C64
     args = (device, dt, m, ncl, tree.ctypes.data_as(_lib._ip), rank.ctypes.data_as(_lib._ip),
             g.ctypes.data_as(_lib._dp), int(op))
-    if op in (0, 1):
+    if op in (0, 1, 4):
         xt, n, nrhs = _col_major(X, torch.complex128)
         y = torch.empty((nrhs, n), dtype=torch.complex128, device=X.device)
         check(lib().hssx_hss_eval(*args, nrhs, C.c_void_p(xt.data_ptr()), C.c_void_p(y.data_ptr()),

@@ -100,3 +100,16 @@ def test_invalid_arguments_rejected():
         assert L.hssx_assemble_ipdg(0, ctypes.byref(d), ctypes.c_void_p(8), None,
                                     ctypes.byref(h)) == -1
     assert L.hssx_assemble_ipdg(0, None, ctypes.c_void_p(8), None, ctypes.byref(h)) == -1
+    # HSS building blocks: op range, and the vectors of ops 0, 1 and 4 (the
+    # complex128 inverse) before any device call
+    tree = (ctypes.c_int32 * 5)(0, 4, -1, -1, 0)
+    rank = (ctypes.c_int32 * 1)(0)
+    gens = (ctypes.c_double * 32)()
+    for op in (-1, 6):
+        assert L.hssx_hss_eval(0, _lib.HSSX_C64, 4, 1, tree, rank, gens, op, 1, ctypes.c_void_p(8),
+                               ctypes.c_void_p(8), 0, None, None, None) == -1
+    for op in (0, 1, 4):
+        assert L.hssx_hss_eval(0, _lib.HSSX_C64, 4, 1, tree, rank, gens, op, 1, None, None, 0,
+                               None, None, None) == -1
+    assert L.hssx_hss_eval(0, _lib.HSSX_C64, 4, 1, tree, rank, gens, 5, 0, None, None, 3, None,
+                           None, None) == -1

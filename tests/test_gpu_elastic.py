@@ -97,11 +97,14 @@ def test_compressed_factor_matches_oracle(name, h_sw):
         assert np.linalg.norm(x[:, r] - ye[:, r]) <= 1e-6 * np.linalg.norm(ye[:, r])
 
 
-def test_c64_factor_flexible_gmres():
-    """complex64 factor inside FP64 flexible GMRES reaches the FP64 target."""
+@pytest.mark.parametrize("wide", [False, True])
+def test_c64_factor_flexible_gmres(wide):
+    """complex64 factor inside FP64 flexible GMRES reaches the FP64 target,
+    also with the telescoping inverses computed in complex128."""
     dev = _dev()
     hx, pr, A = _op("elastic_p1_129")
-    P = hx.Factor(A, tol=1e-4, leaf_size=64, beta=32, h_sw=4, dtype="c64", seed=1)
+    P = hx.Factor(A, tol=1e-4, leaf_size=64, beta=32, h_sw=4, dtype="c64", seed=1,
+                  wide_inverse=wide)
     b = A.load(torch.tensor(pr.f, device=dev))
     x, stats = hx.gmres_solve(A, P, b, flexible=True)
     Ao = fem.assemble_elastic(pr.N, pr.omega, pr.lam, pr.mu, pr.rho)
@@ -123,6 +126,8 @@ def test_elastic_errors_are_reported():
         hx.Factor(A, tol=1e-6, leaf_size=1)
     with pytest.raises(HssxError):
         hx.Factor(A, tol=1e-6, beta=1)
+    with pytest.raises(HssxError):
+        hx.Factor(A, tol=1e-6, dtype="c128", wide_inverse=True)
     with pytest.raises(HssxError):
         A.dAds_contract(torch.zeros(A.n, dtype=torch.complex128, device="cuda:0"),
                         torch.zeros(A.n, dtype=torch.complex128, device="cuda:0"))

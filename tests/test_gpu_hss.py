@@ -97,6 +97,37 @@ def test_telescoping_inverse(name, dtype, tol):
     assert np.linalg.norm(Hd @ Y - X) <= 10 * tol * np.linalg.norm(X)
 
 
+@pytest.mark.parametrize("name", ["c1_root_child", "c129_root_child", "c129_mid"])
+def test_wide_telescoping_inverse(name):
+    """Ops 4 and 5: the complex64 telescoping inverse computed in complex128
+    (the factor option wide_inverse) against dense numpy solves and inverses,
+    to the bounds of the complex64 ops 1 and 3 on the same matrix."""
+    dev = _dev()
+    hx = _hssx()
+    ct = _trees()[name]
+    H = _random(ct, 6, seed=4, shift=40.0)
+    Hd = H.dense()
+    X = np.random.default_rng(2).standard_normal((Hd.shape[0], 3)) + 0.25j
+    Z = np.linalg.solve(Hd, X)
+    Xt = torch.tensor(X, device=dev)
+    Y4 = hx.hss_eval(*_pack(H), 4, X=Xt, dtype="c64").cpu().numpy()
+    assert np.linalg.norm(Y4 - Z) <= 1e-3 * np.linalg.norm(Z)
+    assert np.linalg.norm(Hd @ Y4 - X) <= 1e-2 * np.linalg.norm(X)
+    m = Hd.shape[0]
+    rng = np.random.default_rng(3)
+    ij = np.concatenate([rng.integers(0, m, (300, 2)), np.stack([np.arange(m), np.arange(m)], 1)])
+    Hi = np.linalg.inv(Hd)[ij[:, 0], ij[:, 1]]
+    v5 = hx.hss_eval(*_pack(H), 5, ij=ij, dtype="c64")
+    v3 = hx.hss_eval(*_pack(H), 3, ij=ij, dtype="c64")
+    scale = np.abs(np.linalg.inv(Hd)).max()
+    assert np.abs(v5 - Hi).max() <= 1e-4 * scale
+    assert np.abs(v3 - Hi).max() <= 1e-4 * scale
+    # complex128: ops 4 and 5 are ops 1 and 3
+    Y1 = hx.hss_eval(*_pack(H), 1, X=Xt).cpu().numpy()
+    Y4d = hx.hss_eval(*_pack(H), 4, X=Xt).cpu().numpy()
+    assert np.array_equal(Y1, Y4d)
+
+
 @pytest.mark.parametrize("name", ["c1_root_child", "c129_mid"])
 def test_entry_access(name):
     _dev()
