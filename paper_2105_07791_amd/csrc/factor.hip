@@ -166,7 +166,16 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     HSSX_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
     fs = side->s;
   }
-  if (d_order) launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);
+  if (d_order) {
+    // register-resident Gauss-Jordan when every block fits, else staged in LDS
+    int max_m = 0, max_nc = 0;
+    for (const auto &j : in_lds) {
+      max_m = std::max(max_m, j.m);
+      max_nc = std::max(max_nc, j.ncols);
+    }
+    if (!launch_eliminate_reg<T>((int)in_lds.size(), d_order, err, fs, max_m, max_nc, queue))
+      launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);
+  }
   if (d_small) launch_eliminate<T>((int)small.size(), d_small, err, fs);
   if (d_gd) launch_gemm_sub<T>((int)pr_done.gj.size(), d_gd, pr_done.gm, pr_done.gn, fs);
   if (d_nd) launch_axpby<T>((int)pr_done.neg.size(), d_nd, pr_done.nm, pr_done.nn, fs);

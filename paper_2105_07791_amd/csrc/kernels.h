@@ -77,6 +77,13 @@ template <typename T> struct ElimJob {
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                       size_t lds_bytes = 0, int *queue = nullptr);
+// Register-resident variant for jobs with m == ne <= 64, no negated R block
+// and ncols <= max_nc (at most 320 complex64 or 192 complex128 columns),
+// persistent over the counter *queue (zero before the launch); returns false
+// (nothing launched) when the sizes do not fit
+template <typename T>
+bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
+                          int max_m, int max_nc, int *queue);
 
 // Blocked Gauss-Jordan, one column panel P = [p0, p0 + nb) of one job per
 // entry (jobs of one launch may belong to different fronts):

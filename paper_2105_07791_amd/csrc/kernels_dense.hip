@@ -166,6 +166,121 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
   }
 }
 
+// Gauss-Jordan on small square blocks held in registers: 256 threads, 16 row
+// groups x 16 column groups; thread (i0, cg) keeps rows i0 + 16 r (r < RPT)
+// of columns cg CPT .. cg CPT + CPT - 1.  Rows are not swapped: step p picks
+// the unused row of largest |.|_1 in column p (ties to the smaller row),
+// scales it and removes column p from every other row; the write-back puts
+// the row chosen at step p in position p.  Per step only column p and the
+// scaled pivot row pass through LDS (double-buffered: two barriers a step).
+// Jobs have m == ne <= 16 RPT, ncols <= 16 CPT and no negated R block; the
+// workgroups take jobs from the counter *queue.
+template <typename T, int RPT, int CPT>
+__global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T> *__restrict__ jobs,
+                                                                 int count, int *__restrict__ queue,
+                                                                 int *__restrict__ err_node) {
+  constexpr int RG = 16, NCMAX = 16 * CPT;
+  static_assert(RG * RPT <= 64 && kThreads == 256, "one 64-row block per workgroup");
+  __shared__ T s_abs[2][64];
+  __shared__ cplx<T> s_col[2][64];
+  __shared__ cplx<T> s_row[2][NCMAX];
+  __shared__ int s_order[64], s_pos[64];
+  __shared__ int s_job;
+  const int tid = threadIdx.x, i0 = tid % RG, cg = tid / RG, lane = tid & 63;
+  for (;;) {
+    if (tid == 0) s_job = atomicAdd(queue, 1);
+    if (tid < 64) s_pos[tid] = -1;
+    __syncthreads();
+    const int job = s_job;
+    if (job >= count) break;
+    const ElimJob<T> jb = jobs[job];
+    const int m = jb.m, nc = jb.ncols;
+    const long ld = jb.ld;
+    cplx<T> F[RPT][CPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int i = i0 + r * RG, j = cg * CPT + c;
+        F[r][c] = (i < m && j < nc) ? jb.ptr[i + (long)j * ld] : czero<T>();
+      }
+    unsigned long long used = 0;   // rows already taken as pivots
+    for (int p = 0; p < m; ++p) {
+      const int b = p & 1;
+      // column p, published by its owners (unused rows with their magnitude)
+      if (cg == p / CPT) {
+        const int pc = p % CPT;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+          if (c == pc) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+              const int i = i0 + r * RG;
+              if (i < m) {
+                s_col[b][i] = F[r][c];
+                s_abs[b][i] = ((used >> i) & 1ull) ? (T)-1 : cabs1(F[r][c]);
+              }
+            }
+          }
+      }
+      __syncthreads();
+      // every wave finds the same pivot
+      T best = lane < m ? s_abs[b][lane] : (T)-2;
+      int bi = lane;
+      wave_argmax(best, bi);
+      const bool zero = !(best > (T)0);
+      // a zero (or NaN) column takes the first unused row and is reported
+      const int pv = zero ? __builtin_ctzll(~used) : bi;
+      const cplx<T> inv = zero ? czero<T>() : cinv(s_col[b][pv]);
+      if (tid == 0) {
+        if (zero) atomicCAS(err_node, -1, jb.node);
+        s_order[p] = pv;
+      }
+      used |= 1ull << pv;
+      if (i0 == pv % RG) {
+        const int rr = pv / RG;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (r == rr) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+              F[r][c] = F[r][c] * inv;
+              s_row[b][cg * CPT + c] = F[r][c];
+            }
+          }
+      }
+      __syncthreads();
+      cplx<T> prow[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) prow[c] = s_row[b][cg * CPT + c];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = i0 + r * RG;
+        if (i < m && i != pv) {
+          const cplx<T> a = s_col[b][i];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) cfms(F[r][c], a, prow[c]);
+        }
+      }
+    }
+    if (tid < m) s_pos[s_order[tid]] = tid;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = i0 + r * RG;
+      const int q = i < m ? s_pos[i] : -1;
+      if (q < 0) continue;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int j = cg * CPT + c;
+        if (j >= nc) continue;
+        jb.ptr[q + (long)j * ld] = j < m ? mk((T)(q == j ? 1 : 0), (T)0) : F[r][c];
+      }
+    }
+    __syncthreads();   // s_job, s_order and s_pos are reused by the next job
+  }
+}
+
 template <typename T>
 __device__ void block_argmax(T &v, int &idx, T *sv, int *si) {
   // wave reduction then across waves; ties keep the smaller index
@@ -918,6 +1033,37 @@ void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStrea
 
 
 template <typename T>
+bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
+                          int max_m, int max_nc, int *queue) {
+  if (count <= 0) return true;
+  constexpr bool kF32 = sizeof(T) == sizeof(float);
+  constexpr int kCmax = kF32 ? 20 : 12;
+  if (max_m > 64 || max_nc > 16 * kCmax || !queue) return false;
+  int dev = 0, cus = 256;
+  HSSX_HIP(hipGetDevice(&dev));
+  HSSX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int grid = std::max(1, std::min(count, cus * 4));
+#define HSSX_GJR(R, C)                                                                         \
+  hipLaunchKernelGGL((eliminate_reg_kernel<T, R, C>), dim3(grid), dim3(kThreads), 0, st, jobs, \
+                     count, queue, err_node)
+  const int cpt = max_nc <= 64 ? 4 : max_nc <= 128 ? 8 : max_nc <= 192 ? 12 : 20;
+  if (max_m <= 16) {
+    if (cpt == 4) HSSX_GJR(1, 4);
+    else if (cpt == 8) HSSX_GJR(1, 8);
+    else if (cpt == 12) HSSX_GJR(1, 12);
+    else if constexpr (kF32) HSSX_GJR(1, 20);
+  } else {
+    if (cpt == 4) HSSX_GJR(4, 4);
+    else if (cpt == 8) HSSX_GJR(4, 8);
+    else if (cpt == 12) HSSX_GJR(4, 12);
+    else if constexpr (kF32) HSSX_GJR(4, 20);
+  }
+#undef HSSX_GJR
+  HSSX_HIP(hipGetLastError());
+  return true;
+}
+
+template <typename T>
 void launch_panel_step(int count, const PanelJob<T> *jobs, int max_m, int max_cols,
                        int max_prows, int max_nb, int *err_node, hipStream_t st) {
   if (count <= 0) return;
@@ -979,6 +1125,8 @@ HSSX_ASM(double, float)
 #define HSSX_INST(T)                                                                        \
   template void launch_eliminate<T>(int, const ElimJob<T> *, int *, hipStream_t, size_t,    \
                                     int *);                                                 \
+  template bool launch_eliminate_reg<T>(int, const ElimJob<T> *, int *, hipStream_t, int, int, \
+                                        int *);                                             \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
                                      hipStream_t);                                          \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);           \
