@@ -171,7 +171,7 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     int max_m = 0, max_nc = 0;
     for (const auto &j : in_lds) {
       max_m = std::max(max_m, j.m);
-      max_nc = std::max(max_nc, j.ncols);
+      max_nc = std::max(max_nc, j.ncols - j.m);
     }
     if (!launch_eliminate_reg<T>((int)in_lds.size(), d_order, err, fs, max_m, max_nc, queue))
       launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);

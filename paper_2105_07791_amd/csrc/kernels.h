@@ -65,6 +65,8 @@ void launch_front_assemble(int count, const int *nodes, const FrontDesc *desc,
 // normalised; every other row, including rows >= ne, is reduced.  Columns
 // >= ne of rows >= ne end as the Schur complement.  With negate_r the block
 // (0:ne, ne:m) is negated afterwards.
+// The last ne columns of a job hold the identity on its pivot rows (and
+// zeros below): they receive the inverse of the pivot block.
 template <typename T> struct ElimJob {
   cplx<T> *ptr;
   int ld, m, ncols, ne, negate_r;
@@ -78,9 +80,11 @@ template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                       size_t lds_bytes = 0, int *queue = nullptr);
 // Register-resident variant for jobs with m == ne <= 64, no negated R block
-// and ncols <= max_nc (at most 320 complex64 or 192 complex128 columns),
-// persistent over the counter *queue (zero before the launch); returns false
-// (nothing launched) when the sizes do not fit
+// and ncols - m <= max_nc (at most 320 complex64 or 192 complex128 columns),
+// persistent over the counter *queue (zero before the launch); it inverts in
+// place and relies on the last ne columns holding the identity on input
+// (every job of the factorization is laid out so).  Returns false (nothing
+// launched) when the sizes do not fit
 template <typename T>
 bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                           int max_m, int max_nc, int *queue);

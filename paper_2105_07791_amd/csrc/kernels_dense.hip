@@ -166,15 +166,22 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
   }
 }
 
-// Gauss-Jordan on small square blocks held in registers: 256 threads, 16 row
-// groups x 16 column groups; thread (i0, cg) keeps rows i0 + 16 r (r < RPT)
-// of columns cg CPT .. cg CPT + CPT - 1.  Rows are not swapped: step p picks
-// the unused row of largest |.|_1 in column p (ties to the smaller row),
-// scales it and removes column p from every other row; the write-back puts
-// the row chosen at step p in position p.  Per step only column p and the
-// scaled pivot row pass through LDS (double-buffered: two barriers a step).
-// Jobs have m == ne <= 16 RPT, ncols <= 16 CPT and no negated R block; the
-// workgroups take jobs from the counter *queue.
+// Gauss-Jordan on small square blocks held in registers, inverting in place:
+// a job's last ne columns hold the identity on input and are not read; the
+// kernel works on the first W = ncols - ne columns and writes the inverse of
+// the leading block into those last columns.  256 threads, 16 row groups x
+// 16 column groups; thread (i0, cg) keeps rows i0 + 16 r (r < RPT) of working
+// columns cg CPT .. cg CPT + CPT - 1.  Rows are not swapped: step p picks the
+// unused row of largest |.|_1 in column p (ties to the smaller row) as the
+// pivot row r_p, scales it and removes column p from every other row; slot p
+// then holds column r_p of the accumulated row operations (the identity
+// column that only row r_p touched until this step), i.e. row r_q of slot p
+// is entry (q, r_p) of the inverse.  The write-back puts row r_q in position
+// q, the identity in the leading block and the inverse in the last block.
+// Per step only column p and the scaled pivot row pass through LDS
+// (double-buffered: two barriers a step).  Jobs have m == ne <= 16 RPT,
+// W <= 16 CPT and no negated R block; the workgroups take jobs from the
+// counter *queue.
 template <typename T, int RPT, int CPT>
 __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T> *__restrict__ jobs,
                                                                  int count, int *__restrict__ queue,
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
     const int job = s_job;
     if (job >= count) break;
     const ElimJob<T> jb = jobs[job];
-    const int m = jb.m, nc = jb.ncols;
+    const int m = jb.m, w = jb.ncols - jb.m;
     const long ld = jb.ld;
     cplx<T> F[RPT][CPT];
 #pragma unroll
@@ -202,14 +209,15 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int i = i0 + r * RG, j = cg * CPT + c;
-        F[r][c] = (i < m && j < nc) ? jb.ptr[i + (long)j * ld] : czero<T>();
+        F[r][c] = (i < m && j < w) ? jb.ptr[i + (long)j * ld] : czero<T>();
       }
     unsigned long long used = 0;   // rows already taken as pivots
     for (int p = 0; p < m; ++p) {
       const int b = p & 1;
+      const bool pcol = cg == p / CPT;   // this thread holds slot p
+      const int pc = p % CPT;
       // column p, published by its owners (unused rows with their magnitude)
-      if (cg == p / CPT) {
-        const int pc = p % CPT;
+      if (pcol) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
           if (c == pc) {
@@ -237,6 +245,8 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
         s_order[p] = pv;
       }
       used |= 1ull << pv;
+      // the pivot row, scaled; its slot p becomes inv and is left out of the
+      // update (published as 0)
       if (i0 == pv % RG) {
         const int rr = pv / RG;
 #pragma unroll
@@ -244,8 +254,10 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
           if (r == rr) {
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-              F[r][c] = F[r][c] * inv;
-              s_row[b][cg * CPT + c] = F[r][c];
+              const bool isp = pcol && c == pc;
+              const cplx<T> v = F[r][c] * inv;
+              F[r][c] = isp ? inv : v;
+              s_row[b][cg * CPT + c] = isp ? czero<T>() : v;
             }
           }
       }
@@ -259,7 +271,11 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
         if (i < m && i != pv) {
           const cplx<T> a = s_col[b][i];
 #pragma unroll
-          for (int c = 0; c < CPT; ++c) cfms(F[r][c], a, prow[c]);
+          for (int c = 0; c < CPT; ++c) {
+            cfms(F[r][c], a, prow[c]);
+            // slot p of the other rows: -a inv
+            if (pcol && c == pc) F[r][c] = -(a * inv);
+          }
         }
       }
     }
@@ -273,8 +289,13 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int j = cg * CPT + c;
-        if (j >= nc) continue;
-        jb.ptr[q + (long)j * ld] = j < m ? mk((T)(q == j ? 1 : 0), (T)0) : F[r][c];
+        if (j >= w) continue;
+        if (j < m) {
+          jb.ptr[q + (long)j * ld] = mk((T)(q == j ? 1 : 0), (T)0);
+          jb.ptr[q + (long)(w + s_order[j]) * ld] = F[r][c];
+        } else {
+          jb.ptr[q + (long)j * ld] = F[r][c];
+        }
       }
     }
     __syncthreads();   // s_job, s_order and s_pos are reused by the next job
@@ -1039,6 +1060,7 @@ bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipS
   constexpr bool kF32 = sizeof(T) == sizeof(float);
   constexpr int kCmax = kF32 ? 20 : 12;
   if (max_m > 64 || max_nc > 16 * kCmax || !queue) return false;
+  // max_nc: largest working width ncols - m
   int dev = 0, cus = 256;
   HSSX_HIP(hipGetDevice(&dev));
   HSSX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
