@@ -128,6 +128,28 @@ def test_wide_telescoping_inverse(name):
     assert np.array_equal(Y1, Y4d)
 
 
+@pytest.mark.parametrize("dtype,op", [("c128", 1), ("c64", 1), ("c64", 4)])
+def test_singular_leaf_block_reported(dtype, op):
+    """A zero leaf block makes the telescoping inverse fail with ESINGULAR
+    (the elimination reports its zero pivot); the next call on a regular
+    matrix still succeeds."""
+    dev = _dev()
+    hx = _hssx()
+    from paper_2105_07791_amd._lib import HssxError
+    ct = _trees()["c129_mid"]
+    H = _random(ct, 6, seed=4, shift=40.0)
+    X = torch.tensor(np.ones((H.dense().shape[0], 2)) + 0j, device=dev)
+    leaf = next(iter(H.D))
+    Hz = _random(ct, 6, seed=4, shift=40.0)
+    Hz.D[leaf] = np.zeros_like(Hz.D[leaf])
+    with pytest.raises(HssxError, match="zero pivot"):
+        hx.hss_eval(*_pack(Hz), op, X=X, dtype=dtype)
+    Y = hx.hss_eval(*_pack(H), op, X=X, dtype=dtype).cpu().numpy()
+    Hd = H.dense()
+    Z = np.linalg.solve(Hd, X.cpu().numpy())
+    assert np.linalg.norm(Y - Z) <= 1e-3 * np.linalg.norm(Z)
+
+
 @pytest.mark.parametrize("name", ["c1_root_child", "c129_mid"])
 def test_entry_access(name):
     _dev()
