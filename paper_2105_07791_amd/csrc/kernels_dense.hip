@@ -178,19 +178,18 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
 // column that only row r_p touched until this step), i.e. row r_q of slot p
 // is entry (q, r_p) of the inverse.  The write-back puts row r_q in position
 // q, the identity in the leading block and the inverse in the last block.
-// Per step only column p and the scaled pivot row pass through LDS
-// (double-buffered: two barriers a step).  Jobs have m == ne <= 16 RPT,
+// Per step only column p passes through LDS (double-buffered: one barrier a
+// step); the pivot row comes by lane shuffles.  Jobs have m == ne <= 16 RPT,
 // W <= 16 CPT and no negated R block; the workgroups take jobs from the
 // counter *queue.
 template <typename T, int RPT, int CPT>
 __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T> *__restrict__ jobs,
                                                                  int count, int *__restrict__ queue,
                                                                  int *__restrict__ err_node) {
-  constexpr int RG = 16, NCMAX = 16 * CPT;
+  constexpr int RG = 16;
   static_assert(RG * RPT <= 64 && kThreads == 256, "one 64-row block per workgroup");
   __shared__ T s_abs[2][64];
   __shared__ cplx<T> s_col[2][64];
-  __shared__ cplx<T> s_row[2][NCMAX];
   __shared__ int s_order[64], s_pos[64];
   __shared__ int s_job;
   const int tid = threadIdx.x, i0 = tid % RG, cg = tid / RG, lane = tid & 63;
@@ -245,26 +244,29 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
         s_order[p] = pv;
       }
       used |= 1ull << pv;
-      // the pivot row, scaled; its slot p becomes inv and is left out of the
-      // update (published as 0)
-      if (i0 == pv % RG) {
-        const int rr = pv / RG;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r)
-          if (r == rr) {
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-              const bool isp = pcol && c == pc;
-              const cplx<T> v = F[r][c] * inv;
-              F[r][c] = isp ? inv : v;
-              s_row[b][cg * CPT + c] = isp ? czero<T>() : v;
-            }
-          }
-      }
-      __syncthreads();
+      // the pivot row, scaled: the lane of this 16-lane group that holds row
+      // pv holds it for the same columns (same wavefront), so it comes by a
+      // lane shuffle, not through LDS; its slot p becomes inv and is left out
+      // of the update (0 in prow)
+      const int rr = pv / RG, src = (lane & ~(RG - 1)) | (pv % RG);
+      const bool owner = i0 == pv % RG;
       cplx<T> prow[CPT];
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) prow[c] = s_row[b][cg * CPT + c];
+      for (int c = 0; c < CPT; ++c) {
+        cplx<T> v = czero<T>();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (r == rr) v = F[r][c];
+        v = mk(__shfl(v.re, src), __shfl(v.im, src));
+        const bool isp = pcol && c == pc;
+        const cplx<T> sv = v * inv;
+        prow[c] = isp ? czero<T>() : sv;
+        if (owner) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r)
+            if (r == rr) F[r][c] = isp ? inv : sv;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = i0 + r * RG;
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
         }
       }
     }
+    __syncthreads();   // the last step's s_order entry
     if (tid < m) s_pos[s_order[tid]] = tid;
     __syncthreads();
 #pragma unroll
