@@ -122,11 +122,15 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
   // (pivot rows only; the others follow by the product below), the rest of
   // the few-pivot fronts in one workgroup from global memory
   constexpr size_t kLdsMax = 156 * 1024;   // of the 160 KiB per workgroup
-  std::vector<ElimJob<T>> in_lds, rows_done;
+  std::vector<ElimJob<T>> in_lds, rows_done, reg2;
   size_t lds = 0;
   for (const auto &j : jobs) {
     const size_t b = (size_t)j.ne * j.ncols * sizeof(cplx<T>);
-    if (j.ne < kSmall && j.ne > 0 && b <= kLdsMax) {
+    if (j.ne >= kSmall && j.ne <= 128 && j.m == j.ne && !j.negate_r &&
+        j.ncols - j.m <= eliminate_reg_max_cols<T>(j.ne)) {
+      // square blocks of 64-128 pivots: one register-resident workgroup each
+      reg2.push_back(j);
+    } else if (j.ne < kSmall && j.ne > 0 && b <= kLdsMax) {
       ElimJob<T> q = j;
       q.m = j.ne;
       q.negate_r = 0;
@@ -154,6 +158,20 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
     d_order = sg.put_const(order);
   }
   if (!small.empty()) d_small = sg.put_const(small);
+  int *queue2 = nullptr;
+  ElimJob<T> *d_reg2 = nullptr;
+  int reg2_m = 0, reg2_w = 0;
+  if (!reg2.empty()) {
+    std::stable_sort(reg2.begin(), reg2.end(), [](const ElimJob<T> &a, const ElimJob<T> &b) {
+      return (long)a.ne * a.ncols > (long)b.ne * b.ncols;
+    });
+    for (const auto &j : reg2) {
+      reg2_m = std::max(reg2_m, j.ne);
+      reg2_w = std::max(reg2_w, j.ncols - j.m);
+    }
+    queue2 = sg.put(std::vector<int>{0});
+    d_reg2 = sg.put_const(reg2);
+  }
   // products over the non-pivot rows and the negation of R for the fronts
   // eliminated in LDS, queued on the same stream right after them
   const ProductLists pr_done = product_lists(rows_done);
@@ -177,6 +195,9 @@ void eliminate_jobs(const std::vector<ElimJob<T>> &jobs, int *err, Staging &sg, 
       launch_eliminate<T>((int)in_lds.size(), d_order, err, fs, lds, queue);
   }
   if (d_small) launch_eliminate<T>((int)small.size(), d_small, err, fs);
+  if (d_reg2)
+    HSSX_CHECK(launch_eliminate_reg<T>((int)reg2.size(), d_reg2, err, st, reg2_m, reg2_w, queue2),
+               HSSX_EINVAL, "register elimination sizes");
   if (d_gd) launch_gemm_sub<T>((int)pr_done.gj.size(), d_gd, pr_done.gm, pr_done.gn, fs);
   if (d_nd) launch_axpby<T>((int)pr_done.neg.size(), d_nd, pr_done.nm, pr_done.nn, fs);
   if (big.empty()) return;   // no fork without large fronts

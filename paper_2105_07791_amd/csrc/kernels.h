@@ -79,12 +79,13 @@ template <typename T> struct ElimJob {
 template <typename T>
 void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                       size_t lds_bytes = 0, int *queue = nullptr);
-// Register-resident variant for jobs with m == ne <= 64, no negated R block
-// and ncols - m <= max_nc (at most 320 complex64 or 192 complex128 columns),
-// persistent over the counter *queue (zero before the launch); it inverts in
-// place and relies on the last ne columns holding the identity on input
-// (every job of the factorization is laid out so).  Returns false (nothing
-// launched) when the sizes do not fit
+// Register-resident variant for jobs with m == ne <= 128, no negated R block
+// and ncols - m <= eliminate_reg_max_cols<T>(m), persistent over the counter
+// *queue (zero before the launch); it inverts in place and relies on the
+// last ne columns holding the identity on input (every job of the
+// factorization is laid out so).  Returns false (nothing launched) when the
+// sizes do not fit
+template <typename T> int eliminate_reg_max_cols(int max_m);
 template <typename T>
 bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                           int max_m, int max_nc, int *queue);

@@ -169,9 +169,10 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
 // Gauss-Jordan on small square blocks held in registers, inverting in place:
 // a job's last ne columns hold the identity on input and are not read; the
 // kernel works on the first W = ncols - ne columns and writes the inverse of
-// the leading block into those last columns.  256 threads, 16 row groups x
-// 16 column groups; thread (i0, cg) keeps rows i0 + 16 r (r < RPT) of working
-// columns cg CPT .. cg CPT + CPT - 1.  Rows are not swapped: step p picks the
+// the leading block into those last columns.  NT threads, RG row groups x
+// NT / RG column groups; thread (i0, cg) keeps rows i0 + RG r (r < RPT) of
+// working columns cg CPT .. cg CPT + CPT - 1; the RG threads of a column
+// group sit in one wavefront.  Rows are not swapped: step p picks the
 // unused row of largest |.|_1 in column p (ties to the smaller row) as the
 // pivot row r_p, scales it and removes column p from every other row; slot p
 // then holds column r_p of the accumulated row operations (the identity
@@ -179,23 +180,23 @@ __global__ __launch_bounds__(kThreads) void eliminate_lds_kernel(const ElimJob<T
 // is entry (q, r_p) of the inverse.  The write-back puts row r_q in position
 // q, the identity in the leading block and the inverse in the last block.
 // Per step only column p passes through LDS (double-buffered: one barrier a
-// step); the pivot row comes by lane shuffles.  Jobs have m == ne <= 16 RPT,
-// W <= 16 CPT and no negated R block; the workgroups take jobs from the
-// counter *queue.
-template <typename T, int RPT, int CPT>
-__global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T> *__restrict__ jobs,
-                                                                 int count, int *__restrict__ queue,
-                                                                 int *__restrict__ err_node) {
-  constexpr int RG = 16;
-  static_assert(RG * RPT <= 64 && kThreads == 256, "one 64-row block per workgroup");
-  __shared__ T s_abs[2][64];
-  __shared__ cplx<T> s_col[2][64];
-  __shared__ int s_order[64], s_pos[64];
+// step); the pivot row comes by lane shuffles.  Jobs have m == ne <= RG RPT
+// <= 128, W <= (NT / RG) CPT and no negated R block; the workgroups take jobs
+// from the counter *queue.
+template <typename T, int NT, int RG, int RPT, int CPT>
+__global__ __launch_bounds__(NT) void eliminate_reg_kernel(const ElimJob<T> *__restrict__ jobs,
+                                                           int count, int *__restrict__ queue,
+                                                           int *__restrict__ err_node) {
+  constexpr int MR = RG * RPT;
+  static_assert(MR <= 128 && (RG == 16 || RG == 32) && NT % 64 == 0, "at most 128 rows");
+  __shared__ T s_abs[2][128];
+  __shared__ cplx<T> s_col[2][128];
+  __shared__ int s_order[128], s_pos[128];
   __shared__ int s_job;
   const int tid = threadIdx.x, i0 = tid % RG, cg = tid / RG, lane = tid & 63;
   for (;;) {
     if (tid == 0) s_job = atomicAdd(queue, 1);
-    if (tid < 64) s_pos[tid] = -1;
+    if (tid < 128) s_pos[tid] = -1;
     __syncthreads();
     const int job = s_job;
     if (job >= count) break;
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
         const int i = i0 + r * RG, j = cg * CPT + c;
         F[r][c] = (i < m && j < w) ? jb.ptr[i + (long)j * ld] : czero<T>();
       }
-    unsigned long long used = 0;   // rows already taken as pivots
+    unsigned long long used0 = 0, used1 = 0;   // rows taken as pivots (0-63, 64-127)
     for (int p = 0; p < m; ++p) {
       const int b = p & 1;
       const bool pcol = cg == p / CPT;   // this thread holds slot p
@@ -225,7 +226,8 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
               const int i = i0 + r * RG;
               if (i < m) {
                 s_col[b][i] = F[r][c];
-                s_abs[b][i] = ((used >> i) & 1ull) ? (T)-1 : cabs1(F[r][c]);
+                const bool u = i < 64 ? ((used0 >> i) & 1ull) : ((used1 >> (i - 64)) & 1ull);
+                s_abs[b][i] = u ? (T)-1 : cabs1(F[r][c]);
               }
             }
           }
@@ -234,16 +236,22 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
       // every wave finds the same pivot
       T best = lane < m ? s_abs[b][lane] : (T)-2;
       int bi = lane;
+      if (MR > 64 && lane + 64 < m) {
+        const T o = s_abs[b][lane + 64];
+        if (o > best) { best = o; bi = lane + 64; }
+      }
       wave_argmax(best, bi);
       const bool zero = !(best > (T)0);
       // a zero (or NaN) column takes the first unused row and is reported
-      const int pv = zero ? __builtin_ctzll(~used) : bi;
+      const int first = ~used0 ? __builtin_ctzll(~used0) : 64 + __builtin_ctzll(~used1);
+      const int pv = zero ? first : bi;
       const cplx<T> inv = zero ? czero<T>() : cinv(s_col[b][pv]);
       if (tid == 0) {
         if (zero) atomicCAS(err_node, -1, jb.node);
         s_order[p] = pv;
       }
-      used |= 1ull << pv;
+      if (pv < 64) used0 |= 1ull << pv;
+      else used1 |= 1ull << (pv - 64);
       // the pivot row, scaled: the lane of this 16-lane group that holds row
       // pv holds it for the same columns (same wavefront), so it comes by a
       // lane shuffle, not through LDS; its slot p becomes inv and is left out
@@ -282,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void eliminate_reg_kernel(const ElimJob<T
       }
     }
     __syncthreads();   // the last step's s_order entry
-    if (tid < m) s_pos[s_order[tid]] = tid;
+    for (int t = tid; t < m; t += NT) s_pos[s_order[t]] = t;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -1057,31 +1065,48 @@ void launch_eliminate(int count, const ElimJob<T> *jobs, int *err_node, hipStrea
 
 
 template <typename T>
+int eliminate_reg_max_cols(int max_m) {
+  constexpr bool kF32 = sizeof(T) == sizeof(float);
+  if (max_m <= 64) return kF32 ? 320 : 192;
+  if (max_m <= 128) return kF32 ? 320 : 128;
+  return 0;
+}
+
+template <typename T>
 bool launch_eliminate_reg(int count, const ElimJob<T> *jobs, int *err_node, hipStream_t st,
                           int max_m, int max_nc, int *queue) {
   if (count <= 0) return true;
   constexpr bool kF32 = sizeof(T) == sizeof(float);
-  constexpr int kCmax = kF32 ? 20 : 12;
-  if (max_m > 64 || max_nc > 16 * kCmax || !queue) return false;
   // max_nc: largest working width ncols - m
+  if (max_m > 128 || max_nc > eliminate_reg_max_cols<T>(max_m) || !queue) return false;
   int dev = 0, cus = 256;
   HSSX_HIP(hipGetDevice(&dev));
   HSSX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int grid = std::max(1, std::min(count, cus * 4));
-#define HSSX_GJR(R, C)                                                                         \
-  hipLaunchKernelGGL((eliminate_reg_kernel<T, R, C>), dim3(grid), dim3(kThreads), 0, st, jobs, \
-                     count, queue, err_node)
-  const int cpt = max_nc <= 64 ? 4 : max_nc <= 128 ? 8 : max_nc <= 192 ? 12 : 20;
-  if (max_m <= 16) {
-    if (cpt == 4) HSSX_GJR(1, 4);
-    else if (cpt == 8) HSSX_GJR(1, 8);
-    else if (cpt == 12) HSSX_GJR(1, 12);
-    else if constexpr (kF32) HSSX_GJR(1, 20);
+#define HSSX_GJR(NT, RG, R, C)                                                                  \
+  hipLaunchKernelGGL((eliminate_reg_kernel<T, NT, RG, R, C>),                                   \
+                     dim3(std::max(1, std::min(count, cus * (NT == 256 ? 4 : 2)))), dim3(NT), 0, \
+                     st, jobs, count, queue, err_node)
+  if (max_m <= 64) {
+    const int cpt = max_nc <= 64 ? 4 : max_nc <= 128 ? 8 : max_nc <= 192 ? 12 : 20;
+    if (max_m <= 16) {
+      if (cpt == 4) HSSX_GJR(256, 16, 1, 4);
+      else if (cpt == 8) HSSX_GJR(256, 16, 1, 8);
+      else if (cpt == 12) HSSX_GJR(256, 16, 1, 12);
+      else if constexpr (kF32) HSSX_GJR(256, 16, 1, 20);
+    } else {
+      if (cpt == 4) HSSX_GJR(256, 16, 4, 4);
+      else if (cpt == 8) HSSX_GJR(256, 16, 4, 8);
+      else if (cpt == 12) HSSX_GJR(256, 16, 4, 12);
+      else if constexpr (kF32) HSSX_GJR(256, 16, 4, 20);
+    }
   } else {
-    if (cpt == 4) HSSX_GJR(4, 4);
-    else if (cpt == 8) HSSX_GJR(4, 8);
-    else if (cpt == 12) HSSX_GJR(4, 12);
-    else if constexpr (kF32) HSSX_GJR(4, 20);
+    // 512 threads: 32 row groups of 4 rows, 16 column groups
+    const int cpt = max_nc <= 128 ? 8 : max_nc <= 192 ? 12 : 20;
+    if (cpt == 8) HSSX_GJR(512, 32, 4, 8);
+    else if constexpr (kF32) {
+      if (cpt == 12) HSSX_GJR(512, 32, 4, 12);
+      else HSSX_GJR(512, 32, 4, 20);
+    }
   }
 #undef HSSX_GJR
   HSSX_HIP(hipGetLastError());
@@ -1152,6 +1177,7 @@ HSSX_ASM(double, float)
                                     int *);                                                 \
   template bool launch_eliminate_reg<T>(int, const ElimJob<T> *, int *, hipStream_t, int, int, \
                                         int *);                                             \
+  template int eliminate_reg_max_cols<T>(int);                                              \
   template void launch_panel_step<T>(int, const PanelJob<T> *, int, int, int, int, int *,      \
                                      hipStream_t);                                          \
   template void launch_axpby<T>(int, const AxpbyJob<T> *, int, int, hipStream_t);           \
