@@ -286,7 +286,9 @@ def run_batch(args):
     del Pb, Ab
 
     # the same step with fp32 sampling at tolerance 1e-6: time, iterations and
-    # the difference of the gradients (both solves reach the 1e-8 residual)
+    # the difference of the gradients (both solves reach the 1e-8 residual);
+    # the timed steps' cached factor is released first (device memory)
+    cache.clear()
     ref_opts = dict(opts, tol=1e-6, sample_bf16=False)
     torch.cuda.synchronize()
     tr0 = time.perf_counter()

@@ -344,6 +344,12 @@ class Staging {
     cur_ = 0;
     off_ = 0;
   }
+  // bytes placed since the last recycle
+  size_t used() const {
+    size_t b = off_;
+    for (size_t c = 0; c < cur_ && c < chunks_.size(); ++c) b += chunks_[c].cap;
+    return b;
+  }
   void set_stream(hipStream_t st) { st_ = st; }
   hipStream_t stream() const { return st_; }
 

@@ -374,6 +374,9 @@ inline double compress_flops(const HssCluster &c, const HssInstance &I) {
   return f;
 }
 
+// staged job-array bytes of one factorization before the staging area is
+// reused from its start (after a stream synchronisation at a depth boundary)
+constexpr size_t kStageCap = size_t(512) << 20;
 // rows of one local sample block the compression kernel holds
 constexpr int kMaxLocalRows = 1024;
 // acceptance slack of a stalled complex64 estimate, relative to tol
@@ -1456,6 +1459,15 @@ void factor_impl(hssx_fact_ &P, hipStream_t st, Staging &sg, Arena &ar) {
     // advancing within a factorization, so a repeated one finds its arrays
     // where it left them)
     ar.release(depth_mark);
+    // large forests: once the staged arrays pass kStageCap the stream is
+    // drained and staging starts again at its first position (every staged
+    // array serves one depth; positions stay deterministic, so a repeated
+    // factorization still finds its unchanged arrays in place)
+    if (sg.used() > kStageCap) {
+      HSSX_HIP(hipStreamSynchronize(st));
+      sg.synced();
+      sg.recycle();
+    }
   }
   int bad = -1;
   HSSX_HIP(hipStreamSynchronize(st));
